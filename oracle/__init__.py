@@ -1,0 +1,215 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes wrapper around the serial FP64 CPU oracle.
+
+The oracle is the plain reference implementation of the event-chain move for
+tethered hard-sphere melts (Kampmann, Boltz, Kierfeld, arXiv:1502.06447,
+Sec. II and II.A).  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package; the GPU library never
+does.  It shares no code with the GPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ecmc_oracle.c")
+_LIB = os.environ.get("ECMC_ORACLE_LIB") or os.path.join(_HERE, "libecmc_oracle.so")
+
+OK, E_ARG, E_OVERLAP, E_TETHER, E_BOX, E_CELL_OVERFLOW, E_STUCK, E_CHECK = 0, -1, -2, -3, -4, -5, -6, -9
+EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END = range(6)
+C_HS_LIFT, C_TETHER_LIFT, C_HS_REFLECT, C_TETHER_REFLECT, C_WALL, C_CROSS, C_EC, C_STEPS = range(8)
+NCNT = 8
+
+EVENT_DTYPE = np.dtype([
+    ("sweep", "<u4"), ("domain", "<u4"), ("ec", "<u4"), ("step", "<u4"),
+    ("pivot", "<i4"), ("target", "<i4"), ("kind", "<u4"), ("colour", "<u4"),
+])
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (IEEE binary64, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        i64, i32, u32, u64, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+        L.orc_create.argtypes = [P(vp), dbl, dbl, dbl, ctypes.c_int, i64, vp, i64, vp]
+        L.orc_create.restype = ctypes.c_int
+        L.orc_destroy.argtypes = [vp]
+        L.orc_set_options.argtypes = [vp, i64, ctypes.c_int]
+        L.orc_set_log.argtypes = [vp, vp, i64]
+        L.orc_log_count.argtypes = [vp]
+        L.orc_log_count.restype = i64
+        L.orc_sweep.argtypes = [vp, i64, dbl, u64, ctypes.c_int, ctypes.c_int, u32]
+        L.orc_sweep.restype = ctypes.c_int
+        L.orc_next_event.argtypes = [vp, i32, ctypes.c_int, ctypes.c_int, P(dbl), P(i32), P(ctypes.c_int), P(dbl)]
+        L.orc_run_ec.argtypes = [vp, i32, ctypes.c_int, dbl]
+        L.orc_observables.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, P(i64)]
+        L.orc_n_beads.argtypes = [vp]
+        L.orc_n_beads.restype = i64
+        L.orc_n_cells.argtypes = [vp]
+        L.orc_cell_size.argtypes = [vp]
+        L.orc_cell_size.restype = dbl
+        L.orc_sweep_counter.argtypes = [vp]
+        L.orc_sweep_counter.restype = u32
+        for f in ("orc_get_positions", "orc_get_cells", "orc_get_images"):
+            getattr(L, f).argtypes = [vp, vp]
+            getattr(L, f).restype = None
+        L.orc_counters.argtypes = [vp, vp, P(dbl)]
+        L.orc_counters.restype = None
+        L.orc_set_state.argtypes = [vp, vp, vp, vp, u32]
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_philox4x32_10.restype = None
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: oracle status {code}")
+        self.code = code
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+class Oracle:
+    """One melt held by the CPU oracle."""
+
+    def __init__(self, L: float, sigma: float, b_max: float, positions, bonds, n_cells: int = 0,
+                 event_cap: int = 0, check: int = 0):
+        self._pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        self._bonds = np.ascontiguousarray(bonds, dtype=np.int32).reshape(-1, 2)
+        h = ctypes.c_void_p()
+        st = lib().orc_create(ctypes.byref(h), float(L), float(sigma), float(b_max), int(n_cells),
+                              self._pos.shape[0], self._pos.ctypes.data, self._bonds.shape[0],
+                              self._bonds.ctypes.data if self._bonds.size else None)
+        if st != OK:
+            raise OracleError(st, "orc_create")
+        self._h = h
+        self.L, self.sigma, self.b_max = float(L), float(sigma), float(b_max)
+        self.n_beads = self._pos.shape[0]
+        self._log = None
+        lib().orc_set_options(self._h, int(event_cap), int(check))
+
+    @classmethod
+    def from_melt(cls, melt, **kw):
+        return cls(melt.L, melt.sigma, melt.b_max, melt.positions, melt.bonds, **kw)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().orc_destroy(h)
+            self._h = None
+
+    @property
+    def n_cells(self) -> int:
+        return lib().orc_n_cells(self._h)
+
+    @property
+    def h(self) -> float:
+        return lib().orc_cell_size(self._h)
+
+    @property
+    def sweep_counter(self) -> int:
+        return lib().orc_sweep_counter(self._h)
+
+    def set_options(self, event_cap: int = 0, check: int = 0):
+        lib().orc_set_options(self._h, int(event_cap), int(check))
+
+    def enable_log(self, capacity: int):
+        self._log = np.zeros(int(capacity), dtype=EVENT_DTYPE)
+        lib().orc_set_log(self._h, self._log.ctypes.data, self._log.shape[0])
+
+    def event_log(self) -> np.ndarray:
+        if self._log is None:
+            return np.zeros(0, dtype=EVENT_DTYPE)
+        n = lib().orc_log_count(self._h)
+        if n > self._log.shape[0]:
+            raise OracleError(E_ARG, f"event log overflow ({n} > {self._log.shape[0]})")
+        return self._log[:n].copy()
+
+    def sweep(self, n_ec: int, ell: float, seed: int, tiling: int = 0, D: int = 1,
+              colour_mask: int = 0xFF):
+        st = lib().orc_sweep(self._h, int(n_ec), float(ell), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                             int(tiling), int(D), int(colour_mask))
+        if st != OK:
+            raise OracleError(st, "orc_sweep")
+
+    def run_ec(self, pivot: int, direction: int, ell: float):
+        st = lib().orc_run_ec(self._h, int(pivot), int(direction), float(ell))
+        if st != OK:
+            raise OracleError(st, "orc_run_ec")
+
+    def next_event(self, pivot: int, axis: int, sgn: int):
+        x = ctypes.c_double()
+        j = ctypes.c_int32()
+        k = ctypes.c_int()
+        xc = ctypes.c_double()
+        st = lib().orc_next_event(self._h, int(pivot), int(axis), int(sgn), ctypes.byref(x),
+                                  ctypes.byref(j), ctypes.byref(k), ctypes.byref(xc))
+        if st != OK:
+            raise OracleError(st, "orc_next_event")
+        return x.value, j.value, k.value, xc.value
+
+    def positions(self) -> np.ndarray:
+        out = np.zeros((self.n_beads, 3))
+        lib().orc_get_positions(self._h, out.ctypes.data)
+        return out
+
+    def cells(self) -> np.ndarray:
+        out = np.zeros((self.n_beads, 3), dtype=np.int32)
+        lib().orc_get_cells(self._h, out.ctypes.data)
+        return out
+
+    def images(self) -> np.ndarray:
+        out = np.zeros((self.n_beads, 3), dtype=np.int32)
+        lib().orc_get_images(self._h, out.ctypes.data)
+        return out
+
+    def counters(self):
+        c = np.zeros(NCNT, dtype=np.uint64)
+        d = ctypes.c_double()
+        lib().orc_counters(self._h, c.ctypes.data, ctypes.byref(d))
+        return c, d.value
+
+    def set_state(self, pos, cells, img, sweep_ctr: int):
+        p = np.ascontiguousarray(pos, dtype=np.float64)
+        c = np.ascontiguousarray(cells, dtype=np.int32)
+        i = np.ascontiguousarray(img, dtype=np.int32)
+        st = lib().orc_set_state(self._h, p.ctypes.data, c.ctypes.data, i.ctypes.data, int(sweep_ctr))
+        if st != OK:
+            raise OracleError(st, "orc_set_state")
+
+    def observables(self, nbins: int = 20):
+        n_poly = ctypes.c_int64()
+        lib().orc_observables(self._h, 0, None, None, None, None, ctypes.byref(n_poly))
+        M = n_poly.value
+        r2 = np.zeros(M)
+        rg2 = np.zeros(M)
+        hist = np.zeros(max(nbins, 1), dtype=np.int64)
+        mid = np.zeros((M, 3))
+        lib().orc_observables(self._h, int(nbins), r2.ctypes.data, rg2.ctypes.data, hist.ctypes.data,
+                              mid.ctypes.data, ctypes.byref(n_poly))
+        return {"r2": r2, "rg2": rg2, "hist": hist[:nbins], "mid": mid, "n_poly": M}

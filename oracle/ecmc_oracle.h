@@ -1,0 +1,106 @@
+/*
+ * TEST INFRASTRUCTURE ONLY — plain serial FP64 CPU oracle for the event-chain
+ * (EC) move of tethered hard-sphere chains (Kampmann, Boltz, Kierfeld,
+ * arXiv:1502.06447, Sec. II: Eq. (1), the tether bonds after Eq. (2), the EC
+ * rule of Sec. II, the parallel decomposition of Sec. II.A).
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+ * load this library.  It shares no code, header or table with the GPU library.
+ *
+ * Every function is serial, unblocked and written to be checked by eye against
+ * the paper's steps; speed is not a goal.
+ */
+#ifndef ECMC_ORACLE_H
+#define ECMC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes (same numeric meaning as the GPU library's, written separately) */
+enum {
+    ORC_OK = 0,
+    ORC_E_ARG = -1,
+    ORC_E_OVERLAP = -2,
+    ORC_E_TETHER = -3,
+    ORC_E_BOX = -4,
+    ORC_E_CELL_OVERFLOW = -5,
+    ORC_E_STUCK = -6,
+    ORC_E_CHECK = -9 /* an internal self-check (invariant or brute force) failed */
+};
+
+/* event kinds written to the log */
+enum {
+    ORC_EV_HS_LIFT = 0,        /* hard-sphere contact, struck bead motile: it becomes the pivot */
+    ORC_EV_TETHER_LIFT = 1,    /* tether reaches b_max, partner motile: it becomes the pivot   */
+    ORC_EV_HS_REFLECT = 2,     /* contact with an immotile bead: direction reversed            */
+    ORC_EV_TETHER_REFLECT = 3, /* tether limit with an immotile partner: direction reversed    */
+    ORC_EV_WALL = 4,           /* pivot reaches its domain wall: direction reversed            */
+    ORC_EV_END = 5             /* remaining displacement used up (target = -1)                 */
+};
+
+typedef struct {
+    uint32_t sweep, domain, ec, step;
+    int32_t pivot, target;
+    uint32_t kind, colour;
+} orc_event;
+
+/* counters */
+enum {
+    ORC_C_HS_LIFT = 0,
+    ORC_C_TETHER_LIFT,
+    ORC_C_HS_REFLECT,
+    ORC_C_TETHER_REFLECT,
+    ORC_C_WALL,
+    ORC_C_CROSS,
+    ORC_C_EC,
+    ORC_C_STEPS,
+    ORC_NCNT
+};
+
+typedef struct orc_sys orc_sys;
+
+/* n_cells = 0 picks the largest n with L/n > b_max.  Requires n >= 4. */
+int orc_create(orc_sys **out, double L, double sigma, double bmax, int n_cells, int64_t n_beads,
+               const double *pos, int64_t n_bonds, const int32_t *bonds);
+void orc_destroy(orc_sys *s);
+
+/* event_cap: loop iterations allowed per EC (0 = default 10^7).
+ * check: 0 none; 1 invariants after every event; 2 also brute-force next-event search. */
+int orc_set_options(orc_sys *s, int64_t event_cap, int check);
+int orc_set_log(orc_sys *s, orc_event *buf, int64_t cap);
+int64_t orc_log_count(const orc_sys *s);
+
+/* One sweep: tiling 0 = whole box (one domain, every bead motile), 1 = checkerboard of
+ * D^3-cell domains in 8 colour phases.  colour_mask selects which phases run. */
+int orc_sweep(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, int D,
+              uint32_t colour_mask);
+
+/* Whole-box helpers for unit tests. */
+int orc_next_event(const orc_sys *s, int32_t p, int axis, int sgn, double *x, int32_t *j,
+                   int *kind, double *x_cell);
+int orc_run_ec(orc_sys *s, int32_t p, int dir, double ell);
+
+int orc_observables(const orc_sys *s, int nbins, double *r2, double *rg2, int64_t *hist,
+                    double *mid, int64_t *n_poly);
+
+int64_t orc_n_beads(const orc_sys *s);
+int orc_n_cells(const orc_sys *s);
+double orc_cell_size(const orc_sys *s);
+uint32_t orc_sweep_counter(const orc_sys *s);
+void orc_get_positions(const orc_sys *s, double *out);
+void orc_get_cells(const orc_sys *s, int32_t *out);
+void orc_get_images(const orc_sys *s, int32_t *out);
+void orc_counters(const orc_sys *s, uint64_t *cnt, double *sum_delta);
+int orc_set_state(orc_sys *s, const double *pos, const int32_t *cells, const int32_t *img,
+                  uint32_t sweep_ctr);
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

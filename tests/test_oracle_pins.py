@@ -1,0 +1,511 @@
+"""Pins of the CPU oracle against things the paper and geometry fix.
+
+The oracle (``oracle/``) is the plain serial reference of the event-chain (EC)
+move (Kampmann, Boltz, Kierfeld, arXiv:1502.06447, Sec. II).  Nothing here
+compares the oracle with itself: every expected value comes from a published
+table, a closed form, exact hand geometry, or an independent brute force that
+finds first contacts by bisection on the distance function over all periodic
+images.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1502_06447_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ RNG
+def test_philox_known_answers():
+    """Philox4x32-10 against the published known-answer vectors (Salmon et al., SC'11)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = oracle.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+# ------------------------------------------------------------------ exact geometry
+def _two_body(pos, bonds=(), L=20.0, sigma=1.25, b_max=1.75):
+    return oracle.Oracle(L, sigma, b_max, np.array(pos, dtype=float),
+                         np.array(bonds, dtype=np.int32).reshape(-1, 2))
+
+
+def test_hard_sphere_contact_exact():
+    """sigma = 1.25 and d = (2, 0.75, 0): sigma^2 - d_perp^2 = 1 exactly, so the first
+    contact along +x comes after exactly x = 2 - 1 = 1 (Eq. (1): contact at |d| = sigma)."""
+    o = _two_body([[5.0, 5.0, 5.0], [7.0, 5.75, 5.0]])
+    x, j, kind, _ = o.next_event(0, 0, +1)
+    assert (x, j, kind) == (1.0, 1, 0)
+    x, j, kind, _ = o.next_event(1, 0, -1)       # the same pair seen from bead 1 moving -x
+    assert (x, j, kind) == (1.0, 0, 0)
+    assert o.next_event(0, 0, -1)[1] == -1       # moving away
+    assert o.next_event(0, 2, +1)[1] == -1       # moving along z: d_perp = 2.14 > sigma
+    assert o.next_event(0, 1, +1)[1] == -1       # along +y: d_perp = 2 > sigma
+
+
+def test_collinear_contact_and_tether_limits():
+    """Collinear pair: a hard-sphere hit after d - sigma; a tethered partner behind at
+    exactly b_max stops the pivot at once (x = 0); ahead it is hit as a hard sphere;
+    off the line by exactly sigma it is never touched and the tether decides."""
+    o = _two_body([[5.0, 5.0, 5.0], [7.0, 5.0, 5.0]])
+    assert o.next_event(0, 0, +1)[:3] == (0.75, 1, 0)
+    o = _two_body([[5.0, 5.0, 5.0], [3.25, 5.0, 5.0]], bonds=[[0, 1]])
+    assert o.next_event(0, 0, +1)[:3] == (0.0, 1, 1)          # tether taut behind
+    assert o.next_event(0, 0, -1)[:3] == (0.5, 1, 0)          # hard-sphere contact ahead
+    assert o.next_event(1, 0, -1)[:3] == (0.0, 0, 1)          # seen from the partner
+    o = _two_body([[5.0, 5.0, 5.0], [5.0, 6.75, 5.0]], bonds=[[0, 1]])
+    assert o.next_event(0, 0, +1)[:3] == (0.0, 1, 1)          # perpendicular, taut
+    o = _two_body([[5.0, 5.0, 5.0], [5.5, 6.25, 5.0]], bonds=[[0, 1]])
+    x, j, kind, _ = o.next_event(0, 0, +1)
+    assert (j, kind) == (1, 1) and x == 0.5 + math.sqrt(1.5)
+
+
+def test_cell_face_distance_and_periodic_neighbour():
+    """Distance to the face of the stored cell, and a contact found across the
+    periodic boundary through the wrapped neighbour cell."""
+    L = 20.0
+    o = _two_body([[0.25, 5.0, 5.0], [19.0, 5.75, 5.0]], L=L)
+    h = o.h
+    assert h == L / 11
+    x, j, kind, xc = o.next_event(0, 0, -1)
+    # image of bead 1 at x = -1.0: d = (-1.25, 0.75, 0) -> x = 1.25 - 1 = 0.25
+    assert (x, j, kind, xc) == (0.25, 1, 0, 0.25)
+    x, j, kind, xc = o.next_event(0, 0, +1)
+    assert j == -1 and xc == h - 0.25
+
+
+# ------------------------------------------------------------------ brute force by bisection
+def _first_touch(d, v, radius):
+    """Smallest t >= 0 with |d - t v| = radius for a bead outside the sphere, found by
+    bisection on |d - t v|^2 - radius^2 (no closed form).  None if never touched."""
+    f = lambda t: float(np.dot(d - t * v, d - t * v)) - radius * radius
+    tmin = float(np.dot(d, v))          # closest approach
+    if tmin <= 0 or f(tmin) >= 0:
+        return None
+    lo, hi = 0.0, tmin
+    if f(0.0) <= 0:
+        return 0.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def _tether_limit(d, v, radius):
+    """Largest admissible t >= 0 keeping |d - t v| <= radius (bisection)."""
+    f = lambda t: float(np.dot(d - t * v, d - t * v)) - radius * radius
+    lo = max(0.0, float(np.dot(d, v)))
+    if f(lo) > 0:
+        return 0.0
+    hi = lo + 2 * radius + 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) <= 0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def _brute_next(pos, bonds, L, sigma, b, p, axis, sgn):
+    v = np.zeros(3)
+    v[axis] = sgn
+    best = (math.inf, -1, 0)
+    partners = set(int(q) for (a, c) in bonds for q in (a, c) if p in (a, c)) - {p}
+    for j in range(len(pos)):
+        if j == p:
+            continue
+        for sh in np.ndindex(3, 3, 3):
+            d = pos[j] + (np.array(sh) - 1) * L - pos[p]
+            t = _first_touch(d, v, sigma)
+            if t is not None and (t, j, 0) < best:
+                best = (t, j, 0)
+            if j in partners and np.dot(d, d) <= (b + 1e-9) ** 2:
+                t = _tether_limit(d, v, b)
+                if (t, j, 1) < best:
+                    best = (t, j, 1)
+    return best
+
+
+def _random_tiny_system(rng, n_chain=4, n_per=5, L=6.2, sigma=1.0, b=1.4):
+    """A random valid configuration of short tethered chains (rejection growth)."""
+    for _ in range(1000):
+        pos = []
+        ok = True
+        for c in range(n_chain):
+            for i in range(n_per):
+                for _ in range(500):
+                    if i == 0:
+                        cand = rng.uniform(0, L, 3)
+                    else:
+                        u = rng.normal(size=3)
+                        u /= np.linalg.norm(u)
+                        r = rng.uniform(sigma * 1.01, b * 0.99)
+                        cand = np.mod(pos[-1] + r * u, L)
+                    if all(np.linalg.norm((q - cand) - L * np.round((q - cand) / L)) > sigma * 1.001 for q in pos):
+                        pos.append(cand)
+                        break
+                else:
+                    ok = False
+                    break
+            if not ok:
+                break
+        if ok:
+            pos = np.array(pos)
+            bonds = np.array([[c * n_per + i, c * n_per + i + 1] for c in range(n_chain) for i in range(n_per - 1)],
+                             dtype=np.int32)
+            return pos, bonds
+    raise RuntimeError("could not build a tiny system")
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_next_event_matches_bruteforce(seed):
+    """The cell-list search finds the same first event as a brute force over every bead
+    and every periodic image, whenever that event comes before the cell face; when the
+    face comes first, no bead anywhere is hit before it."""
+    rng = np.random.default_rng(seed)
+    pos, bonds = _random_tiny_system(rng)
+    L, sigma, b = 6.2, 1.0, 1.4
+    o = oracle.Oracle(L, sigma, b, pos, bonds)
+    assert o.n_cells == 4
+    pos = o.positions()
+    checked = 0
+    for p in range(len(pos)):
+        for axis in range(3):
+            for sgn in (1, -1):
+                x, j, kind, xc = o.next_event(p, axis, sgn)
+                bx, bj, bk = _brute_next(pos, bonds, L, sigma, b, p, axis, sgn)
+                if x <= xc:
+                    assert (j, kind) == (bj, bk), (p, axis, sgn)
+                    assert x == pytest.approx(bx, abs=1e-9)
+                    checked += 1
+                else:
+                    assert bx > xc - 1e-12
+    assert checked > 10
+
+
+# ------------------------------------------------------------------ invariants along trajectories
+def _check_valid(pos, bonds, L, sigma, b, tol=1e-10):
+    d = pos[:, None, :] - pos[None, :, :]
+    d -= L * np.round(d / L)
+    r2 = np.einsum("ijk,ijk->ij", d, d)
+    np.fill_diagonal(r2, np.inf)
+    assert r2.min() >= sigma * sigma * (1 - tol)
+    if len(bonds):
+        bb = d[bonds[:, 0], bonds[:, 1]]
+        assert np.einsum("ij,ij->i", bb, bb).max() <= b * b * (1 + tol)
+
+
+@pytest.mark.parametrize("tiling,D,n_cells", [(0, 1, 0), (1, 1, 4)])
+def test_invariants_hold_along_c1_trajectory(melt_c1, tiling, D, n_cells):
+    """Whole-box and checkerboard sweeps on the 16 x 16 melt with the oracle's own
+    per-event checks on (non-overlap, tethers, cell membership, and a brute-force
+    next-event search at every event); then an independent all-pairs check."""
+    m = melt_c1
+    o = oracle.Oracle.from_melt(m, check=2, n_cells=n_cells)
+    for s in range(3):
+        o.sweep(128, 10.0, 100 + s, tiling=tiling, D=D)
+    c, _ = o.counters()
+    assert c[oracle.C_HS_LIFT] > 1000 and c[oracle.C_TETHER_LIFT] > 100
+    _check_valid(o.positions(), m.bonds, m.L, m.sigma, m.b_max)
+    cells = o.cells()
+    h = o.h
+    pos = o.positions()
+    assert np.all(pos >= cells * h - 1e-12) and np.all(pos <= np.minimum((cells + 1) * h, m.L) + 1e-12)
+
+
+# ------------------------------------------------------------------ dimer: p(r) ~ r^2
+def _dimer_samples(tiling, D, L, n_samples, seed, ell=7.3, per=3):
+    m = inputs.dimer(L, seed=seed)
+    o = oracle.Oracle.from_melt(m)
+    out = np.empty(n_samples)
+    for k in range(n_samples):
+        o.sweep(per, ell, seed * 1000003 + k, tiling=tiling, D=D)
+        p = o.positions()
+        d = p[1] - p[0]
+        d -= L * np.round(d / L)
+        out[k] = np.linalg.norm(d)
+    return out
+
+
+def _ks_uniform_r2(r, sigma=1.0, b=1.4):
+    """Kolmogorov-Smirnov distance to the isolated-dimer law p(r) = 3 r^2 / (b^3 - sigma^3)."""
+    from scipy import stats
+    cdf = lambda x: np.clip((x ** 3 - sigma ** 3) / (b ** 3 - sigma ** 3), 0, 1)
+    return stats.kstest(r, cdf)
+
+
+@pytest.mark.parametrize("tiling,D,L", [(0, 1, 8.0), (1, 1, 6.0), (1, 2, 12.0)])
+def test_isolated_dimer_bond_length_distribution(tiling, D, L):
+    """An isolated tethered dimer samples a uniform density in the shell sigma <= r <= b_max,
+    so p(r) is proportional to r^2: mean 3/4 (b^4 - s^4)/(b^3 - s^3) = 1.22202 for b = 1.4.
+    Checked in whole-box mode and with the checkerboard decomposition on (walls, immotile
+    partners, colour phases)."""
+    r = _dimer_samples(tiling, D, L, 6000, seed=5 + D + tiling)
+    assert r.min() >= 1.0 - 1e-10 and r.max() <= 1.4 + 1e-10
+    ks = _ks_uniform_r2(r)
+    assert ks.pvalue > 1e-3, ks
+    mean_exact = 0.75 * (1.4 ** 4 - 1) / (1.4 ** 3 - 1)
+    assert abs(mean_exact - 1.22202) < 1e-5
+    assert abs(r.mean() - mean_exact) < 5 * r.std() / math.sqrt(len(r) / 4)
+
+
+# ------------------------------------------------------------------ short chains vs direct sampling
+def _direct_chain_samples(rng, N, n, sigma=1.0, b=1.4):
+    """Exact Boltzmann sampling of an isolated tethered hard-sphere chain: bond vectors
+    uniform in the shell [sigma, b], rejection if any non-bonded pair is closer than sigma."""
+    out = []
+    while len(out) < n:
+        k = 4 * (n - len(out)) + 16
+        u = rng.uniform(size=(k, N - 1))
+        r = (sigma ** 3 + u * (b ** 3 - sigma ** 3)) ** (1 / 3)
+        v = rng.normal(size=(k, N - 1, 3))
+        v /= np.linalg.norm(v, axis=2)[:, :, None]
+        bonds = r[:, :, None] * v
+        x = np.concatenate([np.zeros((k, 1, 3)), np.cumsum(bonds, axis=1)], axis=1)
+        d = np.linalg.norm(x[:, :, None, :] - x[:, None, :, :], axis=3)
+        ok = np.ones(k, dtype=bool)
+        for i in range(N):
+            for j in range(i + 2, N):
+                ok &= d[:, i, j] >= sigma
+        out.extend(list(x[ok]))
+    return np.array(out[:n])
+
+
+def _shape(x):
+    R2 = np.sum((x[:, -1] - x[:, 0]) ** 2, axis=1)
+    cm = x.mean(axis=1, keepdims=True)
+    Rg2 = np.mean(np.sum((x - cm) ** 2, axis=2), axis=1)
+    r13 = np.linalg.norm(x[:, 2] - x[:, 0], axis=1)
+    return R2, Rg2, r13
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_short_isolated_chain_matches_direct_sampler(N):
+    """<R^2>, <R_g^2> and the distribution of |r_1 - r_3| of an isolated tethered chain
+    sampled by ECs agree with direct rejection sampling of the exact Boltzmann weight."""
+    from scipy import stats
+    rng = np.random.default_rng(100 + N)
+    ref = _direct_chain_samples(rng, N, 20000)
+    L = 20.0
+    m = inputs.isolated_chain(N, L, seed=N)
+    o = oracle.Oracle.from_melt(m)
+    samples = []
+    for k in range(5000):
+        o.sweep(2 * N, 6.1, 7000 + k)
+        p = o.positions()
+        x = p - p[0]
+        x -= L * np.round(x / L)
+        samples.append(x)
+    ec = np.array(samples)
+    R2e, Rg2e, r13e = _shape(ec)
+    R2r, Rg2r, r13r = _shape(ref)
+    for a, bb in ((R2e, R2r), (Rg2e, Rg2r)):
+        err = math.sqrt(4 * a.var() / len(a) + bb.var() / len(bb))
+        assert abs(a.mean() - bb.mean()) < 4 * err, (a.mean(), bb.mean(), err)
+    assert stats.ks_2samp(r13e[::2], r13r).pvalue > 1e-3
+
+
+# ------------------------------------------------------------------ hard-sphere pressure
+def _cs(eta):
+    return (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3
+
+
+@pytest.mark.parametrize("eta", [0.10, 0.20])
+def test_pressure_from_lifts_matches_carnahan_starling(eta):
+    """For unbonded spheres in whole-box mode the lifting statistics give the pressure,
+    beta P / rho = 1 + <sum of lift separations along v> / ell (the standard event-chain
+    estimator; the contact theorem 1 + 4 eta g(sigma) with the mean lift 2 sigma / 3).
+    Compared with Carnahan-Starling (table in tests/golden)."""
+    table = {float(a): float(z) for a, z in (l.split() for l in open(os.path.join(GOLDEN, "carnahan_starling.txt"))
+                                             if l.strip() and not l.startswith("#"))}
+    assert abs(table[eta] - _cs(eta)) < 1e-4
+    m = inputs.hs_fluid(1000, eta, seed=3)
+    o = oracle.Oracle.from_melt(m)
+    ell = 4.0
+    for s in range(20):                          # melt the lattice
+        o.sweep(1000, ell, 50 + s)
+    c0, d0 = o.counters()
+    for s in range(200):
+        o.sweep(1000, ell, 500 + s)
+    c1, d1 = o.counters()
+    n_ec = int(c1[oracle.C_EC] - c0[oracle.C_EC])
+    Z = 1 + (d1 - d0) / (n_ec * ell)
+    assert abs(Z - table[eta]) / table[eta] < 0.015, (Z, table[eta])
+
+
+# ------------------------------------------------------------------ determinism / checkpoint
+def test_same_seed_same_trajectory_and_checkpoint(melt_c1):
+    m = melt_c1
+    a = oracle.Oracle.from_melt(m, n_cells=4)
+    b = oracle.Oracle.from_melt(m, n_cells=4)
+    a.enable_log(10 ** 6)
+    b.enable_log(10 ** 6)
+    for s in range(2):
+        a.sweep(256, 10.0, 9 + s, tiling=1, D=1)
+    b.sweep(256, 10.0, 9, tiling=1, D=1)
+    state = (b.positions(), b.cells(), b.images(), b.sweep_counter)
+    c = oracle.Oracle.from_melt(m, n_cells=4)
+    c.set_state(*state)
+    c.enable_log(10 ** 6)
+    c.sweep(256, 10.0, 10, tiling=1, D=1)
+    la = a.event_log()
+    lb = b.event_log()
+    lc = c.event_log()
+    assert np.array_equal(np.concatenate([lb, lc]), la)
+    assert np.array_equal(a.positions(), c.positions())
+    d = oracle.Oracle.from_melt(m, n_cells=4)
+    d.sweep(256, 10.0, 99, tiling=1, D=1)
+    assert not np.array_equal(d.positions(), b.positions())
+
+
+# ------------------------------------------------------------------ schedule
+def test_checkerboard_schedule_properties(melt_c1):
+    """Every logged event of a colour phase belongs to a domain of that colour, each
+    non-empty domain runs K = ceil(n_ec / n_domains) ECs, and walls appear only in
+    decomposed mode."""
+    m = melt_c1
+    o = oracle.Oracle.from_melt(m, n_cells=4)
+    o.enable_log(10 ** 6)
+    o.sweep(300, 10.0, 4, tiling=1, D=1)
+    log = o.event_log()
+    nd = 4
+    dx = log["domain"] % nd
+    dy = (log["domain"] // nd) % nd
+    dz = log["domain"] // (nd * nd)
+    col = (dx & 1) | ((dy & 1) << 1) | ((dz & 1) << 2)
+    assert np.array_equal(col, log["colour"])
+    ends = log[log["kind"] == oracle.EV_END]
+    per_dom = np.bincount(ends["domain"], minlength=nd ** 3)
+    K = -(-300 // nd ** 3)
+    assert set(np.unique(per_dom)) <= {0, K}
+    assert (log["kind"] == oracle.EV_WALL).any()
+    w = oracle.Oracle.from_melt(m)
+    w.enable_log(10 ** 6)
+    w.sweep(300, 10.0, 4, tiling=0)
+    lw = w.event_log()
+    assert not np.isin(lw["kind"], [oracle.EV_WALL, oracle.EV_HS_REFLECT, oracle.EV_TETHER_REFLECT]).any()
+    assert (lw["kind"] == oracle.EV_END).sum() == 300
+
+
+def test_pivot_and_direction_draws_are_uniform(melt_c1):
+    """Whole-box ECs start from every bead and along every direction equally often (chi^2)."""
+    from scipy import stats
+    m = melt_c1
+    o = oracle.Oracle.from_melt(m)
+    o.enable_log(4 * 10 ** 6)
+    o.sweep(25600, 0.0, 1234)
+    log = o.event_log()
+    ends = log[log["kind"] == oracle.EV_END]
+    assert len(ends) == 25600
+    counts = np.bincount(ends["pivot"], minlength=256)   # ell = 0: the pivot never changes
+    assert stats.chisquare(counts).pvalue > 1e-3
+
+
+# ------------------------------------------------------------------ observables
+def test_observables_closed_forms():
+    """Straight chain of N beads at spacing a: R^2 = ((N-1) a)^2, R_g^2 = a^2 (N^2-1)/12;
+    unchanged when the chain crosses the periodic boundary; bond lengths in the right bin."""
+    L, N, a = 12.0, 6, 1.25
+    for x0 in (1.0, 8.5):                         # the second start wraps around x = L
+        pos = np.zeros((N, 3))
+        pos[:, 0] = np.mod(x0 + a * np.arange(N), L)
+        pos[:, 1:] = 3.0
+        bonds = np.array([[i, i + 1] for i in range(N - 1)], dtype=np.int32)
+        o = oracle.Oracle(L, 1.0, 1.4, pos, bonds)
+        ob = o.observables(nbins=8)
+        assert ob["n_poly"] == 1
+        assert ob["r2"][0] == pytest.approx(((N - 1) * a) ** 2, rel=1e-14)
+        assert ob["rg2"][0] == pytest.approx(a * a * (N * N - 1) / 12, rel=1e-12)
+        # (1.25 - 1) / 0.4 * 8 = 5 -> bin 5
+        assert ob["hist"].tolist() == [0, 0, 0, 0, 0, N - 1, 0, 0]
+        assert ob["mid"][0][0] == pytest.approx(x0 + a * (N // 2) if x0 + a * (N // 2) < L else x0 + a * (N // 2) - L)
+
+
+# ------------------------------------------------------------------ input validation
+def test_error_codes():
+    pos = np.array([[1.0, 1.0, 1.0], [1.5, 1.0, 1.0]])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Oracle(10.0, 1.0, 1.4, pos, np.zeros((0, 2)))
+    assert e.value.code == oracle.E_OVERLAP
+    pos = np.array([[1.0, 1.0, 1.0], [2.5, 1.0, 1.0]])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Oracle(10.0, 1.0, 1.4, pos, [[0, 1]])
+    assert e.value.code == oracle.E_TETHER
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Oracle(5.0, 1.0, 1.4, pos, np.zeros((0, 2)))
+    assert e.value.code == oracle.E_BOX
+    pos3 = np.array([[1.0, 1.0, 1.0], [2.2, 1.0, 1.0], [3.4, 1.0, 1.0]])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Oracle(10.0, 1.0, 1.4, pos3, [[0, 1], [1, 2], [2, 0]])
+    assert e.value.code == oracle.E_ARG
+    o = oracle.Oracle(10.0, 1.0, 1.4, pos3, [[0, 1], [1, 2]], event_cap=1)
+    with pytest.raises(oracle.OracleError) as e:
+        o.sweep(10, 5.0, 1)
+    assert e.value.code == oracle.E_STUCK
+
+
+def _philox_py(ctr, key):
+    """Philox4x32-10 written out in Python from its published definition (the known-answer
+    test above pins the C version; this one is checked against the same vectors)."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    c = list(ctr)
+    k = list(key)
+    for r in range(10):
+        if r:
+            k = [(k[0] + W0) & 0xFFFFFFFF, (k[1] + W1) & 0xFFFFFFFF]
+        p0, p1 = M0 * c[0], M1 * c[2]
+        c = [(p1 >> 32) ^ c[1] ^ k[0], p1 & 0xFFFFFFFF, (p0 >> 32) ^ c[3] ^ k[1], p0 & 0xFFFFFFFF]
+    return c
+
+
+def test_checkerboard_pivot_schedule_reconstructed(melt_c1):
+    """With ell = 0 nothing moves, so every logged EC start can be recomputed from the
+    schedule's definition: offsets o_a = floor(u_a D / 2^32) from counter (0, 0, sweep, 1),
+    colours by domain-index parity, K = ceil(n_ec / n_domains) ECs per non-empty domain,
+    pivot = the floor(u_0 m / 2^32)-th smallest id among the m beads of the domain, from
+    counter (k, domain, sweep, 0) keyed by the 64-bit seed."""
+    assert _philox_py([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0]) == \
+        [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+    m = melt_c1
+    D, n_ec = 2, 300
+    o = oracle.Oracle.from_melt(m, n_cells=4)
+    cells = o.cells()
+    o.enable_log(10 ** 5)
+    seeds = [0x123456789ABCDEF0, 77, 2 ** 40 + 5]
+    for seed in seeds:
+        o.sweep(n_ec, 0.0, seed, tiling=1, D=D)
+    log = o.event_log()
+    n, nd = 4, 2
+    K = -(-n_ec // nd ** 3)
+    expect = []
+    for sweep, seed in enumerate(seeds):
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        u = _philox_py([0, 0, sweep, 1], key)
+        off = [(u[a] * D) >> 32 for a in range(3)]
+        dom = ((cells - np.array(off)) % n) // D
+        did = dom[:, 0] + nd * (dom[:, 1] + nd * dom[:, 2])
+        for colour in range(8):
+            for d in range(nd ** 3):
+                dx, dy, dz = d % nd, (d // nd) % nd, d // nd ** 2
+                if ((dx & 1) | ((dy & 1) << 1) | ((dz & 1) << 2)) != colour:
+                    continue
+                beads = np.sort(np.flatnonzero(did == d))
+                if len(beads) == 0:
+                    continue
+                for k in range(K):
+                    uu = _philox_py([k, d, sweep, 0], key)
+                    expect.append((sweep, d, k, int(beads[(uu[0] * len(beads)) >> 32])))
+    got = [(int(r["sweep"]), int(r["domain"]), int(r["ec"]), int(r["pivot"])) for r in log]
+    assert all(r["kind"] == oracle.EV_END for r in log)
+    assert got == expect
