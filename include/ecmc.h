@@ -1,0 +1,173 @@
+/*
+ * ecmc.h — C ABI of the MI355X (gfx950) event-chain Monte Carlo library for
+ * dense melts of tethered hard-sphere bead chains.
+ *
+ * The method is the event-chain (EC) move of Kampmann, Boltz and Kierfeld,
+ * "Monte Carlo Simulation of Dense Polymer Melts Using Event Chain Algorithms"
+ * (arXiv:1502.06447):
+ *   - model (Sec. II, Eq. (1) and the tether variant stated after Eq. (2)):
+ *     hard spheres of diameter sigma between all bead pairs, bonded neighbours
+ *     joined by tethers of maximal length l_max (the paper's b_max), periodic cube;
+ *   - EC move (Sec. II, the four-step rule and its generalisation to several
+ *     interaction partners): a pivot moves along +-x/+-y/+-z by the smallest
+ *     admissible displacement x = min_i x_i, the displacement passes to the argmin
+ *     bead, until the total length ell is used up;
+ *   - parallel decomposition (Sec. II.A): domains redrawn every sweep, beads outside
+ *     the active domain immotile, ECs reflected at domain walls and at immotile beads.
+ *
+ * Conventions for every call:
+ *   - no C++ types or exceptions cross this boundary; every call returns an
+ *     ecmc_status and ecmc_last_error() holds a message for the last failure;
+ *   - host arrays passed in are copied (the caller keeps ownership); host arrays
+ *     passed out are written in full before the call returns;
+ *   - the library never allocates device memory: all device state lives in the
+ *     caller's workspace (ecmc_options.workspace, sized by ecmc_workspace_size);
+ *   - all device work is enqueued on ecmc_options.stream (a hipStream_t, NULL = the
+ *     default stream).  ecmc_sweep returns after enqueueing; device-side errors
+ *     (cell overflow, event cap) surface at the next synchronising call
+ *     (ecmc_synchronize, ecmc_observables, ecmc_get_*);
+ *   - a context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef ECMC_H
+#define ECMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ecmc_ctx ecmc_ctx;
+
+typedef enum {
+    ECMC_OK = 0,
+    ECMC_E_ARG = -1,           /* invalid argument (NaN, bad bond list, ring, size) */
+    ECMC_E_OVERLAP = -2,       /* two beads closer than sigma (1 - 2e-12)            */
+    ECMC_E_TETHER = -3,        /* a bond longer than l_max (1 + 2e-12)               */
+    ECMC_E_BOX = -4,           /* cells: n >= 4, L/n > l_max; checkerboard: n/D even */
+    ECMC_E_CELL_OVERFLOW = -5, /* a cell or a domain staging area ran out of slots   */
+    ECMC_E_STUCK = -6,         /* an EC exceeded event_cap loop iterations           */
+    ECMC_E_DEVICE = -7,        /* a HIP runtime call failed                          */
+    ECMC_E_WORKSPACE = -8      /* workspace missing, too small or misaligned         */
+} ecmc_status;
+
+enum { ECMC_PREC_FP64 = 0, ECMC_PREC_MIXED = 1 };
+enum { ECMC_TILING_WHOLE = 0, ECMC_TILING_CHECKER = 1 };
+
+/* event kinds in the event log */
+enum {
+    ECMC_EV_HS_LIFT = 0,        /* contact, struck bead motile: it becomes the pivot       */
+    ECMC_EV_TETHER_LIFT = 1,    /* tether taut, partner motile: it becomes the pivot       */
+    ECMC_EV_HS_REFLECT = 2,     /* contact with an immotile bead: direction reversed       */
+    ECMC_EV_TETHER_REFLECT = 3, /* tether taut with an immotile partner: direction reversed */
+    ECMC_EV_WALL = 4,           /* pivot at its domain wall: direction reversed            */
+    ECMC_EV_END = 5             /* displacement used up (target = -1)                      */
+};
+
+typedef struct {
+    int32_t precision;          /* ECMC_PREC_FP64 (mixed precision is not built yet)        */
+    int32_t tiling;             /* ECMC_TILING_WHOLE: one domain, every bead motile;
+                                   ECMC_TILING_CHECKER: D^3-cell domains, 8 colour phases  */
+    int32_t n_cells;            /* cells per axis; 0 = largest n with L/n > l_max           */
+    int32_t domain_cells;       /* D, cells per domain edge (checkerboard)                  */
+    int32_t cell_capacity;      /* bead slots per cell; 0 = 16                              */
+    int32_t stage_capacity;     /* beads one domain (plus its one-cell halo) may hold;
+                                   0 = automatic; at most 1024                              */
+    int64_t event_cap;          /* loop iterations allowed per EC; 0 = 10^7                 */
+    int64_t event_log_capacity; /* event records kept; 0 = no log (the fast path)           */
+    int32_t time_kernels;       /* nonzero: time every sweep kernel with HIP events         */
+    int32_t reserved;
+    void *workspace;            /* device memory owned by the caller (256-byte aligned)     */
+    size_t workspace_bytes;
+    void *stream;               /* hipStream_t for every launch and copy; NULL = default    */
+} ecmc_options;
+
+typedef struct {
+    uint64_t hs_lift, tether_lift, hs_reflect, tether_reflect, wall, cross, ec, steps;
+    double sum_delta;           /* sum over lifts of (d_par - x): pressure estimator        */
+    uint32_t error_flags;       /* device error word (bit 0 staging, 1 cell, 2 stuck,
+                                   3 log full)                                              */
+    uint32_t pad;
+} ecmc_counters;
+
+typedef struct {
+    uint32_t sweep, domain, ec, step;
+    int32_t pivot, target;
+    uint32_t kind, colour;
+} ecmc_event;
+
+/* Fills *opt with the defaults (FP64, checkerboard, D = 2, automatic sizes). */
+void ecmc_default_options(ecmc_options *opt);
+
+/* Bytes of device workspace ecmc_init needs for n_beads beads in a cube of edge box
+ * with the given options (workspace fields are ignored).  Errors as ecmc_init. */
+ecmc_status ecmc_workspace_size(double box, double sigma, double l_max, int64_t n_beads,
+                                const ecmc_options *opt, size_t *bytes);
+
+/* Creates a context.  positions: host [n_beads][3] doubles, wrapped into [0, box) and
+ * binned into closed cells [k h, (k+1) h]; bonds: host [n_bonds][2] bead indices forming
+ * linear chains (degree <= 2, no rings).  Validates the start (no overlap, no stretched
+ * tether, box and domain geometry), builds the cell lists, copies everything into the
+ * workspace and waits for the copies.  *out is NULL on failure. */
+ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, int64_t n_beads,
+                      const double *positions, int64_t n_bonds, const int32_t *bonds,
+                      const ecmc_options *opt);
+
+/* One sweep (Sec. II.A: the decomposition is redrawn every sweep): a partition offset,
+ * then the 8 colour phases in order; every non-empty active domain runs
+ * K = ceil(n_chains / n_domains) ECs of length ell (whole-box tiling: n_chains ECs).
+ * Random numbers: Philox4x32-10 keyed by seed, counter (k, domain, sweep, 0) for the
+ * pivot and direction of EC k, (0, 0, sweep, 1) for the offsets.  Asynchronous. */
+ecmc_status ecmc_sweep(ecmc_ctx *ctx, int64_t n_chains, double ell, uint64_t seed);
+
+/* As ecmc_sweep, running only the colour phases whose bit is set in colour_mask. */
+ecmc_status ecmc_sweep_colours(ecmc_ctx *ctx, int64_t n_chains, double ell, uint64_t seed,
+                               uint32_t colour_mask);
+
+/* Waits for the stream and reports device-side errors. */
+ecmc_status ecmc_synchronize(ecmc_ctx *ctx);
+
+/* Observables (Sec. III.A): per polymer (chains walked from their smaller-id end) the
+ * squared end-to-end distance r2 (sum of minimum-image bonds), the squared radius of
+ * gyration rg2, the middle bead floor(N/2) in image-unwrapped coordinates mid [3];
+ * a histogram of bond lengths on [sigma, l_max] with nbins bins (0 < nbins <= 1024).
+ * Host outputs of n_poly entries (any may be NULL); *n_poly receives the polymer count.
+ * Synchronises. */
+ecmc_status ecmc_observables(ecmc_ctx *ctx, int32_t nbins, double *r2, double *rg2,
+                             int64_t *hist, double *mid, int64_t *n_poly);
+
+/* Host copies of the state: positions [n][3], cell indices [n][3], image counters [n][3]. */
+ecmc_status ecmc_get_positions(ecmc_ctx *ctx, double *out);
+ecmc_status ecmc_get_cells(ecmc_ctx *ctx, int32_t *out);
+ecmc_status ecmc_get_images(ecmc_ctx *ctx, int32_t *out);
+ecmc_status ecmc_get_counters(ecmc_ctx *ctx, ecmc_counters *out);
+ecmc_status ecmc_reset_counters(ecmc_ctx *ctx);
+
+/* Copies up to capacity log records (unordered across domains) to out and the total
+ * number written since the last clear to *n_total. */
+ecmc_status ecmc_get_event_log(ecmc_ctx *ctx, ecmc_event *out, int64_t capacity, int64_t *n_total);
+ecmc_status ecmc_clear_event_log(ecmc_ctx *ctx);
+
+/* Checkpoint restore: positions, cells and images [n][3] as returned by ecmc_get_*,
+ * plus the sweep counter; the cell lists are rebuilt. */
+ecmc_status ecmc_set_state(ecmc_ctx *ctx, const double *positions, const int32_t *cells,
+                           const int32_t *images, uint32_t sweep_counter);
+
+/* Sum of the HIP-event durations of the sweep kernels since the last call, and their
+ * number (needs time_kernels).  Synchronises. */
+ecmc_status ecmc_kernel_time(ecmc_ctx *ctx, double *ms, int64_t *launches);
+
+uint32_t ecmc_sweep_counter(const ecmc_ctx *ctx);
+int32_t ecmc_n_cells(const ecmc_ctx *ctx);
+double ecmc_cell_size(const ecmc_ctx *ctx);
+int32_t ecmc_stage_capacity(const ecmc_ctx *ctx);
+
+void ecmc_destroy(ecmc_ctx *ctx);
+const char *ecmc_status_str(ecmc_status s);
+const char *ecmc_last_error(const ecmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -58,6 +58,8 @@ def lib():
         L.orc_log_count.restype = i64
         L.orc_sweep.argtypes = [vp, i64, dbl, u64, ctypes.c_int, ctypes.c_int, u32]
         L.orc_sweep.restype = ctypes.c_int
+        L.orc_sweep_subset.argtypes = [vp, i64, dbl, u64, ctypes.c_int, u32, vp, i64]
+        L.orc_sweep_subset.restype = ctypes.c_int
         L.orc_next_event.argtypes = [vp, i32, ctypes.c_int, ctypes.c_int, P(dbl), P(i32), P(ctypes.c_int), P(dbl)]
         L.orc_run_ec.argtypes = [vp, i32, ctypes.c_int, dbl]
         L.orc_observables.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, P(i64)]
@@ -156,6 +158,13 @@ class Oracle:
                              int(tiling), int(D), int(colour_mask))
         if st != OK:
             raise OracleError(st, "orc_sweep")
+
+    def sweep_subset(self, n_ec: int, ell: float, seed: int, D: int, colour_mask: int, domains):
+        d = np.ascontiguousarray(np.sort(np.asarray(domains, dtype=np.uint32)))
+        st = lib().orc_sweep_subset(self._h, int(n_ec), float(ell), int(seed) & 0xFFFFFFFFFFFFFFFF, int(D),
+                                    int(colour_mask), d.ctypes.data, d.shape[0])
+        if st != OK:
+            raise OracleError(st, "orc_sweep_subset")
 
     def run_ec(self, pivot: int, direction: int, ell: float):
         st = lib().orc_run_ec(self._h, int(pivot), int(direction), float(ell))

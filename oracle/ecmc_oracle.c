@@ -632,8 +632,19 @@ static int cmp_i32(const void *a, const void *b) {
 }
 
 /* ---------------------------------------------------------------- sweep */
-int orc_sweep(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, int D,
-              uint32_t colour_mask) {
+static int in_list(const uint32_t *list, int64_t n, uint32_t v) {
+    int64_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (list[mid] == v) return 1;
+        if (list[mid] < v) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return 0;
+}
+
+static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, int D,
+                      uint32_t colour_mask, const uint32_t *only, int64_t n_only) {
     if (n_ec < 0 || !(ell >= 0) || !isfinite(ell)) return ORC_E_ARG;
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     const uint32_t sweep = s->sweep_ctr;
@@ -687,6 +698,7 @@ int orc_sweep(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, i
                         dm.dom[1] = dy;
                         dm.dom[2] = dz;
                         dm.domain = (uint32_t)(dx + nd * (dy + nd * dz));
+                        if (only && !in_list(only, n_only, dm.domain)) continue;
                         /* the domain's beads in ascending id */
                         int64_t m = 0;
                         for (int tz = 0; tz < D; ++tz)
@@ -716,6 +728,18 @@ int orc_sweep(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, i
     free(mot);
     s->sweep_ctr++;
     return st;
+}
+
+int orc_sweep(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, int D,
+              uint32_t colour_mask) {
+    return sweep_impl(s, n_ec, ell, seed, tiling, D, colour_mask, NULL, 0);
+}
+
+int orc_sweep_subset(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int D, uint32_t colour_mask,
+                     const uint32_t *domains, int64_t n_domains) {
+    for (int64_t i = 1; i < n_domains; ++i)
+        if (domains[i] <= domains[i - 1]) return ORC_E_ARG;
+    return sweep_impl(s, n_ec, ell, seed, 1, D, colour_mask, domains, n_domains);
 }
 
 /* ---------------------------------------------------------------- observables */

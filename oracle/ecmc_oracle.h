@@ -78,6 +78,12 @@ int64_t orc_log_count(const orc_sys *s);
 int orc_sweep(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, int D,
               uint32_t colour_mask);
 
+/* As orc_sweep with tiling 1, but only the listed domains (strictly ascending ids) run their
+ * ECs; every other domain is left untouched.  Domains of one colour phase never interact,
+ * so the listed domains end exactly as in a full sweep's first selected phase. */
+int orc_sweep_subset(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int D, uint32_t colour_mask,
+                     const uint32_t *domains, int64_t n_domains);
+
 /* Whole-box helpers for unit tests. */
 int orc_next_event(const orc_sys *s, int32_t p, int axis, int sgn, double *x, int32_t *j,
                    int *kind, double *x_cell);

@@ -1,0 +1,95 @@
+// Internal declarations shared by the host library (ecmc_api.cpp) and the gfx950
+// kernels (ecmc_kernels.hip).  Not part of the public ABI (include/ecmc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ecmc.h"
+
+namespace ecmc {
+
+// device error word bits
+enum : uint32_t {
+    ERR_STAGE = 1u << 0,  // a domain plus halo held more beads than the staging capacity
+    ERR_CELL = 1u << 1,   // a cell list ran out of slots
+    ERR_STUCK = 1u << 2,  // an EC exceeded the per-EC iteration cap
+    ERR_LOG = 1u << 3,    // event log full (records dropped; informational)
+};
+
+// counter slots in the device counter block
+enum { C_HS_LIFT = 0, C_TETHER_LIFT, C_HS_REFLECT, C_TETHER_REFLECT, C_WALL, C_CROSS, C_EC, C_STEPS, NCNT };
+
+// packed cell word of a bead: cx | cy << 10 | cz << 20, bit 30 = motile in this phase
+constexpr int CELL_BITS = 10;
+constexpr int32_t CELL_MASK = (1 << CELL_BITS) - 1;
+constexpr int32_t MOTILE_BIT = 1 << 30;
+constexpr int MAX_CELLS_PER_AXIS = 1023;
+constexpr int MAX_STAGE = 1024;       // staging capacity limit (16 beads per lane)
+
+__host__ __device__ inline int32_t pack_cell(int cx, int cy, int cz) {
+    return cx | (cy << CELL_BITS) | (cz << (2 * CELL_BITS));
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), used on the host for the partition
+// offsets and on the device for the per-EC draws.
+__host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t x0 = (uint32_t)(m1 >> 32) ^ c[1] ^ k0;
+        const uint32_t x2 = (uint32_t)(m0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)m1;
+        c[3] = (uint32_t)m0;
+        c[0] = x0;
+        c[2] = x2;
+    }
+}
+
+// uniform integer in [0, m) from one 32-bit draw
+__host__ __device__ inline uint32_t scale_u32(uint32_t u, uint32_t m) {
+    return (uint32_t)(((uint64_t)u * m) >> 32);
+}
+
+struct PhaseArgs {
+    double *px, *py, *pz;      // [n] positions
+    int32_t *cellp;            // [n] packed cell words (motile bit clear)
+    int32_t *img;              // [3n] periodic image counters
+    const int32_t *part;       // [2n] tethered partners, -1 = none
+    int32_t *ccount;           // [nc^3] beads per cell
+    int32_t *cids;             // [nc^3 * cap] bead ids per cell
+    unsigned long long *cnt;   // [NCNT]
+    double *sum_delta;
+    unsigned int *err;
+    ecmc_event *log;
+    unsigned long long *log_n;
+    long long log_cap;
+    double L, h, sig2, b2, ell;
+    long long K, event_cap;
+    int n, D, nd, cap, whole, colour;
+    int off[3];
+    uint32_t key0, key1, sweep;
+};
+
+struct ObsArgs {
+    const double *px, *py, *pz;
+    const int32_t *img;
+    const int32_t *porder;     // [n] beads in chain order
+    const int32_t *pstart;     // [npoly + 1]
+    int64_t npoly;
+    double L, halfL, sigma, bmax;
+    int nbins;
+    double *r2, *rg2, *mid;    // [npoly], [npoly], [3 npoly]
+    unsigned long long *hist;  // [nbins]
+};
+
+// launchers (ecmc_kernels.hip)
+hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s);
+hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
+bool bpl_supported(int bpl);
+
+}  // namespace ecmc

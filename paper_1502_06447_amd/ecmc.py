@@ -1,0 +1,312 @@
+"""Python binding of the C ABI in ``include/ecmc.h`` (ctypes; argument marshalling only).
+
+Every step of the event-chain path runs in the gfx950 kernels of ``libecmc.so``.
+PyTorch only supplies the device workspace (a uint8 tensor) and the stream.  If
+the library is missing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libecmc.so")
+
+OK, E_ARG, E_OVERLAP, E_TETHER, E_BOX, E_CELL_OVERFLOW, E_STUCK, E_DEVICE, E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+PREC_FP64, PREC_MIXED = 0, 1
+TILING_WHOLE, TILING_CHECKER = 0, 1
+EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END = range(6)
+
+EVENT_DTYPE = np.dtype([
+    ("sweep", "<u4"), ("domain", "<u4"), ("ec", "<u4"), ("step", "<u4"),
+    ("pivot", "<i4"), ("target", "<i4"), ("kind", "<u4"), ("colour", "<u4"),
+])
+
+
+class ecmc_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("tiling", ctypes.c_int32),
+        ("n_cells", ctypes.c_int32),
+        ("domain_cells", ctypes.c_int32),
+        ("cell_capacity", ctypes.c_int32),
+        ("stage_capacity", ctypes.c_int32),
+        ("event_cap", ctypes.c_int64),
+        ("event_log_capacity", ctypes.c_int64),
+        ("time_kernels", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class ecmc_counters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in
+                ("hs_lift", "tether_lift", "hs_reflect", "tether_reflect", "wall", "cross", "ec", "steps")] + [
+        ("sum_delta", ctypes.c_double), ("error_flags", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class EcmcError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what}: {msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = (
+    "ecmc_default_options", "ecmc_workspace_size", "ecmc_init", "ecmc_sweep", "ecmc_sweep_colours",
+    "ecmc_synchronize", "ecmc_observables", "ecmc_get_positions", "ecmc_get_cells", "ecmc_get_images",
+    "ecmc_get_counters", "ecmc_reset_counters", "ecmc_get_event_log", "ecmc_clear_event_log",
+    "ecmc_set_state", "ecmc_kernel_time", "ecmc_sweep_counter", "ecmc_n_cells", "ecmc_cell_size",
+    "ecmc_stage_capacity", "ecmc_destroy", "ecmc_status_str", "ecmc_last_error",
+)
+
+
+def lib():
+    """Load libecmc.so (built by ``__graft_entry__.build()``); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, vp = ctypes.POINTER, ctypes.c_void_p
+    i32, i64, u32, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+    st = ctypes.c_int
+    opt_p = P(ecmc_options)
+    sig = {
+        "ecmc_default_options": (None, [opt_p]),
+        "ecmc_workspace_size": (st, [dbl, dbl, dbl, i64, opt_p, P(ctypes.c_size_t)]),
+        "ecmc_init": (st, [P(vp), dbl, dbl, dbl, i64, vp, i64, vp, opt_p]),
+        "ecmc_sweep": (st, [vp, i64, dbl, u64]),
+        "ecmc_sweep_colours": (st, [vp, i64, dbl, u64, u32]),
+        "ecmc_synchronize": (st, [vp]),
+        "ecmc_observables": (st, [vp, i32, vp, vp, vp, vp, P(i64)]),
+        "ecmc_get_positions": (st, [vp, vp]),
+        "ecmc_get_cells": (st, [vp, vp]),
+        "ecmc_get_images": (st, [vp, vp]),
+        "ecmc_get_counters": (st, [vp, P(ecmc_counters)]),
+        "ecmc_reset_counters": (st, [vp]),
+        "ecmc_get_event_log": (st, [vp, vp, i64, P(i64)]),
+        "ecmc_clear_event_log": (st, [vp]),
+        "ecmc_set_state": (st, [vp, vp, vp, vp, u32]),
+        "ecmc_kernel_time": (st, [vp, P(dbl), P(i64)]),
+        "ecmc_sweep_counter": (u32, [vp]),
+        "ecmc_n_cells": (i32, [vp]),
+        "ecmc_cell_size": (dbl, [vp]),
+        "ecmc_stage_capacity": (i32, [vp]),
+        "ecmc_destroy": (None, [vp]),
+        "ecmc_status_str": (ctypes.c_char_p, [st]),
+        "ecmc_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code: int, what: str, ctx=None):
+    if code != OK:
+        msg = lib().ecmc_last_error(ctx).decode()
+        raise EcmcError(code, what, msg or lib().ecmc_status_str(code).decode())
+
+
+# ---------------------------------------------------------------- thin wrappers (same names)
+def ecmc_default_options() -> ecmc_options:
+    o = ecmc_options()
+    lib().ecmc_default_options(ctypes.byref(o))
+    return o
+
+
+def ecmc_workspace_size(box: float, sigma: float, l_max: float, n_beads: int, opt: ecmc_options) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().ecmc_workspace_size(box, sigma, l_max, n_beads, ctypes.byref(opt), ctypes.byref(n)),
+           "ecmc_workspace_size")
+    return n.value
+
+
+def ecmc_init(box, sigma, l_max, positions, bonds, opt: ecmc_options):
+    pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+    bnd = np.ascontiguousarray(bonds, dtype=np.int32).reshape(-1, 2)
+    h = ctypes.c_void_p()
+    _check(lib().ecmc_init(ctypes.byref(h), box, sigma, l_max, pos.shape[0], pos.ctypes.data, bnd.shape[0],
+                           bnd.ctypes.data if bnd.size else None, ctypes.byref(opt)), "ecmc_init")
+    return h
+
+
+def ecmc_sweep(ctx, n_chains: int, ell: float, seed: int):
+    _check(lib().ecmc_sweep(ctx, int(n_chains), float(ell), int(seed) & 0xFFFFFFFFFFFFFFFF), "ecmc_sweep", ctx)
+
+
+def ecmc_sweep_colours(ctx, n_chains: int, ell: float, seed: int, colour_mask: int):
+    _check(lib().ecmc_sweep_colours(ctx, int(n_chains), float(ell), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                    int(colour_mask)), "ecmc_sweep_colours", ctx)
+
+
+def ecmc_synchronize(ctx):
+    _check(lib().ecmc_synchronize(ctx), "ecmc_synchronize", ctx)
+
+
+def ecmc_destroy(ctx):
+    lib().ecmc_destroy(ctx)
+
+
+# ---------------------------------------------------------------- convenience object
+@dataclass
+class Options:
+    tiling: int = TILING_CHECKER
+    domain_cells: int = 2
+    n_cells: int = 0
+    cell_capacity: int = 0
+    stage_capacity: int = 0
+    event_cap: int = 0
+    event_log_capacity: int = 0
+    time_kernels: bool = False
+    precision: int = PREC_FP64
+
+
+class Melt:
+    """A melt resident on the GPU: the context plus its torch-owned workspace."""
+
+    def __init__(self, L: float, sigma: float, b_max: float, positions, bonds, options: Options | None = None,
+                 device: str = "cuda", stream=None):
+        import torch
+        o = options or Options()
+        opt = ecmc_default_options()
+        opt.precision = o.precision
+        opt.tiling = o.tiling
+        opt.domain_cells = o.domain_cells
+        opt.n_cells = o.n_cells
+        opt.cell_capacity = o.cell_capacity
+        opt.stage_capacity = o.stage_capacity
+        opt.event_cap = o.event_cap
+        opt.event_log_capacity = o.event_log_capacity
+        opt.time_kernels = 1 if o.time_kernels else 0
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        nbytes = ecmc_workspace_size(L, sigma, b_max, pos.shape[0], opt)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        opt.workspace = aligned
+        opt.workspace_bytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        opt.stream = self.stream.cuda_stream
+        self.opt = opt
+        self.L, self.sigma, self.b_max = float(L), float(sigma), float(b_max)
+        self.n_beads = pos.shape[0]
+        self.log_capacity = int(o.event_log_capacity)
+        self.ctx = ecmc_init(L, sigma, b_max, pos, bonds, opt)
+
+    @classmethod
+    def from_melt(cls, melt, options: Options | None = None, **kw):
+        return cls(melt.L, melt.sigma, melt.b_max, melt.positions, melt.bonds, options, **kw)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            ecmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- path
+    def sweep(self, n_chains: int, ell: float, seed: int, colour_mask: int = 0xFF):
+        if colour_mask == 0xFF:
+            ecmc_sweep(self.ctx, n_chains, ell, seed)
+        else:
+            ecmc_sweep_colours(self.ctx, n_chains, ell, seed, colour_mask)
+
+    def synchronize(self):
+        ecmc_synchronize(self.ctx)
+
+    # -- state
+    @property
+    def n_cells(self) -> int:
+        return lib().ecmc_n_cells(self.ctx)
+
+    @property
+    def h(self) -> float:
+        return lib().ecmc_cell_size(self.ctx)
+
+    @property
+    def stage_capacity(self) -> int:
+        return lib().ecmc_stage_capacity(self.ctx)
+
+    @property
+    def sweep_counter(self) -> int:
+        return lib().ecmc_sweep_counter(self.ctx)
+
+    def positions(self) -> np.ndarray:
+        out = np.zeros((self.n_beads, 3))
+        _check(lib().ecmc_get_positions(self.ctx, out.ctypes.data), "ecmc_get_positions", self.ctx)
+        return out
+
+    def cells(self) -> np.ndarray:
+        out = np.zeros((self.n_beads, 3), dtype=np.int32)
+        _check(lib().ecmc_get_cells(self.ctx, out.ctypes.data), "ecmc_get_cells", self.ctx)
+        return out
+
+    def images(self) -> np.ndarray:
+        out = np.zeros((self.n_beads, 3), dtype=np.int32)
+        _check(lib().ecmc_get_images(self.ctx, out.ctypes.data), "ecmc_get_images", self.ctx)
+        return out
+
+    def counters(self) -> dict:
+        c = ecmc_counters()
+        _check(lib().ecmc_get_counters(self.ctx, ctypes.byref(c)), "ecmc_get_counters", self.ctx)
+        return c.as_dict()
+
+    def reset_counters(self):
+        _check(lib().ecmc_reset_counters(self.ctx), "ecmc_reset_counters", self.ctx)
+
+    def event_log(self) -> np.ndarray:
+        n = ctypes.c_int64()
+        _check(lib().ecmc_get_event_log(self.ctx, None, 0, ctypes.byref(n)), "ecmc_get_event_log", self.ctx)
+        if n.value > self.log_capacity:
+            raise EcmcError(E_ARG, "event_log", f"log overflow: {n.value} records > capacity {self.log_capacity}")
+        out = np.zeros(n.value, dtype=EVENT_DTYPE)
+        _check(lib().ecmc_get_event_log(self.ctx, out.ctypes.data, n.value, ctypes.byref(n)), "ecmc_get_event_log",
+               self.ctx)
+        return out
+
+    def clear_event_log(self):
+        _check(lib().ecmc_clear_event_log(self.ctx), "ecmc_clear_event_log", self.ctx)
+
+    def set_state(self, pos, cells, img, sweep_counter: int):
+        p = np.ascontiguousarray(pos, dtype=np.float64)
+        c = np.ascontiguousarray(cells, dtype=np.int32)
+        i = np.ascontiguousarray(img, dtype=np.int32)
+        _check(lib().ecmc_set_state(self.ctx, p.ctypes.data, c.ctypes.data, i.ctypes.data, int(sweep_counter)),
+               "ecmc_set_state", self.ctx)
+
+    def kernel_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().ecmc_kernel_time(self.ctx, ctypes.byref(ms), ctypes.byref(n)), "ecmc_kernel_time", self.ctx)
+        return ms.value, n.value
+
+    def observables(self, nbins: int = 20) -> dict:
+        n_poly = ctypes.c_int64()
+        _check(lib().ecmc_observables(self.ctx, nbins, None, None, None, None, ctypes.byref(n_poly)),
+               "ecmc_observables", self.ctx)
+        M = n_poly.value
+        r2 = np.zeros(M)
+        rg2 = np.zeros(M)
+        hist = np.zeros(nbins, dtype=np.int64)
+        mid = np.zeros((M, 3))
+        _check(lib().ecmc_observables(self.ctx, nbins, r2.ctypes.data, rg2.ctypes.data, hist.ctypes.data,
+                                      mid.ctypes.data, ctypes.byref(n_poly)), "ecmc_observables", self.ctx)
+        return {"r2": r2, "rg2": rg2, "hist": hist, "mid": mid, "n_poly": M}

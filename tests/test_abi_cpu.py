@@ -1,0 +1,96 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared symbol,
+and the host-side validation answers without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1502_06447_amd import ecmc, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ecmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ecmc_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    L = ecmc.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(ecmc.EXPORTS)
+
+
+def test_status_strings_and_defaults():
+    L = ecmc.lib()
+    for code in range(-8, 1):
+        assert L.ecmc_status_str(code)
+    o = ecmc.ecmc_default_options()
+    assert o.precision == ecmc.PREC_FP64 and o.tiling == ecmc.TILING_CHECKER and o.domain_cells == 2
+
+
+def test_workspace_size_and_geometry_errors():
+    o = ecmc.ecmc_default_options()
+    n = ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
+    assert n > 1 << 20 * 0 and n > 50 * (1 << 20)
+    o.domain_cells = 3  # 76 cells per axis is not divisible by 3
+    with pytest.raises(ecmc.EcmcError) as e:
+        ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
+    assert e.value.code == ecmc.E_BOX
+    o = ecmc.ecmc_default_options()
+    with pytest.raises(ecmc.EcmcError) as e:
+        ecmc.ecmc_workspace_size(5.0, 1.0, 1.4, 10, o)          # n = 3 < 4
+    assert e.value.code == ecmc.E_BOX
+    with pytest.raises(ecmc.EcmcError) as e:
+        ecmc.ecmc_workspace_size(20.0, 1.0, 0.9, 10, o)         # l_max < sigma
+    assert e.value.code == ecmc.E_ARG
+    o.precision = ecmc.PREC_MIXED
+    with pytest.raises(ecmc.EcmcError) as e:
+        ecmc.ecmc_workspace_size(20.0, 1.0, 1.4, 10, o)
+    assert e.value.code == ecmc.E_ARG
+
+
+def _init_status(pos, bonds, L=10.0, tiling=ecmc.TILING_WHOLE, workspace=True):
+    """ecmc_init with a placeholder workspace address: the host validation runs before
+    anything is copied to the device, so invalid inputs are refused without a GPU."""
+    o = ecmc.ecmc_default_options()
+    o.tiling = tiling
+    if workspace:
+        o.workspace = 1 << 20
+        o.workspace_bytes = 1 << 40
+    h = ctypes.c_void_p()
+    p = np.ascontiguousarray(pos, dtype=np.float64)
+    b = np.ascontiguousarray(bonds, dtype=np.int32).reshape(-1, 2)
+    return ecmc.lib().ecmc_init(ctypes.byref(h), L, 1.0, 1.4, p.shape[0], p.ctypes.data, b.shape[0],
+                                b.ctypes.data if b.size else None, ctypes.byref(o))
+
+
+def test_host_validation_without_gpu():
+    two = np.array([[1.0, 1.0, 1.0], [1.5, 1.0, 1.0]])
+    assert _init_status(two, np.zeros((0, 2))) == ecmc.E_OVERLAP
+    far = np.array([[1.0, 1.0, 1.0], [2.5, 1.0, 1.0]])
+    assert _init_status(far, [[0, 1]]) == ecmc.E_TETHER
+    tri = np.array([[1.0, 1.0, 1.0], [2.2, 1.0, 1.0], [3.4, 1.0, 1.0]])
+    assert _init_status(tri, [[0, 1], [1, 2], [2, 0]]) == ecmc.E_ARG          # ring
+    assert _init_status(tri, [[0, 1], [0, 1]]) == ecmc.E_ARG                  # duplicate
+    assert _init_status(np.array([[np.nan, 1.0, 1.0]]), np.zeros((0, 2))) == ecmc.E_ARG
+    assert _init_status(tri, [[0, 1]], workspace=False) == ecmc.E_WORKSPACE
+    assert _init_status(tri, [[0, 1]], L=5.0) == ecmc.E_BOX
+
+
+def test_generators_shapes(melt_c1):
+    m = melt_c1
+    assert m.positions.shape == (256, 3) and m.bonds.shape == (240, 2)
+    assert abs(m.eta - 0.30) < 1e-12
+    big = inputs.lattice_chains(64, 64, 0.45, seed=2)
+    assert big.n_beads == 4096 and abs(big.eta - 0.45) < 1e-12
+    d = big.positions[big.bonds[:, 1]] - big.positions[big.bonds[:, 0]]
+    d -= big.L * np.round(d / big.L)
+    r = np.linalg.norm(d, axis=1)
+    assert r.min() >= 1.0 and r.max() <= 1.4
