@@ -14,6 +14,11 @@
  *     bead, until the total length ell is used up;
  *   - parallel decomposition (Sec. II.A): domains redrawn every sweep, beads outside
  *     the active domain immotile, ECs reflected at domain walls and at immotile beads.
+ *   - two shortcuts this library adds (exact in real arithmetic, identical in the CPU
+ *     reference): from its second reflection on, an EC retraces its path back and forth
+ *     with period twice the length W used between the first two reflections, so whole
+ *     periods of the remaining displacement are skipped (W = 0 ends the EC); a run of
+ *     zero-length events that returns to an earlier state (nothing can move) ends the EC.
  *
  * Conventions for every call:
  *   - no C++ types or exceptions cross this boundary; every call returns an
@@ -62,7 +67,13 @@ enum {
     ECMC_EV_HS_REFLECT = 2,     /* contact with an immotile bead: direction reversed       */
     ECMC_EV_TETHER_REFLECT = 3, /* tether taut with an immotile partner: direction reversed */
     ECMC_EV_WALL = 4,           /* pivot at its domain wall: direction reversed            */
-    ECMC_EV_END = 5             /* displacement used up (target = -1)                      */
+    ECMC_EV_END = 5,            /* displacement used up (target = -1)                      */
+    ECMC_EV_PERIOD = 6,         /* a repeated reflection: whole periods 2W of the retraced
+                                   path were dropped from the remaining displacement; the EC
+                                   goes on (target = -1)                                   */
+    ECMC_EV_CYCLE = 7           /* zero-length events returned to an earlier state, or a
+                                   repeated reflection with W = 0 (nothing can move any
+                                   more): ends the EC (target = -1)                        */
 };
 
 typedef struct {
@@ -73,11 +84,16 @@ typedef struct {
     int32_t domain_cells;       /* D, cells per domain edge (checkerboard)                  */
     int32_t cell_capacity;      /* bead slots per cell; 0 = 16                              */
     int32_t stage_capacity;     /* beads one domain (plus its one-cell halo) may hold;
-                                   0 = automatic; at most 1024                              */
+                                   0 = automatic: a first launch sized for the typical
+                                   domain and a second one (up to 1024) for the rare
+                                   larger domains; > 0 = one launch of this capacity, a
+                                   larger domain is ECMC_E_CELL_OVERFLOW; at most 1024      */
     int64_t event_cap;          /* loop iterations allowed per EC; 0 = 10^7                 */
     int64_t event_log_capacity; /* event records kept; 0 = no log (the fast path)           */
     int32_t time_kernels;       /* nonzero: time every sweep kernel with HIP events         */
-    int32_t reserved;
+    int32_t exact_search;       /* nonzero: evaluate every staged bead in FP64 at every event
+                                   instead of the single-precision screen (same results; a
+                                   checking mode, needs event_log_capacity > 0)             */
     void *workspace;            /* device memory owned by the caller (256-byte aligned)     */
     size_t workspace_bytes;
     void *stream;               /* hipStream_t for every launch and copy; NULL = default    */
@@ -85,6 +101,8 @@ typedef struct {
 
 typedef struct {
     uint64_t hs_lift, tether_lift, hs_reflect, tether_reflect, wall, cross, ec, steps;
+    uint64_t periodic, cycle;   /* repeated reflections that dropped whole periods / ECs
+                                   ended by a zero-length cycle                             */
     double sum_delta;           /* sum over lifts of (d_par - x): pressure estimator        */
     uint32_t error_flags;       /* device error word (bit 0 staging, 1 cell, 2 stuck,
                                    3 log full)                                              */

@@ -19,9 +19,9 @@ _SRC = os.path.join(_HERE, "ecmc_oracle.c")
 _LIB = os.environ.get("ECMC_ORACLE_LIB") or os.path.join(_HERE, "libecmc_oracle.so")
 
 OK, E_ARG, E_OVERLAP, E_TETHER, E_BOX, E_CELL_OVERFLOW, E_STUCK, E_CHECK = 0, -1, -2, -3, -4, -5, -6, -9
-EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END = range(6)
-C_HS_LIFT, C_TETHER_LIFT, C_HS_REFLECT, C_TETHER_REFLECT, C_WALL, C_CROSS, C_EC, C_STEPS = range(8)
-NCNT = 8
+EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END, EV_PERIOD, EV_CYCLE = range(8)
+C_HS_LIFT, C_TETHER_LIFT, C_HS_REFLECT, C_TETHER_REFLECT, C_WALL, C_CROSS, C_EC, C_STEPS, C_PERIOD, C_CYCLE = range(10)
+NCNT = 10
 
 EVENT_DTYPE = np.dtype([
     ("sweep", "<u4"), ("domain", "<u4"), ("ec", "<u4"), ("step", "<u4"),

@@ -31,6 +31,14 @@
  *  - ties: END before interaction before cell face; interactions ordered by
  *    (x, bead id, hard sphere before tether);
  *  - negative x from rounding is clamped to 0;
+ *  - after two reflections of one EC with only lifts and cell crossings between them
+ *    (displacement W between them), the EC retraces its path between the two fixed stops
+ *    for ever (a reflection reverses the chain of events exactly), so it is periodic
+ *    with period 2W: x_max is reduced to fmod(x_max, 2W) and the EC goes on; W = 0
+ *    means nothing can move and ends the EC;
+ *  - a run of zero-length events that returns to the same (pivot, direction, pivot cell)
+ *    repeats forever with nothing moving; it is detected (Brent's cycle search over the
+ *    run) and ends the EC;
  *  - random numbers: Philox4x32-10 keyed by the 64-bit seed; EC draws use counter
  *    (k, domain, sweep, 0), the partition offsets use (0, 0, sweep, 1).
  */
@@ -535,12 +543,50 @@ static int check_pivot(const orc_sys *s, int32_t p) {
     return ORC_OK;
 }
 
+/* Second reflection of the EC: between the previous reflection (x_max then xref) and this
+ * one the EC has used W = xref - x_max, and from here on it retraces its path between the
+ * two stops with period 2W.  Whole periods are dropped: x_max = fmod(x_max, 2W).  Returns 1
+ * if the EC ends here (W = 0: nothing between the stops can move). */
+static int periodic(orc_sys *s, const orc_dom *dm, uint32_t step, int32_t p, double xref, double *xmax) {
+    const double W = xref - *xmax;
+    if (!(W > 0.0)) {
+        log_event(s, dm, step, p, -1, ORC_EV_CYCLE);
+        s->cnt[ORC_C_CYCLE]++;
+        return 1;
+    }
+    const double r = fmod(*xmax, W + W);
+    if (r < *xmax) {
+        *xmax = r;
+        log_event(s, dm, step, p, -1, ORC_EV_PERIOD);
+        s->cnt[ORC_C_PERIOD]++;
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------- one EC */
 static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double ell) {
     double xmax = ell;
     uint32_t step = 0;
+    int reflected = 0; /* a reflection happened in this EC ...                     */
+    double xref = 0.0; /* ... with this much displacement left after it           */
+    uint32_t run = 0;  /* consecutive zero-length events */
+    int32_t saved_p = -1, saved_sgn = 0, saved_c = -1;
     s->cnt[ORC_C_EC]++;
     for (;;) {
+        if (run > 0) {
+            /* zero-length run: the state (pivot, direction, pivot cell) repeating means a cycle */
+            const int32_t c = s->cell[3 * p + axis];
+            if (p == saved_p && sgn == saved_sgn && c == saved_c) {
+                log_event(s, dm, step, p, -1, ORC_EV_CYCLE);
+                s->cnt[ORC_C_CYCLE]++;
+                return ORC_OK;
+            }
+            if ((run & (run - 1)) == 0) {
+                saved_p = p;
+                saved_sgn = sgn;
+                saved_c = c;
+            }
+        }
         if ((int64_t)step >= s->event_cap) return ORC_E_STUCK;
         step++;
         s->cnt[ORC_C_STEPS]++;
@@ -565,6 +611,12 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
         }
         if (b.x <= xc) {
             /* interaction event: move to contact / tether limit (steps 2-3) */
+            if (b.x > 0.0) {
+                run = 0;
+                saved_p = -1;
+            } else {
+                run++;
+            }
             *ra = sgn > 0 ? *ra + b.x : *ra - b.x;
             xmax = xmax - b.x;
             const int motile = cell_in_domain(s, dm, s->cell + 3 * b.j);
@@ -577,11 +629,20 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
             } else {
                 log_event(s, dm, step, p, b.j, b.kind == 0 ? ORC_EV_HS_REFLECT : ORC_EV_TETHER_REFLECT);
                 s->cnt[b.kind == 0 ? ORC_C_HS_REFLECT : ORC_C_TETHER_REFLECT]++;
+                if (reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+                reflected = 1;
+                xref = xmax;
                 sgn = -sgn;
             }
             continue;
         }
         /* cell-face event: the pivot is set onto the face */
+        if (xc > 0.0) {
+            run = 0;
+            saved_p = -1;
+        } else {
+            run++;
+        }
         const int c = s->cell[3 * p + axis];
         *ra = sgn > 0 ? s->bnd[c + 1] : s->bnd[c];
         xmax = xmax - xc;
@@ -612,6 +673,9 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
         } else {
             log_event(s, dm, step, p, -1, ORC_EV_WALL);
             s->cnt[ORC_C_WALL]++;
+            if (reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+            reflected = 1;
+            xref = xmax;
             sgn = -sgn;
         }
         if (s->check >= 1 && check_pivot(s, p)) return ORC_E_CHECK;
@@ -670,7 +734,7 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
         }
     } else if (tiling == 1) {
         const int n = s->n;
-        if (D < 1 || n % D != 0 || (n / D) % 2 != 0 || n / D < 2) {
+        if (D < 2 || n % D != 0 || (n / D) % 2 != 0) {
             free(mot);
             return ORC_E_BOX;
         }

@@ -38,7 +38,11 @@ enum {
     ORC_EV_HS_REFLECT = 2,     /* contact with an immotile bead: direction reversed            */
     ORC_EV_TETHER_REFLECT = 3, /* tether limit with an immotile partner: direction reversed    */
     ORC_EV_WALL = 4,           /* pivot reaches its domain wall: direction reversed            */
-    ORC_EV_END = 5             /* remaining displacement used up (target = -1)                 */
+    ORC_EV_END = 5,            /* remaining displacement used up (target = -1)                 */
+    ORC_EV_PERIOD = 6,         /* second reflection of the EC: whole periods of the retraced
+                                  path between the two stops dropped from x_max (target = -1) */
+    ORC_EV_CYCLE = 7           /* nothing can move any more (zero-length cycle or a zero period
+                                  between two stops): ends the EC (target = -1)               */
 };
 
 typedef struct {
@@ -57,6 +61,8 @@ enum {
     ORC_C_CROSS,
     ORC_C_EC,
     ORC_C_STEPS,
+    ORC_C_PERIOD,
+    ORC_C_CYCLE,
     ORC_NCNT
 };
 

@@ -64,8 +64,10 @@ struct Geometry {
     double h = 0;
     int D = 1;
     int nd = 1;
-    int bpl = 0;
+    int bpl = 0;     // beads per lane of the first staging tier
     int stage = 0;
+    int bpl2 = 0;    // second tier for the rare domains above 64 * bpl (0 = none)
+    int bpl3 = 0;    // third tier above 64 * bpl2 (0 = none)
 };
 
 }  // namespace
@@ -73,6 +75,8 @@ struct Geometry {
 struct ecmc_ctx {
     ecmc_options opt;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;       // second stream for the larger staging tiers
+    hipEvent_t fork = nullptr, join = nullptr;
     double L = 0, sigma = 0, lmax = 0, sig2 = 0, b2 = 0;
     int64_t nb = 0, npoly = 0;
     Geometry g;
@@ -114,6 +118,8 @@ ecmc_status geometry(double L, double sigma, double lmax, int64_t nb, const ecmc
         return fail(c, ECMC_E_ARG, "need finite box > 0, sigma > 0, l_max >= sigma");
     if (nb < 1 || nb > 0x7fffffffLL) return fail(c, ECMC_E_ARG, "bead count %lld out of range", (long long)nb);
     if (o.precision != ECMC_PREC_FP64) return fail(c, ECMC_E_ARG, "only ECMC_PREC_FP64 is built");
+    if (o.exact_search && o.event_log_capacity <= 0)
+        return fail(c, ECMC_E_ARG, "exact_search is built only together with the event log");
     int n = o.n_cells;
     if (n == 0) {
         n = (int)std::floor(L / lmax);
@@ -132,15 +138,19 @@ ecmc_status geometry(double L, double sigma, double lmax, int64_t nb, const ecmc
             return fail(c, ECMC_E_BOX, "whole-box tiling needs n^3 <= 1024 cells (n = %d)", n);
     } else if (o.tiling == ECMC_TILING_CHECKER) {
         const int D = o.domain_cells;
-        if (D < 1 || n % D != 0 || (n / D) % 2 != 0)
-            return fail(c, ECMC_E_BOX, "checkerboard needs n %% D == 0 and n/D even (n = %d, D = %d)", n, D);
+        // D >= 2: the integer offset drawn from [0, D) is what moves the partition between
+        // sweeps; with D = 1 it is always 0 and every bead stays in its cell for good.
+        if (D < 2 || n % D != 0 || (n / D) % 2 != 0)
+            return fail(c, ECMC_E_BOX, "checkerboard needs D >= 2, n %% D == 0 and n/D even (n = %d, D = %d)", n, D);
         g.D = D;
         g.nd = n / D;
         if (o.stage_capacity > 0) {
             g.stage = o.stage_capacity;
         } else {
+            // first tier sized for the typical domain; the few above it go to a second launch
             const double mean = std::pow((double)(D + 2), 3) * (double)nb / ((double)n * n * n);
-            g.stage = (int)std::ceil(mean + 8.0 * std::sqrt(mean) + 16.0);
+            g.stage = (int)std::ceil(mean + 3.0 * std::sqrt(mean) + 2.0);
+            g.bpl2 = 16;
         }
     } else {
         return fail(c, ECMC_E_ARG, "unknown tiling %d", o.tiling);
@@ -159,6 +169,12 @@ ecmc_status geometry(double L, double sigma, double lmax, int64_t nb, const ecmc
     while (pick < 16 && ndc > 64 * pick) pick = *std::find_if(std::begin(ok), std::end(ok), [&](int v) { return v > pick; });
     if (ndc > 64 * pick) return fail(c, ECMC_E_BOX, "a domain of %d cells exceeds the staging area", ndc);
     g.bpl = pick;
+    if (g.bpl2) {
+        // tier 2 one step above tier 1, tier 3 the full 16 beads per lane
+        const int* nxt = std::find_if(std::begin(ok), std::end(ok), [&](int v) { return v > pick; });
+        g.bpl2 = nxt == std::end(ok) ? 0 : *nxt;
+        g.bpl3 = (g.bpl2 && g.bpl2 < 16) ? 16 : 0;
+    }
     return ECMC_OK;
 }
 
@@ -348,7 +364,7 @@ ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, in
     c->cap = opt->cell_capacity > 0 ? opt->cell_capacity : DEFAULT_CAP;
     auto bail = [&](ecmc_status s) {
         g_err = c->err;
-        delete c;
+        ecmc_destroy(c);
         return s;
     };
     ecmc_status st = geometry(box, sigma, l_max, n_beads, *opt, c->g, c);
@@ -358,6 +374,12 @@ ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, in
         return bail(fail(c, ECMC_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)", c->lay.total,
                          opt->workspace_bytes));
     c->ws = (char *)opt->workspace;
+    if (c->g.bpl2) {
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(c, ECMC_E_DEVICE, "creating the second stream failed"));
+    }
 
     HostState hs;
     hs.px.resize(n_beads);
@@ -419,6 +441,31 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
     a.sweep = c->sweep_ctr;
+    a.exact_search = c->opt.exact_search ? 1 : 0;
+    {
+        // Single-precision screen (see first_event).  Screening coordinates are frame
+        // coordinates rounded once to float, so every float displacement is within
+        // delta = 6 u X of the FP64 one (u = 2^-24, X the largest coordinate or displacement:
+        // the frame edge, or L for the whole box).  For |d_perp| <= b the float d_perp^2 is
+        // then within m = 4 b delta + 2 delta^2 + 8 u b^2 of the FP64 value, the argument of
+        // the square root within m + 4 u b^2, the square root within the square root of that
+        // (the ill-conditioned grazing case), and the estimate of x within
+        // delta + sqrt(m + 4 u b^2) + 4 u b + u (X + b).  The interval half-width is twice that.
+        const double u = std::ldexp(1.0, -24);
+        const double bm = std::max(c->sigma, c->lmax);
+        const bool whole = c->opt.tiling == ECMC_TILING_WHOLE;
+        const double X = whole ? c->L : (c->g.D + 2) * c->g.h;
+        const double delta = 6.0 * u * X + 1e-12 * c->L;
+        const double m = 4.0 * bm * delta + 2.0 * delta * delta + 8.0 * u * bm * bm;
+        const double err = 2.0 * (delta + std::sqrt(m + 4.0 * u * bm * bm) + 4.0 * u * bm + u * (X + bm));
+        const float inf = __builtin_huge_valf();
+        a.p_sure = std::nextafter((float)delta, inf);
+        a.in_lo = std::nextafter((float)(c->sig2 - m), 0.0f);
+        a.in_hi = std::nextafter((float)(c->sig2 + m), inf);
+        a.err_f = std::nextafter((float)err, inf);
+        a.sig2f = (float)c->sig2;
+        a.b2f = (float)c->b2;
+    }
     const bool log = c->opt.event_log_capacity > 0;
     auto launch = [&](int grid) -> ecmc_status {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -427,7 +474,26 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
             HIP_OK(c, hipEventCreate(&e1));
             HIP_OK(c, hipEventRecord(e0, c->stream));
         }
+        // the tiers take disjoint sets of domains of one colour, which never interact: the
+        // larger (rarer) tiers run on a second stream concurrently with the first
+        if (c->g.bpl2) {
+            HIP_OK(c, hipEventRecord(c->fork, c->stream));
+            HIP_OK(c, hipStreamWaitEvent(c->side, c->fork, 0));
+            PhaseArgs b = a;
+            b.stage_lo = 64 * c->g.bpl;
+            b.stage_hi = c->g.bpl3 ? 64 * c->g.bpl2 : 0x7fffffff;
+            HIP_OK(c, launch_phase(b, c->g.bpl2, log, grid, c->side));
+            if (c->g.bpl3) {
+                b.stage_lo = 64 * c->g.bpl2;
+                b.stage_hi = 0x7fffffff;
+                HIP_OK(c, launch_phase(b, c->g.bpl3, log, grid, c->side));
+            }
+            HIP_OK(c, hipEventRecord(c->join, c->side));
+        }
+        a.stage_lo = 0;
+        a.stage_hi = c->g.bpl2 ? 64 * c->g.bpl : 0x7fffffff;
         HIP_OK(c, launch_phase(a, c->g.bpl, log, grid, c->stream));
+        if (c->g.bpl2) HIP_OK(c, hipStreamWaitEvent(c->stream, c->join, 0));
         if (c->opt.time_kernels) {
             HIP_OK(c, hipEventRecord(e1, c->stream));
             c->timing.emplace_back(e0, e1);
@@ -550,6 +616,8 @@ ecmc_status ecmc_get_counters(ecmc_ctx *c, ecmc_counters *out) {
     out->cross = v[C_CROSS];
     out->ec = v[C_EC];
     out->steps = v[C_STEPS];
+    out->periodic = v[C_PERIOD];
+    out->cycle = v[C_CYCLE];
     HIP_OK(c, hipMemcpy(&out->sum_delta, c->ws + c->lay.dsum, 8, hipMemcpyDeviceToHost));
     HIP_OK(c, hipMemcpy(&out->error_flags, c->ws + c->lay.err, 4, hipMemcpyDeviceToHost));
     return ECMC_OK;
@@ -640,10 +708,18 @@ ecmc_status ecmc_kernel_time(ecmc_ctx *c, double *ms, int64_t *launches) {
 uint32_t ecmc_sweep_counter(const ecmc_ctx *c) { return c ? c->sweep_ctr : 0; }
 int32_t ecmc_n_cells(const ecmc_ctx *c) { return c ? c->g.n : 0; }
 double ecmc_cell_size(const ecmc_ctx *c) { return c ? c->g.h : 0.0; }
-int32_t ecmc_stage_capacity(const ecmc_ctx *c) { return c ? 64 * c->g.bpl : 0; }
+int32_t ecmc_stage_capacity(const ecmc_ctx *c) {
+    return c ? 64 * (c->g.bpl3 ? c->g.bpl3 : (c->g.bpl2 ? c->g.bpl2 : c->g.bpl)) : 0;
+}
 
 void ecmc_destroy(ecmc_ctx *c) {
     if (!c) return;
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->join) (void)hipEventDestroy(c->join);
     if (!c->timing.empty()) {
         (void)hipStreamSynchronize(c->stream);
         for (auto &p : c->timing) {

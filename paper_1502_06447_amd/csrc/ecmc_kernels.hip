@@ -94,94 +94,262 @@ __device__ __forceinline__ int cell_of(int32_t m, int ax) { return (m >> (ax * C
 // cell faces: bnd(k) = k h for k < n, bnd(n) = L
 __device__ __forceinline__ double face(int k, int n, double h, double L) { return k < n ? (double)k * h : L; }
 
-// ------------------------------------------------------------------ candidates
-// Every lane holds BPL staged beads in a frame rotated to the current axis of motion:
-// A = coordinate along the axis, B and C = the other two (cyclic order).  For each
-// staged bead: the displacement from the pivot (periodic shift from the cell-index
-// difference, added after the subtraction), its component along the motion d_par and
-// the squared distance from the line of motion d_perp^2; then one candidate:
+// ------------------------------------------------------------------ event search
+// Every lane holds single-precision screening copies of its BPL staged beads, in the
+// domain frame (coordinates relative to the frame's lower corner, unwrapped across the
+// periodic boundary) rotated to the current axis of motion: A along the axis, B and C
+// the other two in cyclic order.  The exact FP64 positions, cell words and tether
+// partners of the staged beads live in LDS and are read only for the few beads the
+// screen cannot rule out.
+template <int BPL, bool WHOLE>
+struct Lanes {
+    float A[BPL], B[BPL], C[BPL];
+    int32_t META[WHOLE ? BPL : 1];  // whole box: cell words for the periodic shift of the screen
+};
+
+// the current pivot, uniform across the wavefront
+struct Pivot {
+    int P;            // staged index
+    int32_t meta;     // cell word
+    int32_t part;     // staged indices of the tethered partners (16 bits each, 0xFFFF = none)
+    double a, b, c;   // FP64 position in the rotated frame
+    float fa, fb, fc; // screening copy
+};
+
+// the staged data in LDS
+struct Stage {
+    double *px, *py, *pz;  // FP64 x, y, z
+    int32_t *meta;
+    int32_t *part;
+    int32_t *id;
+    __device__ __forceinline__ double *axis(int ax) const { return ax == 0 ? px : (ax == 1 ? py : pz); }
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float fminf_(float a, float b) { return b < a ? b : a; }
+
+__device__ __forceinline__ float wave_min_f32(float v) {
+    v = fminf_(v, dpp_f32<0xB1>(v));
+    v = fminf_(v, dpp_f32<0x4E>(v));
+    v = fminf_(v, dpp_f32<0x141>(v));
+    v = fminf_(v, dpp_f32<0x140>(v));
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return fminf_(fminf_(r0, r1), fminf_(r2, r3));
+}
+
+// Exact FP64 candidate of one staged bead: displacement from the pivot (periodic shift
+// from the cell-index difference, added after the subtraction), d_par and d_perp^2, then
 //   hard sphere, if d_par > 0 and d_perp^2 < sigma^2:  x = d_par - sqrt(sigma^2 - d_perp^2)
 //   tether, for a partner of the pivot that is not hit:  x = d_par + sqrt(max(b^2 - d_perp^2, 0))
 // (for a partner that is hit the contact always comes first: x_hs <= d_par <= x_tether),
-// clamped at 0.  The lane keeps the smallest (x, staged index); staged indices follow
-// bead ids, so this is the order by id.
-template <int BPL>
-struct Lanes {
-    double A[BPL], B[BPL], C[BPL];
-    int32_t META[BPL], PART[BPL];
+// clamped at 0.  Returns whether the bead is a candidate at all.
+template <bool WRAP>
+__device__ __forceinline__ bool exact_candidate(double A, double B, double C, int32_t meta, const Pivot &pv, int sha,
+                                                int shb, int shc, double sgnd, double sig2, double b2, double L,
+                                                bool partner, double &x, bool &hs) {
+    double da = A - pv.a;
+    double db = B - pv.b;
+    double dc = C - pv.c;
+    if (WRAP) {
+        const int ea = (int)((meta >> sha) & CELL_MASK) - (int)((pv.meta >> sha) & CELL_MASK);
+        const int eb = (int)((meta >> shb) & CELL_MASK) - (int)((pv.meta >> shb) & CELL_MASK);
+        const int ec = (int)((meta >> shc) & CELL_MASK) - (int)((pv.meta >> shc) & CELL_MASK);
+        da = da + (ea > 1 ? -L : (ea < -1 ? L : 0.0));
+        db = db + (eb > 1 ? -L : (eb < -1 ? L : 0.0));
+        dc = dc + (ec > 1 ? -L : (ec < -1 ? L : 0.0));
+    }
+    const double dpar = da * sgnd;
+    const double pb = db * db;
+    const double pc = dc * dc;
+    const double dperp2 = pb + pc;
+    hs = (dpar > 0.0) && (dperp2 < sig2);
+    double arg = (hs ? sig2 : b2) - dperp2;
+    if (!(arg > 0.0)) arg = 0.0;
+    const double sq = __builtin_sqrt(arg);
+    double v = hs ? dpar - sq : dpar + sq;
+    if (!(v > 0.0)) v = 0.0;
+    x = v;
+    return hs || partner;
+}
+
+// Single-precision screen constants (derived on the host, see ecmc_api.cpp).
+struct ScreenK {
+    float sig2f, b2f;    // sigma^2, b^2 in float
+    float in_lo, in_hi;  // float d_perp^2 below in_lo: surely inside sigma; not below in_hi: surely not
+    float p_sure;        // float d_par above it: surely ahead; d_par ahead implies float d_par > -p_sure
+    float err;           // bound on |x_float - x_exact| for every candidate
+    float Lf;
 };
 
-struct Pivot {
-    int P, slot, owner;
+// The winner of the event search and the data the pivot needs if it is lifted to it.
+struct Hit {
+    double x;
+    unsigned key;       // staged index * 2 + kind (0 hard sphere, 1 tether)
+    double a, b, c;     // FP64 position of the struck bead (rotated frame)
     int32_t meta, part;
-    double a, b, c;
 };
 
-template <int BPL, bool WRAP>
-__device__ __forceinline__ void candidates(const Lanes<BPL> &R, const Pivot &pv, int sha, int shb, int shc,
-                                           double sgnd, double sig2, double b2, double L, double &bx,
-                                           unsigned &bkey) {
+// First interaction event of the pivot: the exact minimum over all staged beads of
+// (x, staged index, kind).
+//  1. Screen: a float estimate of every bead's x gives an interval [lo, hi] that
+//     provably contains the exact x of each bead that is a candidate at all.
+//  2. One float min-reduction of hi over the wavefront gives a threshold t.
+//  3. Only beads with lo <= t are evaluated exactly, from LDS (normally one bead).  Their
+//     exact minimum x* is certified when x* <= t; otherwise t is raised to x* and the step
+//     repeats.  A bead left out has exact x >= lo > t >= x*, so the result is exact.
+// With EXACT every staged bead is evaluated in FP64 (the reference search).
+template <int BPL, bool WHOLE, bool EXACT>
+__device__ __forceinline__ Hit first_event(const Lanes<BPL, WHOLE> &R, const Stage &st, const Pivot &pv, int ax,
+                                           int sha, int shb, int shc, double sgnd, double sig2, double b2, double L,
+                                           bool wr, const ScreenK &K, int S) {
     const int lane = lane_id();
     const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
-    bx = INF;
-    bkey = 0xFFFFFFFFu;
+    const float sgnf = sgnd > 0.0 ? 1.0f : -1.0f;
+    const double *pA = st.axis(ax);
+    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
+    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
+    float lo[BPL];  // +inf for beads that cannot be candidates
+    float hmin = __builtin_huge_valf();
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
         const int idx = k * 64 + lane;
-        double da = R.A[k] - pv.a;
-        double db = R.B[k] - pv.b;
-        double dc = R.C[k] - pv.c;
-        if (WRAP) {
+        const bool me = idx == pv.P;
+        const bool partner = (idx == q0) || (idx == q1);
+        if (EXACT) {
+            lo[k] = (idx < S && !me) ? 0.0f : __builtin_huge_valf();
+            hmin = 0.0f;
+            continue;
+        }
+        float da = R.A[k] - pv.fa;
+        float db = R.B[k] - pv.fb;
+        float dc = R.C[k] - pv.fc;
+        if (WHOLE) {
             const int ea = (int)((R.META[k] >> sha) & CELL_MASK) - (int)((pv.meta >> sha) & CELL_MASK);
             const int eb = (int)((R.META[k] >> shb) & CELL_MASK) - (int)((pv.meta >> shb) & CELL_MASK);
             const int ec = (int)((R.META[k] >> shc) & CELL_MASK) - (int)((pv.meta >> shc) & CELL_MASK);
-            da = da + (ea > 1 ? -L : (ea < -1 ? L : 0.0));
-            db = db + (eb > 1 ? -L : (eb < -1 ? L : 0.0));
-            dc = dc + (ec > 1 ? -L : (ec < -1 ? L : 0.0));
+            da = da + (ea > 1 ? -K.Lf : (ea < -1 ? K.Lf : 0.0f));
+            db = db + (eb > 1 ? -K.Lf : (eb < -1 ? K.Lf : 0.0f));
+            dc = dc + (ec > 1 ? -K.Lf : (ec < -1 ? K.Lf : 0.0f));
         }
-        const double dpar = da * sgnd;
-        const double pb = db * db;
-        const double pc = dc * dc;
-        const double dperp2 = pb + pc;
-        const bool hs = (dpar > 0.0) && (dperp2 < sig2);
-        const bool partner = (idx == q0) || (idx == q1);
-        double arg = (hs ? sig2 : b2) - dperp2;
-        if (!(arg > 0.0)) arg = 0.0;
-        const double sq = __builtin_sqrt(arg);
-        double x = hs ? dpar - sq : dpar + sq;
-        if (!(x > 0.0)) x = 0.0;
-        const bool ok = (idx != pv.P) && (hs || partner);
-        if (ok && x < bx) {
-            bx = x;
-            bkey = (unsigned)(idx * 2 + (hs ? 0 : 1));
+        const float p = da * sgnf;
+        const float q = db * db + dc * dc;
+        const bool hs_sure = (p > K.p_sure) && (q < K.in_lo);
+        const bool hs_maybe = (p > -K.p_sure) && (q < K.in_hi);
+        // the estimate follows the hard-sphere formula whenever a contact is possible; a
+        // partner that may or may not be hit gets the interval spanning both formulas
+        const float cc = hs_maybe ? K.sig2f : K.b2f;
+        const float sr = __builtin_amdgcn_sqrtf(fmaxf(cc - q, 0.0f));
+        const float est = fmaxf(hs_maybe ? p - sr : p + sr, 0.0f);
+        float l = est - K.err, hg = est + K.err;
+        const bool amb = partner && hs_maybe && !hs_sure;
+        if (__builtin_expect(__ballot(amb) != 0, 0)) {
+            if (amb) {
+                const float st2 = __builtin_amdgcn_sqrtf(fmaxf(K.b2f - q, 0.0f));
+                const float et = fmaxf(p + st2, 0.0f);
+                l = fminf(l, et - K.err);
+                hg = fmaxf(hg, et + K.err);
+            }
         }
+        const bool cand = !me && (hs_maybe || partner);
+        lo[k] = cand ? l : __builtin_huge_valf();
+        hmin = fminf_(hmin, cand ? hg : __builtin_huge_valf());
     }
+    Hit h;
+    h.x = INF;
+    h.key = 0xFFFFFFFFu;
+    h.a = h.b = h.c = 0.0;
+    h.meta = 0;
+    h.part = -1;
+    const float t0 = EXACT ? 0.0f : wave_min_f32(hmin);
+    if (!EXACT && !(t0 < __builtin_huge_valf())) return h;
+    double thr = EXACT ? INF : (double)t0;
+    double bx = INF, bA = 0.0, bB = 0.0, bC = 0.0;
+    unsigned bkey = 0xFFFFFFFFu;
+    int32_t bmeta = 0, bpart = -1;
+    unsigned done = 0;
+    double xs;
+    for (;;) {
+#pragma unroll
+        for (int k = 0; k < BPL; ++k) {
+            // lo is +inf for the pivot itself, for empty slots and for beads the screen rules
+            // out: they are never evaluated, also when the threshold has been widened to +inf
+            const bool mem = !((done >> k) & 1u) && lo[k] < __builtin_huge_valf() && (double)lo[k] <= thr;
+            if (__ballot(mem)) {
+                if (mem) {
+                    const int idx = k * 64 + lane;
+                    const double A = pA[idx], B = pB[idx], C = pC[idx];
+                    const int32_t m = st.meta[idx];
+                    const bool partner = (idx == q0) || (idx == q1);
+                    double x;
+                    bool hs;
+                    const bool ok = (idx != pv.P) &&
+                                    (wr ? exact_candidate<true>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
+                                                                partner, x, hs)
+                                        : exact_candidate<false>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
+                                                                 partner, x, hs));
+                    const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
+                    if (ok && (x < bx || (x == bx && kk < bkey))) {
+                        bx = x;
+                        bkey = kk;
+                        bA = A;
+                        bB = B;
+                        bC = C;
+                        bmeta = m;
+                        bpart = st.part[idx];
+                    }
+                    done |= 1u << k;
+                }
+            }
+        }
+        xs = wave_min_f64(bx);
+        if (xs <= thr) break;
+        // the threshold came from a screened bead that is no candidate after all: widen
+        thr = xs;
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < BPL; ++k)
+            more = more || (!((done >> k) & 1u) && lo[k] < __builtin_huge_valf() && (double)lo[k] <= thr);
+        if (!__ballot(more)) break;
+    }
+    if (!(xs < INF)) return h;
+    const unsigned long long tie = __ballot(bx == xs);
+    int wl;
+    if (__popcll(tie) == 1) {
+        wl = (int)(__ffsll((long long)tie) - 1);
+        h.key = (unsigned)rdlane((int)bkey, wl);
+    } else {
+        h.key = wave_min_u32(bx == xs ? bkey : 0xFFFFFFFFu);
+        wl = (int)((h.key >> 1) & 63u);
+    }
+    h.x = xs;
+    h.a = rdlane(bA, wl);
+    h.b = rdlane(bB, wl);
+    h.c = rdlane(bC, wl);
+    h.meta = rdlane((int)bmeta, wl);
+    h.part = rdlane((int)bpart, wl);
+    return h;
 }
 
 // Select element `slot` (uniform) of a lane's register array.  Written as a masked OR so
 // that the compiler cannot turn it into an indexed load, which would move the array out
 // of VGPRs into scratch memory.
 template <int BPL>
-__device__ __forceinline__ double pick(const double (&V)[BPL], int slot) {
-    unsigned long long acc = 0;
-#pragma unroll
-    for (int k = 0; k < BPL; ++k) {
-        const unsigned long long m = 0ull - (unsigned long long)(slot == k);
-        acc |= (unsigned long long)__double_as_longlong(V[k]) & m;
-    }
-    return __longlong_as_double((long long)acc);
-}
-
-template <int BPL>
-__device__ __forceinline__ int32_t pick(const int32_t (&V)[BPL], int slot) {
+__device__ __forceinline__ float pick(const float (&V)[BPL], int slot) {
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < BPL; ++k) acc |= (uint32_t)V[k] & (0u - (uint32_t)(slot == k));
-    return (int32_t)acc;
+    for (int k = 0; k < BPL; ++k) acc |= (uint32_t)__float_as_int(V[k]) & (0u - (uint32_t)(slot == k));
+    return __int_as_float((int)acc);
 }
 
 template <int BPL>
-__device__ __forceinline__ void put(double (&V)[BPL], int slot, int owner, double v) {
+__device__ __forceinline__ void put(float (&V)[BPL], int slot, int owner, float v) {
     const bool me = lane_id() == owner;
 #pragma unroll
     for (int k = 0; k < BPL; ++k)
@@ -196,59 +364,47 @@ __device__ __forceinline__ void put(int32_t (&V)[BPL], int slot, int owner, int3
         if (slot == k && me) V[k] = v;
 }
 
-template <int BPL>
-__device__ __forceinline__ Pivot load_pivot(int P, const Lanes<BPL> &R) {
-    Pivot v;
-    v.P = P;
-    v.slot = P >> 6;
-    v.owner = P & 63;
-    v.a = rdlane(pick(R.A, v.slot), v.owner);
-    v.b = rdlane(pick(R.B, v.slot), v.owner);
-    v.c = rdlane(pick(R.C, v.slot), v.owner);
-    v.meta = rdlane(pick(R.META, v.slot), v.owner);
-    v.part = rdlane(pick(R.PART, v.slot), v.owner);
-    return v;
-}
-
-// the pivot only moves along A, so only that coordinate and the cell word change
-template <int BPL>
-__device__ __forceinline__ void store_pivot(const Pivot &v, Lanes<BPL> &R) {
-    put(R.A, v.slot, v.owner, v.a);
-    put(R.META, v.slot, v.owner, v.meta);
-}
-
-__device__ __forceinline__ double blend(unsigned long long m, double x, double y) {
-    const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
-    const unsigned long long by = (unsigned long long)__double_as_longlong(y);
-    return __longlong_as_double((long long)((bx & m) | (by & ~m)));
+__device__ __forceinline__ float fblend(uint32_t m, float x, float y) {
+    return __int_as_float((int)(((uint32_t)__float_as_int(x) & m) | ((uint32_t)__float_as_int(y) & ~m)));
 }
 
 // cyclic change of the frame: (A, B, C) = (r[ax], r[ax+1], r[ax+2]) for the new axis.
 // A bitwise blend rather than two branches, so that the arrays stay in VGPRs.
-template <int BPL>
-__device__ __forceinline__ void rotate(Lanes<BPL> &R, int from, int to) {
+template <int BPL, bool WHOLE>
+__device__ __forceinline__ void rotate(Lanes<BPL, WHOLE> &R, int from, int to) {
     const int r = (to - from + 3) % 3;
     if (r == 0) return;
-    const unsigned long long m = 0ull - (unsigned long long)(r == 1);
+    const uint32_t m = 0u - (uint32_t)(r == 1);
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
-        const double a = R.A[k], b = R.B[k], c = R.C[k];
-        R.A[k] = blend(m, b, c);
-        R.B[k] = blend(m, c, a);
-        R.C[k] = blend(m, a, b);
+        const float a = R.A[k], b = R.B[k], c = R.C[k];
+        R.A[k] = fblend(m, b, c);
+        R.B[k] = fblend(m, c, a);
+        R.C[k] = fblend(m, a, b);
     }
 }
 
+// Per-wave event counters: lane C_* of one VGPR holds counter C_* (32 bits suffice for
+// one phase of one domain), so that they do not occupy scalar registers.
 struct Tally {
-    unsigned long long hs, tl, hr, tr, wall, cross, ec, steps;
+    uint32_t v;
     double dsum;
+    __device__ __forceinline__ void inc(int which) { v += (lane_id() == which) ? 1u : 0u; }
 };
 
 struct Frame {
     int ds[3];      // first cell of the domain per axis
+    int fs[3];      // first cell of the frame (domain plus halo) per axis
+    double O[3];    // lower corner of the frame (screening origin)
     int S;          // staged beads
     uint32_t domain;
 };
+
+// screening coordinate of a bead at r in cell c along an axis with frame start fs, origin O
+__device__ __forceinline__ float frame_u(double r, int c, int fs, double L, double O) {
+    const double w = c < fs ? r + L : r;
+    return (float)(w - O);
+}
 
 __device__ __forceinline__ void log_event(const PhaseArgs &a, const Frame &f, long long k, long long step, int p,
                                           int t, int kind) {
@@ -262,38 +418,97 @@ __device__ __forceinline__ void log_event(const PhaseArgs &a, const Frame &f, lo
     }
 }
 
-// One EC along axis ax (the lanes' frame is already rotated to it), direction sign
-// sgn, from staged pivot P0, x_max = ell.  Returns false if the iteration cap was hit.
-template <int BPL, bool LOG>
-__device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const int32_t *s_id, Lanes<BPL> &R,
-                                       int P0, int ax, int sgn, bool wr, long long k, Tally &t) {
+// A reflection after an earlier one in the same EC.  Between two reflections every move is
+// reversible (a lift is undone by the reverse lift, a stop sends the pivot back), so after
+// the second one the EC runs back to the first and then repeats: whatever is left of x_max
+// only matters modulo twice the length W used between them.  Whole periods are dropped
+// (logged PERIOD); W == 0 means nothing can move and ends the EC (CYCLE, returns true).
+template <bool LOG>
+__device__ __forceinline__ bool repeat_reflection(const PhaseArgs &a, const Frame &f, long long k, long long step,
+                                                  int id, double xref, double &xmax, Tally &t) {
+    const double w = xref - xmax;
+    if (!(w > 0.0)) {
+        t.inc(C_CYCLE);
+        if (LOG) log_event(a, f, k, step, id, -1, ECMC_EV_CYCLE);
+        return true;
+    }
+    const double r = fmod(xmax, w + w);
+    if (r < xmax) {
+        xmax = r;
+        t.inc(C_PERIOD);
+        if (LOG) log_event(a, f, k, step, id, -1, ECMC_EV_PERIOD);
+    }
+    return false;
+}
+
+// Write the pivot's position along the axis and its cell word back to LDS, and its
+// screening coordinate to the owner lane.
+template <int BPL, bool WHOLE>
+__device__ __forceinline__ void store_pivot(const Pivot &pv, const Stage &st, double *pA, Lanes<BPL, WHOLE> &R) {
+    if (lane_id() == 0) {
+        pA[pv.P] = pv.a;
+        st.meta[pv.P] = pv.meta;
+    }
+    put(R.A, pv.P >> 6, pv.P & 63, pv.fa);
+    if (WHOLE) put(R.META, pv.P >> 6, pv.P & 63, pv.meta);
+}
+
+// One EC along axis ax (the lanes' frame is already rotated to it), direction sign sgn,
+// from staged pivot P0, x_max = ell.  Returns false if the iteration cap was hit.
+template <int BPL, bool LOG, bool EXACT, bool WHOLE>
+__device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const Stage &st, Lanes<BPL, WHOLE> &R,
+                                       int P0, int ax, int sgn, bool wr, long long k, const ScreenK &K, Tally &t) {
     const int n = a.n;
     const double L = a.L, h = a.h;
-    const int sha = ax * CELL_BITS, shb = ((ax + 1) % 3) * CELL_BITS, shc = ((ax + 2) % 3) * CELL_BITS;
+    const int axb = ax == 2 ? 0 : ax + 1, axc = ax == 0 ? 2 : ax - 1;
+    const int sha = ax * CELL_BITS, shb = axb * CELL_BITS, shc = axc * CELL_BITS;
     const int dsa = f.ds[0] * (ax == 0) + f.ds[1] * (ax == 1) + f.ds[2] * (ax == 2);
-    Pivot pv = load_pivot(P0, R);
+    const int fsa = f.fs[0] * (ax == 0) + f.fs[1] * (ax == 1) + f.fs[2] * (ax == 2);
+    const double Oa = f.O[0] * (ax == 0) + f.O[1] * (ax == 1) + f.O[2] * (ax == 2);
+    double *pA = st.axis(ax);
+    Pivot pv;
+    pv.P = P0;
+    pv.a = pA[P0];
+    pv.b = st.axis(axb)[P0];
+    pv.c = st.axis(axc)[P0];
+    pv.meta = st.meta[P0];
+    pv.part = st.part[P0];
+    pv.fa = __int_as_float(rdlane(__float_as_int(pick(R.A, P0 >> 6)), P0 & 63));
+    pv.fb = __int_as_float(rdlane(__float_as_int(pick(R.B, P0 >> 6)), P0 & 63));
+    pv.fc = __int_as_float(rdlane(__float_as_int(pick(R.C, P0 >> 6)), P0 & 63));
     double xmax = a.ell;
     long long step = 0;
-    ++t.ec;
+    bool reflected = false;  // a reflection happened in this EC ...
+    double xref = 0.0;       // ... with this much displacement left after it
+    unsigned run = 0;      // consecutive zero-length events
+    int saved_p = -1, saved_sgn = 0, saved_c = -1;
+    t.inc(C_EC);
     for (;;) {
+        if (run > 0) {
+            // zero-length run: the state (pivot, direction, pivot cell) repeating is a cycle
+            const int cc = (pv.meta >> sha) & CELL_MASK;
+            if (pv.P == saved_p && sgn == saved_sgn && cc == saved_c) {
+                store_pivot(pv, st, pA, R);
+                t.inc(C_CYCLE);
+                if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_CYCLE);
+                return true;
+            }
+            if ((run & (run - 1)) == 0) {
+                saved_p = pv.P;
+                saved_sgn = sgn;
+                saved_c = cc;
+            }
+        }
         if (step >= a.event_cap) {
-            store_pivot(pv, R);
+            store_pivot(pv, st, pA, R);
             return false;
         }
         ++step;
-        ++t.steps;
+        t.inc(C_STEPS);
         const double sgnd = sgn > 0 ? 1.0 : -1.0;
-        double bx;
-        unsigned bkey;
-        if (wr) candidates<BPL, true>(R, pv, sha, shb, shc, sgnd, a.sig2, a.b2, L, bx, bkey);
-        else candidates<BPL, false>(R, pv, sha, shb, shc, sgnd, a.sig2, a.b2, L, bx, bkey);
-        const double xint = wave_min_f64(bx);
-        unsigned key = 0xFFFFFFFFu;
-        if (xint < INF) {
-            const unsigned long long tie = __ballot(bx == xint);
-            if (__popcll(tie) == 1) key = (unsigned)rdlane((int)bkey, (int)(__ffsll((long long)tie) - 1));
-            else key = wave_min_u32(bx == xint ? bkey : 0xFFFFFFFFu);
-        }
+        const Hit hit = first_event<BPL, WHOLE, EXACT>(R, st, pv, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, K,
+                                                        f.S);
+        const double xint = hit.x;
         const int c = (pv.meta >> sha) & CELL_MASK;
         const double r_old = pv.a;
         double xc = sgn > 0 ? face(c + 1, n, h, L) - r_old : r_old - face(c, n, h, L);
@@ -302,43 +517,66 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
         if (xmax <= mlim) {
             // END: the pivot takes the rest of the displacement
             pv.a = sgn > 0 ? r_old + xmax : r_old - xmax;
-            store_pivot(pv, R);
-            if (LOG) log_event(a, f, k, step, s_id[pv.P], -1, ECMC_EV_END);
+            pv.fa = frame_u(pv.a, c, fsa, L, Oa);
+            store_pivot(pv, st, pA, R);
+            if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_END);
             return true;
         }
         if (xint <= xc) {
             // interaction event: move to contact / tether limit
+            if (xint > 0.0) {
+                run = 0;
+                saved_p = -1;
+            } else {
+                ++run;
+            }
             pv.a = sgn > 0 ? r_old + xint : r_old - xint;
+            pv.fa = frame_u(pv.a, c, fsa, L, Oa);
             xmax = xmax - xint;
-            const int j = (int)(key >> 1);
-            const int kind = (int)(key & 1u);
-            const int jslot = j >> 6, jown = j & 63;
-            const int32_t jmeta = rdlane(pick(R.META, jslot), jown);
-            if (jmeta & MOTILE_BIT) {
+            const int j = (int)(hit.key >> 1);
+            const int kind = (int)(hit.key & 1u);
+            if (hit.meta & MOTILE_BIT) {
                 // lift: the struck bead continues the chain; accumulate (d_par - x)
-                const double jr = rdlane(pick(R.A, jslot), jown);
-                double da = jr - r_old;
+                double da = hit.a - r_old;
                 if (wr) {
-                    const int e = (int)((jmeta >> sha) & CELL_MASK) - c;
+                    const int e = (int)((hit.meta >> sha) & CELL_MASK) - c;
                     da = da + (e > 1 ? -L : (e < -1 ? L : 0.0));
                 }
                 const double dpar = da * sgnd;
                 t.dsum += dpar - xint;
-                if (kind == 0) ++t.hs;
-                else ++t.tl;
-                if (LOG) log_event(a, f, k, step, s_id[pv.P], s_id[j], kind == 0 ? ECMC_EV_HS_LIFT : ECMC_EV_TETHER_LIFT);
-                store_pivot(pv, R);
-                pv = load_pivot(j, R);
+                t.inc(kind == 0 ? C_HS_LIFT : C_TETHER_LIFT);
+                if (LOG) log_event(a, f, k, step, st.id[pv.P], st.id[j], kind == 0 ? ECMC_EV_HS_LIFT : ECMC_EV_TETHER_LIFT);
+                store_pivot(pv, st, pA, R);
+                pv.P = j;
+                pv.a = hit.a;
+                pv.b = hit.b;
+                pv.c = hit.c;
+                pv.meta = hit.meta;
+                pv.part = hit.part;
+                pv.fa = __int_as_float(rdlane(__float_as_int(pick(R.A, j >> 6)), j & 63));
+                pv.fb = __int_as_float(rdlane(__float_as_int(pick(R.B, j >> 6)), j & 63));
+                pv.fc = __int_as_float(rdlane(__float_as_int(pick(R.C, j >> 6)), j & 63));
             } else {
-                if (kind == 0) ++t.hr;
-                else ++t.tr;
+                t.inc(kind == 0 ? C_HS_REFLECT : C_TETHER_REFLECT);
                 if (LOG)
-                    log_event(a, f, k, step, s_id[pv.P], s_id[j], kind == 0 ? ECMC_EV_HS_REFLECT : ECMC_EV_TETHER_REFLECT);
+                    log_event(a, f, k, step, st.id[pv.P], st.id[j], kind == 0 ? ECMC_EV_HS_REFLECT : ECMC_EV_TETHER_REFLECT);
+                if (reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+                    store_pivot(pv, st, pA, R);
+                    return true;
+                }
+                reflected = true;
+                xref = xmax;
                 sgn = -sgn;
             }
             continue;
         }
         // cell-face event: the pivot is set onto the face
+        if (xc > 0.0) {
+            run = 0;
+            saved_p = -1;
+        } else {
+            ++run;
+        }
         pv.a = sgn > 0 ? face(c + 1, n, h, L) : face(c, n, h, L);
         xmax = xmax - xc;
         int nc = c + sgn;
@@ -355,37 +593,50 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
             pv.meta = (pv.meta & ~(CELL_MASK << sha)) | (nc << sha);
             if (wrapped > 0) {
                 pv.a = 0.0;
-                if (lane_id() == 0) a.img[3 * s_id[pv.P] + ax] += 1;
+                if (lane_id() == 0) a.img[3 * st.id[pv.P] + ax] += 1;
             } else if (wrapped < 0) {
                 pv.a = L;
-                if (lane_id() == 0) a.img[3 * s_id[pv.P] + ax] -= 1;
+                if (lane_id() == 0) a.img[3 * st.id[pv.P] + ax] -= 1;
             }
-            ++t.cross;
+            pv.fa = frame_u(pv.a, nc, fsa, L, Oa);
+            t.inc(C_CROSS);
         } else {
-            ++t.wall;
-            if (LOG) log_event(a, f, k, step, s_id[pv.P], -1, ECMC_EV_WALL);
+            pv.fa = frame_u(pv.a, c, fsa, L, Oa);
+            t.inc(C_WALL);
+            if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_WALL);
+            if (reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+                store_pivot(pv, st, pA, R);
+                return true;
+            }
+            reflected = true;
+            xref = xmax;
             sgn = -sgn;
         }
     }
 }
 
 // ------------------------------------------------------------------ phase kernel
-template <int BPL, bool LOG>
+template <int BPL, bool LOG, bool EXACT, bool WHOLE>
 __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
     constexpr int SMAX = 64 * BPL;
-    __shared__ int32_t s_id[SMAX];    // staged bead ids, ascending
-    __shared__ int32_t s_meta[SMAX];
-    __shared__ int32_t t_id[SMAX];    // unsorted ids, then the motile list
-    __shared__ int32_t t_meta[SMAX];  // unsorted cell words, then write-back counters
+    __shared__ double s_pos[3][SMAX];  // FP64 staged positions; s_pos[2] first holds the
+                                       // unsorted staging lists (ids, cell words)
+    __shared__ int32_t s_id[SMAX];     // staged bead ids, ascending
+    __shared__ int32_t s_meta[SMAX];   // cell words (+ motile bit)
+    __shared__ int32_t s_part[SMAX];   // tethered partners as staged indices; then write-back counters
+    __shared__ int32_t s_mot[SMAX];    // motile staged indices, ascending
+    int32_t *t_id = reinterpret_cast<int32_t *>(&s_pos[2][0]);
+    int32_t *t_meta = t_id + SMAX;
 
     const int lane = lane_id();
     const int n = a.n;
+    const double L = a.L, h = a.h;
 
     // ---- which domain
     Frame f;
     int dom[3] = {0, 0, 0};
     f.domain = 0;
-    if (!a.whole) {
+    if (!WHOLE) {
         const int nd2 = a.nd >> 1;
         const int b = blockIdx.x;
         dom[0] = 2 * (b % nd2) + (a.colour & 1);
@@ -393,45 +644,55 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
         dom[2] = 2 * (b / (nd2 * nd2)) + ((a.colour >> 2) & 1);
         f.domain = (uint32_t)(dom[0] + a.nd * (dom[1] + a.nd * dom[2]));
     }
-    const int F = a.whole ? n : a.D + 2;
-    int fs[3];
+    const int F = WHOLE ? n : a.D + 2;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        f.ds[ax] = a.whole ? 0 : (a.off[ax] + dom[ax] * a.D) % n;
-        fs[ax] = a.whole ? 0 : (f.ds[ax] - 1 + n) % n;
+        f.ds[ax] = WHOLE ? 0 : (a.off[ax] + dom[ax] * a.D) % n;
+        f.fs[ax] = WHOLE ? 0 : (f.ds[ax] - 1 + n) % n;
+        f.O[ax] = WHOLE ? 0.0 : face(f.fs[ax], n, h, L);
     }
     // the frame (domain + halo) wraps the periodic box on some axis
-    const bool wraps = a.whole || fs[0] + F > n || fs[1] + F > n || fs[2] + F > n;
+    const bool wraps = WHOLE || f.fs[0] + F > n || f.fs[1] + F > n || f.fs[2] + F > n;
 
-    // ---- stage the frame's beads: cell counts, prefix sum, ids and cell words
+    // ---- stage the frame's beads: count first; a domain outside this launch's staging
+    // tier (stage_lo, stage_hi] is left to the launch of the other tier
     const int nfc = F * F * F;
     int S = 0;
+    for (int base = 0; base < nfc; base += 64) {
+        const int c = base + lane;
+        int cnt = 0;
+        if (c < nfc) {
+            const int fx = c % F, fy = (c / F) % F, fz = c / (F * F);
+            cnt = a.ccount[(f.fs[0] + fx) % n + n * ((f.fs[1] + fy) % n + n * ((f.fs[2] + fz) % n))];
+        }
+        S += rdlane(wave_incl_scan(cnt), 63);
+    }
+    if (S <= a.stage_lo || S > a.stage_hi) return;
+    if (S > SMAX) {
+        if (lane == 0) atomicOr(a.err, ERR_STAGE);
+        return;
+    }
+    S = 0;
     for (int base = 0; base < nfc; base += 64) {
         const int c = base + lane;
         int cnt = 0, flat = 0;
         int32_t word = 0;
         if (c < nfc) {
             const int fx = c % F, fy = (c / F) % F, fz = c / (F * F);
-            const int cx = (fs[0] + fx) % n, cy = (fs[1] + fy) % n, cz = (fs[2] + fz) % n;
+            const int cx = (f.fs[0] + fx) % n, cy = (f.fs[1] + fy) % n, cz = (f.fs[2] + fz) % n;
             flat = cx + n * (cy + n * cz);
-            const bool mot = a.whole || (fx >= 1 && fx <= a.D && fy >= 1 && fy <= a.D && fz >= 1 && fz <= a.D);
+            const bool mot = WHOLE || (fx >= 1 && fx <= a.D && fy >= 1 && fy <= a.D && fz >= 1 && fz <= a.D);
             word = pack_cell(cx, cy, cz) | (mot ? MOTILE_BIT : 0);
             cnt = a.ccount[flat];
         }
         const int incl = wave_incl_scan(cnt);
         const int excl = incl - cnt;
         const int tot = rdlane(incl, 63);
-        if (S + incl <= SMAX) {
-            for (int i = 0; i < cnt; ++i) {
-                t_id[S + excl + i] = a.cids[(long long)flat * a.cap + i];
-                t_meta[S + excl + i] = word;
-            }
+        for (int i = 0; i < cnt; ++i) {
+            t_id[S + excl + i] = a.cids[(long long)flat * a.cap + i];
+            t_meta[S + excl + i] = word;
         }
         S += tot;
-    }
-    if (S > SMAX) {
-        if (lane == 0) atomicOr(a.err, ERR_STAGE);
-        return;
     }
     f.S = S;
     __syncthreads();
@@ -445,22 +706,28 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
     }
     __syncthreads();
 
-    // lanes' beads in frame (x, y, z); empty slots far away so they never yield a candidate
-    Lanes<BPL> R;
+    // FP64 positions and partners into LDS; screening copies into the lanes (empty slots far
+    // away, so that they never pass the screen)
+    Lanes<BPL, WHOLE> R;
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
         const int idx = k * 64 + lane;
-        R.A[k] = R.B[k] = R.C[k] = 1.0e30;
-        R.META[k] = 0;
-        R.PART[k] = -1;
+        R.A[k] = R.B[k] = R.C[k] = 1.0e30f;
+        if (WHOLE) R.META[k] = 0;
         if (idx < S) {
             const int id = s_id[idx];
-            R.META[k] = s_meta[idx];
-            R.A[k] = a.px[id];
-            R.B[k] = a.py[id];
-            R.C[k] = a.pz[id];
-            if (R.META[k] & MOTILE_BIT) {
-                int packed = 0;
+            const int32_t m = s_meta[idx];
+            const double x = a.px[id], y = a.py[id], z = a.pz[id];
+            s_pos[0][idx] = x;
+            s_pos[1][idx] = y;
+            s_pos[2][idx] = z;
+            R.A[k] = frame_u(x, cell_of(m, 0), f.fs[0], L, f.O[0]);
+            R.B[k] = frame_u(y, cell_of(m, 1), f.fs[1], L, f.O[1]);
+            R.C[k] = frame_u(z, cell_of(m, 2), f.fs[2], L, f.O[2]);
+            if (WHOLE) R.META[k] = m;
+            int packed = -1;
+            if (m & MOTILE_BIT) {
+                packed = 0;
                 for (int tt = 0; tt < 2; ++tt) {
                     const int g = a.part[2 * id + tt];
                     int found = 0xFFFF;
@@ -479,63 +746,66 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
                     }
                     packed |= found << (16 * tt);
                 }
-                R.PART[k] = packed;
             }
+            s_part[idx] = packed;
         }
     }
-    // motile list in ascending id (reuses t_id)
+    // motile list in ascending id
     int nmot = 0;
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
         const int idx = k * 64 + lane;
-        const bool m = idx < S && (R.META[k] & MOTILE_BIT);
+        const bool m = idx < S && (s_meta[idx] & MOTILE_BIT);
         const unsigned long long bal = __ballot(m);
-        if (m) t_id[nmot + mbcnt(bal)] = idx;
+        if (m) s_mot[nmot + mbcnt(bal)] = idx;
         nmot += __popcll(bal);
     }
     __syncthreads();
 
     // ---- ECs
-    Tally t = {0, 0, 0, 0, 0, 0, 0, 0, 0.0};
+    const Stage st = {&s_pos[0][0], &s_pos[1][0], &s_pos[2][0], s_meta, s_part, s_id};
+    const ScreenK K = {a.sig2f, a.b2f, a.in_lo, a.in_hi, a.p_sure, a.err_f, (float)L};
+    Tally t = {0u, 0.0};
     bool ok = true;
     int cur = 0;  // axis the lanes' frame is rotated to
     for (long long k = 0; k < a.K && nmot > 0 && ok; ++k) {
         uint32_t ctr[4] = {(uint32_t)k, f.domain, a.sweep, 0u};
         philox4x32_10(ctr, a.key0, a.key1);
-        const int P0 = __builtin_amdgcn_readfirstlane(t_id[scale_u32(ctr[0], (uint32_t)nmot)]);
+        const int P0 = __builtin_amdgcn_readfirstlane(s_mot[scale_u32(ctr[0], (uint32_t)nmot)]);
         const uint32_t dir = scale_u32(ctr[1], 6u);
         const int ax = __builtin_amdgcn_readfirstlane((int)(dir >> 1));
         const int sgn = (dir & 1u) ? -1 : 1;
         rotate(R, cur, ax);
         cur = ax;
-        ok = run_ec<BPL, LOG>(a, f, s_id, R, P0, ax, sgn, wraps, k, t);
+        ok = run_ec<BPL, LOG, EXACT, WHOLE>(a, f, st, R, P0, ax, sgn, wraps, k, K, t);
     }
-    rotate(R, cur, 0);
+    __syncthreads();
 
     // ---- write back the motile beads and the domain's cell lists
-    const int ndc = a.whole ? n * n * n : a.D * a.D * a.D;
-    for (int i = lane; i < ndc; i += 64) t_meta[i] = 0;
+    const int ndc = WHOLE ? n * n * n : a.D * a.D * a.D;
+    for (int i = lane; i < ndc; i += 64) s_part[i] = 0;
     __syncthreads();
     bool overflow = false;
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
         const int idx = k * 64 + lane;
-        if (idx < S && (R.META[k] & MOTILE_BIT)) {
+        const int32_t m = idx < S ? s_meta[idx] : 0;
+        if (idx < S && (m & MOTILE_BIT)) {
             const int id = s_id[idx];
-            a.px[id] = R.A[k];
-            a.py[id] = R.B[k];
-            a.pz[id] = R.C[k];
-            const int32_t w = R.META[k] & ~MOTILE_BIT;
+            a.px[id] = s_pos[0][idx];
+            a.py[id] = s_pos[1][idx];
+            a.pz[id] = s_pos[2][idx];
+            const int32_t w = m & ~MOTILE_BIT;
             a.cellp[id] = w;
             const int cx = cell_of(w, 0), cy = cell_of(w, 1), cz = cell_of(w, 2);
             int lc;
-            if (a.whole) {
+            if (WHOLE) {
                 lc = cx + n * (cy + n * cz);
             } else {
                 const int tx = (cx - f.ds[0] + n) % n, ty = (cy - f.ds[1] + n) % n, tz = (cz - f.ds[2] + n) % n;
                 lc = tx + a.D * (ty + a.D * tz);
             }
-            const int slot = atomicAdd(&t_meta[lc], 1);
+            const int slot = atomicAdd(&s_part[lc], 1);
             if (slot < a.cap) a.cids[(long long)(cx + n * (cy + n * cz)) * a.cap + slot] = id;
             else overflow = true;
         }
@@ -543,7 +813,7 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
     __syncthreads();
     for (int i = lane; i < ndc; i += 64) {
         int cx, cy, cz;
-        if (a.whole) {
+        if (WHOLE) {
             cx = i % n;
             cy = (i / n) % n;
             cz = i / (n * n);
@@ -552,20 +822,13 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
             cy = (f.ds[1] + (i / a.D) % a.D) % n;
             cz = (f.ds[2] + i / (a.D * a.D)) % n;
         }
-        const int v = t_meta[i];
+        const int v = s_part[i];
         a.ccount[cx + n * (cy + n * cz)] = v < a.cap ? v : a.cap;
     }
     if (__ballot(overflow) && lane == 0) atomicOr(a.err, ERR_CELL);
+    if (lane < NCNT && t.v) atomicAdd(&a.cnt[lane], (unsigned long long)t.v);
     if (lane == 0) {
         if (!ok) atomicOr(a.err, ERR_STUCK);
-        if (t.hs) atomicAdd(&a.cnt[C_HS_LIFT], t.hs);
-        if (t.tl) atomicAdd(&a.cnt[C_TETHER_LIFT], t.tl);
-        if (t.hr) atomicAdd(&a.cnt[C_HS_REFLECT], t.hr);
-        if (t.tr) atomicAdd(&a.cnt[C_TETHER_REFLECT], t.tr);
-        if (t.wall) atomicAdd(&a.cnt[C_WALL], t.wall);
-        if (t.cross) atomicAdd(&a.cnt[C_CROSS], t.cross);
-        if (t.ec) atomicAdd(&a.cnt[C_EC], t.ec);
-        if (t.steps) atomicAdd(&a.cnt[C_STEPS], t.steps);
         if (t.dsum != 0.0) atomicAdd(a.sum_delta, t.dsum);
     }
 }
@@ -647,11 +910,20 @@ bool bpl_supported(int bpl) {
     }
 }
 
+// The plain FP64 search is built only together with the event log (it exists to check
+// the screened search, which is the production path).
+template <int BPL, bool WHOLE>
+static hipError_t launch_bpl(const PhaseArgs &a, bool log, int grid, hipStream_t s) {
+    if (a.exact_search && !log) return hipErrorInvalidValue;
+    if (log && a.exact_search) hipLaunchKernelGGL((k_phase<BPL, true, true, WHOLE>), dim3(grid), dim3(64), 0, s, a);
+    else if (log) hipLaunchKernelGGL((k_phase<BPL, true, false, WHOLE>), dim3(grid), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_phase<BPL, false, false, WHOLE>), dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int BPL>
 static hipError_t launch_bpl(const PhaseArgs &a, bool log, int grid, hipStream_t s) {
-    if (log) hipLaunchKernelGGL((k_phase<BPL, true>), dim3(grid), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((k_phase<BPL, false>), dim3(grid), dim3(64), 0, s, a);
-    return hipGetLastError();
+    return a.whole ? launch_bpl<BPL, true>(a, log, grid, s) : launch_bpl<BPL, false>(a, log, grid, s);
 }
 
 hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s) {

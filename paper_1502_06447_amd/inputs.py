@@ -14,10 +14,14 @@ Recipes (all draws from ``numpy.random.default_rng(seed)``):
 
 * ``saw_chains``   - chains grown as self-avoiding random walks with a fixed
   bond length (default 1.2 sigma); the small parity melt.
-* ``lattice_chains`` - dense melts: a simple-cubic lattice with spacing
-  a = L / floor(L / sigma) >= sigma, walked by a boustrophedon Hamiltonian
-  path; chains are consecutive segments of that path.  A random lattice
-  shift and axis permutation come from the seed.
+* ``lattice_chains`` - dense melts: the smallest simple-cubic lattice with at
+  least M N sites and spacing a = L / n_l >= sigma, walked by a boustrophedon
+  Hamiltonian path; chains are consecutive segments of that path, with the
+  n_l^3 - M N vacancies spread evenly as gaps between chains.  A random lattice
+  shift and axis permutation come from the seed, and every bead is jittered
+  by up to 0.45 (a - sigma) / sqrt(3) per coordinate so that no bond is
+  exactly parallel to an axis (exactly aligned, fully stretched bonds stall an
+  axis-parallel event chain).
 * ``hs_fluid``     - unbonded spheres on a lattice (pressure checks).
 * ``isolated_chain`` / ``dimer`` - single short chains in a large box.
 * ``batch_melts``  - many independent melts of mixed N, M and eta.
@@ -161,28 +165,46 @@ def _snake_sites(nl: int) -> np.ndarray:
 
 def lattice_chains(n_poly: int, n_per: int, eta: float, seed: int, sigma: float = 1.0,
                    b_max: float = 1.4, L: float | None = None) -> Melt:
-    """Dense start: chains laid along a Hamiltonian walk of a simple-cubic
-    lattice of spacing a = L / floor(L/sigma) (sigma <= a <= b_max)."""
+    """Dense start: chains laid along a Hamiltonian walk of a simple-cubic lattice of
+    spacing a = L / n_l (sigma <= a <= b_max), n_l the smallest edge with n_l^3 >= M N
+    (or floor(L / sigma) if that spacing would be below sigma)."""
     rng = np.random.default_rng(seed)
     n = n_poly * n_per
     if L is None:
         L = box_for(n, eta, sigma)
-    nl = int(math.floor(L / sigma))
+    nl = int(math.ceil(n ** (1.0 / 3.0) - 1e-9))
+    while nl ** 3 < n:
+        nl += 1
+    if L / nl < sigma:
+        nl = int(math.floor(L / sigma))
     a = L / nl
     if nl ** 3 < n:
         raise ValueError(f"lattice {nl}^3 too small for {n} beads")
     if not (sigma <= a <= b_max):
         raise ValueError(f"lattice spacing {a} outside [sigma, b_max]")
     sites = _snake_sites(nl)
-    start = int(rng.integers(0, nl ** 3 - n + 1))
-    sites = sites[start:start + n]
+    free = nl ** 3 - n
+    start = np.arange(n_poly, dtype=np.int64) * n_per + (np.arange(n_poly, dtype=np.int64) * free) // max(n_poly, 1)
+    idx = (start[:, None] + np.arange(n_per, dtype=np.int64)[None, :]).ravel()
+    # for even n_l the walk closes on itself through the periodic boundary, so it may start
+    # anywhere; for odd n_l it starts at site 0
+    shift_path = int(rng.integers(0, nl ** 3)) if nl % 2 == 0 else 0
+    sites = sites[(idx + shift_path) % (nl ** 3)]
     perm = rng.permutation(3)
     sites = sites[:, perm]
     shift = rng.uniform(0.0, a, 3)
-    pos = _wrap(sites.astype(np.float64) * a + shift[None, :], L)
-    return Melt(L=L, positions=pos, bonds=_chain_bonds(n_poly, n_per), sigma=sigma,
+    jit = 0.45 * (a - sigma) / math.sqrt(3.0)
+    pos = sites.astype(np.float64) * a + shift[None, :] + rng.uniform(-jit, jit, (n, 3))
+    pos = _wrap(pos, L)
+    bonds = _chain_bonds(n_poly, n_per)
+    if len(bonds):
+        d = pos[bonds[:, 1]] - pos[bonds[:, 0]]
+        d -= L * np.round(d / L)
+        if np.einsum("ij,ij->i", d, d).max() > b_max * b_max:
+            raise ValueError("a chain crosses the end of the lattice walk; use another seed")
+    return Melt(L=L, positions=pos, bonds=bonds, sigma=sigma,
                 b_max=b_max, n_poly=n_poly, n_per=n_per,
-                meta={"recipe": "lattice", "seed": seed, "eta": eta, "a": a})
+                meta={"recipe": "lattice", "seed": seed, "eta": eta, "a": a, "jitter": jit})
 
 
 def hs_fluid(n: int, eta: float, seed: int, sigma: float = 1.0) -> Melt:

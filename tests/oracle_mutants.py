@@ -30,6 +30,8 @@ MUTANTS = {
     "rg_index": ("if (rg2) rg2[q] = g / (double)N;", "if (rg2) rg2[q] = g / (double)(N - 1);"),
     "pivot_rng": ("const int32_t p = mot[below(u[0], (uint32_t)m)];",
                   "const int32_t p = mot[below(u[0], (uint32_t)(m > 1 ? m - 1 : m))];"),
+    "period_half": ("const double r = fmod(*xmax, W + W);", "const double r = fmod(*xmax, W);"),
+    "period_no_cycle": ("if (!(W > 0.0)) {", "if (W < 0.0) {"),
     # equivalent mutants: no observable difference is expected
     "tie_kind (equivalent)": ("(j == b->j && kind < b->kind)", "(j == b->j && kind > b->kind)"),
     "face_add (rounding only)": ("*ra = sgn > 0 ? s->bnd[c + 1] : s->bnd[c];", "*ra = sgn > 0 ? *ra + xc : *ra - xc;"),

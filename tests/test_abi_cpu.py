@@ -43,6 +43,10 @@ def test_workspace_size_and_geometry_errors():
     with pytest.raises(ecmc.EcmcError) as e:
         ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
     assert e.value.code == ecmc.E_BOX
+    o.domain_cells = 1  # the partition would never move (offset always 0): not ergodic
+    with pytest.raises(ecmc.EcmcError) as e:
+        ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
+    assert e.value.code == ecmc.E_BOX
     o = ecmc.ecmc_default_options()
     with pytest.raises(ecmc.EcmcError) as e:
         ecmc.ecmc_workspace_size(5.0, 1.0, 1.4, 10, o)          # n = 3 < 4
