@@ -105,7 +105,7 @@ typedef struct {
                                    ended by a zero-length cycle                             */
     double sum_delta;           /* sum over lifts of (d_par - x): pressure estimator        */
     uint32_t error_flags;       /* device error word (bit 0 staging, 1 cell, 2 stuck,
-                                   3 log full)                                              */
+                                   3 log full, 4 cell lists changed during staging)         */
     uint32_t pad;
 } ecmc_counters;
 
@@ -146,7 +146,8 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *ctx, int64_t n_chains, double ell, uint
 /* Waits for the stream and reports device-side errors. */
 ecmc_status ecmc_synchronize(ecmc_ctx *ctx);
 
-/* Observables (Sec. III.A): per polymer (chains walked from their smaller-id end) the
+/* Observables (Sec. IV.A, the g1 and R_g^2 definitions; the end-to-end distance of the
+ * appendix): per polymer (chains walked from their smaller-id end) the
  * squared end-to-end distance r2 (sum of minimum-image bonds), the squared radius of
  * gyration rg2, the middle bead floor(N/2) in image-unwrapped coordinates mid [3];
  * a histogram of bond lengths on [sigma, l_max] with nbins bins (0 < nbins <= 1024).

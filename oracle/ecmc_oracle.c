@@ -807,7 +807,7 @@ int orc_sweep_subset(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int D,
 }
 
 /* ---------------------------------------------------------------- observables */
-/* Per polymer (Sec. III.A): end-to-end vector R as the sum of minimum-image bond
+/* Per polymer (Sec. IV.A and the appendix): end-to-end vector R as the sum of minimum-image bond
  * vectors, R_g^2 = N^-1 sum_i (u_i - u_cm)^2 over the unwrapped chain u (reading
  * the garbled index range as i = 1..N), the middle bead floor(N/2) (0-based) in
  * image-unwrapped coordinates for g1, and a histogram of bond lengths on

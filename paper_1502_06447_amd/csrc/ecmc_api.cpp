@@ -21,7 +21,8 @@ constexpr int DEFAULT_CAP = 16;
 constexpr int MAX_BINS = 1024;
 
 struct Layout {
-    size_t px, py, pz, cellp, img, part, ccount, cids, porder, pstart, r2, rg2, mid, hist, cnt, dsum, err, log_n, log;
+    size_t px, py, pz, cellp, img, part, ccount, cids, dstage, porder, pstart, r2, rg2, mid, hist, cnt, dsum, err, log_n,
+        log;
     size_t total;
 };
 
@@ -44,6 +45,7 @@ Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap) {
     l.part = take(8 * nb);
     l.ccount = take(4 * nc);
     l.cids = take(4 * nc * cap);
+    l.dstage = take(4 * (nc / 8 + 1));  // one count per domain of a colour phase (at most n^3 / 64)
     l.porder = take(4 * nb);
     l.pstart = take(4 * (nb + 1));
     l.r2 = take(8 * nb);
@@ -321,6 +323,7 @@ ecmc_status check_device(ecmc_ctx *c) {
     if (e & ERR_STAGE) return fail(c, ECMC_E_CELL_OVERFLOW, "a domain exceeded the staging capacity %d", c->g.stage);
     if (e & ERR_CELL) return fail(c, ECMC_E_CELL_OVERFLOW, "a cell exceeded its capacity %d", c->cap);
     if (e & ERR_STUCK) return fail(c, ECMC_E_STUCK, "an EC exceeded %lld iterations", (long long)c->opt.event_cap);
+    if (e & ERR_RECOUNT) return fail(c, ECMC_E_DEVICE, "a domain's cell lists changed between its count and its staging");
     return ECMC_OK;
 }
 
@@ -422,6 +425,7 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     a.part = c->dev<int32_t>(c->lay.part);
     a.ccount = c->dev<int32_t>(c->lay.ccount);
     a.cids = c->dev<int32_t>(c->lay.cids);
+    a.dstage = c->dev<int32_t>(c->lay.dstage);
     a.cnt = c->dev<unsigned long long>(c->lay.cnt);
     a.sum_delta = c->dev<double>(c->lay.dsum);
     a.err = c->dev<unsigned int>(c->lay.err);
@@ -474,6 +478,10 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
             HIP_OK(c, hipEventCreate(&e1));
             HIP_OK(c, hipEventRecord(e0, c->stream));
         }
+        // every domain's bead count first, on the main stream: the tier launches pick their
+        // domains by it and never recount (a count taken while another tier rewrites a
+        // domain's cell lists could be half-updated and claim that domain twice)
+        HIP_OK(c, launch_count(a, grid, c->stream));
         // the tiers take disjoint sets of domains of one colour, which never interact: the
         // larger (rarer) tiers run on a second stream concurrently with the first
         if (c->g.bpl2) {

@@ -15,6 +15,7 @@ enum : uint32_t {
     ERR_CELL = 1u << 1,   // a cell list ran out of slots
     ERR_STUCK = 1u << 2,  // an EC exceeded the per-EC iteration cap
     ERR_LOG = 1u << 3,    // event log full (records dropped; informational)
+    ERR_RECOUNT = 1u << 4,  // a domain's cell lists no longer matched its count (internal error)
 };
 
 // counter slots in the device counter block
@@ -62,6 +63,7 @@ struct PhaseArgs {
     const int32_t *part;       // [2n] tethered partners, -1 = none
     int32_t *ccount;           // [nc^3] beads per cell
     int32_t *cids;             // [nc^3 * cap] bead ids per cell
+    int32_t *dstage;           // [grid] beads in each domain's frame, counted before the phase
     unsigned long long *cnt;   // [NCNT]
     double *sum_delta;
     unsigned int *err;
@@ -91,6 +93,7 @@ struct ObsArgs {
 };
 
 // launchers (ecmc_kernels.hip)
+hipError_t launch_count(const PhaseArgs &a, int grid, hipStream_t s);
 hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s);
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
 bool bpl_supported(int bpl);

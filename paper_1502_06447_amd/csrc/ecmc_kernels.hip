@@ -615,6 +615,54 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
     }
 }
 
+// ------------------------------------------------------------------ domain frames
+// Domain b of the launch's colour: its first cell per axis (ds), the frame of domain plus
+// one-cell halo (fs, origin O, edge F cells), and whether that frame wraps the box.
+template <bool WHOLE>
+__device__ __forceinline__ void frame_of(const PhaseArgs &a, int b, Frame &f, int &F, bool &wraps) {
+    const int n = a.n;
+    int dom[3] = {0, 0, 0};
+    f.domain = 0;
+    if (!WHOLE) {
+        const int nd2 = a.nd >> 1;
+        dom[0] = 2 * (b % nd2) + (a.colour & 1);
+        dom[1] = 2 * ((b / nd2) % nd2) + ((a.colour >> 1) & 1);
+        dom[2] = 2 * (b / (nd2 * nd2)) + ((a.colour >> 2) & 1);
+        f.domain = (uint32_t)(dom[0] + a.nd * (dom[1] + a.nd * dom[2]));
+    }
+    F = WHOLE ? n : a.D + 2;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        f.ds[ax] = WHOLE ? 0 : (a.off[ax] + dom[ax] * a.D) % n;
+        f.fs[ax] = WHOLE ? 0 : (f.ds[ax] - 1 + n) % n;
+        f.O[ax] = WHOLE ? 0.0 : face(f.fs[ax], n, a.h, a.L);
+    }
+    wraps = WHOLE || f.fs[0] + F > n || f.fs[1] + F > n || f.fs[2] + F > n;
+}
+
+// Beads in the frame of every domain of the phase, one wavefront per domain, taken before
+// the phase's tier launches start: they run concurrently and pick their domains by it.
+template <bool WHOLE>
+__global__ __launch_bounds__(64) void k_count(const PhaseArgs a) {
+    Frame f;
+    int F;
+    bool wraps;
+    frame_of<WHOLE>(a, blockIdx.x, f, F, wraps);
+    const int n = a.n, lane = lane_id();
+    const int nfc = F * F * F;
+    int S = 0;
+    for (int base = 0; base < nfc; base += 64) {
+        const int c = base + lane;
+        int cnt = 0;
+        if (c < nfc) {
+            const int fx = c % F, fy = (c / F) % F, fz = c / (F * F);
+            cnt = a.ccount[(f.fs[0] + fx) % n + n * ((f.fs[1] + fy) % n + n * ((f.fs[2] + fz) % n))];
+        }
+        S += rdlane(wave_incl_scan(cnt), 63);
+    }
+    if (lane == 0) a.dstage[blockIdx.x] = S;
+}
+
 // ------------------------------------------------------------------ phase kernel
 template <int BPL, bool LOG, bool EXACT, bool WHOLE>
 __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
@@ -634,45 +682,22 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
 
     // ---- which domain
     Frame f;
-    int dom[3] = {0, 0, 0};
-    f.domain = 0;
-    if (!WHOLE) {
-        const int nd2 = a.nd >> 1;
-        const int b = blockIdx.x;
-        dom[0] = 2 * (b % nd2) + (a.colour & 1);
-        dom[1] = 2 * ((b / nd2) % nd2) + ((a.colour >> 1) & 1);
-        dom[2] = 2 * (b / (nd2 * nd2)) + ((a.colour >> 2) & 1);
-        f.domain = (uint32_t)(dom[0] + a.nd * (dom[1] + a.nd * dom[2]));
-    }
-    const int F = WHOLE ? n : a.D + 2;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        f.ds[ax] = WHOLE ? 0 : (a.off[ax] + dom[ax] * a.D) % n;
-        f.fs[ax] = WHOLE ? 0 : (f.ds[ax] - 1 + n) % n;
-        f.O[ax] = WHOLE ? 0.0 : face(f.fs[ax], n, h, L);
-    }
-    // the frame (domain + halo) wraps the periodic box on some axis
-    const bool wraps = WHOLE || f.fs[0] + F > n || f.fs[1] + F > n || f.fs[2] + F > n;
+    int F;
+    bool wraps;
+    frame_of<WHOLE>(a, blockIdx.x, f, F, wraps);
 
-    // ---- stage the frame's beads: count first; a domain outside this launch's staging
-    // tier (stage_lo, stage_hi] is left to the launch of the other tier
-    const int nfc = F * F * F;
-    int S = 0;
-    for (int base = 0; base < nfc; base += 64) {
-        const int c = base + lane;
-        int cnt = 0;
-        if (c < nfc) {
-            const int fx = c % F, fy = (c / F) % F, fz = c / (F * F);
-            cnt = a.ccount[(f.fs[0] + fx) % n + n * ((f.fs[1] + fy) % n + n * ((f.fs[2] + fz) % n))];
-        }
-        S += rdlane(wave_incl_scan(cnt), 63);
-    }
-    if (S <= a.stage_lo || S > a.stage_hi) return;
-    if (S > SMAX) {
+    // ---- stage the frame's beads.  The count comes from k_count, taken before any tier of
+    // this phase ran: a block of another tier may be rewriting this domain's cell lists, so
+    // a count read here could be a half-updated one.  A domain outside this launch's tier
+    // (stage_lo, stage_hi] belongs to another launch and is left alone.
+    const int S0 = __builtin_amdgcn_readfirstlane(a.dstage[blockIdx.x]);
+    if (S0 <= a.stage_lo || S0 > a.stage_hi) return;
+    if (S0 > SMAX) {
         if (lane == 0) atomicOr(a.err, ERR_STAGE);
         return;
     }
-    S = 0;
+    const int nfc = F * F * F;
+    int S = 0;
     for (int base = 0; base < nfc; base += 64) {
         const int c = base + lane;
         int cnt = 0, flat = 0;
@@ -689,10 +714,18 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
         const int excl = incl - cnt;
         const int tot = rdlane(incl, 63);
         for (int i = 0; i < cnt; ++i) {
-            t_id[S + excl + i] = a.cids[(long long)flat * a.cap + i];
-            t_meta[S + excl + i] = word;
+            const int at = S + excl + i;
+            if (at < S0) {
+                t_id[at] = a.cids[(long long)flat * a.cap + i];
+                t_meta[at] = word;
+            }
         }
         S += tot;
+    }
+    if (S != S0) {
+        // the cell lists changed since the count: nothing of this domain is touched
+        if (lane == 0) atomicOr(a.err, ERR_RECOUNT);
+        return;
     }
     f.S = S;
     __syncthreads();
@@ -834,71 +867,110 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
 }
 
 // ------------------------------------------------------------------ observables
-// One thread per polymer: R = sum of minimum-image bonds, unwrapped positions u for the
-// centre of mass and R_g^2 = N^-1 sum (u - u_cm)^2, the middle bead unwrapped with its
-// image counters, bond lengths binned on [sigma, b_max].
-__global__ void k_observables(const ObsArgs a) {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.npoly;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s = a.pstart[q], e = a.pstart[q + 1];
-        const int64_t N = e - s;
-        auto mi = [&](double d) { return d > a.halfL ? d - a.L : (d < -a.halfL ? d + a.L : d); };
-        const int i0 = a.porder[s];
-        double u0 = a.px[i0], u1 = a.py[i0], u2 = a.pz[i0];
-        double R0 = 0.0, R1 = 0.0, R2 = 0.0;
-        double s0 = u0, s1 = u1, s2 = u2;
-        for (int64_t t = s + 1; t < e; ++t) {
-            const int ia = a.porder[t - 1], ib = a.porder[t];
-            const double d0 = mi(a.px[ib] - a.px[ia]);
-            const double d1 = mi(a.py[ib] - a.py[ia]);
-            const double d2 = mi(a.pz[ib] - a.pz[ia]);
-            R0 += d0;
-            u0 += d0;
-            s0 += u0;
-            R1 += d1;
-            u1 += d1;
-            s1 += u1;
-            R2 += d2;
-            u2 += d2;
-            s2 += u2;
-            if (a.hist) {
-                const double q0 = d0 * d0;
-                const double q1 = d1 * d1;
-                const double q2 = d2 * d2;
-                const double len = __builtin_sqrt(q0 + q1 + q2);
-                int bin = (int)__builtin_floor((len - a.sigma) / (a.bmax - a.sigma) * a.nbins);
-                if (bin < 0) bin = 0;
-                if (bin > a.nbins - 1) bin = a.nbins - 1;
-                atomicAdd(&a.hist[bin], 1ull);
-            }
-        }
-        const double c0 = s0 / (double)N, c1 = s1 / (double)N, c2 = s2 / (double)N;
-        const double r0 = R0 * R0;
-        const double r1 = R1 * R1;
-        const double r2 = R2 * R2;
-        a.r2[q] = r0 + r1 + r2;
-        double g = 0.0;
-        double v0 = a.px[i0], v1 = a.py[i0], v2 = a.pz[i0];
-        for (int64_t t = s; t < e; ++t) {
-            if (t > s) {
-                const int ia = a.porder[t - 1], ib = a.porder[t];
-                v0 += mi(a.px[ib] - a.px[ia]);
-                v1 += mi(a.py[ib] - a.py[ia]);
-                v2 += mi(a.pz[ib] - a.pz[ia]);
-            }
-            const double w0 = (v0 - c0) * (v0 - c0);
-            g += w0;
-            const double w1 = (v1 - c1) * (v1 - c1);
-            g += w1;
-            const double w2 = (v2 - c2) * (v2 - c2);
-            g += w2;
-        }
-        a.rg2[q] = g / (double)N;
-        const int im = a.porder[s + N / 2];
-        a.mid[3 * q + 0] = a.px[im] + (double)a.img[3 * im + 0] * a.L;
-        a.mid[3 * q + 1] = a.py[im] + (double)a.img[3 * im + 1] * a.L;
-        a.mid[3 * q + 2] = a.pz[im] + (double)a.img[3 * im + 2] * a.L;
+// sum over the wavefront, returned to every lane (fixed order, so reproducible)
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v = v + dpp_f64<0xB1>(v);
+    v = v + dpp_f64<0x4E>(v);
+    v = v + dpp_f64<0x141>(v);
+    v = v + dpp_f64<0x140>(v);
+    const double r0 = rdlane(v, 0), r1 = rdlane(v, 16), r2 = rdlane(v, 32), r3 = rdlane(v, 48);
+    return (r0 + r1) + (r2 + r3);
+}
+
+// inclusive prefix sum of doubles over the wavefront
+__device__ __forceinline__ double wave_scan_f64(double v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
     }
+    return v;
+}
+
+// One wavefront per polymer (observables of Sec. IV.A and the appendix).  Lane t of a chunk holds chain position
+// base + t: its minimum-image bond vector to the previous bead, prefix-summed over the wave
+// (plus the carry of the earlier chunks), is the bead's unwrapped position u relative to the
+// first bead.  R is the last u; R_g^2 = N^-1 sum u^2 - |N^-1 sum u|^2 (positions relative to
+// the first bead keep the cancellation small); the middle bead floor(N/2) is unwrapped with
+// its image counters; bond lengths are binned in LDS, one global add per bin and block.
+constexpr int OBS_WAVES = 4;
+constexpr int OBS_MAX_BINS = 1024;
+
+__global__ __launch_bounds__(64 * OBS_WAVES) void k_observables(const ObsArgs a) {
+    __shared__ unsigned s_hist[OBS_MAX_BINS];
+    const int lane = lane_id();
+    const int w = (int)threadIdx.x >> 6;
+    for (int i = (int)threadIdx.x; i < a.nbins; i += 64 * OBS_WAVES) s_hist[i] = 0u;
+    __syncthreads();
+    auto mi = [&](double d) { return d > a.halfL ? d - a.L : (d < -a.halfL ? d + a.L : d); };
+    for (int64_t q = (int64_t)blockIdx.x * OBS_WAVES + w; q < a.npoly; q += (int64_t)gridDim.x * OBS_WAVES) {
+        const int64_t s = a.pstart[q];
+        const int N = (int)(a.pstart[q + 1] - s);
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0;  // u of the last bead of the previous chunk
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, sq = 0.0;
+        for (int base = 0; base < N; base += 64) {
+            const int t = base + lane;
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+            if (t < N) {
+                const int ib = a.porder[s + t];
+                if (t > 0) {
+                    const int ia = a.porder[s + t - 1];
+                    d0 = mi(a.px[ib] - a.px[ia]);
+                    d1 = mi(a.py[ib] - a.py[ia]);
+                    d2 = mi(a.pz[ib] - a.pz[ia]);
+                    if (a.hist) {
+                        const double q0 = d0 * d0;
+                        const double q1 = d1 * d1;
+                        const double q2 = d2 * d2;
+                        const double len = __builtin_sqrt(q0 + q1 + q2);
+                        int bin = (int)__builtin_floor((len - a.sigma) / (a.bmax - a.sigma) * a.nbins);
+                        if (bin < 0) bin = 0;
+                        if (bin > a.nbins - 1) bin = a.nbins - 1;
+                        atomicAdd(&s_hist[bin], 1u);
+                    }
+                }
+                if (t == N / 2) {
+                    a.mid[3 * q + 0] = a.px[ib] + (double)a.img[3 * ib + 0] * a.L;
+                    a.mid[3 * q + 1] = a.py[ib] + (double)a.img[3 * ib + 1] * a.L;
+                    a.mid[3 * q + 2] = a.pz[ib] + (double)a.img[3 * ib + 2] * a.L;
+                }
+            }
+            const double u0 = c0 + wave_scan_f64(d0);
+            const double u1 = c1 + wave_scan_f64(d1);
+            const double u2 = c2 + wave_scan_f64(d2);
+            if (t < N) {
+                s0 += u0;
+                s1 += u1;
+                s2 += u2;
+                const double w0 = u0 * u0;
+                const double w1 = u1 * u1;
+                const double w2 = u2 * u2;
+                sq += (w0 + w1) + w2;
+            }
+            c0 = rdlane(u0, 63);  // lanes past the chain end add zero bonds
+            c1 = rdlane(u1, 63);
+            c2 = rdlane(u2, 63);
+        }
+        const double m0 = wave_sum_f64(s0) / (double)N;
+        const double m1 = wave_sum_f64(s1) / (double)N;
+        const double m2 = wave_sum_f64(s2) / (double)N;
+        const double qq = wave_sum_f64(sq) / (double)N;
+        if (lane == 0) {
+            const double r0 = c0 * c0;
+            const double r1 = c1 * c1;
+            const double r2 = c2 * c2;
+            a.r2[q] = (r0 + r1) + r2;
+            const double g0 = m0 * m0;
+            const double g1 = m1 * m1;
+            const double g2 = m2 * m2;
+            a.rg2[q] = qq - ((g0 + g1) + g2);
+        }
+    }
+    __syncthreads();
+    if (a.hist)
+        for (int i = (int)threadIdx.x; i < a.nbins; i += 64 * OBS_WAVES)
+            if (s_hist[i]) atomicAdd(&a.hist[i], (unsigned long long)s_hist[i]);
 }
 
 }  // namespace
@@ -940,12 +1012,18 @@ hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStre
     }
 }
 
+hipError_t launch_count(const PhaseArgs &a, int grid, hipStream_t s) {
+    if (a.whole) hipLaunchKernelGGL(k_count<true>, dim3(grid), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_count<false>, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s) {
     if (a.npoly <= 0) return hipSuccess;
-    const int block = 256;
-    int64_t grid = (a.npoly + block - 1) / block;
-    if (grid > 4096) grid = 4096;
-    hipLaunchKernelGGL(k_observables, dim3((unsigned)grid), dim3(block), 0, s, a);
+    if (a.nbins < 1 || a.nbins > OBS_MAX_BINS) return hipErrorInvalidValue;
+    int64_t grid = (a.npoly + OBS_WAVES - 1) / OBS_WAVES;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL(k_observables, dim3((unsigned)grid), dim3(64 * OBS_WAVES), 0, s, a);
     return hipGetLastError();
 }
 

@@ -31,8 +31,10 @@ MUTANTS = {
     "pivot_rng": ("const int32_t p = mot[below(u[0], (uint32_t)m)];",
                   "const int32_t p = mot[below(u[0], (uint32_t)(m > 1 ? m - 1 : m))];"),
     "period_half": ("const double r = fmod(*xmax, W + W);", "const double r = fmod(*xmax, W);"),
-    "period_no_cycle": ("if (!(W > 0.0)) {", "if (W < 0.0) {"),
     # equivalent mutants: no observable difference is expected
+    # (W = 0 means every event between the two reflections had zero length, so the zero-length
+    # cycle search ends the same EC a few steps later with the same positions)
+    "period_no_cycle (equivalent)": ("if (!(W > 0.0)) {", "if (W < 0.0) {"),
     "tie_kind (equivalent)": ("(j == b->j && kind < b->kind)", "(j == b->j && kind > b->kind)"),
     "face_add (rounding only)": ("*ra = sgn > 0 ? s->bnd[c + 1] : s->bnd[c];", "*ra = sgn > 0 ? *ra + xc : *ra - xc;"),
 }

@@ -522,3 +522,74 @@ def test_checkerboard_pivot_schedule_reconstructed(melt_c1):
     got = [(int(r["sweep"]), int(r["domain"]), int(r["ec"]), int(r["pivot"])) for r in log]
     assert all(r["kind"] == oracle.EV_END for r in log)
     assert got == expect
+
+
+def _offsets(seed, sweep, D):
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    u = _philox_py([0, 0, sweep, 1], key)
+    return key, [(u[a] * D) >> 32 for a in range(3)]
+
+
+@pytest.mark.parametrize("colour", range(8))
+def test_colour_phase_moves_only_its_domains(melt_c1, colour):
+    """Sec. II.A: during a colour phase only beads of that colour's domains may move; every
+    other bead keeps its position, cell and image counters bit for bit (whether it was hit
+    and reflected an EC or not)."""
+    m = melt_c1
+    n, D, nd, seed = 4, 2, 2, 4242 + colour
+    o = oracle.Oracle.from_melt(m, n_cells=n)
+    p0, c0, i0 = o.positions(), o.cells(), o.images()
+    o.sweep(256, 10.0, seed, tiling=1, D=D, colour_mask=1 << colour)
+    _, off = _offsets(seed, 0, D)
+    dom = ((c0 - np.array(off)) % n) // D
+    col = (dom[:, 0] & 1) | ((dom[:, 1] & 1) << 1) | ((dom[:, 2] & 1) << 2)
+    still = col != colour
+    assert still.any() and (~still).any()
+    assert np.array_equal(o.positions()[still], p0[still])
+    assert np.array_equal(o.cells()[still], c0[still])
+    assert np.array_equal(o.images()[still], i0[still])
+    assert not np.array_equal(o.positions()[~still], p0[~still])
+    c, _ = o.counters()
+    assert c[oracle.C_HS_REFLECT] > 0
+
+
+def test_lone_bead_bounces_between_domain_walls():
+    """A bead alone in a periodic box with the checkerboard on: its EC runs straight to the
+    domain wall and then bounces between the two walls of its domain, so after the first wall
+    the motion is a billiard of period 2 W (W = D h, the domain width).  Its end point follows
+    from unfolding that billiard, computed here from the schedule's definition (offsets and
+    direction from Philox) for many random starts, lengths and seeds."""
+    rng = np.random.default_rng(8)
+    L, n, D = 12.0, 8, 2
+    h, nd = L / n, n // D
+    for trial in range(80):
+        x = rng.uniform(0, L, size=3)
+        ell = float(rng.uniform(0.0, 40.0))
+        seed = int(rng.integers(0, 2 ** 63))
+        o = oracle.Oracle(L, 1.0, 1.4, x[None, :], np.zeros((0, 2)), n_cells=n)
+        cell = o.cells()[0]
+        x = o.positions()[0]
+        o.sweep(nd ** 3, ell, seed, tiling=1, D=D)
+        key, off = _offsets(seed, 0, D)
+        dom = ((cell - np.array(off)) % n) // D
+        d = int(dom[0] + nd * (dom[1] + nd * dom[2]))
+        u = _philox_py([0, d, 0, 0], key)
+        direction = (u[1] * 6) >> 32
+        ax, s = direction >> 1, (-1.0 if direction & 1 else 1.0)
+        first = (off[ax] + dom[ax] * D) % n          # first cell of the domain along ax
+        lo = first * h
+        x0 = x[ax] + (L if cell[ax] < first else 0.0)  # unwrap a domain that wraps the box
+        hi = lo + D * h
+        W = hi - lo
+        a = hi - x0 if s > 0 else x0 - lo
+        if ell <= a:
+            end = x0 + s * ell
+        else:
+            r = math.fmod(ell - a, 2 * W)
+            w1, w2 = (hi, lo) if s > 0 else (lo, hi)
+            end = w1 - s * r if r <= W else w2 + s * (r - W)
+        got = o.positions()[0]
+        assert abs((got[ax] - end + L / 2) % L - L / 2) < 1e-9, (trial, got[ax], end)
+        for b in range(3):
+            if b != ax:
+                assert got[b] == x[b]
