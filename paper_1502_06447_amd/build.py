@@ -25,18 +25,19 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm toolchain required to build libecmc.so)")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
+def build(verbose: bool = False, out: str = LIB, defines: tuple = ()) -> str:
+    """Compile the library to ``out``; ``defines`` are extra -D macros (tuning knobs)."""
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-ffp-contract=off", "-fno-fast-math",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"), "-o", tmp, "-x", "hip"] + SOURCES
+           "-I", os.path.join(ROOT, "include")] + [f"-D{d}" for d in defines] + ["-o", tmp, "-x", "hip"] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

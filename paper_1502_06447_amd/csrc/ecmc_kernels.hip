@@ -36,16 +36,20 @@ __device__ __forceinline__ double rdlane(double v, int lane) {
 
 __device__ __forceinline__ int rdlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+// DPP lane moves within a row of 16 lanes.  Only full permutations are used (every lane has
+// a source); the lane's own value is the fallback a disabled source would give, so that a
+// reduction can never pick up a value that no lane holds.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int l = __double2loint(v), u = __double2hiint(v);
+    const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(u, u, CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp_u32(unsigned v) {
-    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+    return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
 }
 
 __device__ __forceinline__ double fmin_(double a, double b) { return b < a ? b : a; }
@@ -118,16 +122,20 @@ struct Pivot {
 
 // the staged data in LDS
 struct Stage {
-    double *px, *py, *pz;  // FP64 x, y, z
+    double *pos;           // FP64 x, y, z: three rows of `stride` doubles
+    int stride;
     int32_t *meta;
     int32_t *part;
     int32_t *id;
-    __device__ __forceinline__ double *axis(int ax) const { return ax == 0 ? px : (ax == 1 ? py : pz); }
+    // address arithmetic rather than a select of three pointers, which the compiler turns
+    // into a pointer table in scratch memory
+    __device__ __forceinline__ double *axis(int ax) const { return pos + ax * stride; }
 };
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    const int i = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false));
 }
 
 __device__ __forceinline__ float fminf_(float a, float b) { return b < a ? b : a; }
@@ -196,34 +204,53 @@ struct Hit {
     int32_t meta, part;
 };
 
-// First interaction event of the pivot: the exact minimum over all staged beads of
-// (x, staged index, kind).
-//  1. Screen: a float estimate of every bead's x gives an interval [lo, hi] that
-//     provably contains the exact x of each bead that is a candidate at all.
-//  2. One float min-reduction of hi over the wavefront gives a threshold t.
-//  3. Only beads with lo <= t are evaluated exactly, from LDS (normally one bead).  Their
-//     exact minimum x* is certified when x* <= t; otherwise t is raised to x* and the step
-//     repeats.  A bead left out has exact x >= lo > t >= x*, so the result is exact.
-// With EXACT every staged bead is evaluated in FP64 (the reference search).
+// The single-precision screen of one event search.  For every staged bead the lane holding
+// it computes a float estimate of the bead's x and an interval [lo, hi] that provably holds
+// the exact x of each bead that is a candidate at all (lo = +inf for beads that cannot be).
+// t = min hi and l = min lo over the wavefront: the exact interaction distance x_int lies in
+// [l, t] whenever a candidate exists (x_int = +inf, l = t = +inf otherwise).
+template <int BPL>
+struct Screen {
+    float lo[BPL];
+    float t, l;
+};
+
+// minima of two floats over the wavefront, interleaved so that the two reductions share
+// their latency
+__device__ __forceinline__ void wave_min2_f32(float &u, float &v) {
+    u = fminf_(u, dpp_f32<0xB1>(u));
+    v = fminf_(v, dpp_f32<0xB1>(v));
+    u = fminf_(u, dpp_f32<0x4E>(u));
+    v = fminf_(v, dpp_f32<0x4E>(v));
+    u = fminf_(u, dpp_f32<0x141>(u));
+    v = fminf_(v, dpp_f32<0x141>(v));
+    u = fminf_(u, dpp_f32<0x140>(u));
+    v = fminf_(v, dpp_f32<0x140>(v));
+    const float u0 = __int_as_float(rdlane(__float_as_int(u), 0)), u1 = __int_as_float(rdlane(__float_as_int(u), 16));
+    const float u2 = __int_as_float(rdlane(__float_as_int(u), 32)), u3 = __int_as_float(rdlane(__float_as_int(u), 48));
+    const float v0 = __int_as_float(rdlane(__float_as_int(v), 0)), v1 = __int_as_float(rdlane(__float_as_int(v), 16));
+    const float v2 = __int_as_float(rdlane(__float_as_int(v), 32)), v3 = __int_as_float(rdlane(__float_as_int(v), 48));
+    u = fminf_(fminf_(u0, u1), fminf_(u2, u3));
+    v = fminf_(fminf_(v0, v1), fminf_(v2, v3));
+}
+
+// With EXACT every staged bead other than the pivot is a member of the exact search (the
+// reference search); l is then 0 if there is any such bead.
 template <int BPL, bool WHOLE, bool EXACT>
-__device__ __forceinline__ Hit first_event(const Lanes<BPL, WHOLE> &R, const Stage &st, const Pivot &pv, int ax,
-                                           int sha, int shb, int shc, double sgnd, double sig2, double b2, double L,
-                                           bool wr, const ScreenK &K, int S) {
+__device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> &R, const Pivot &pv, int sha, int shb,
+                                       int shc, double sgnd, const ScreenK &K, int S) {
     const int lane = lane_id();
     const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
     const float sgnf = sgnd > 0.0 ? 1.0f : -1.0f;
-    const double *pA = st.axis(ax);
-    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
-    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
-    float lo[BPL];  // +inf for beads that cannot be candidates
-    float hmin = __builtin_huge_valf();
+    float hmin = __builtin_huge_valf(), lmin = __builtin_huge_valf();
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
         const int idx = k * 64 + lane;
         const bool me = idx == pv.P;
         const bool partner = (idx == q0) || (idx == q1);
         if (EXACT) {
-            lo[k] = (idx < S && !me) ? 0.0f : __builtin_huge_valf();
+            sc.lo[k] = (idx < S && !me) ? 0.0f : __builtin_huge_valf();
+            lmin = fminf_(lmin, sc.lo[k]);
             hmin = 0.0f;
             continue;
         }
@@ -258,82 +285,136 @@ __device__ __forceinline__ Hit first_event(const Lanes<BPL, WHOLE> &R, const Sta
             }
         }
         const bool cand = !me && (hs_maybe || partner);
-        lo[k] = cand ? l : __builtin_huge_valf();
+        sc.lo[k] = cand ? l : __builtin_huge_valf();
         hmin = fminf_(hmin, cand ? hg : __builtin_huge_valf());
+        lmin = fminf_(lmin, sc.lo[k]);
     }
+    wave_min2_f32(hmin, lmin);
+    sc.t = EXACT ? (lmin < __builtin_huge_valf() ? 0.0f : __builtin_huge_valf()) : hmin;
+    sc.l = lmin;
+}
+
+// Exact first interaction event after the screen: the minimum over all staged beads of
+// (x, staged index, kind), evaluated in FP64 from LDS only for the beads whose interval
+// starts at or below the threshold t (normally one bead).  Their exact minimum x* is
+// certified when x* <= t; otherwise t is raised to x* and the step repeats.  A bead left
+// out has exact x >= lo > t >= x*, so the result is exact.  When a single bead passes,
+// it is evaluated on its own lane and broadcast without a wavefront reduction.
+//
+// Every branch below depends on wavefront-uniform values only (ballots, readlanes and
+// readfirstlane'd flags), so the wavefront never splits: the DPP reductions need all lanes.
+struct Best {
+    double x, A, B, C;
+    unsigned key;
+    int32_t meta, part;
+};
+
+// evaluate in FP64 the beads of this lane that are members (lo <= thr, not yet done)
+template <int BPL>
+__device__ __forceinline__ void search_pass(const Screen<BPL> &sc, double thr, unsigned &done, Best &b,
+                                            const Stage &st, const Pivot &pv, const double *pA, const double *pB,
+                                            const double *pC, int q0, int q1, int sha, int shb, int shc,
+                                            double sgnd, double sig2, double b2, double L, bool wr) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < BPL; ++k) {
+        const bool mem = !((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr;
+        if (__ballot(mem)) {
+            if (mem) {
+                const int idx = k * 64 + lane;
+                const double A = pA[idx], B = pB[idx], C = pC[idx];
+                const int32_t m = st.meta[idx];
+                const bool partner = (idx == q0) || (idx == q1);
+                double x;
+                bool hs;
+                const bool ok = (idx != pv.P) &&
+                                (wr ? exact_candidate<true>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner,
+                                                            x, hs)
+                                    : exact_candidate<false>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
+                                                             partner, x, hs));
+                const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
+                if (ok && (x < b.x || (x == b.x && kk < b.key))) {
+                    b.x = x;
+                    b.key = kk;
+                    b.A = A;
+                    b.B = B;
+                    b.C = C;
+                    b.meta = m;
+                    b.part = st.part[idx];
+                }
+            }
+        }
+        if (mem) done |= 1u << k;
+    }
+}
+
+__device__ __forceinline__ void take(Hit &h, const Best &b, int wl) {
+    h.x = rdlane(b.x, wl);
+    h.key = (unsigned)rdlane((int)b.key, wl);
+    h.a = rdlane(b.A, wl);
+    h.b = rdlane(b.B, wl);
+    h.c = rdlane(b.C, wl);
+    h.meta = rdlane((int)b.meta, wl);
+    h.part = rdlane((int)b.part, wl);
+}
+
+template <int BPL, bool WHOLE, bool EXACT>
+__device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, const Pivot &pv, int ax, int sha,
+                                      int shb, int shc, double sgnd, double sig2, double b2, double L, bool wr) {
+    const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
+    const double *pA = st.axis(ax);
+    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
+    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
     Hit h;
     h.x = INF;
     h.key = 0xFFFFFFFFu;
     h.a = h.b = h.c = 0.0;
     h.meta = 0;
     h.part = -1;
-    const float t0 = EXACT ? 0.0f : wave_min_f32(hmin);
-    if (!EXACT && !(t0 < __builtin_huge_valf())) return h;
-    double thr = EXACT ? INF : (double)t0;
-    double bx = INF, bA = 0.0, bB = 0.0, bC = 0.0;
-    unsigned bkey = 0xFFFFFFFFu;
-    int32_t bmeta = 0, bpart = -1;
+    if (!(sc.l < __builtin_huge_valf())) return h;
+    double thr = EXACT ? INF : (double)sc.t;
+    Best b = {INF, 0.0, 0.0, 0.0, 0xFFFFFFFFu, 0, -1};
     unsigned done = 0;
-    double xs;
-    for (;;) {
+    int nmem = 0;
 #pragma unroll
-        for (int k = 0; k < BPL; ++k) {
-            // lo is +inf for the pivot itself, for empty slots and for beads the screen rules
-            // out: they are never evaluated, also when the threshold has been widened to +inf
-            const bool mem = !((done >> k) & 1u) && lo[k] < __builtin_huge_valf() && (double)lo[k] <= thr;
-            if (__ballot(mem)) {
-                if (mem) {
-                    const int idx = k * 64 + lane;
-                    const double A = pA[idx], B = pB[idx], C = pC[idx];
-                    const int32_t m = st.meta[idx];
-                    const bool partner = (idx == q0) || (idx == q1);
-                    double x;
-                    bool hs;
-                    const bool ok = (idx != pv.P) &&
-                                    (wr ? exact_candidate<true>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
-                                                                partner, x, hs)
-                                        : exact_candidate<false>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
-                                                                 partner, x, hs));
-                    const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
-                    if (ok && (x < bx || (x == bx && kk < bkey))) {
-                        bx = x;
-                        bkey = kk;
-                        bA = A;
-                        bB = B;
-                        bC = C;
-                        bmeta = m;
-                        bpart = st.part[idx];
-                    }
-                    done |= 1u << k;
-                }
+    for (int k = 0; k < BPL; ++k)
+        nmem += __popcll(__ballot(sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr));
+    search_pass<BPL>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
+    if (nmem == 1) {
+        // one bead passed the screen: it set the threshold (its own hi is t), so when it is
+        // a candidate its exact x <= t is the certified minimum
+        const unsigned long long own = __ballot(b.x < INF);
+        if (own) {
+            const int wl = (int)(__ffsll((long long)own) - 1);
+            const double x1 = rdlane(b.x, wl);
+            if (__builtin_amdgcn_readfirstlane((int)(x1 <= thr))) {
+                take(h, b, wl);
+                return h;
             }
         }
-        xs = wave_min_f64(bx);
-        if (xs <= thr) break;
+    }
+    double xs = wave_min_f64(b.x);
+    while (!__builtin_amdgcn_readfirstlane((int)(xs <= thr))) {
         // the threshold came from a screened bead that is no candidate after all: widen
         thr = xs;
         bool more = false;
 #pragma unroll
         for (int k = 0; k < BPL; ++k)
-            more = more || (!((done >> k) & 1u) && lo[k] < __builtin_huge_valf() && (double)lo[k] <= thr);
+            more = more || (!((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr);
         if (!__ballot(more)) break;
+        search_pass<BPL>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
+        xs = wave_min_f64(b.x);
     }
     if (!(xs < INF)) return h;
-    const unsigned long long tie = __ballot(bx == xs);
+    const unsigned long long tie = __ballot(b.x == xs);
     int wl;
     if (__popcll(tie) == 1) {
         wl = (int)(__ffsll((long long)tie) - 1);
-        h.key = (unsigned)rdlane((int)bkey, wl);
     } else {
-        h.key = wave_min_u32(bx == xs ? bkey : 0xFFFFFFFFu);
-        wl = (int)((h.key >> 1) & 63u);
+        const unsigned key = wave_min_u32(b.x == xs ? b.key : 0xFFFFFFFFu);
+        wl = (int)((key >> 1) & 63u);
     }
-    h.x = xs;
-    h.a = rdlane(bA, wl);
-    h.b = rdlane(bB, wl);
-    h.c = rdlane(bC, wl);
-    h.meta = rdlane((int)bmeta, wl);
-    h.part = rdlane((int)bpart, wl);
+    take(h, b, wl);
     return h;
 }
 
@@ -506,13 +587,27 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
         ++step;
         t.inc(C_STEPS);
         const double sgnd = sgn > 0 ? 1.0 : -1.0;
-        const Hit hit = first_event<BPL, WHOLE, EXACT>(R, st, pv, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, K,
-                                                        f.S);
-        const double xint = hit.x;
         const int c = (pv.meta >> sha) & CELL_MASK;
         const double r_old = pv.a;
         double xc = sgn > 0 ? face(c + 1, n, h, L) - r_old : r_old - face(c, n, h, L);
         if (!(xc > 0.0)) xc = 0.0;
+        Screen<BPL> sc;
+        screen<BPL, WHOLE, EXACT>(sc, R, pv, sha, shb, shc, sgnd, K, f.S);
+        // the exact interaction distance is at least sc.l: when the end of the EC or the cell
+        // face comes strictly first (end: at or before), no exact search is needed
+        const double lbound = (double)sc.l;
+        const bool skip = __builtin_amdgcn_readfirstlane((int)((xmax <= xc && xmax <= lbound) || xc < lbound)) != 0;
+        Hit hit;
+        if (skip) {
+            hit.x = INF;
+            hit.key = 0xFFFFFFFFu;
+            hit.a = hit.b = hit.c = 0.0;
+            hit.meta = 0;
+            hit.part = -1;
+        } else {
+            hit = search<BPL, WHOLE, EXACT>(sc, st, pv, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr);
+        }
+        const double xint = hit.x;
         const double mlim = xint < xc ? xint : xc;
         if (xmax <= mlim) {
             // END: the pivot takes the rest of the displacement
@@ -664,8 +759,19 @@ __global__ __launch_bounds__(64) void k_count(const PhaseArgs a) {
 }
 
 // ------------------------------------------------------------------ phase kernel
+// Occupancy hint for the phase kernel (waves per SIMD the register allocation aims at;
+// 0 = the compiler's choice).  A build-time tuning knob.
+#ifndef ECMC_PHASE_WAVES_PER_EU
+#define ECMC_PHASE_WAVES_PER_EU 0
+#endif
+#if ECMC_PHASE_WAVES_PER_EU > 0
+#define ECMC_PHASE_ATTR __attribute__((amdgpu_waves_per_eu(ECMC_PHASE_WAVES_PER_EU)))
+#else
+#define ECMC_PHASE_ATTR
+#endif
+
 template <int BPL, bool LOG, bool EXACT, bool WHOLE>
-__global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
+__global__ __launch_bounds__(64) ECMC_PHASE_ATTR void k_phase(const PhaseArgs a) {
     constexpr int SMAX = 64 * BPL;
     __shared__ double s_pos[3][SMAX];  // FP64 staged positions; s_pos[2] first holds the
                                        // unsorted staging lists (ids, cell words)
@@ -796,7 +902,7 @@ __global__ __launch_bounds__(64) void k_phase(const PhaseArgs a) {
     __syncthreads();
 
     // ---- ECs
-    const Stage st = {&s_pos[0][0], &s_pos[1][0], &s_pos[2][0], s_meta, s_part, s_id};
+    const Stage st = {&s_pos[0][0], SMAX, s_meta, s_part, s_id};
     const ScreenK K = {a.sig2f, a.b2f, a.in_lo, a.in_hi, a.p_sure, a.err_f, (float)L};
     Tally t = {0u, 0.0};
     bool ok = true;

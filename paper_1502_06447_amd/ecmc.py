@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libecmc.so")
+# the in-tree build; ECMC_LIB names another build of the same sources (a tuning variant)
+LIB_PATH = os.environ.get("ECMC_LIB") or os.path.join(_HERE, "libecmc.so")
 
 OK, E_ARG, E_OVERLAP, E_TETHER, E_BOX, E_CELL_OVERFLOW, E_STUCK, E_DEVICE, E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC_FP64, PREC_MIXED = 0, 1
