@@ -37,6 +37,27 @@ def bytes_per_event(beads_per_cell: float) -> float:
     return 18 * beads_per_cell * 28 + 18 * 4 + 3 * 28 + 24
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ecmc_phase_c3_1M_fp64_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1502_06447_amd", "csrc", "ecmc_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per colour phase from the committed FETCH_SIZE / WRITE_SIZE summary, or None
+    when there is none or the kernel source has changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].strip().split(": ", 1)
+            fields[k.strip("`")] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != src or "hbm_bytes_per_phase" not in fields:
+        return None
+    return float(fields["hbm_bytes_per_phase"])
+
+
 WORKLOADS = {
     "c3": dict(M=16384, N=64, eta=0.45, ell=20.0, D=2, label="16384 chains x 64 beads (1,048,576), eta=0.45"),
     "c2": dict(M=500, N=32, eta=0.45, ell=20.0, D=1, label="500 chains x 32 beads (16,000), eta=0.45"),
@@ -78,6 +99,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device once (a plain copy kernel of known size, "
+                         "the scale for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU run is not part of this build",
@@ -90,6 +114,15 @@ def main():
 
     w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"# copy probe: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
     melt = inputs.lattice_chains(w["M"], w["N"], w["eta"], seed=args.seed)
     g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], time_kernels=True))
     nb = melt.n_beads
@@ -125,13 +158,7 @@ def main():
     sweeps = launches  # one timing pair per colour phase
     kernel_s = kms / 1e3
     achieved = events * B / kernel_s / 1e9 if kernel_s > 0 else 0.0
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "ecmc_phase_c3_traffic.json")
-    if args.workload == "c3" and os.path.exists(tpath):
-        try:
-            traffic = json.load(open(tpath)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic() if args.workload == "c3" else None
     out = {
         "metric": "collision events/s",
         "value": value,
