@@ -36,9 +36,8 @@ __device__ __forceinline__ double rdlane(double v, int lane) {
 
 __device__ __forceinline__ int rdlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
-// DPP lane moves within a row of 16 lanes.  Only full permutations are used (every lane has
-// a source); the lane's own value is the fallback a disabled source would give, so that a
-// reduction can never pick up a value that no lane holds.
+// DPP lane move within a row of 16 lanes (a full permutation: every lane has a source; the
+// lane's own value is the fallback a disabled source would give).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const int l = __double2loint(v), u = __double2hiint(v);
@@ -47,35 +46,57 @@ __device__ __forceinline__ double dpp_f64(double v) {
     return __hiloint2double(hi, lo);
 }
 
-template <int CTRL>
-__device__ __forceinline__ unsigned dpp_u32(unsigned v) {
-    return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
-}
-
-__device__ __forceinline__ double fmin_(double a, double b) { return b < a ? b : a; }
-
-// minimum over the wavefront, returned to every lane: butterfly inside each row of 16
-// lanes (quad_perm 1032, quad_perm 2301, half-row mirror, row mirror), then the four
-// row results read out and combined uniformly.
-__device__ __forceinline__ double wave_min_f64(double v) {
-    v = fmin_(v, dpp_f64<0xB1>(v));
-    v = fmin_(v, dpp_f64<0x4E>(v));
-    v = fmin_(v, dpp_f64<0x141>(v));
-    v = fmin_(v, dpp_f64<0x140>(v));
-    const double r0 = rdlane(v, 0), r1 = rdlane(v, 16), r2 = rdlane(v, 32), r3 = rdlane(v, 48);
-    return fmin_(fmin_(r0, r1), fmin_(r2, r3));
-}
 
 __device__ __forceinline__ unsigned umin_(unsigned a, unsigned b) { return b < a ? b : a; }
 
+// One step of a wavefront min-reduction of unsigned words: the lane's value against the one
+// the DPP control brings in; lanes outside row_mask, or with no source, keep their own (the
+// identity 0xFFFFFFFF stands in).  The compiler folds the move into v_min_u32_dpp.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned umin_dpp(unsigned v) {
+    return umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)v, CTRL, ROWS, 0xF, false));
+}
+
+// Minimum over the wavefront, returned to every lane.  Within each row of 16 lanes a
+// butterfly (quad_perm 1032, quad_perm 2301, half-row mirror, row mirror), then row 1 takes
+// row 0 (row_bcast:15), row 3 takes row 2, and rows 2-3 take row 1 (row_bcast:31): lane 63
+// holds the minimum of all 64 lanes.
 __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
-    v = umin_(v, dpp_u32<0xB1>(v));
-    v = umin_(v, dpp_u32<0x4E>(v));
-    v = umin_(v, dpp_u32<0x141>(v));
-    v = umin_(v, dpp_u32<0x140>(v));
-    const unsigned r0 = (unsigned)rdlane((int)v, 0), r1 = (unsigned)rdlane((int)v, 16);
-    const unsigned r2 = (unsigned)rdlane((int)v, 32), r3 = (unsigned)rdlane((int)v, 48);
-    return umin_(umin_(r0, r1), umin_(r2, r3));
+    v = umin_dpp<0xB1, 0xF>(v);
+    v = umin_dpp<0x4E, 0xF>(v);
+    v = umin_dpp<0x141, 0xF>(v);
+    v = umin_dpp<0x140, 0xF>(v);
+    v = umin_dpp<0x142, 0xA>(v);
+    v = umin_dpp<0x143, 0xC>(v);
+    return (unsigned)rdlane((int)v, 63);
+}
+
+// two such reductions interleaved (they share the latency of the DPP steps)
+__device__ __forceinline__ void wave_min2_u32(unsigned &u, unsigned &v) {
+    u = umin_dpp<0xB1, 0xF>(u);
+    v = umin_dpp<0xB1, 0xF>(v);
+    u = umin_dpp<0x4E, 0xF>(u);
+    v = umin_dpp<0x4E, 0xF>(v);
+    u = umin_dpp<0x141, 0xF>(u);
+    v = umin_dpp<0x141, 0xF>(v);
+    u = umin_dpp<0x140, 0xF>(u);
+    v = umin_dpp<0x140, 0xF>(v);
+    u = umin_dpp<0x142, 0xA>(u);
+    v = umin_dpp<0x142, 0xA>(v);
+    u = umin_dpp<0x143, 0xC>(u);
+    v = umin_dpp<0x143, 0xC>(v);
+    u = (unsigned)rdlane((int)u, 63);
+    v = (unsigned)rdlane((int)v, 63);
+}
+
+// Minimum over the wavefront of a value that is >= 0 or +inf.  For such doubles the bit
+// patterns order like the numbers, so the high words are reduced first and then the low
+// words of the lanes that hold the smallest high word.
+__device__ __forceinline__ double wave_min_nonneg_f64(double v) {
+    const unsigned hi = (unsigned)__double2hiint(v), lo = (unsigned)__double2loint(v);
+    const unsigned mh = wave_min_u32(hi);
+    const unsigned ml = wave_min_u32(hi == mh ? lo : 0xFFFFFFFFu);
+    return __hiloint2double((int)mh, (int)ml);
 }
 
 // inclusive prefix sum over the wavefront (staging only)
@@ -131,26 +152,6 @@ struct Stage {
     // into a pointer table in scratch memory
     __device__ __forceinline__ double *axis(int ax) const { return pos + ax * stride; }
 };
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_f32(float v) {
-    const int i = __float_as_int(v);
-    return __int_as_float(__builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ float fminf_(float a, float b) { return b < a ? b : a; }
-
-__device__ __forceinline__ float wave_min_f32(float v) {
-    v = fminf_(v, dpp_f32<0xB1>(v));
-    v = fminf_(v, dpp_f32<0x4E>(v));
-    v = fminf_(v, dpp_f32<0x141>(v));
-    v = fminf_(v, dpp_f32<0x140>(v));
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-    return fminf_(fminf_(r0, r1), fminf_(r2, r3));
-}
 
 // Exact FP64 candidate of one staged bead: displacement from the pivot (periodic shift
 // from the cell-index difference, added after the subtraction), d_par and d_perp^2, then
@@ -215,25 +216,6 @@ struct Screen {
     float t, l;
 };
 
-// minima of two floats over the wavefront, interleaved so that the two reductions share
-// their latency
-__device__ __forceinline__ void wave_min2_f32(float &u, float &v) {
-    u = fminf_(u, dpp_f32<0xB1>(u));
-    v = fminf_(v, dpp_f32<0xB1>(v));
-    u = fminf_(u, dpp_f32<0x4E>(u));
-    v = fminf_(v, dpp_f32<0x4E>(v));
-    u = fminf_(u, dpp_f32<0x141>(u));
-    v = fminf_(v, dpp_f32<0x141>(v));
-    u = fminf_(u, dpp_f32<0x140>(u));
-    v = fminf_(v, dpp_f32<0x140>(v));
-    const float u0 = __int_as_float(rdlane(__float_as_int(u), 0)), u1 = __int_as_float(rdlane(__float_as_int(u), 16));
-    const float u2 = __int_as_float(rdlane(__float_as_int(u), 32)), u3 = __int_as_float(rdlane(__float_as_int(u), 48));
-    const float v0 = __int_as_float(rdlane(__float_as_int(v), 0)), v1 = __int_as_float(rdlane(__float_as_int(v), 16));
-    const float v2 = __int_as_float(rdlane(__float_as_int(v), 32)), v3 = __int_as_float(rdlane(__float_as_int(v), 48));
-    u = fminf_(fminf_(u0, u1), fminf_(u2, u3));
-    v = fminf_(fminf_(v0, v1), fminf_(v2, v3));
-}
-
 // With EXACT every staged bead other than the pivot is a member of the exact search (the
 // reference search); l is then 0 if there is any such bead.
 template <int BPL, bool WHOLE, bool EXACT>
@@ -242,7 +224,10 @@ __device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> 
     const int lane = lane_id();
     const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
     const float sgnf = sgnd > 0.0 ? 1.0f : -1.0f;
-    float hmin = __builtin_huge_valf(), lmin = __builtin_huge_valf();
+    // minima of hi and lo as bit patterns: both are >= 0 (or +inf), where the unsigned order of
+    // the patterns is the order of the numbers
+    constexpr unsigned INFB = 0x7F800000u;
+    unsigned hmin = INFB, lmin = INFB;
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
         const int idx = k * 64 + lane;
@@ -250,8 +235,8 @@ __device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> 
         const bool partner = (idx == q0) || (idx == q1);
         if (EXACT) {
             sc.lo[k] = (idx < S && !me) ? 0.0f : __builtin_huge_valf();
-            lmin = fminf_(lmin, sc.lo[k]);
-            hmin = 0.0f;
+            lmin = umin_(lmin, __float_as_uint(sc.lo[k]));
+            hmin = 0u;
             continue;
         }
         float da = R.A[k] - pv.fa;
@@ -285,13 +270,15 @@ __device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> 
             }
         }
         const bool cand = !me && (hs_maybe || partner);
-        sc.lo[k] = cand ? l : __builtin_huge_valf();
-        hmin = fminf_(hmin, cand ? hg : __builtin_huge_valf());
-        lmin = fminf_(lmin, sc.lo[k]);
+        // the exact x is >= 0, so lo is clamped there: still a lower bound, and the
+        // membership test lo <= t (t >= 0) is unchanged
+        sc.lo[k] = cand ? fmaxf(l, 0.0f) : __builtin_huge_valf();
+        hmin = umin_(hmin, cand ? __float_as_uint(hg) : INFB);
+        lmin = umin_(lmin, __float_as_uint(sc.lo[k]));
     }
-    wave_min2_f32(hmin, lmin);
-    sc.t = EXACT ? (lmin < __builtin_huge_valf() ? 0.0f : __builtin_huge_valf()) : hmin;
-    sc.l = lmin;
+    wave_min2_u32(hmin, lmin);
+    sc.t = EXACT ? (lmin < INFB ? 0.0f : __builtin_huge_valf()) : __uint_as_float(hmin);
+    sc.l = __uint_as_float(lmin);
 }
 
 // Exact first interaction event after the screen: the minimum over all staged beads of
@@ -393,7 +380,7 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
             }
         }
     }
-    double xs = wave_min_f64(b.x);
+    double xs = wave_min_nonneg_f64(b.x);
     while (!__builtin_amdgcn_readfirstlane((int)(xs <= thr))) {
         // the threshold came from a screened bead that is no candidate after all: widen
         thr = xs;
@@ -403,7 +390,7 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
             more = more || (!((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr);
         if (!__ballot(more)) break;
         search_pass<BPL>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
-        xs = wave_min_f64(b.x);
+        xs = wave_min_nonneg_f64(b.x);
     }
     if (!(xs < INF)) return h;
     const unsigned long long tie = __ballot(b.x == xs);
@@ -508,13 +495,13 @@ template <bool LOG>
 __device__ __forceinline__ bool repeat_reflection(const PhaseArgs &a, const Frame &f, long long k, long long step,
                                                   int id, double xref, double &xmax, Tally &t) {
     const double w = xref - xmax;
-    if (!(w > 0.0)) {
+    if (!__builtin_amdgcn_readfirstlane((int)(w > 0.0))) {
         t.inc(C_CYCLE);
         if (LOG) log_event(a, f, k, step, id, -1, ECMC_EV_CYCLE);
         return true;
     }
     const double r = fmod(xmax, w + w);
-    if (r < xmax) {
+    if (__builtin_amdgcn_readfirstlane((int)(r < xmax))) {
         xmax = r;
         t.inc(C_PERIOD);
         if (LOG) log_event(a, f, k, step, id, -1, ECMC_EV_PERIOD);
@@ -552,8 +539,8 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
     pv.a = pA[P0];
     pv.b = st.axis(axb)[P0];
     pv.c = st.axis(axc)[P0];
-    pv.meta = st.meta[P0];
-    pv.part = st.part[P0];
+    pv.meta = __builtin_amdgcn_readfirstlane(st.meta[P0]);
+    pv.part = __builtin_amdgcn_readfirstlane(st.part[P0]);
     pv.fa = __int_as_float(rdlane(__float_as_int(pick(R.A, P0 >> 6)), P0 & 63));
     pv.fb = __int_as_float(rdlane(__float_as_int(pick(R.B, P0 >> 6)), P0 & 63));
     pv.fc = __int_as_float(rdlane(__float_as_int(pick(R.C, P0 >> 6)), P0 & 63));
@@ -609,7 +596,11 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
         }
         const double xint = hit.x;
         const double mlim = xint < xc ? xint : xc;
-        if (xmax <= mlim) {
+        // the event (0 end, 1 interaction, 2 cell face) as a wavefront-uniform value: the
+        // FP64 values compared are the same in every lane, and a uniform branch keeps the
+        // whole step in scalar control flow
+        const int ev = __builtin_amdgcn_readfirstlane(xmax <= mlim ? 0 : (xint <= xc ? 1 : 2));
+        if (ev == 0) {
             // END: the pivot takes the rest of the displacement
             pv.a = sgn > 0 ? r_old + xmax : r_old - xmax;
             pv.fa = frame_u(pv.a, c, fsa, L, Oa);
@@ -617,9 +608,9 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
             if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_END);
             return true;
         }
-        if (xint <= xc) {
+        if (ev == 1) {
             // interaction event: move to contact / tether limit
-            if (xint > 0.0) {
+            if (__builtin_amdgcn_readfirstlane((int)(xint > 0.0))) {
                 run = 0;
                 saved_p = -1;
             } else {
@@ -666,7 +657,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
             continue;
         }
         // cell-face event: the pivot is set onto the face
-        if (xc > 0.0) {
+        if (__builtin_amdgcn_readfirstlane((int)(xc > 0.0))) {
             run = 0;
             saved_p = -1;
         } else {
@@ -913,7 +904,7 @@ __global__ __launch_bounds__(64) ECMC_PHASE_ATTR void k_phase(const PhaseArgs a)
         const int P0 = __builtin_amdgcn_readfirstlane(s_mot[scale_u32(ctr[0], (uint32_t)nmot)]);
         const uint32_t dir = scale_u32(ctr[1], 6u);
         const int ax = __builtin_amdgcn_readfirstlane((int)(dir >> 1));
-        const int sgn = (dir & 1u) ? -1 : 1;
+        const int sgn = __builtin_amdgcn_readfirstlane((dir & 1u) ? -1 : 1);
         rotate(R, cur, ax);
         cur = ax;
         ok = run_ec<BPL, LOG, EXACT, WHOLE>(a, f, st, R, P0, ax, sgn, wraps, k, K, t);
