@@ -90,6 +90,28 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5) -> dict:
             "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
 
 
+def precision_check(melt, w, sweeps: int) -> dict:
+    """Both precisions from the same start through the same sweeps (untimed): the screened
+    kernel must reproduce the plain FP64 kernel bit for bit."""
+    import numpy as np
+    from paper_1502_06447_amd import ecmc
+    res = {}
+    for name, prec in (("mixed", ecmc.PREC_MIXED), ("fp64", ecmc.PREC_FP64)):
+        g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], precision=prec))
+        for i in range(sweeps):
+            g.sweep(melt.n_beads, w["ell"], 7000 + i)
+        g.synchronize()
+        res[name] = (g.positions(), g.observables(nbins=32)["r2"].mean(), g.counters())
+        g.close()
+    (pm, r2m, cm), (pf, r2f, cf) = res["mixed"], res["fp64"]
+    return {"sweeps": sweeps, "beads": int(melt.n_beads), "positions_identical": bool(np.array_equal(pm, pf)),
+            "max_position_drift": float(np.abs(pm - pf).max()), "r2_mixed": float(r2m), "r2_fp64": float(r2f),
+            "r2_shift": float(r2m - r2f),
+            # event counts exactly; the sum of lift overlaps to rounding (atomic adds in any order)
+            "event_counts_identical": all(cm[k] == cf[k] for k in cm if k not in ("error_flags", "sum_delta")),
+            "sum_delta_rel_diff": float(abs(cm["sum_delta"] - cf["sum_delta"]) / max(abs(cf["sum_delta"]), 1e-300))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +119,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"),
+                    help="mixed: single-precision screen + FP64 evaluation (default); fp64: every staged "
+                         "bead evaluated in FP64 at every event (the plain kernel); identical results")
+    ap.add_argument("--no-precision-check", action="store_true",
+                    help="skip the untimed comparison of the two precisions after the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -124,7 +151,9 @@ def main():
         del src, dst
         print(f"# copy probe: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
     melt = inputs.lattice_chains(w["M"], w["N"], w["eta"], seed=args.seed)
-    g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], time_kernels=True))
+    prec = ecmc.PREC_MIXED if args.precision == "mixed" else ecmc.PREC_FP64
+    g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], time_kernels=True,
+                                               precision=prec))
     nb = melt.n_beads
     n = g.n_cells
     beads_per_cell = nb / n ** 3
@@ -174,7 +203,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {w['label']}, ell={w['ell']} sigma, checkerboard D={w['D']}, "
-                        f"{n}^3 cells, FP64",
+                        f"{n}^3 cells, FP64 results ({args.precision} event search)",
+            "precision": args.precision,
             "beads": nb, "chains": w["M"], "beads_per_chain": w["N"], "eta": w["eta"], "ell": w["ell"],
             "domain_cells": w["D"], "cells_per_axis": n, "parallelism": "single GPU",
         },
@@ -195,6 +225,8 @@ def main():
                     "HIP-event time of the phase kernels",
         },
     }
+    if not args.no_precision_check:
+        out["precision_check"] = precision_check(melt, w, sweeps=2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds)
         out["cpu_baseline"]["vs_gpu"] = value / out["cpu_baseline"]["value"]

@@ -77,7 +77,11 @@ enum {
 };
 
 typedef struct {
-    int32_t precision;          /* ECMC_PREC_FP64 (mixed precision is not built yet)        */
+    int32_t precision;          /* ECMC_PREC_MIXED (default): a single-precision screen of
+                                   every staged bead bounds its next-event distance, and only
+                                   the beads that can come first are evaluated in FP64; the
+                                   results are identical to ECMC_PREC_FP64, which evaluates
+                                   every staged bead in FP64 at every event (the plain kernel) */
     int32_t tiling;             /* ECMC_TILING_WHOLE: one domain, every bead motile;
                                    ECMC_TILING_CHECKER: D^3-cell domains, 8 colour phases  */
     int32_t n_cells;            /* cells per axis; 0 = largest n with L/n > l_max           */
@@ -85,15 +89,13 @@ typedef struct {
     int32_t cell_capacity;      /* bead slots per cell; 0 = 16                              */
     int32_t stage_capacity;     /* beads one domain (plus its one-cell halo) may hold;
                                    0 = automatic: a first launch sized for the typical
-                                   domain and a second one (up to 1024) for the rare
-                                   larger domains; > 0 = one launch of this capacity, a
-                                   larger domain is ECMC_E_CELL_OVERFLOW; at most 1024      */
+                                   domain and two more (the next size up, and 1024) for
+                                   the rare larger domains, run concurrently; > 0 = one
+                                   launch of this capacity, a larger domain is
+                                   ECMC_E_CELL_OVERFLOW; at most 1024                       */
     int64_t event_cap;          /* loop iterations allowed per EC; 0 = 10^7                 */
     int64_t event_log_capacity; /* event records kept; 0 = no log (the fast path)           */
-    int32_t time_kernels;       /* nonzero: time every sweep kernel with HIP events         */
-    int32_t exact_search;       /* nonzero: evaluate every staged bead in FP64 at every event
-                                   instead of the single-precision screen (same results; a
-                                   checking mode, needs event_log_capacity > 0)             */
+    int32_t time_kernels;       /* nonzero: time every colour phase with HIP events          */
     void *workspace;            /* device memory owned by the caller (256-byte aligned)     */
     size_t workspace_bytes;
     void *stream;               /* hipStream_t for every launch and copy; NULL = default    */
@@ -115,7 +117,7 @@ typedef struct {
     uint32_t kind, colour;
 } ecmc_event;
 
-/* Fills *opt with the defaults (FP64, checkerboard, D = 2, automatic sizes). */
+/* Fills *opt with the defaults (screened precision, checkerboard, D = 2, automatic sizes). */
 void ecmc_default_options(ecmc_options *opt);
 
 /* Bytes of device workspace ecmc_init needs for n_beads beads in a cube of edge box

@@ -119,9 +119,8 @@ ecmc_status geometry(double L, double sigma, double lmax, int64_t nb, const ecmc
     if (!(std::isfinite(L) && L > 0 && std::isfinite(sigma) && sigma > 0 && std::isfinite(lmax) && lmax >= sigma))
         return fail(c, ECMC_E_ARG, "need finite box > 0, sigma > 0, l_max >= sigma");
     if (nb < 1 || nb > 0x7fffffffLL) return fail(c, ECMC_E_ARG, "bead count %lld out of range", (long long)nb);
-    if (o.precision != ECMC_PREC_FP64) return fail(c, ECMC_E_ARG, "only ECMC_PREC_FP64 is built");
-    if (o.exact_search && o.event_log_capacity <= 0)
-        return fail(c, ECMC_E_ARG, "exact_search is built only together with the event log");
+    if (o.precision != ECMC_PREC_FP64 && o.precision != ECMC_PREC_MIXED)
+        return fail(c, ECMC_E_ARG, "precision must be ECMC_PREC_FP64 or ECMC_PREC_MIXED (got %d)", o.precision);
     int n = o.n_cells;
     if (n == 0) {
         n = (int)std::floor(L / lmax);
@@ -333,7 +332,7 @@ extern "C" {
 
 void ecmc_default_options(ecmc_options *o) {
     std::memset(o, 0, sizeof *o);
-    o->precision = ECMC_PREC_FP64;
+    o->precision = ECMC_PREC_MIXED;
     o->tiling = ECMC_TILING_CHECKER;
     o->domain_cells = 2;
 }
@@ -445,9 +444,9 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
     a.sweep = c->sweep_ctr;
-    a.exact_search = c->opt.exact_search ? 1 : 0;
+    a.exact_search = c->opt.precision == ECMC_PREC_FP64 ? 1 : 0;
     {
-        // Single-precision screen (see first_event).  Screening coordinates are frame
+        // Single-precision screen (see screen() in the kernels).  Screening coordinates are frame
         // coordinates rounded once to float, so every float displacement is within
         // delta = 6 u X of the FP64 one (u = 2^-24, X the largest coordinate or displacement:
         // the frame edge, or L for the whole box).  For |d_perp| <= b the float d_perp^2 is

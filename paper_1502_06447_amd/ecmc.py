@@ -38,7 +38,6 @@ class ecmc_options(ctypes.Structure):
         ("event_cap", ctypes.c_int64),
         ("event_log_capacity", ctypes.c_int64),
         ("time_kernels", ctypes.c_int32),
-        ("exact_search", ctypes.c_int32),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
@@ -174,8 +173,7 @@ class Options:
     event_cap: int = 0
     event_log_capacity: int = 0
     time_kernels: bool = False
-    precision: int = PREC_FP64
-    exact_search: bool = False
+    precision: int = PREC_MIXED
 
 
 class Melt:
@@ -195,7 +193,6 @@ class Melt:
         opt.event_cap = o.event_cap
         opt.event_log_capacity = o.event_log_capacity
         opt.time_kernels = 1 if o.time_kernels else 0
-        opt.exact_search = 1 if o.exact_search else 0
         pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
         nbytes = ecmc_workspace_size(L, sigma, b_max, pos.shape[0], opt)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -210,6 +207,8 @@ class Melt:
         self.n_beads = pos.shape[0]
         self.log_capacity = int(o.event_log_capacity)
         self.ctx = ecmc_init(L, sigma, b_max, pos, bonds, opt)
+        # linear chains (the library rejects anything else): one polymer per bead minus bonds
+        self.n_poly = self.n_beads - int(np.asarray(bonds).reshape(-1, 2).shape[0])
 
     @classmethod
     def from_melt(cls, melt, options: Options | None = None, **kw):
@@ -304,13 +303,12 @@ class Melt:
 
     def observables(self, nbins: int = 20) -> dict:
         n_poly = ctypes.c_int64()
-        _check(lib().ecmc_observables(self.ctx, nbins, None, None, None, None, ctypes.byref(n_poly)),
-               "ecmc_observables", self.ctx)
-        M = n_poly.value
+        M = self.n_poly
         r2 = np.zeros(M)
         rg2 = np.zeros(M)
         hist = np.zeros(nbins, dtype=np.int64)
         mid = np.zeros((M, 3))
         _check(lib().ecmc_observables(self.ctx, nbins, r2.ctypes.data, rg2.ctypes.data, hist.ctypes.data,
                                       mid.ctypes.data, ctypes.byref(n_poly)), "ecmc_observables", self.ctx)
+        assert n_poly.value == M
         return {"r2": r2, "rg2": rg2, "hist": hist, "mid": mid, "n_poly": M}

@@ -32,7 +32,7 @@ def test_status_strings_and_defaults():
     for code in range(-8, 1):
         assert L.ecmc_status_str(code)
     o = ecmc.ecmc_default_options()
-    assert o.precision == ecmc.PREC_FP64 and o.tiling == ecmc.TILING_CHECKER and o.domain_cells == 2
+    assert o.precision == ecmc.PREC_MIXED and o.tiling == ecmc.TILING_CHECKER and o.domain_cells == 2
 
 
 def test_workspace_size_and_geometry_errors():
@@ -54,7 +54,7 @@ def test_workspace_size_and_geometry_errors():
     with pytest.raises(ecmc.EcmcError) as e:
         ecmc.ecmc_workspace_size(20.0, 1.0, 0.9, 10, o)         # l_max < sigma
     assert e.value.code == ecmc.E_ARG
-    o.precision = ecmc.PREC_MIXED
+    o.precision = 7                                              # neither FP64 nor MIXED
     with pytest.raises(ecmc.EcmcError) as e:
         ecmc.ecmc_workspace_size(20.0, 1.0, 1.4, 10, o)
     assert e.value.code == ecmc.E_ARG

@@ -71,7 +71,7 @@ def _compare(g, o, tol=1e-9):
 def test_whole_box_c1_event_sequence_bit_exact(melt_c1, exact):
     """16 x 16 melt, eta = 0.30, whole box (n = 5): 3 sweeps of 2,000 ECs with ell = 10 sigma,
     with the single-precision screen and with the plain FP64 search."""
-    p, g, o = _pair(melt_c1, ecmc.TILING_WHOLE, exact_search=exact)
+    p, g, o = _pair(melt_c1, ecmc.TILING_WHOLE, precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
     for s in range(3):
         p.sweep(2000, 10.0, 11 + s)
     n, dp = _compare(g, o)
@@ -83,7 +83,7 @@ def test_whole_box_c1_event_sequence_bit_exact(melt_c1, exact):
 def test_checkerboard_c1_event_sequence_bit_exact(melt_c1, exact):
     """Checkerboard decomposition on the 16 x 16 melt (n = 4, D = 2: one domain per colour):
     walls, immotile reflections, every domain frame wrapping the periodic box."""
-    p, g, o = _pair(melt_c1, ecmc.TILING_CHECKER, D=2, n_cells=4, exact_search=exact)
+    p, g, o = _pair(melt_c1, ecmc.TILING_CHECKER, D=2, n_cells=4, precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
     for s in range(4):
         p.sweep(256, 10.0, 70 + s)
     n, _ = _compare(g, o)
@@ -99,7 +99,7 @@ def melt_c2():
 def test_c2_dense_melt_bit_exact(melt_c2, D, n_cells, exact):
     """500 x 32 melt at eta = 0.45 (n = 16, D = 2: 64 domains per colour; n = 18, D = 3: 27),
     2 sweeps of 16,000 ECs with ell = 20 sigma."""
-    p, g, o = _pair(melt_c2, ecmc.TILING_CHECKER, D=D, n_cells=n_cells, log=40_000_000, exact_search=exact)
+    p, g, o = _pair(melt_c2, ecmc.TILING_CHECKER, D=D, n_cells=n_cells, log=40_000_000, precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
     for s in range(2):
         p.sweep(16000, 20.0, 5 + s)
     n, _ = _compare(g, o)
