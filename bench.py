@@ -90,6 +90,27 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5) -> dict:
             "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
 
 
+def copy_bandwidth(gib: int = 2, reps: int = 5) -> float:
+    """HBM bandwidth of a plain device-to-device copy on this GPU, GB/s (read + written bytes
+    over the best of a few HIP-event-timed copies)."""
+    import torch
+    n = gib << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n / best / 1e9
+
+
 def precision_check(melt, w, sweeps: int) -> dict:
     """Both precisions from the same start through the same sweeps (untimed): the screened
     kernel must reproduce the plain FP64 kernel bit for bit."""
@@ -225,6 +246,7 @@ def main():
                     "HIP-event time of the phase kernels",
         },
     }
+    out["roofline"]["measured_copy_GBps"] = copy_bandwidth()
     if not args.no_precision_check:
         out["precision_check"] = precision_check(melt, w, sweeps=2)
     if not args.no_cpu_baseline:

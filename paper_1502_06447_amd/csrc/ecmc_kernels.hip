@@ -296,8 +296,10 @@ struct Best {
     int32_t meta, part;
 };
 
-// evaluate in FP64 the beads of this lane that are members (lo <= thr, not yet done)
-template <int BPL>
+// evaluate in FP64 the beads of this lane that are members (lo <= thr, not yet done).  The
+// first pass has thr = t, a float: lo <= t is then compared in single precision, which is
+// the same comparison.
+template <int BPL, bool FIRST>
 __device__ __forceinline__ void search_pass(const Screen<BPL> &sc, double thr, unsigned &done, Best &b,
                                             const Stage &st, const Pivot &pv, const double *pA, const double *pB,
                                             const double *pC, int q0, int q1, int sha, int shb, int shc,
@@ -305,7 +307,8 @@ __device__ __forceinline__ void search_pass(const Screen<BPL> &sc, double thr, u
     const int lane = lane_id();
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
-        const bool mem = !((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr;
+        const bool mem = FIRST ? sc.lo[k] <= sc.t
+                               : !((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr;
         if (__ballot(mem)) {
             if (mem) {
                 const int idx = k * 64 + lane;
@@ -364,9 +367,8 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
     unsigned done = 0;
     int nmem = 0;
 #pragma unroll
-    for (int k = 0; k < BPL; ++k)
-        nmem += __popcll(__ballot(sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr));
-    search_pass<BPL>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
+    for (int k = 0; k < BPL; ++k) nmem += __popcll(__ballot(sc.lo[k] <= sc.t));
+    search_pass<BPL, true>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
     if (nmem == 1) {
         // one bead passed the screen: it set the threshold (its own hi is t), so when it is
         // a candidate its exact x <= t is the certified minimum
@@ -389,7 +391,7 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
         for (int k = 0; k < BPL; ++k)
             more = more || (!((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr);
         if (!__ballot(more)) break;
-        search_pass<BPL>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
+        search_pass<BPL, false>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
         xs = wave_min_nonneg_f64(b.x);
     }
     if (!(xs < INF)) return h;
