@@ -15,7 +15,8 @@ event at the algorithmic bytes of a cell-list search over the 18-cell forward
 neighbourhood (1,384 B at this density, FP64) against 8 TB/s of HBM; the kernel
 itself keeps each domain in registers, so its measured HBM traffic is far below.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c5] [--precision mixed|fp64]
+       [--swap]
 """
 from __future__ import annotations
 
@@ -60,11 +61,12 @@ def measured_traffic():
 
 WORKLOADS = {
     "c3": dict(M=16384, N=64, eta=0.45, ell=20.0, D=2, label="16384 chains x 64 beads (1,048,576), eta=0.45"),
-    "c2": dict(M=500, N=32, eta=0.45, ell=20.0, D=1, label="500 chains x 32 beads (16,000), eta=0.45"),
+    "c2": dict(M=500, N=32, eta=0.45, ell=20.0, D=3, label="500 chains x 32 beads (16,000), eta=0.45"),
+    "c5": dict(M=2048, N=512, eta=0.45, ell=20.0, D=2, label="2048 chains x 512 beads (1,048,576), eta=0.45"),
 }
 
 
-def cpu_baseline(w, seconds: float = 12.0, seed: int = 5) -> dict:
+def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False) -> dict:
     """The CPU oracle (serial, one core) on a bounded sample of the same workload: an
     independent 64 x 64 melt at the same packing fraction, ell and domain size."""
     import oracle
@@ -72,6 +74,7 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5) -> dict:
 
     m = inputs.lattice_chains(64, 64, w["eta"], seed=seed)
     o = oracle.Oracle.from_melt(m)
+    o.set_swap(swap)
     for s in range(2):  # melt the lattice like the GPU warm-up does
         o.sweep(m.n_beads, w["ell"], 100 + s, tiling=1, D=w["D"])
     c0, _ = o.counters()
@@ -83,7 +86,7 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5) -> dict:
     dt = time.perf_counter() - t0
     c1, _ = o.counters()
     ev = int(sum(c1[i] - c0[i] for i in (oracle.C_HS_LIFT, oracle.C_TETHER_LIFT, oracle.C_HS_REFLECT,
-                                          oracle.C_TETHER_REFLECT)))
+                                          oracle.C_TETHER_REFLECT, oracle.C_SWAP)))
     return {"value": ev / dt, "unit": "collision events/s", "cores": 1, "kind": "oracle",
             "sample": f"64 x 64 beads (4,096), eta={w['eta']}, ell={w['ell']}, D={w['D']}: {k} sweeps "
                       f"after 2 warm-up sweeps, {dt:.1f} s, single thread",
@@ -111,14 +114,15 @@ def copy_bandwidth(gib: int = 2, reps: int = 5) -> float:
     return 2.0 * n / best / 1e9
 
 
-def precision_check(melt, w, sweeps: int) -> dict:
+def precision_check(melt, w, sweeps: int, swap: bool = False) -> dict:
     """Both precisions from the same start through the same sweeps (untimed): the screened
     kernel must reproduce the plain FP64 kernel bit for bit."""
     import numpy as np
     from paper_1502_06447_amd import ecmc
     res = {}
     for name, prec in (("mixed", ecmc.PREC_MIXED), ("fp64", ecmc.PREC_FP64)):
-        g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], precision=prec))
+        g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], precision=prec,
+                                                   swap_moves=swap))
         for i in range(sweeps):
             g.sweep(melt.n_beads, w["ell"], 7000 + i)
         g.synchronize()
@@ -143,6 +147,7 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"),
                     help="mixed: single-precision screen + FP64 evaluation (default); fp64: every staged "
                          "bead evaluated in FP64 at every event (the plain kernel); identical results")
+    ap.add_argument("--swap", action="store_true", help="swap moves at hard-sphere contacts (Sec. II.C)")
     ap.add_argument("--no-precision-check", action="store_true",
                     help="skip the untimed comparison of the two precisions after the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -174,7 +179,7 @@ def main():
     melt = inputs.lattice_chains(w["M"], w["N"], w["eta"], seed=args.seed)
     prec = ecmc.PREC_MIXED if args.precision == "mixed" else ecmc.PREC_FP64
     g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], time_kernels=True,
-                                               precision=prec))
+                                               precision=prec, swap_moves=args.swap))
     nb = melt.n_beads
     n = g.n_cells
     beads_per_cell = nb / n ** 3
@@ -201,14 +206,14 @@ def main():
     c1 = g.counters()
     kms, launches = g.kernel_time()
     d = {k: c1[k] - c0[k] for k in c1 if k not in ("error_flags",)}
-    events = d["hs_lift"] + d["tether_lift"] + d["hs_reflect"] + d["tether_reflect"]
+    events = d["hs_lift"] + d["tether_lift"] + d["hs_reflect"] + d["tether_reflect"] + d["swap"]
     ecs = d["ec"]
     value = events / dt
     B = bytes_per_event(beads_per_cell)
     sweeps = launches  # one timing pair per colour phase
     kernel_s = kms / 1e3
     achieved = events * B / kernel_s / 1e9 if kernel_s > 0 else 0.0
-    traffic = measured_traffic() if args.workload == "c3" else None
+    traffic = measured_traffic() if args.workload == "c3" and not args.swap else None
     out = {
         "metric": "collision events/s",
         "value": value,
@@ -224,8 +229,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {w['label']}, ell={w['ell']} sigma, checkerboard D={w['D']}, "
-                        f"{n}^3 cells, FP64 results ({args.precision} event search)",
-            "precision": args.precision,
+                        f"{n}^3 cells, FP64 results ({args.precision} event search)"
+                        + (", swap moves" if args.swap else ""),
+            "precision": args.precision, "swap_moves": bool(args.swap),
             "beads": nb, "chains": w["M"], "beads_per_chain": w["N"], "eta": w["eta"], "ell": w["ell"],
             "domain_cells": w["D"], "cells_per_axis": n, "parallelism": "single GPU",
         },
@@ -248,9 +254,9 @@ def main():
     }
     out["roofline"]["measured_copy_GBps"] = copy_bandwidth()
     if not args.no_precision_check:
-        out["precision_check"] = precision_check(melt, w, sweeps=2)
+        out["precision_check"] = precision_check(melt, w, sweeps=2, swap=args.swap)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds, swap=args.swap)
         out["cpu_baseline"]["vs_gpu"] = value / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
 

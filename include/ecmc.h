@@ -71,9 +71,13 @@ enum {
     ECMC_EV_PERIOD = 6,         /* a repeated reflection: whole periods 2W of the retraced
                                    path were dropped from the remaining displacement; the EC
                                    goes on (target = -1)                                   */
-    ECMC_EV_CYCLE = 7           /* zero-length events returned to an earlier state, or a
+    ECMC_EV_CYCLE = 7,          /* zero-length events returned to an earlier state, or a
                                    repeated reflection with W = 0 (nothing can move any
                                    more): ends the EC (target = -1)                        */
+    ECMC_EV_SWAP = 8            /* swap move (Sec. II.C, with swap_moves): at a hard-sphere
+                                   contact with a motile bead the two exchanged positions
+                                   (every tether of both within l_max afterwards); the pivot
+                                   goes on from the struck bead's place                    */
 };
 
 typedef struct {
@@ -96,6 +100,8 @@ typedef struct {
     int64_t event_cap;          /* loop iterations allowed per EC; 0 = 10^7                 */
     int64_t event_log_capacity; /* event records kept; 0 = no log (the fast path)           */
     int32_t time_kernels;       /* nonzero: time every colour phase with HIP events          */
+    int32_t swap_moves;         /* nonzero: propose a swap (Sec. II.C) at every hard-sphere
+                                   contact with a motile bead instead of lifting at once    */
     void *workspace;            /* device memory owned by the caller (256-byte aligned)     */
     size_t workspace_bytes;
     void *stream;               /* hipStream_t for every launch and copy; NULL = default    */
@@ -105,7 +111,8 @@ typedef struct {
     uint64_t hs_lift, tether_lift, hs_reflect, tether_reflect, wall, cross, ec, steps;
     uint64_t periodic, cycle;   /* repeated reflections that dropped whole periods / ECs
                                    ended by a zero-length cycle                             */
-    double sum_delta;           /* sum over lifts of (d_par - x): pressure estimator        */
+    uint64_t swap;              /* accepted swap moves                                      */
+    double sum_delta;           /* sum over lifts and swaps of (d_par - x): pressure estimator */
     uint32_t error_flags;       /* device error word (bit 0 staging, 1 cell, 2 stuck,
                                    3 log full, 4 cell lists changed during staging)         */
     uint32_t pad;

@@ -19,9 +19,10 @@ _SRC = os.path.join(_HERE, "ecmc_oracle.c")
 _LIB = os.environ.get("ECMC_ORACLE_LIB") or os.path.join(_HERE, "libecmc_oracle.so")
 
 OK, E_ARG, E_OVERLAP, E_TETHER, E_BOX, E_CELL_OVERFLOW, E_STUCK, E_CHECK = 0, -1, -2, -3, -4, -5, -6, -9
-EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END, EV_PERIOD, EV_CYCLE = range(8)
-C_HS_LIFT, C_TETHER_LIFT, C_HS_REFLECT, C_TETHER_REFLECT, C_WALL, C_CROSS, C_EC, C_STEPS, C_PERIOD, C_CYCLE = range(10)
-NCNT = 10
+EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END, EV_PERIOD, EV_CYCLE, EV_SWAP = range(9)
+C_HS_LIFT, C_TETHER_LIFT, C_HS_REFLECT, C_TETHER_REFLECT, C_WALL, C_CROSS, C_EC, C_STEPS, C_PERIOD, C_CYCLE, C_SWAP = \
+    range(11)
+NCNT = 11
 
 EVENT_DTYPE = np.dtype([
     ("sweep", "<u4"), ("domain", "<u4"), ("ec", "<u4"), ("step", "<u4"),
@@ -53,6 +54,7 @@ def lib():
         L.orc_create.restype = ctypes.c_int
         L.orc_destroy.argtypes = [vp]
         L.orc_set_options.argtypes = [vp, i64, ctypes.c_int]
+        L.orc_set_swap.argtypes = [vp, ctypes.c_int]
         L.orc_set_log.argtypes = [vp, vp, i64]
         L.orc_log_count.argtypes = [vp]
         L.orc_log_count.restype = i64
@@ -139,6 +141,10 @@ class Oracle:
 
     def set_options(self, event_cap: int = 0, check: int = 0):
         lib().orc_set_options(self._h, int(event_cap), int(check))
+
+    def set_swap(self, on: bool = True):
+        """Swap moves at hard-sphere contacts (Sec. II.C) for the following ECs."""
+        lib().orc_set_swap(self._h, 1 if on else 0)
 
     def enable_log(self, capacity: int):
         self._log = np.zeros(int(capacity), dtype=EVENT_DTYPE)

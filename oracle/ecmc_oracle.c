@@ -40,7 +40,10 @@
  *    repeats forever with nothing moving; it is detected (Brent's cycle search over the
  *    run) and ends the EC;
  *  - random numbers: Philox4x32-10 keyed by the 64-bit seed; EC draws use counter
- *    (k, domain, sweep, 0), the partition offsets use (0, 0, sweep, 1).
+ *    (k, domain, sweep, 0), the partition offsets use (0, 0, sweep, 1);
+ *  - swap moves (Sec. II.C, optional): proposed at every hard-sphere contact with a motile
+ *    bead; accepted iff all tethers of both beads are within b_max after the exchange
+ *    (squared minimum-image lengths, summed over x, y, z, compared with b_max^2).
  */
 #include "ecmc_oracle.h"
 
@@ -65,6 +68,7 @@ struct orc_sys {
     uint32_t sweep_ctr;
     int64_t event_cap;
     int check;
+    int swap;          /* swap moves at hard-sphere contacts (Sec. II.C) */
     orc_event *log;
     int64_t log_cap, log_n;
     uint64_t cnt[ORC_NCNT];
@@ -341,6 +345,11 @@ int orc_set_options(orc_sys *s, int64_t event_cap, int check) {
     return ORC_OK;
 }
 
+int orc_set_swap(orc_sys *s, int on) {
+    s->swap = on ? 1 : 0;
+    return ORC_OK;
+}
+
 int orc_set_log(orc_sys *s, orc_event *buf, int64_t cap) {
     s->log = buf;
     s->log_cap = buf ? cap : 0;
@@ -543,6 +552,61 @@ static int check_pivot(const orc_sys *s, int32_t p) {
     return ORC_OK;
 }
 
+/* ---------------------------------------------------------------- swap move */
+/* Squared minimum-image distance of two positions, summed over x, y, z in that order. */
+static double dist2(const orc_sys *s, const double *u, const double *v) {
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double d = mi(s, u[a] - v[a]);
+        d2 += d * d;
+    }
+    return d2;
+}
+
+/* Sec. II.C: at a hard-sphere contact the pivot p and the struck bead j may exchange
+ * positions.  Bonds stay with the beads, so the exchange changes the lengths of the tethers
+ * of p and of j; hard spheres cannot overlap (the set of occupied positions is unchanged).
+ * With tethers the Metropolis acceptance min(1, exp(-dE)) is 1 when every tether of p and
+ * of j is at most b_max after the exchange and 0 otherwise. */
+static int swap_allowed(const orc_sys *s, int32_t p, int32_t j) {
+    const double *rp = &s->r[3 * p], *rj = &s->r[3 * j];
+    for (int t = 0; t < 2; ++t) {
+        const int32_t q = s->nbr[2 * p + t]; /* p moves to rj */
+        if (q >= 0 && dist2(s, rj, q == j ? rp : &s->r[3 * q]) > s->b2) return 0;
+        const int32_t u = s->nbr[2 * j + t]; /* j moves to rp */
+        if (u >= 0 && dist2(s, rp, u == p ? rj : &s->r[3 * u]) > s->b2) return 0;
+    }
+    return 1;
+}
+
+/* Exchange positions, cells and cell-list entries of p and j.  The unwrapped position of p
+ * moves by the minimum-image vector from p to j (and that of j by its opposite), so an
+ * exchange across the periodic boundary shifts the image counters by one. */
+static int swap_beads(orc_sys *s, int32_t p, int32_t j) {
+    for (int a = 0; a < 3; ++a) {
+        const double raw = s->r[3 * j + a] - s->r[3 * p + a];
+        const int sh = raw > s->halfL ? -1 : (raw < -s->halfL ? 1 : 0);
+        s->img[3 * p + a] += sh;
+        s->img[3 * j + a] -= sh;
+        const double t = s->r[3 * p + a];
+        s->r[3 * p + a] = s->r[3 * j + a];
+        s->r[3 * j + a] = t;
+    }
+    const int32_t *cp = s->cell + 3 * p, *cj = s->cell + 3 * j;
+    const int kp = cidx(s, cp[0], cp[1], cp[2]), kj = cidx(s, cj[0], cj[1], cj[2]);
+    if (kp != kj) {
+        cell_remove(s, kp, p);
+        cell_remove(s, kj, j);
+        if (cell_add(s, kj, p) || cell_add(s, kp, j)) return ORC_E_ARG;
+    }
+    for (int a = 0; a < 3; ++a) {
+        const int32_t t = s->cell[3 * p + a];
+        s->cell[3 * p + a] = s->cell[3 * j + a];
+        s->cell[3 * j + a] = t;
+    }
+    return ORC_OK;
+}
+
 /* Second reflection of the EC: between the previous reflection (x_max then xref) and this
  * one the EC has used W = xref - x_max, and from here on it retraces its path between the
  * two stops with period 2W.  Whole periods are dropped: x_max = fmod(x_max, 2W).  Returns 1
@@ -621,7 +685,17 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
             xmax = xmax - b.x;
             const int motile = cell_in_domain(s, dm, s->cell + 3 * b.j);
             if (s->check >= 1 && check_pivot(s, p)) return ORC_E_CHECK;
-            if (motile) {
+            if (motile && s->swap && b.kind == 0 && swap_allowed(s, p, b.j)) {
+                /* swap (Sec. II.C): the pivot takes the struck bead's place and goes on; its
+                 * identity has advanced by d_par > 0, so a zero-length run is over */
+                log_event(s, dm, step, p, b.j, ORC_EV_SWAP);
+                s->cnt[ORC_C_SWAP]++;
+                s->sum_delta += b.dpar - b.x;
+                if (swap_beads(s, p, b.j)) return ORC_E_ARG;
+                if (s->check >= 1 && (check_pivot(s, p) || check_pivot(s, b.j))) return ORC_E_CHECK;
+                run = 0;
+                saved_p = -1;
+            } else if (motile) {
                 log_event(s, dm, step, p, b.j, b.kind == 0 ? ORC_EV_HS_LIFT : ORC_EV_TETHER_LIFT);
                 s->cnt[b.kind == 0 ? ORC_C_HS_LIFT : ORC_C_TETHER_LIFT]++;
                 s->sum_delta += b.dpar - b.x;

@@ -41,6 +41,8 @@ enum {
     ORC_EV_END = 5,            /* remaining displacement used up (target = -1)                 */
     ORC_EV_PERIOD = 6,         /* second reflection of the EC: whole periods of the retraced
                                   path between the two stops dropped from x_max (target = -1) */
+    ORC_EV_SWAP = 8,           /* hard-sphere contact with a motile bead: the pivot and the
+                                  struck bead exchanged positions, the pivot goes on          */
     ORC_EV_CYCLE = 7           /* nothing can move any more (zero-length cycle or a zero period
                                   between two stops): ends the EC (target = -1)               */
 };
@@ -63,6 +65,7 @@ enum {
     ORC_C_STEPS,
     ORC_C_PERIOD,
     ORC_C_CYCLE,
+    ORC_C_SWAP,
     ORC_NCNT
 };
 
@@ -76,6 +79,9 @@ void orc_destroy(orc_sys *s);
 /* event_cap: loop iterations allowed per EC (0 = default 10^7).
  * check: 0 none; 1 invariants after every event; 2 also brute-force next-event search. */
 int orc_set_options(orc_sys *s, int64_t event_cap, int check);
+
+/* Swap moves (Sec. II.C) on (1) or off (0, the default) for the following ECs. */
+int orc_set_swap(orc_sys *s, int on);
 int orc_set_log(orc_sys *s, orc_event *buf, int64_t cap);
 int64_t orc_log_count(const orc_sys *s);
 

@@ -445,6 +445,8 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     a.key1 = (uint32_t)(seed >> 32);
     a.sweep = c->sweep_ctr;
     a.exact_search = c->opt.precision == ECMC_PREC_FP64 ? 1 : 0;
+    a.swap = c->opt.swap_moves ? 1 : 0;
+    a.halfL = 0.5 * c->L;
     {
         // Single-precision screen (see screen() in the kernels).  Screening coordinates are frame
         // coordinates rounded once to float, so every float displacement is within
@@ -624,6 +626,7 @@ ecmc_status ecmc_get_counters(ecmc_ctx *c, ecmc_counters *out) {
     out->ec = v[C_EC];
     out->steps = v[C_STEPS];
     out->periodic = v[C_PERIOD];
+    out->swap = v[C_SWAP];
     out->cycle = v[C_CYCLE];
     HIP_OK(c, hipMemcpy(&out->sum_delta, c->ws + c->lay.dsum, 8, hipMemcpyDeviceToHost));
     HIP_OK(c, hipMemcpy(&out->error_flags, c->ws + c->lay.err, 4, hipMemcpyDeviceToHost));

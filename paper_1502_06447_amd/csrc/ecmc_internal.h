@@ -19,7 +19,8 @@ enum : uint32_t {
 };
 
 // counter slots in the device counter block
-enum { C_HS_LIFT = 0, C_TETHER_LIFT, C_HS_REFLECT, C_TETHER_REFLECT, C_WALL, C_CROSS, C_EC, C_STEPS, C_PERIOD, C_CYCLE, NCNT };
+enum { C_HS_LIFT = 0, C_TETHER_LIFT, C_HS_REFLECT, C_TETHER_REFLECT, C_WALL, C_CROSS, C_EC, C_STEPS, C_PERIOD, C_CYCLE, C_SWAP,
+       NCNT };
 
 // packed cell word of a bead: cx | cy << 10 | cz << 20, bit 30 = motile in this phase
 constexpr int CELL_BITS = 10;
@@ -70,11 +71,12 @@ struct PhaseArgs {
     ecmc_event *log;
     unsigned long long *log_n;
     long long log_cap;
-    double L, h, sig2, b2, ell;
+    double L, h, sig2, b2, ell, halfL;
     long long K, event_cap;
     int n, D, nd, cap, whole, colour;
     int stage_lo, stage_hi;    // this launch takes the domains staging S beads, stage_lo < S <= stage_hi
     int exact_search;          // 1: evaluate every staged bead in FP64 (reference search)
+    int swap;                  // 1: swap moves at hard-sphere contacts with motile beads
     float sig2f, b2f, in_lo, in_hi, p_sure, err_f;  // single-precision screen constants
     int off[3];
     uint32_t key0, key1, sweep;

@@ -511,6 +511,47 @@ __device__ __forceinline__ bool repeat_reflection(const PhaseArgs &a, const Fram
     return false;
 }
 
+// ------------------------------------------------------------------ swap move (Sec. II.C)
+__device__ __forceinline__ double min_image(double d, double L, double hL) { return d > hL ? d - L : (d < -hL ? d + L : d); }
+
+// Squared minimum-image distance from u to v, both given in the frame rotated to axis ax
+// (components along ax, ax+1, ax+2), summed over x, y, z in that order.
+__device__ __forceinline__ double dist2_rot(int ax, double ua, double ub, double uc, double va, double vb, double vc,
+                                            double L, double hL) {
+    const double da = min_image(ua - va, L, hL), db = min_image(ub - vb, L, hL), dc = min_image(uc - vc, L, hL);
+    const double qa = da * da, qb = db * db, qc = dc * dc;
+    return ax == 0 ? (qa + qb) + qc : (ax == 1 ? (qc + qa) + qb : (qb + qc) + qa);
+}
+
+// The exchange of pivot p (now at its contact point) and the struck bead j is accepted when
+// every tether of p (measured from j's place) and of j (from p's place) is within b_max: the
+// Metropolis acceptance of a tethered chain, whose energy is 0 or infinite.  Partners are
+// staged indices (0xFFFF: none); the pivot's own LDS entry is stale during an EC, so a
+// partner that is the other bead of the pair is measured at its new place.
+__device__ __forceinline__ bool swap_allowed(const Stage &st, const Pivot &pv, const Hit &hit, int J, int ax,
+                                             double L, double hL, double b2) {
+    const double *pA = st.axis(ax);
+    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
+    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
+    bool ok = true;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int q = (pv.part >> (16 * t)) & 0xFFFF;  // p moves to j's place
+        if (q != 0xFFFF) {
+            const bool qj = q == J;
+            const double va = qj ? pv.a : pA[q], vb = qj ? pv.b : pB[q], vc = qj ? pv.c : pC[q];
+            ok = ok && !(dist2_rot(ax, hit.a, hit.b, hit.c, va, vb, vc, L, hL) > b2);
+        }
+        const int u = (hit.part >> (16 * t)) & 0xFFFF;  // j moves to p's place
+        if (u != 0xFFFF) {
+            const bool up = u == pv.P;
+            const double va = up ? hit.a : pA[u], vb = up ? hit.b : pB[u], vc = up ? hit.c : pC[u];
+            ok = ok && !(dist2_rot(ax, pv.a, pv.b, pv.c, va, vb, vc, L, hL) > b2);
+        }
+    }
+    return __builtin_amdgcn_readfirstlane((int)ok) != 0;
+}
+
 // Write the pivot's position along the axis and its cell word back to LDS, and its
 // screening coordinate to the owner lane.
 template <int BPL, bool WHOLE>
@@ -632,6 +673,58 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
                 }
                 const double dpar = da * sgnd;
                 t.dsum += dpar - xint;
+                if (a.swap && kind == 0 && swap_allowed(st, pv, hit, j, ax, L, a.halfL, a.b2)) {
+                    // swap (Sec. II.C): p and j exchange places, p goes on from j's; p's
+                    // identity advanced by d_par > 0, so a zero-length run is over
+                    t.inc(C_SWAP);
+                    if (LOG) log_event(a, f, k, step, st.id[pv.P], st.id[j], ECMC_EV_SWAP);
+                    const float ja = __int_as_float(rdlane(__float_as_int(pick(R.A, j >> 6)), j & 63));
+                    const float jb = __int_as_float(rdlane(__float_as_int(pick(R.B, j >> 6)), j & 63));
+                    const float jc = __int_as_float(rdlane(__float_as_int(pick(R.C, j >> 6)), j & 63));
+                    double *pB = st.axis(axb), *pC = st.axis(axc);
+                    if (lane_id() == 0) {
+                        // image counters: p moves by the minimum-image vector to j, j back
+                        const int ip = st.id[pv.P], ij = st.id[j];
+                        const double ra[3] = {hit.a - pv.a, hit.b - pv.b, hit.c - pv.c};
+                        const int gx[3] = {ax, axb, axc};
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const int sh = ra[q] > a.halfL ? -1 : (ra[q] < -a.halfL ? 1 : 0);
+                            if (sh) {
+                                a.img[3 * ip + gx[q]] += sh;
+                                a.img[3 * ij + gx[q]] -= sh;
+                            }
+                        }
+                        pA[j] = pv.a;
+                        pB[j] = pv.b;
+                        pC[j] = pv.c;
+                        st.meta[j] = pv.meta;
+                        pA[pv.P] = hit.a;
+                        pB[pv.P] = hit.b;
+                        pC[pv.P] = hit.c;
+                        st.meta[pv.P] = hit.meta;
+                    }
+                    put(R.A, j >> 6, j & 63, pv.fa);
+                    put(R.B, j >> 6, j & 63, pv.fb);
+                    put(R.C, j >> 6, j & 63, pv.fc);
+                    put(R.A, pv.P >> 6, pv.P & 63, ja);
+                    put(R.B, pv.P >> 6, pv.P & 63, jb);
+                    put(R.C, pv.P >> 6, pv.P & 63, jc);
+                    if (WHOLE) {
+                        put(R.META, j >> 6, j & 63, pv.meta);
+                        put(R.META, pv.P >> 6, pv.P & 63, hit.meta);
+                    }
+                    pv.a = hit.a;
+                    pv.b = hit.b;
+                    pv.c = hit.c;
+                    pv.meta = hit.meta;
+                    pv.fa = ja;
+                    pv.fb = jb;
+                    pv.fc = jc;
+                    run = 0;
+                    saved_p = -1;
+                    continue;
+                }
                 t.inc(kind == 0 ? C_HS_LIFT : C_TETHER_LIFT);
                 if (LOG) log_event(a, f, k, step, st.id[pv.P], st.id[j], kind == 0 ? ECMC_EV_HS_LIFT : ECMC_EV_TETHER_LIFT);
                 store_pivot(pv, st, pA, R);

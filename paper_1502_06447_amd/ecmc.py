@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("ECMC_LIB") or os.path.join(_HERE, "libecmc.so")
 OK, E_ARG, E_OVERLAP, E_TETHER, E_BOX, E_CELL_OVERFLOW, E_STUCK, E_DEVICE, E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC_FP64, PREC_MIXED = 0, 1
 TILING_WHOLE, TILING_CHECKER = 0, 1
-EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END, EV_PERIOD, EV_CYCLE = range(8)
+EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END, EV_PERIOD, EV_CYCLE, EV_SWAP = range(9)
 
 EVENT_DTYPE = np.dtype([
     ("sweep", "<u4"), ("domain", "<u4"), ("ec", "<u4"), ("step", "<u4"),
@@ -38,6 +38,7 @@ class ecmc_options(ctypes.Structure):
         ("event_cap", ctypes.c_int64),
         ("event_log_capacity", ctypes.c_int64),
         ("time_kernels", ctypes.c_int32),
+        ("swap_moves", ctypes.c_int32),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
@@ -47,7 +48,7 @@ class ecmc_options(ctypes.Structure):
 class ecmc_counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("hs_lift", "tether_lift", "hs_reflect", "tether_reflect", "wall", "cross", "ec", "steps",
-                 "periodic", "cycle")] + [
+                 "periodic", "cycle", "swap")] + [
         ("sum_delta", ctypes.c_double), ("error_flags", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
@@ -174,6 +175,7 @@ class Options:
     event_log_capacity: int = 0
     time_kernels: bool = False
     precision: int = PREC_MIXED
+    swap_moves: bool = False
 
 
 class Melt:
@@ -193,6 +195,7 @@ class Melt:
         opt.event_cap = o.event_cap
         opt.event_log_capacity = o.event_log_capacity
         opt.time_kernels = 1 if o.time_kernels else 0
+        opt.swap_moves = 1 if o.swap_moves else 0
         pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
         nbytes = ecmc_workspace_size(L, sigma, b_max, pos.shape[0], opt)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)

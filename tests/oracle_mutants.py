@@ -31,6 +31,8 @@ MUTANTS = {
     "pivot_rng": ("const int32_t p = mot[below(u[0], (uint32_t)m)];",
                   "const int32_t p = mot[below(u[0], (uint32_t)(m > 1 ? m - 1 : m))];"),
     "period_half": ("const double r = fmod(*xmax, W + W);", "const double r = fmod(*xmax, W);"),
+    "swap_skip_j": ("        if (u >= 0 && dist2(s, rp, u == p ? rj : &s->r[3 * u]) > s->b2) return 0;\n", ""),
+    "swap_image_sign": ("        s->img[3 * p + a] += sh;", "        s->img[3 * p + a] -= sh;"),
     # equivalent mutants: no observable difference is expected
     # (W = 0 means every event between the two reflections had zero length, so the zero-length
     # cycle search ends the same EC a few steps later with the same positions)

@@ -22,6 +22,7 @@ class _Pair:
         opts = ecmc.Options(tiling=tiling, domain_cells=D, n_cells=n_cells, event_log_capacity=log, **kw)
         self.g = ecmc.Melt.from_melt(melt, opts)
         self.o = oracle.Oracle.from_melt(melt, n_cells=n_cells)
+        self.o.set_swap(kw.get("swap_moves", False))
         if log:
             self.o.enable_log(log)
         self.tiling, self.D = tiling, D
@@ -61,7 +62,8 @@ def _compare(g, o, tol=1e-9):
     for k, idx in (("hs_lift", oracle.C_HS_LIFT), ("tether_lift", oracle.C_TETHER_LIFT),
                    ("hs_reflect", oracle.C_HS_REFLECT), ("tether_reflect", oracle.C_TETHER_REFLECT),
                    ("wall", oracle.C_WALL), ("cross", oracle.C_CROSS), ("ec", oracle.C_EC),
-                   ("steps", oracle.C_STEPS), ("periodic", oracle.C_PERIOD), ("cycle", oracle.C_CYCLE)):
+                   ("steps", oracle.C_STEPS), ("periodic", oracle.C_PERIOD), ("cycle", oracle.C_CYCLE),
+                   ("swap", oracle.C_SWAP)):
         assert cg[k] == co[idx], k
     assert cg["sum_delta"] == pytest.approx(dsum, rel=1e-9, abs=1e-9)  # FP64 atomic sum over domains
     return len(lg), dp
@@ -90,6 +92,19 @@ def test_checkerboard_c1_event_sequence_bit_exact(melt_c1, exact):
     assert n > 10_000
 
 
+@pytest.mark.parametrize("tiling,exact", [(ecmc.TILING_WHOLE, False), (ecmc.TILING_CHECKER, False),
+                                          (ecmc.TILING_CHECKER, True)])
+def test_swap_moves_c1_event_sequence_bit_exact(melt_c1, tiling, exact):
+    """Swap moves (Sec. II.C) on the 16 x 16 melt: every proposal, acceptance, exchange of
+    positions and image correction as in the oracle, whole box and checkerboard."""
+    p, g, o = _pair(melt_c1, tiling, D=2, n_cells=0 if tiling == ecmc.TILING_WHOLE else 4, swap_moves=True,
+                    precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
+    for s in range(4):
+        p.sweep(256, 10.0, 170 + s)
+    n, _ = _compare(g, o)
+    assert n > 10_000 and g.counters()["swap"] > 100
+
+
 @pytest.fixture(scope="module")
 def melt_c2():
     return inputs.lattice_chains(500, 32, 0.45, seed=2)
@@ -104,6 +119,15 @@ def test_c2_dense_melt_bit_exact(melt_c2, D, n_cells, exact):
         p.sweep(16000, 20.0, 5 + s)
     n, _ = _compare(g, o)
     assert n > 250_000
+
+
+def test_swap_moves_c2_dense_melt_bit_exact(melt_c2):
+    """Swap moves in the 500 x 32 melt at eta = 0.45 (n = 18, D = 3), 2 sweeps."""
+    p, g, o = _pair(melt_c2, ecmc.TILING_CHECKER, D=3, n_cells=18, log=40_000_000, swap_moves=True)
+    for s in range(2):
+        p.sweep(16000, 20.0, 25 + s)
+    n, _ = _compare(g, o)
+    assert n > 250_000 and g.counters()["swap"] > 100
 
 
 def test_observables_match_oracle(melt_c2):
@@ -170,18 +194,20 @@ def melt_c3():
     return inputs.lattice_chains(16384, 64, 0.45, seed=3)
 
 
-def test_c3_full_size_sampled_domains(melt_c3):
+@pytest.mark.parametrize("swap", [False, True])
+def test_c3_full_size_sampled_domains(melt_c3, swap):
     """1,048,576 beads (16,384 x 64, eta = 0.45, n = 76, D = 2) in the launch configuration
     the benchmark times: one colour phase on the GPU; the oracle replays 32 sampled domains
     of that phase (domains of one phase never interact), and the beads of those domains
-    must end with identical positions, cells and image counters."""
+    must end with identical positions, cells and image counters; without and with swaps."""
     m = melt_c3
-    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2))
+    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, swap_moves=swap))
     assert g.n_cells == 76
     n_ec = m.n_beads
     g.sweep(n_ec, 20.0, 77, colour_mask=0x01)
     g.synchronize()
     o = oracle.Oracle.from_melt(m)
+    o.set_swap(swap)
     cells0 = o.cells()
     rng = np.random.default_rng(0)
     nd = 38
@@ -203,6 +229,7 @@ def test_c3_full_size_sampled_domains(melt_c3):
     assert np.array_equal(g.images()[mine], o.images()[mine])
     c, _ = o.counters()
     assert c[oracle.C_EC] == 20 * len(np.unique(did[np.isin(did, pick)]))
+    assert (g.counters()["swap"] > 0) == swap   # over the whole phase (rarely accepted from a lattice start)
 
 
 def test_c3_invariants_after_full_sweeps(melt_c3):

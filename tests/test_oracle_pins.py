@@ -297,16 +297,18 @@ def _shape(x):
     return R2, Rg2, r13
 
 
-@pytest.mark.parametrize("N", [3, 5])
-def test_short_isolated_chain_matches_direct_sampler(N):
+@pytest.mark.parametrize("N,swap", [(3, False), (5, False), (3, True), (5, True)])
+def test_short_isolated_chain_matches_direct_sampler(N, swap):
     """<R^2>, <R_g^2> and the distribution of |r_1 - r_3| of an isolated tethered chain
-    sampled by ECs agree with direct rejection sampling of the exact Boltzmann weight."""
+    sampled by ECs agree with direct rejection sampling of the exact Boltzmann weight; also
+    with swap moves (Sec. II.C), which exchange touching beads of the chain."""
     from scipy import stats
     rng = np.random.default_rng(100 + N)
     ref = _direct_chain_samples(rng, N, 20000)
     L = 20.0
     m = inputs.isolated_chain(N, L, seed=N)
     o = oracle.Oracle.from_melt(m)
+    o.set_swap(swap)
     samples = []
     for k in range(5000):
         o.sweep(2 * N, 6.1, 7000 + k)
@@ -321,6 +323,79 @@ def test_short_isolated_chain_matches_direct_sampler(N):
         err = math.sqrt(4 * a.var() / len(a) + bb.var() / len(bb))
         assert abs(a.mean() - bb.mean()) < 4 * err, (a.mean(), bb.mean(), err)
     assert stats.ks_2samp(r13e[::2], r13r).pvalue > 1e-3
+    c, _ = o.counters()
+    assert (c[oracle.C_SWAP] > 100) == swap
+
+
+# ------------------------------------------------------------------ swap move
+def _two_chains(b0):
+    """Chains (0, 1) and (2, 3) in a box of 12: bead 1 moving +x touches bead 2 after 0.5."""
+    pos = np.array([b0, [2.2, 5.0, 5.0], [3.7, 5.0, 5.0], [3.2, 6.15, 5.0]])
+    return oracle.Oracle(12.0, 1.0, 1.4, pos, [[0, 1], [2, 3]], n_cells=8)
+
+
+def test_swap_exact_cases():
+    """Sec. II.C worked by hand.  Bead 1 (+x, ell = 0.8) touches bead 2 after x = 0.5.
+    (a) Bead 0 at (2.2, 5, 6.3) (its tether stays slack until x = sqrt(1.96 - 1.69) = 0.52):
+    after an exchange bead 1 would sit 1.98 from its partner, so the swap is refused and bead 2
+    is lifted (it moves the remaining 0.3; its tether to bead 3 is
+    then sqrt(0.8^2 + 1.15^2) = 1.40089 > 1.4, so it stops after the root of
+    (0.5 + x)^2 + 1.15^2 = 1.96, x = sqrt(0.6375) - 0.5, and hands over to bead 3).
+    (b) Bead 0 at (3.0, 5, 6.1): both beads keep their tethers within 1.4 after the exchange,
+    so bead 1 takes bead 2's place (3.7, 5, 5), bead 2 goes to the contact point (2.7, 5, 5),
+    and bead 1 goes on: its tether to bead 0 (d = (-0.7, 0, 1.1)) becomes taut after
+    -0.7 + sqrt(1.96 - 1.21) = 0.16603, then bead 0 takes the rest, 0.8 - 0.5 - 0.16603."""
+    o = _two_chains([2.2, 5.0, 6.3])
+    o.set_swap(True)
+    o.enable_log(100)
+    o.run_ec(1, 0, 0.8)
+    p = o.positions()
+    x2 = math.sqrt(1.96 - 1.15 ** 2) - 0.5
+    assert abs(p[1, 0] - 2.7) < 1e-12 and abs(p[2, 0] - (3.7 + x2)) < 1e-12
+    assert abs(p[3, 0] - (3.2 + 0.3 - x2)) < 1e-12
+    kinds = [int(k) for k in o.event_log()["kind"]]
+    assert oracle.EV_SWAP not in kinds and kinds[:2] == [oracle.EV_HS_LIFT, oracle.EV_TETHER_LIFT]
+    o = _two_chains([3.0, 5.0, 6.1])
+    o.set_swap(True)
+    o.enable_log(100)
+    o.run_ec(1, 0, 0.8)
+    p = o.positions()
+    xt = -0.7 + math.sqrt(1.96 - 1.21)
+    assert abs(p[1, 0] - (3.7 + xt)) < 1e-12 and abs(p[2, 0] - 2.7) < 1e-12
+    assert abs(p[0, 0] - (3.0 + 0.3 - xt)) < 1e-12
+    assert np.array_equal(p[3], [3.2, 6.15, 5.0])
+    log = o.event_log()
+    assert [int(k) for k in log["kind"][:3]] == [oracle.EV_SWAP, oracle.EV_TETHER_LIFT, oracle.EV_END]
+    assert (int(log["pivot"][0]), int(log["target"][0])) == (1, 2)
+    c, _ = o.counters()
+    assert c[oracle.C_SWAP] == 1 and c[oracle.C_HS_LIFT] == 0
+
+
+@pytest.mark.parametrize("tiling,D,n_cells", [(0, 1, 0), (1, 2, 4)])
+def test_swap_invariants_and_unwrapped_bonds(melt_c1, tiling, D, n_cells):
+    """With swaps on, the per-event checks hold (no overlap, no stretched tether, brute-force
+    next event) and image counters stay consistent: for every bond the unwrapped difference
+    (position + image x L) minus the minimum-image bond vector is a whole number of boxes
+    that never changes, across cell crossings and exchanges through the periodic boundary."""
+    m = melt_c1
+    o = oracle.Oracle.from_melt(m, check=2, n_cells=n_cells)
+    o.set_swap(True)
+
+    def box_offsets():
+        p, u = o.positions(), o.positions() + o.images() * m.L
+        d = p[m.bonds[:, 1]] - p[m.bonds[:, 0]]
+        d -= m.L * np.round(d / m.L)
+        k = (u[m.bonds[:, 1]] - u[m.bonds[:, 0]] - d) / m.L
+        assert np.abs(k - np.round(k)).max() < 1e-9
+        return np.round(k).astype(int)
+
+    k0 = box_offsets()
+    for s in range(4):
+        o.sweep(256, 10.0, 300 + s, tiling=tiling, D=D)
+        assert np.array_equal(box_offsets(), k0)
+    c, _ = o.counters()
+    assert c[oracle.C_SWAP] > 50
+    _check_valid(o.positions(), m.bonds, m.L, m.sigma, m.b_max)
 
 
 # ------------------------------------------------------------------ hard-sphere pressure
