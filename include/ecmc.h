@@ -165,6 +165,14 @@ ecmc_status ecmc_synchronize(ecmc_ctx *ctx);
 ecmc_status ecmc_observables(ecmc_ctx *ctx, int32_t nbins, double *r2, double *rg2,
                              int64_t *hist, double *mid, int64_t *n_poly);
 
+/* Shape analysis (appendix, moment of inertia tensor; the centre of mass that g2 of Sec. IV.A
+ * measures the middle bead against): per polymer, chains unwrapped from their smaller-id end,
+ * the gyration tensor G = N^-1 sum (u - u_cm)(u - u_cm)^T as gyr [6] (xx, yy, zz, xy, xz, yz),
+ * its eigenvalues l1 >= l2 >= l3 as eig [3] (the moment of inertia tensor of the chain is
+ * N (tr G 1 - G), eigenvalues N (tr G - l_i)), and the centre of mass in image-unwrapped
+ * coordinates com [3].  Host outputs of n_poly entries (any may be NULL).  Synchronises. */
+ecmc_status ecmc_shape(ecmc_ctx *ctx, double *gyr, double *eig, double *com, int64_t *n_poly);
+
 /* Host copies of the state: positions [n][3], cell indices [n][3], image counters [n][3]. */
 ecmc_status ecmc_get_positions(ecmc_ctx *ctx, double *out);
 ecmc_status ecmc_get_cells(ecmc_ctx *ctx, int32_t *out);

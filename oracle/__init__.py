@@ -65,6 +65,9 @@ def lib():
         L.orc_next_event.argtypes = [vp, i32, ctypes.c_int, ctypes.c_int, P(dbl), P(i32), P(ctypes.c_int), P(dbl)]
         L.orc_run_ec.argtypes = [vp, i32, ctypes.c_int, dbl]
         L.orc_observables.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, P(i64)]
+        L.orc_gyration.argtypes = [vp, i64, vp]
+        L.orc_gyration.restype = None
+        L.orc_shape.argtypes = [vp, vp, vp]
         L.orc_n_beads.argtypes = [vp]
         L.orc_n_beads.restype = i64
         L.orc_n_cells.argtypes = [vp]
@@ -141,6 +144,17 @@ class Oracle:
 
     def set_options(self, event_cap: int = 0, check: int = 0):
         lib().orc_set_options(self._h, int(event_cap), int(check))
+
+    def shape(self) -> dict:
+        """Per polymer: gyration tensor [n, 6] (xx, yy, zz, xy, xz, yz), its eigenvalues [n, 3]
+        in descending order (numpy's symmetric eigensolver), unwrapped centre of mass [n, 3]."""
+        n = self.observables(nbins=1)["n_poly"]
+        gyr = np.zeros((n, 6))
+        com = np.zeros((n, 3))
+        st = lib().orc_shape(self._h, gyr.ctypes.data, com.ctypes.data)
+        if st != OK:
+            raise OracleError(st, "orc_shape")
+        return {"gyr": gyr, "eig": tensor_eigenvalues(gyr), "com": com, "n_poly": n}
 
     def set_swap(self, on: bool = True):
         """Swap moves at hard-sphere contacts (Sec. II.C) for the following ECs."""
@@ -228,3 +242,42 @@ class Oracle:
         lib().orc_observables(self._h, int(nbins), r2.ctypes.data, rg2.ctypes.data, hist.ctypes.data,
                               mid.ctypes.data, ctypes.byref(n_poly))
         return {"r2": r2, "rg2": rg2, "hist": hist[:nbins], "mid": mid, "n_poly": M}
+
+
+def gyration(u) -> np.ndarray:
+    """Gyration tensor (xx, yy, zz, xy, xz, yz) of one unwrapped chain u [n, 3]."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+    g = np.zeros(6)
+    lib().orc_gyration(u.ctypes.data, u.shape[0], g.ctypes.data)
+    return g
+
+
+def tensor_eigenvalues(g) -> np.ndarray:
+    """Eigenvalues, descending, of symmetric 3 x 3 tensors given as [..., 6] (xx, yy, zz, xy, xz, yz)."""
+    g = np.asarray(g, dtype=np.float64)
+    m = np.empty(g.shape[:-1] + (3, 3))
+    m[..., 0, 0], m[..., 1, 1], m[..., 2, 2] = g[..., 0], g[..., 1], g[..., 2]
+    m[..., 0, 1] = m[..., 1, 0] = g[..., 3]
+    m[..., 0, 2] = m[..., 2, 0] = g[..., 4]
+    m[..., 1, 2] = m[..., 2, 1] = g[..., 5]
+    return np.linalg.eigvalsh(m)[..., ::-1]
+
+
+def shape_descriptors(eig) -> dict:
+    """Appendix (moment of inertia tensor) from gyration eigenvalues l1 >= l2 >= l3 per polymer,
+    with the inertia eigenvalues I_i = tr G - l_i taken in descending order (I1 >= I2 >= I3:
+    the order that makes b, c >= 0 and gives the printed infinite-chain limits): kappa^2 =
+    4 (1 - 3 (I1 I2 + I2 I3 + I3 I1) / (tr I)^2), the ratios <I1 + I2 - I3> / <tr I> etc.,
+    and <4 b^2 + 3 c^2> / <tr I>^2 with b = (I1 + I2)/2 - I3, c = I1 - I2."""
+    eig = np.asarray(eig, dtype=np.float64)
+    S = eig.sum(axis=-1, keepdims=True)
+    I = np.sort(S - eig, axis=-1)[..., ::-1]
+    tr = I.sum(axis=-1)
+    k2 = 4.0 * (1.0 - 3.0 * (I[..., 0] * I[..., 1] + I[..., 1] * I[..., 2] + I[..., 2] * I[..., 0]) / tr ** 2)
+    b = 0.5 * (I[..., 0] + I[..., 1]) - I[..., 2]
+    c = I[..., 0] - I[..., 1]
+    return {"kappa2": float(k2.mean()),
+            "r_123": float((I[..., 0] + I[..., 1] - I[..., 2]).mean() / tr.mean()),
+            "r_132": float((I[..., 0] - I[..., 1] + I[..., 2]).mean() / tr.mean()),
+            "r_231": float((-I[..., 0] + I[..., 1] + I[..., 2]).mean() / tr.mean()),
+            "solc": float((4 * b ** 2 + 3 * c ** 2).mean() / tr.mean() ** 2)}

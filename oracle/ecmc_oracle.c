@@ -886,6 +886,52 @@ int orc_sweep_subset(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int D,
  * the garbled index range as i = 1..N), the middle bead floor(N/2) (0-based) in
  * image-unwrapped coordinates for g1, and a histogram of bond lengths on
  * [sigma, b_max] with nbins equal bins. */
+/* Shape analysis (appendix, moment of inertia tensor): the gyration tensor by its definition,
+ * centre of mass first, then the mean outer product of the positions relative to it. */
+void orc_gyration(const double *u, int64_t n, double g[6]) {
+    double cm[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = 0; k < n; ++k)
+        for (int a = 0; a < 3; ++a) cm[a] += u[3 * k + a];
+    for (int a = 0; a < 3; ++a) cm[a] /= (double)n;
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int m = 0; m < 6; ++m) {
+        double acc = 0.0;
+        for (int64_t k = 0; k < n; ++k) acc += (u[3 * k + ia[m]] - cm[ia[m]]) * (u[3 * k + ib[m]] - cm[ib[m]]);
+        g[m] = acc / (double)n;
+    }
+}
+
+int orc_shape(const orc_sys *s, double *gyr, double *com) {
+    double *u = NULL;
+    int64_t ucap = 0;
+    for (int64_t q = 0; q < s->npoly; ++q) {
+        const int64_t a = s->pstart[q], e = s->pstart[q + 1];
+        const int64_t N = e - a;
+        if (N > ucap) {
+            free(u);
+            ucap = N;
+            u = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+            if (!u) return ORC_E_ARG;
+        }
+        /* unwrapped chain: the first bead with its image counters, then minimum-image bonds */
+        const int32_t i0 = s->porder[a];
+        for (int k = 0; k < 3; ++k) u[k] = s->r[3 * i0 + k] + (double)s->img[3 * i0 + k] * s->L;
+        for (int64_t t = 1; t < N; ++t) {
+            const int32_t j0 = s->porder[a + t - 1], j1 = s->porder[a + t];
+            for (int k = 0; k < 3; ++k) u[3 * t + k] = u[3 * (t - 1) + k] + mi(s, s->r[3 * j1 + k] - s->r[3 * j0 + k]);
+        }
+        if (gyr) orc_gyration(u, N, gyr + 6 * q);
+        if (com)
+            for (int k = 0; k < 3; ++k) {
+                double acc = 0.0;
+                for (int64_t t = 0; t < N; ++t) acc += u[3 * t + k];
+                com[3 * q + k] = acc / (double)N;
+            }
+    }
+    free(u);
+    return ORC_OK;
+}
+
 int orc_observables(const orc_sys *s, int nbins, double *r2, double *rg2, int64_t *hist,
                     double *mid, int64_t *n_poly) {
     if (n_poly) *n_poly = s->npoly;

@@ -101,6 +101,16 @@ int orc_next_event(const orc_sys *s, int32_t p, int axis, int sgn, double *x, in
                    int *kind, double *x_cell);
 int orc_run_ec(orc_sys *s, int32_t p, int dir, double ell);
 
+/* Gyration tensor of one chain given unwrapped, u [n][3]: G = n^-1 sum_k (u_k - u_cm)(u_k - u_cm)^T
+ * (two passes), stored as xx, yy, zz, xy, xz, yz.  The moment of inertia tensor of the appendix
+ * is n (tr G 1 - G): same eigenvectors, eigenvalues n (tr G - lambda_i). */
+void orc_gyration(const double *u, int64_t n, double g[6]);
+
+/* Per polymer of the current state (chains unwrapped from their first bead by minimum-image
+ * bonds): gyration tensor gyr [n_poly][6] and the centre of mass in image-unwrapped
+ * coordinates com [n_poly][3] (either may be NULL). */
+int orc_shape(const orc_sys *s, double *gyr, double *com);
+
 int orc_observables(const orc_sys *s, int nbins, double *r2, double *rg2, int64_t *hist,
                     double *mid, int64_t *n_poly);
 

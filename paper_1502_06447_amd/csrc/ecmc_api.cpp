@@ -21,8 +21,8 @@ constexpr int DEFAULT_CAP = 16;
 constexpr int MAX_BINS = 1024;
 
 struct Layout {
-    size_t px, py, pz, cellp, img, part, ccount, cids, dstage, porder, pstart, r2, rg2, mid, hist, cnt, dsum, err, log_n,
-        log;
+    size_t px, py, pz, cellp, img, part, ccount, cids, dstage, porder, pstart, r2, rg2, mid, shape, hist, cnt, dsum, err,
+        log_n, log;
     size_t total;
 };
 
@@ -51,6 +51,7 @@ Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap) {
     l.r2 = take(8 * nb);
     l.rg2 = take(8 * nb);
     l.mid = take(24 * nb);
+    l.shape = take(96 * nb);  // gyration tensor, eigenvalues, centre of mass: 12 doubles per polymer
     l.hist = take(8 * MAX_BINS);
     l.cnt = take(8 * NCNT);
     l.dsum = take(8);
@@ -573,6 +574,31 @@ ecmc_status ecmc_observables(ecmc_ctx *c, int32_t nbins, double *r2, double *rg2
     if (rg2) HIP_OK(c, hipMemcpy(rg2, o.rg2, 8 * c->npoly, hipMemcpyDeviceToHost));
     if (mid) HIP_OK(c, hipMemcpy(mid, o.mid, 24 * c->npoly, hipMemcpyDeviceToHost));
     if (hist) HIP_OK(c, hipMemcpy(hist, o.hist, 8 * nbins, hipMemcpyDeviceToHost));
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_shape(ecmc_ctx *c, double *gyr, double *eig, double *com, int64_t *n_poly) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    if (n_poly) *n_poly = c->npoly;
+    ObsArgs o{};
+    o.px = c->dev<double>(c->lay.px);
+    o.py = c->dev<double>(c->lay.py);
+    o.pz = c->dev<double>(c->lay.pz);
+    o.img = c->dev<int32_t>(c->lay.img);
+    o.porder = c->dev<int32_t>(c->lay.porder);
+    o.pstart = c->dev<int32_t>(c->lay.pstart);
+    o.npoly = c->npoly;
+    o.L = c->L;
+    o.halfL = 0.5 * c->L;
+    o.gyr = c->dev<double>(c->lay.shape);
+    o.eig = o.gyr + 6 * c->npoly;
+    o.com = o.eig + 3 * c->npoly;
+    HIP_OK(c, launch_shape(o, c->stream));
+    ecmc_status st = check_device(c);
+    if (st) return st;
+    if (gyr) HIP_OK(c, hipMemcpy(gyr, o.gyr, 48 * c->npoly, hipMemcpyDeviceToHost));
+    if (eig) HIP_OK(c, hipMemcpy(eig, o.eig, 24 * c->npoly, hipMemcpyDeviceToHost));
+    if (com) HIP_OK(c, hipMemcpy(com, o.com, 24 * c->npoly, hipMemcpyDeviceToHost));
     return ECMC_OK;
 }
 

@@ -91,6 +91,7 @@ struct ObsArgs {
     double L, halfL, sigma, bmax;
     int nbins;
     double *r2, *rg2, *mid;    // [npoly], [npoly], [3 npoly]
+    double *gyr, *eig, *com;   // shape: [6 npoly], [3 npoly], [3 npoly]
     unsigned long long *hist;  // [nbins]
 };
 
@@ -98,6 +99,7 @@ struct ObsArgs {
 hipError_t launch_count(const PhaseArgs &a, int grid, hipStream_t s);
 hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s);
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
+hipError_t launch_shape(const ObsArgs &a, hipStream_t s);
 bool bpl_supported(int bpl);
 
 }  // namespace ecmc

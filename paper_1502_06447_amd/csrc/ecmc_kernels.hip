@@ -1163,6 +1163,98 @@ __global__ __launch_bounds__(64 * OBS_WAVES) void k_observables(const ObsArgs a)
             if (s_hist[i]) atomicAdd(&a.hist[i], (unsigned long long)s_hist[i]);
 }
 
+// Eigenvalues, descending, of a symmetric 3 x 3 matrix (xx, yy, zz, xy, xz, yz): the
+// trigonometric closed form of the characteristic cubic.  With q = tr/3 and
+// B = (G - q 1) / p, p = sqrt(tr((G - q 1)^2) / 6), the eigenvalues are
+// q + 2 p cos(phi + 2 pi k / 3) with phi = acos(det(B) / 2) / 3.
+__device__ void sym3_eigenvalues(const double g[6], double e[3]) {
+    const double xx = g[0], yy = g[1], zz = g[2], xy = g[3], xz = g[4], yz = g[5];
+    const double p1 = (xy * xy + xz * xz) + yz * yz;
+    const double q = ((xx + yy) + zz) / 3.0;
+    const double dx = xx - q, dy = yy - q, dz = zz - q;
+    const double p2 = ((dx * dx + dy * dy) + dz * dz) + 2.0 * p1;
+    if (!(p2 > 0.0)) {
+        e[0] = e[1] = e[2] = q;
+        return;
+    }
+    const double p = sqrt(p2 / 6.0);
+    const double bxx = dx / p, byy = dy / p, bzz = dz / p, bxy = xy / p, bxz = xz / p, byz = yz / p;
+    const double det = bxx * (byy * bzz - byz * byz) - bxy * (bxy * bzz - byz * bxz) + bxz * (bxy * byz - byy * bxz);
+    double r = 0.5 * det;
+    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+    const double phi = acos(r) / 3.0;
+    const double two_pi_3 = 2.0943951023931954923;  // 2 pi / 3
+    e[0] = q + 2.0 * p * cos(phi);
+    e[2] = q + 2.0 * p * cos(phi + two_pi_3);
+    e[1] = 3.0 * q - e[0] - e[2];
+}
+
+// Shape analysis (appendix, moment of inertia tensor; the centre of mass for g2 of
+// Sec. IV.A): one wavefront per polymer.  As in k_observables the chain is unwrapped from its
+// first bead by prefix sums of minimum-image bond vectors; the sums of u and of u_a u_b give
+// the gyration tensor G = N^-1 sum u u^T - u_cm u_cm^T (positions relative to the first bead
+// keep the cancellation small), its eigenvalues, and the centre of mass in image-unwrapped
+// coordinates.
+__global__ __launch_bounds__(64 * OBS_WAVES) void k_shape(const ObsArgs a) {
+    const int lane = lane_id();
+    const int w = (int)threadIdx.x >> 6;
+    auto mi = [&](double d) { return d > a.halfL ? d - a.L : (d < -a.halfL ? d + a.L : d); };
+    for (int64_t q = (int64_t)blockIdx.x * OBS_WAVES + w; q < a.npoly; q += (int64_t)gridDim.x * OBS_WAVES) {
+        const int64_t s = a.pstart[q];
+        const int N = (int)(a.pstart[q + 1] - s);
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, sxx = 0.0, syy = 0.0, szz = 0.0, sxy = 0.0, sxz = 0.0, syz = 0.0;
+        for (int base = 0; base < N; base += 64) {
+            const int t = base + lane;
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+            if (t < N && t > 0) {
+                const int ia = a.porder[s + t - 1], ib = a.porder[s + t];
+                d0 = mi(a.px[ib] - a.px[ia]);
+                d1 = mi(a.py[ib] - a.py[ia]);
+                d2 = mi(a.pz[ib] - a.pz[ia]);
+            }
+            const double u0 = c0 + wave_scan_f64(d0);
+            const double u1 = c1 + wave_scan_f64(d1);
+            const double u2 = c2 + wave_scan_f64(d2);
+            if (t < N) {
+                s0 += u0;
+                s1 += u1;
+                s2 += u2;
+                sxx += u0 * u0;
+                syy += u1 * u1;
+                szz += u2 * u2;
+                sxy += u0 * u1;
+                sxz += u0 * u2;
+                syz += u1 * u2;
+            }
+            c0 = rdlane(u0, 63);
+            c1 = rdlane(u1, 63);
+            c2 = rdlane(u2, 63);
+        }
+        const double inv = 1.0 / (double)N;
+        const double m0 = wave_sum_f64(s0) * inv, m1 = wave_sum_f64(s1) * inv, m2 = wave_sum_f64(s2) * inv;
+        double g[6];
+        g[0] = wave_sum_f64(sxx) * inv - m0 * m0;
+        g[1] = wave_sum_f64(syy) * inv - m1 * m1;
+        g[2] = wave_sum_f64(szz) * inv - m2 * m2;
+        g[3] = wave_sum_f64(sxy) * inv - m0 * m1;
+        g[4] = wave_sum_f64(sxz) * inv - m0 * m2;
+        g[5] = wave_sum_f64(syz) * inv - m1 * m2;
+        if (lane == 0) {
+            double e[3];
+            sym3_eigenvalues(g, e);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) a.gyr[6 * q + k] = g[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a.eig[3 * q + k] = e[k];
+            const int i0 = a.porder[s];
+            a.com[3 * q + 0] = a.px[i0] + (double)a.img[3 * i0 + 0] * a.L + m0;
+            a.com[3 * q + 1] = a.py[i0] + (double)a.img[3 * i0 + 1] * a.L + m1;
+            a.com[3 * q + 2] = a.pz[i0] + (double)a.img[3 * i0 + 2] * a.L + m2;
+        }
+    }
+}
+
 }  // namespace
 
 bool bpl_supported(int bpl) {
@@ -1205,6 +1297,14 @@ hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStre
 hipError_t launch_count(const PhaseArgs &a, int grid, hipStream_t s) {
     if (a.whole) hipLaunchKernelGGL(k_count<true>, dim3(grid), dim3(64), 0, s, a);
     else hipLaunchKernelGGL(k_count<false>, dim3(grid), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shape(const ObsArgs &a, hipStream_t s) {
+    if (a.npoly <= 0) return hipSuccess;
+    int64_t grid = (a.npoly + OBS_WAVES - 1) / OBS_WAVES;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL(k_shape, dim3((unsigned)grid), dim3(64 * OBS_WAVES), 0, s, a);
     return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ _lib = None
 
 EXPORTS = (
     "ecmc_default_options", "ecmc_workspace_size", "ecmc_init", "ecmc_sweep", "ecmc_sweep_colours",
-    "ecmc_synchronize", "ecmc_observables", "ecmc_get_positions", "ecmc_get_cells", "ecmc_get_images",
+    "ecmc_synchronize", "ecmc_observables", "ecmc_shape", "ecmc_get_positions", "ecmc_get_cells", "ecmc_get_images",
     "ecmc_get_counters", "ecmc_reset_counters", "ecmc_get_event_log", "ecmc_clear_event_log",
     "ecmc_set_state", "ecmc_kernel_time", "ecmc_sweep_counter", "ecmc_n_cells", "ecmc_cell_size",
     "ecmc_stage_capacity", "ecmc_destroy", "ecmc_status_str", "ecmc_last_error",
@@ -92,6 +92,7 @@ def lib():
         "ecmc_sweep_colours": (st, [vp, i64, dbl, u64, u32]),
         "ecmc_synchronize": (st, [vp]),
         "ecmc_observables": (st, [vp, i32, vp, vp, vp, vp, P(i64)]),
+        "ecmc_shape": (st, [vp, vp, vp, vp, P(i64)]),
         "ecmc_get_positions": (st, [vp, vp]),
         "ecmc_get_cells": (st, [vp, vp]),
         "ecmc_get_images": (st, [vp, vp]),
@@ -315,3 +316,36 @@ class Melt:
                                       mid.ctypes.data, ctypes.byref(n_poly)), "ecmc_observables", self.ctx)
         assert n_poly.value == M
         return {"r2": r2, "rg2": rg2, "hist": hist, "mid": mid, "n_poly": M}
+
+    def shape(self) -> dict:
+        """Per polymer: gyration tensor [M, 6] (xx, yy, zz, xy, xz, yz), its eigenvalues [M, 3]
+        (descending) and the image-unwrapped centre of mass [M, 3], computed on the GPU."""
+        n_poly = ctypes.c_int64()
+        M = self.n_poly
+        gyr, eig, com = np.zeros((M, 6)), np.zeros((M, 3)), np.zeros((M, 3))
+        _check(lib().ecmc_shape(self.ctx, gyr.ctypes.data, eig.ctypes.data, com.ctypes.data, ctypes.byref(n_poly)),
+               "ecmc_shape", self.ctx)
+        assert n_poly.value == M
+        return {"gyr": gyr, "eig": eig, "com": com, "n_poly": M}
+
+
+def shape_descriptors(eig) -> dict:
+    """Ensemble shape descriptors (appendix, Table II) from per-polymer gyration eigenvalues
+    l1 >= l2 >= l3 (Melt.shape()["eig"]).  The moment of inertia eigenvalues are
+    I_i = tr G - l_i, here in descending order I1 >= I2 >= I3, the order under which the
+    asphericity b = (I1 + I2)/2 - I3 and acylindricity c = I1 - I2 are non-negative and the
+    quoted infinite-chain limits hold.  Returns <kappa^2> with
+    kappa^2 = 4 (1 - 3 (I1 I2 + I2 I3 + I3 I1) / (tr I)^2), the three ratios
+    <I1 + I2 - I3>/<tr I>, <I1 - I2 + I3>/<tr I>, <-I1 + I2 + I3>/<tr I>, and
+    <4 b^2 + 3 c^2> / <tr I>^2."""
+    lam = np.asarray(eig, dtype=np.float64).reshape(-1, 3)
+    tot = lam[:, 0] + lam[:, 1] + lam[:, 2]
+    i1, i2, i3 = tot - lam[:, 2], tot - lam[:, 1], tot - lam[:, 0]   # descending
+    tr = i1 + i2 + i3
+    pair = i1 * i2 + i2 * i3 + i3 * i1
+    b = 0.5 * (i1 + i2) - i3
+    c = i1 - i2
+    mt = tr.mean()
+    return {"kappa2": float(np.mean(4.0 * (1.0 - 3.0 * pair / tr ** 2))),
+            "r_123": float(np.mean(i1 + i2 - i3) / mt), "r_132": float(np.mean(i1 - i2 + i3) / mt),
+            "r_231": float(np.mean(-i1 + i2 + i3) / mt), "solc": float(np.mean(4 * b * b + 3 * c * c) / mt ** 2)}

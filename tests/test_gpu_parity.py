@@ -142,6 +142,24 @@ def test_observables_match_oracle(melt_c2):
     assert np.array_equal(og["hist"], oo["hist"])
 
 
+def test_shape_analysis_matches_oracle(melt_c2):
+    """Gyration tensors, eigenvalues and unwrapped centres of mass per polymer (appendix shape
+    analysis; the centre of mass of g2) against the oracle, after 2 sweeps of the 500 x 32 melt;
+    the ensemble descriptors of Table II from both."""
+    p, g, o = _pair(melt_c2, ecmc.TILING_CHECKER, D=3, n_cells=18, log=0)
+    for s in range(2):
+        p.sweep(16000, 20.0, 31 + s)
+    sg, so = g.shape(), o.shape()
+    assert sg["n_poly"] == so["n_poly"] == 500
+    tr = so["gyr"][:, :3].sum(axis=1)[:, None]
+    assert np.all(np.abs(sg["gyr"] - so["gyr"]) <= 1e-10 * tr)
+    assert np.all(np.abs(sg["eig"] - so["eig"]) <= 1e-9 * tr)
+    np.testing.assert_allclose(sg["com"], so["com"], rtol=0, atol=1e-9)
+    dg, do = ecmc.shape_descriptors(sg["eig"]), oracle.shape_descriptors(so["eig"])
+    for k in do:
+        assert abs(dg[k] - do[k]) < 1e-9, k
+
+
 def test_edge_cases_zero_length_and_empty(melt_c1):
     """ell = 0 (every EC ends at once), n_chains = 0 (nothing runs, the sweep counter still
     advances), and a dilute box where most domains are empty."""
@@ -242,6 +260,13 @@ def test_c3_invariants_after_full_sweeps(melt_c3):
     g.synchronize()
     pos = g.positions()
     L = m.L
+    # shape analysis of all 16,384 chains against the oracle put into the same state
+    o = oracle.Oracle.from_melt(m)
+    o.set_state(pos, g.cells(), g.images(), g.sweep_counter)
+    sg, so = g.shape(), o.shape()
+    tr = so["gyr"][:, :3].sum(axis=1)[:, None]
+    assert np.all(np.abs(sg["gyr"] - so["gyr"]) <= 1e-10 * tr) and np.all(np.abs(sg["eig"] - so["eig"]) <= 1e-9 * tr)
+    np.testing.assert_allclose(sg["com"], so["com"], rtol=0, atol=1e-8)
     d = pos[m.bonds[:, 1]] - pos[m.bonds[:, 0]]
     d -= L * np.round(d / L)
     assert np.einsum("ij,ij->i", d, d).max() <= 1.4 ** 2 * (1 + 1e-10)

@@ -668,3 +668,58 @@ def test_lone_bead_bounces_between_domain_walls():
         for b in range(3):
             if b != ax:
                 assert got[b] == x[b]
+
+
+# ------------------------------------------------------------------ shape analysis (appendix)
+def test_gyration_closed_forms():
+    """A straight rod of N beads at spacing a has one gyration eigenvalue a^2 (N^2 - 1) / 12
+    and two zeros (kappa^2 = 1); four beads on a square of side a have a^2/4, a^2/4, 0
+    (kappa^2 = 1/4)."""
+    a, N = 1.3, 9
+    rod = np.zeros((N, 3))
+    rod[:, 1] = a * np.arange(N)
+    e = oracle.tensor_eigenvalues(oracle.gyration(rod))
+    assert np.allclose(e, [a * a * (N * N - 1) / 12, 0, 0], atol=1e-12)
+    assert abs(oracle.shape_descriptors(e[None, :])["kappa2"] - 1.0) < 1e-12
+    sq = a * np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], float) + [0.3, -2.0, 5.0]
+    g = oracle.gyration(sq)
+    assert np.allclose(g, [a * a / 4, a * a / 4, 0, 0, 0, 0], atol=1e-12)
+    assert abs(oracle.shape_descriptors(oracle.tensor_eigenvalues(g)[None, :])["kappa2"] - 0.25) < 1e-12
+
+
+def test_shape_descriptors_of_long_random_walks_match_the_limits():
+    """Long freely jointed chains (random walks of unit steps, N = 512) approach the limits the
+    appendix quotes: <I1+I2-I3>, <I1-I2+I3>, <-I1+I2+I3> over <tr I> -> 0.754, 0.175, 0.0646
+    and <4b^2 + 3c^2> / <tr I>^2 -> 2/3 (within 3 %: finite N, sampling, approximate limits).
+    This pins the eigenvalue order and the normalisations."""
+    rng = np.random.default_rng(12)
+    N, M = 512, 8000
+    v = rng.normal(size=(M, N - 1, 3))
+    v /= np.linalg.norm(v, axis=2)[:, :, None]
+    x = np.concatenate([np.zeros((M, 1, 3)), np.cumsum(v, axis=1)], axis=1)
+    g = np.array([oracle.gyration(c) for c in x])
+    d = oracle.shape_descriptors(oracle.tensor_eigenvalues(g))
+    for key, lim in (("r_123", 0.754), ("r_132", 0.175), ("r_231", 0.0646), ("solc", 2.0 / 3.0)):
+        assert abs(d[key] - lim) / lim < 0.03, (key, d[key], lim)
+    assert 0.36 < d["kappa2"] < 0.43
+
+
+def test_shape_of_a_melt_is_consistent_with_rg2(melt_c1):
+    """orc_shape (unwrapped chains through image counters) against orc_observables: the trace
+    of each gyration tensor is that polymer's R_g^2, and the centre of mass equals the mean of
+    the chain unwrapped independently here."""
+    m = melt_c1
+    o = oracle.Oracle.from_melt(m, n_cells=4)
+    for s in range(2):
+        o.sweep(256, 10.0, 40 + s, tiling=1, D=2)
+    sh = o.shape()
+    ob = o.observables(nbins=8)
+    assert np.allclose(sh["gyr"][:, :3].sum(axis=1), ob["rg2"], rtol=1e-12, atol=0)
+    p, img = o.positions(), o.images()
+    for q in range(4):
+        ids = np.arange(16 * q, 16 * q + 16)
+        d = np.diff(p[ids], axis=0)
+        d -= m.L * np.round(d / m.L)
+        u = np.concatenate([(p[ids[0]] + img[ids[0]] * m.L)[None, :], p[ids[0]] + img[ids[0]] * m.L + np.cumsum(d, 0)])
+        assert np.allclose(sh["com"][q], u.mean(axis=0), atol=1e-10)
+        assert np.allclose(sh["gyr"][q], oracle.gyration(u), atol=1e-10)
