@@ -59,6 +59,7 @@ typedef enum {
 
 enum { ECMC_PREC_FP64 = 0, ECMC_PREC_MIXED = 1 };
 enum { ECMC_TILING_WHOLE = 0, ECMC_TILING_CHECKER = 1 };
+enum { ECMC_SCHED_SWEEP = 0, ECMC_SCHED_PHASES = 1 };
 
 /* event kinds in the event log */
 enum {
@@ -92,16 +93,25 @@ typedef struct {
     int32_t domain_cells;       /* D, cells per domain edge (checkerboard)                  */
     int32_t cell_capacity;      /* bead slots per cell; 0 = 16                              */
     int32_t stage_capacity;     /* beads one domain (plus its one-cell halo) may hold;
-                                   0 = automatic: a first launch sized for the typical
-                                   domain and two more (the next size up, and 1024) for
-                                   the rare larger domains, run concurrently; > 0 = one
-                                   launch of this capacity, a larger domain is
+                                   0 = automatic: LDS staging sized for the typical domain,
+                                   the rare larger domains staged in workspace slots (one
+                                   sweep launch) or run by two more launches of the next
+                                   size up and 1024 beads (by phases); > 0 = LDS staging of
+                                   this capacity only, a larger domain is
                                    ECMC_E_CELL_OVERFLOW; at most 1024                       */
     int64_t event_cap;          /* loop iterations allowed per EC; 0 = 10^7                 */
     int64_t event_log_capacity; /* event records kept; 0 = no log (the fast path)           */
-    int32_t time_kernels;       /* nonzero: time every colour phase with HIP events          */
+    int32_t time_kernels;       /* nonzero: time every sweep launch (or colour phase, by
+                                   phases) with HIP events                                  */
     int32_t swap_moves;         /* nonzero: propose a swap (Sec. II.C) at every hard-sphere
                                    contact with a motile bead instead of lifting at once    */
+    int32_t schedule;           /* checkerboard sweeps (identical results either way):
+                                   ECMC_SCHED_SWEEP (default): one launch per sweep, each
+                                   domain started as soon as its neighbours of earlier
+                                   colours are done (no device-wide wait between phases);
+                                   ECMC_SCHED_PHASES: one launch set per colour phase. A
+                                   colour_mask other than all eight colours, or a staging
+                                   capacity above 512 beads, always runs by phases          */
     void *workspace;            /* device memory owned by the caller (256-byte aligned)     */
     size_t workspace_bytes;
     void *stream;               /* hipStream_t for every launch and copy; NULL = default    */
@@ -114,7 +124,8 @@ typedef struct {
     uint64_t swap;              /* accepted swap moves                                      */
     double sum_delta;           /* sum over lifts and swaps of (d_par - x): pressure estimator */
     uint32_t error_flags;       /* device error word (bit 0 staging, 1 cell, 2 stuck,
-                                   3 log full, 4 cell lists changed during staging)         */
+                                   3 log full, 4 cell lists changed during staging,
+                                   5 a wait of the sweep launch ran out of polls)           */
     uint32_t pad;
 } ecmc_counters;
 

@@ -14,7 +14,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libecmc.so")
-SOURCES = [os.path.join(CSRC, "ecmc_kernels.hip"), os.path.join(CSRC, "ecmc_api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("ecmc_kernels.hip", "ecmc_sweep.hip", "ecmc_api.cpp")]
+HEADERS = [os.path.join(CSRC, f) for f in ("ecmc_device.h", "ecmc_internal.h")]
 ARCH = os.environ.get("ECMC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -26,17 +27,39 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, out: str = LIB, defines: tuple = ()) -> str:
-    """Compile the library to ``out``; ``defines`` are extra -D macros (tuning knobs)."""
-    tmp = out + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-ffp-contract=off", "-fno-fast-math",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include")] + [f"-D{d}" for d in defines] + ["-o", tmp, "-x", "hip"] + SOURCES
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, out)
+    """Compile the library to ``out``; ``defines`` are extra -D macros (tuning knobs).
+
+    Each source is compiled to an object of its own, all at once, then linked."""
+    from concurrent.futures import ThreadPoolExecutor
+    flags = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+             "-ffp-contract=off", "-fno-fast-math",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument",
+             "-I", os.path.join(ROOT, "include")] + [f"-D{d}" for d in defines]
+    objs = [out + "." + os.path.basename(src) + ".o" for src in SOURCES]
+
+    def compile_one(src_obj):
+        src, obj = src_obj
+        cmd = [hipcc()] + flags + ["-c", "-o", obj, "-x", "hip", src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd).returncode
+
+    try:
+        with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+            codes = list(ex.map(compile_one, zip(SOURCES, objs)))
+        if any(codes):
+            raise subprocess.CalledProcessError(max(codes), "hipcc -c")
+        tmp = out + ".tmp"
+        cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return out
 
 

@@ -19,16 +19,17 @@ namespace {
 constexpr int64_t DEFAULT_EVENT_CAP = 10000000;
 constexpr int DEFAULT_CAP = 16;
 constexpr int MAX_BINS = 1024;
+constexpr int SLOW_SLOTS = 512;  // workspace staging slots of the dependency-ordered sweep
 
 struct Layout {
-    size_t px, py, pz, cellp, img, part, ccount, cids, dstage, porder, pstart, r2, rg2, mid, shape, hist, cnt, dsum, err,
-        log_n, log;
+    size_t px, py, pz, cellp, img, part, ccount, cids, dstage, done, queue, slow_lock, slow, porder, pstart, r2, rg2,
+        mid, shape, hist, cnt, dsum, err, log_n, log;
     size_t total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap) {
+Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap, int nslow, int slow_cap) {
     Layout l{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -46,6 +47,10 @@ Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap) {
     l.ccount = take(4 * nc);
     l.cids = take(4 * nc * cap);
     l.dstage = take(4 * (nc / 8 + 1));  // one count per domain of a colour phase (at most n^3 / 64)
+    l.done = take(4 * (nc / 8 + 1));    // one stamp per domain (D >= 2: at most n^3 / 8)
+    l.queue = take(8);
+    l.slow_lock = take(4 * (size_t)std::max(nslow, 0));
+    l.slow = take((size_t)std::max(nslow, 0) * (size_t)std::max(slow_cap, 0) * SLOW_SLOT_BYTES_PER_BEAD);
     l.porder = take(4 * nb);
     l.pstart = take(4 * (nb + 1));
     l.r2 = take(8 * nb);
@@ -71,6 +76,9 @@ struct Geometry {
     int stage = 0;
     int bpl2 = 0;    // second tier for the rare domains above 64 * bpl (0 = none)
     int bpl3 = 0;    // third tier above 64 * bpl2 (0 = none)
+    bool sweep = false;  // one dependency-ordered launch per sweep
+    int nslow = 0;       // its workspace staging slots for domains above 64 * bpl
+    int slow_cap = 0;    // beads per slot
 };
 
 }  // namespace
@@ -87,6 +95,7 @@ struct ecmc_ctx {
     Layout lay{};
     char *ws = nullptr;
     uint32_t sweep_ctr = 0;
+    uint32_t epoch = 0;               // stamp of the last dependency-ordered launch
     std::string err;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;
     template <class T>
@@ -122,6 +131,8 @@ ecmc_status geometry(double L, double sigma, double lmax, int64_t nb, const ecmc
     if (nb < 1 || nb > 0x7fffffffLL) return fail(c, ECMC_E_ARG, "bead count %lld out of range", (long long)nb);
     if (o.precision != ECMC_PREC_FP64 && o.precision != ECMC_PREC_MIXED)
         return fail(c, ECMC_E_ARG, "precision must be ECMC_PREC_FP64 or ECMC_PREC_MIXED (got %d)", o.precision);
+    if (o.schedule != ECMC_SCHED_SWEEP && o.schedule != ECMC_SCHED_PHASES)
+        return fail(c, ECMC_E_ARG, "schedule must be ECMC_SCHED_SWEEP or ECMC_SCHED_PHASES (got %d)", o.schedule);
     int n = o.n_cells;
     if (n == 0) {
         n = (int)std::floor(L / lmax);
@@ -176,6 +187,20 @@ ecmc_status geometry(double L, double sigma, double lmax, int64_t nb, const ecmc
         const int* nxt = std::find_if(std::begin(ok), std::end(ok), [&](int v) { return v > pick; });
         g.bpl2 = nxt == std::end(ok) ? 0 : *nxt;
         g.bpl3 = (g.bpl2 && g.bpl2 < 16) ? 16 : 0;
+    }
+    if (o.tiling == ECMC_TILING_CHECKER && o.schedule == ECMC_SCHED_SWEEP && sweep_bpl_supported(g.bpl)) {
+        g.sweep = true;
+        if (g.bpl2) {
+            // automatic capacity: the domains above the LDS staging area go to workspace slots
+            // that hold any frame up to the staging limit
+            const int cap = o.cell_capacity > 0 ? o.cell_capacity : DEFAULT_CAP;
+            const int64_t most = (int64_t)(g.D + 2) * (g.D + 2) * (g.D + 2) * cap;
+            if (most > 64 * g.bpl) {
+                const int64_t ndpc = (int64_t)(g.nd / 2) * (g.nd / 2) * (g.nd / 2);
+                g.slow_cap = (int)std::min<int64_t>(most, MAX_STAGE);
+                g.nslow = (int)std::min<int64_t>(ndpc, SLOW_SLOTS);
+            }
+        }
     }
     return ECMC_OK;
 }
@@ -311,6 +336,10 @@ ecmc_status upload(ecmc_ctx *c, const HostState &hs, bool topology) {
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.dsum, 0, 8, s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.err, 0, 4, s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.log_n, 0, 8, s));
+        const size_t nc8 = nc / 8 + 1;
+        HIP_OK(c, hipMemsetAsync(c->ws + c->lay.done, 0, 4 * nc8, s));
+        HIP_OK(c, hipMemsetAsync(c->ws + c->lay.queue, 0, 8, s));
+        if (c->g.nslow > 0) HIP_OK(c, hipMemsetAsync(c->ws + c->lay.slow_lock, 0, 4 * (size_t)c->g.nslow, s));
     }
     HIP_OK(c, hipStreamSynchronize(s));
     return ECMC_OK;
@@ -324,6 +353,7 @@ ecmc_status check_device(ecmc_ctx *c) {
     if (e & ERR_CELL) return fail(c, ECMC_E_CELL_OVERFLOW, "a cell exceeded its capacity %d", c->cap);
     if (e & ERR_STUCK) return fail(c, ECMC_E_STUCK, "an EC exceeded %lld iterations", (long long)c->opt.event_cap);
     if (e & ERR_RECOUNT) return fail(c, ECMC_E_DEVICE, "a domain's cell lists changed between its count and its staging");
+    if (e & ERR_WAIT) return fail(c, ECMC_E_DEVICE, "a wait of the dependency-ordered sweep ran out of polls");
     return ECMC_OK;
 }
 
@@ -345,7 +375,7 @@ ecmc_status ecmc_workspace_size(double box, double sigma, double l_max, int64_t 
     ecmc_status st = geometry(box, sigma, l_max, n_beads, *opt, g, nullptr);
     if (st) return st;
     const int cap = opt->cell_capacity > 0 ? opt->cell_capacity : DEFAULT_CAP;
-    *bytes = make_layout(n_beads, g.n, cap, opt->event_log_capacity).total;
+    *bytes = make_layout(n_beads, g.n, cap, opt->event_log_capacity, g.nslow, g.slow_cap).total;
     return ECMC_OK;
 }
 
@@ -372,7 +402,7 @@ ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, in
     };
     ecmc_status st = geometry(box, sigma, l_max, n_beads, *opt, c->g, c);
     if (st) return bail(st);
-    c->lay = make_layout(n_beads, c->g.n, c->cap, opt->event_log_capacity);
+    c->lay = make_layout(n_beads, c->g.n, c->cap, opt->event_log_capacity, c->g.nslow, c->g.slow_cap);
     if (!opt->workspace || opt->workspace_bytes < c->lay.total || ((uintptr_t)opt->workspace & 255))
         return bail(fail(c, ECMC_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)", c->lay.total,
                          opt->workspace_bytes));
@@ -426,6 +456,12 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     a.ccount = c->dev<int32_t>(c->lay.ccount);
     a.cids = c->dev<int32_t>(c->lay.cids);
     a.dstage = c->dev<int32_t>(c->lay.dstage);
+    a.done = c->dev<uint32_t>(c->lay.done);
+    a.queue = c->dev<uint32_t>(c->lay.queue);
+    a.slow = c->dev<double>(c->lay.slow);
+    a.slow_lock = c->dev<uint32_t>(c->lay.slow_lock);
+    a.nslow = c->g.nslow;
+    a.slow_cap = c->g.nslow > 0 ? c->g.slow_cap : 0;
     a.cnt = c->dev<unsigned long long>(c->lay.cnt);
     a.sum_delta = c->dev<double>(c->lay.dsum);
     a.err = c->dev<unsigned int>(c->lay.err);
@@ -525,10 +561,31 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
         philox4x32_10(ctr, a.key0, a.key1);
         for (int ax = 0; ax < 3; ++ax) a.off[ax] = (int)scale_u32(ctr[ax], (uint32_t)c->g.D);
         const int grid = (int)((nd / 2) * (nd / 2) * (nd / 2));
-        for (int colour = 0; colour < 8 && st == ECMC_OK && a.K > 0; ++colour) {
-            if (!((colour_mask >> colour) & 1u)) continue;
-            a.colour = colour;
-            st = launch(grid);
+        if (c->g.sweep && (colour_mask & 0xFFu) == 0xFFu) {
+            // all eight colours in one dependency-ordered launch
+            if (a.K > 0) {
+                if (++c->epoch == 0) ++c->epoch;
+                a.epoch = c->epoch;
+                a.ndpc = grid;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (c->opt.time_kernels) {
+                    HIP_OK(c, hipEventCreate(&e0));
+                    HIP_OK(c, hipEventCreate(&e1));
+                    HIP_OK(c, hipEventRecord(e0, c->stream));
+                }
+                int waves = 0;
+                HIP_OK(c, launch_sweep(a, c->g.bpl, log, &waves, c->stream));
+                if (c->opt.time_kernels) {
+                    HIP_OK(c, hipEventRecord(e1, c->stream));
+                    c->timing.emplace_back(e0, e1);
+                }
+            }
+        } else {
+            for (int colour = 0; colour < 8 && st == ECMC_OK && a.K > 0; ++colour) {
+                if (!((colour_mask >> colour) & 1u)) continue;
+                a.colour = colour;
+                st = launch(grid);
+            }
         }
     }
     c->sweep_ctr++;

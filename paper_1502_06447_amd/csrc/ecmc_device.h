@@ -1,0 +1,1122 @@
+// Device code of the event-chain (EC) move for tethered hard-sphere melts on gfx950
+// (Kampmann, Boltz, Kierfeld, arXiv:1502.06447, Sec. II and II.A), shared by the two
+// schedules of a sweep: one launch per colour phase (ecmc_kernels.hip) and one
+// dependency-ordered launch per sweep (ecmc_sweep.hip).
+//
+// One wavefront (64 lanes) owns one active domain at a time.  It stages the domain and its
+// one-cell halo from the cell lists: the staged beads are sorted by id and dealt out to the
+// lanes, BPL beads per lane, with single-precision screening copies of the positions in
+// VGPRs and the FP64 positions, cell words and tether partners in LDS.  Every event then
+// costs one pass over the lane's BPL beads (one candidate each: a hard-sphere contact, or
+// for a tethered partner of the pivot that is not hit, the tether limit), a wavefront
+// min-reduction through DPP, an FP64 evaluation of the few beads the screen cannot rule
+// out, and a uniform update of the pivot.  Nothing in the event loop touches HBM; the
+// domain ends by writing back its motile beads and rebuilding its cell lists.
+//
+// Floating point: binary64, round to nearest, no contraction (built with
+// -ffp-contract=off), correctly rounded sqrt; the operation order of every candidate
+// distance, face distance and position update is fixed so that results are reproducible
+// bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ecmc_internal.h"
+
+namespace ecmc {
+
+namespace {
+
+constexpr double INF = __builtin_huge_val();
+
+// ------------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ double rdlane(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int rdlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// DPP lane move within a row of 16 lanes (a full permutation: every lane has a source; the
+// lane's own value is the fallback a disabled source would give).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int l = __double2loint(v), u = __double2hiint(v);
+    const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(u, u, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+
+__device__ __forceinline__ unsigned umin_(unsigned a, unsigned b) { return b < a ? b : a; }
+
+// One step of a wavefront min-reduction of unsigned words: the lane's value against the one
+// the DPP control brings in; lanes outside row_mask, or with no source, keep their own (the
+// identity 0xFFFFFFFF stands in).  The compiler folds the move into v_min_u32_dpp.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned umin_dpp(unsigned v) {
+    return umin_(v, (unsigned)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)v, CTRL, ROWS, 0xF, false));
+}
+
+// Minimum over the wavefront, returned to every lane.  Within each row of 16 lanes a
+// butterfly (quad_perm 1032, quad_perm 2301, half-row mirror, row mirror), then row 1 takes
+// row 0 (row_bcast:15), row 3 takes row 2, and rows 2-3 take row 1 (row_bcast:31): lane 63
+// holds the minimum of all 64 lanes.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+    v = umin_dpp<0xB1, 0xF>(v);
+    v = umin_dpp<0x4E, 0xF>(v);
+    v = umin_dpp<0x141, 0xF>(v);
+    v = umin_dpp<0x140, 0xF>(v);
+    v = umin_dpp<0x142, 0xA>(v);
+    v = umin_dpp<0x143, 0xC>(v);
+    return (unsigned)rdlane((int)v, 63);
+}
+
+// two such reductions interleaved (they share the latency of the DPP steps)
+__device__ __forceinline__ void wave_min2_u32(unsigned &u, unsigned &v) {
+    u = umin_dpp<0xB1, 0xF>(u);
+    v = umin_dpp<0xB1, 0xF>(v);
+    u = umin_dpp<0x4E, 0xF>(u);
+    v = umin_dpp<0x4E, 0xF>(v);
+    u = umin_dpp<0x141, 0xF>(u);
+    v = umin_dpp<0x141, 0xF>(v);
+    u = umin_dpp<0x140, 0xF>(u);
+    v = umin_dpp<0x140, 0xF>(v);
+    u = umin_dpp<0x142, 0xA>(u);
+    v = umin_dpp<0x142, 0xA>(v);
+    u = umin_dpp<0x143, 0xC>(u);
+    v = umin_dpp<0x143, 0xC>(v);
+    u = (unsigned)rdlane((int)u, 63);
+    v = (unsigned)rdlane((int)v, 63);
+}
+
+// Minimum over the wavefront of a value that is >= 0 or +inf.  For such doubles the bit
+// patterns order like the numbers, so the high words are reduced first and then the low
+// words of the lanes that hold the smallest high word.
+__device__ __forceinline__ double wave_min_nonneg_f64(double v) {
+    const unsigned hi = (unsigned)__double2hiint(v), lo = (unsigned)__double2loint(v);
+    const unsigned mh = wave_min_u32(hi);
+    const unsigned ml = wave_min_u32(hi == mh ? lo : 0xFFFFFFFFu);
+    return __hiloint2double((int)mh, (int)ml);
+}
+
+// inclusive prefix sum over the wavefront (staging only)
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int mbcnt(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ int cell_of(int32_t m, int ax) { return (m >> (ax * CELL_BITS)) & CELL_MASK; }
+
+// cell faces: bnd(k) = k h for k < n, bnd(n) = L
+__device__ __forceinline__ double face(int k, int n, double h, double L) { return k < n ? (double)k * h : L; }
+
+// ------------------------------------------------------------------ event search
+// Every lane holds single-precision screening copies of its BPL staged beads, in the
+// domain frame (coordinates relative to the frame's lower corner, unwrapped across the
+// periodic boundary) rotated to the current axis of motion: A along the axis, B and C
+// the other two in cyclic order.  The exact FP64 positions, cell words and tether
+// partners of the staged beads live in LDS and are read only for the few beads the
+// screen cannot rule out.
+template <int NS, bool WHOLE>
+struct Lanes {
+    float A[NS], B[NS], C[NS];
+    int32_t META[WHOLE ? NS : 1];  // whole box: cell words for the periodic shift of the screen
+};
+
+// Register slots of the screening copies: the plain FP64 search (EXACT) screens nothing and
+// keeps a single unused slot.
+constexpr int lane_slots(int bpl, bool exact) { return exact ? 1 : bpl; }
+
+// the current pivot, uniform across the wavefront
+struct Pivot {
+    int P;            // staged index
+    int32_t meta;     // cell word
+    int32_t part;     // staged indices of the tethered partners (16 bits each, 0xFFFF = none)
+    double a, b, c;   // FP64 position in the rotated frame
+    float fa, fb, fc; // screening copy
+};
+
+// the staged data in LDS
+struct Stage {
+    double *pos;           // FP64 x, y, z: three rows of `stride` doubles
+    int stride;
+    int32_t *meta;
+    int32_t *part;
+    int32_t *id;
+    // address arithmetic rather than a select of three pointers, which the compiler turns
+    // into a pointer table in scratch memory
+    __device__ __forceinline__ double *axis(int ax) const { return pos + ax * stride; }
+};
+
+// Exact FP64 candidate of one staged bead: displacement from the pivot (periodic shift
+// from the cell-index difference, added after the subtraction), d_par and d_perp^2, then
+//   hard sphere, if d_par > 0 and d_perp^2 < sigma^2:  x = d_par - sqrt(sigma^2 - d_perp^2)
+//   tether, for a partner of the pivot that is not hit:  x = d_par + sqrt(max(b^2 - d_perp^2, 0))
+// (for a partner that is hit the contact always comes first: x_hs <= d_par <= x_tether),
+// clamped at 0.  Returns whether the bead is a candidate at all.
+template <bool WRAP>
+__device__ __forceinline__ bool exact_candidate(double A, double B, double C, int32_t meta, const Pivot &pv, int sha,
+                                                int shb, int shc, double sgnd, double sig2, double b2, double L,
+                                                bool partner, double &x, bool &hs) {
+    double da = A - pv.a;
+    double db = B - pv.b;
+    double dc = C - pv.c;
+    if (WRAP) {
+        const int ea = (int)((meta >> sha) & CELL_MASK) - (int)((pv.meta >> sha) & CELL_MASK);
+        const int eb = (int)((meta >> shb) & CELL_MASK) - (int)((pv.meta >> shb) & CELL_MASK);
+        const int ec = (int)((meta >> shc) & CELL_MASK) - (int)((pv.meta >> shc) & CELL_MASK);
+        da = da + (ea > 1 ? -L : (ea < -1 ? L : 0.0));
+        db = db + (eb > 1 ? -L : (eb < -1 ? L : 0.0));
+        dc = dc + (ec > 1 ? -L : (ec < -1 ? L : 0.0));
+    }
+    const double dpar = da * sgnd;
+    const double pb = db * db;
+    const double pc = dc * dc;
+    const double dperp2 = pb + pc;
+    hs = (dpar > 0.0) && (dperp2 < sig2);
+    double arg = (hs ? sig2 : b2) - dperp2;
+    if (!(arg > 0.0)) arg = 0.0;
+    const double sq = __builtin_sqrt(arg);
+    double v = hs ? dpar - sq : dpar + sq;
+    if (!(v > 0.0)) v = 0.0;
+    x = v;
+    return hs || partner;
+}
+
+// Single-precision screen constants (derived on the host, see ecmc_api.cpp).
+struct ScreenK {
+    float sig2f, b2f;    // sigma^2, b^2 in float
+    float in_lo, in_hi;  // float d_perp^2 below in_lo: surely inside sigma; not below in_hi: surely not
+    float p_sure;        // float d_par above it: surely ahead; d_par ahead implies float d_par > -p_sure
+    float err;           // bound on |x_float - x_exact| for every candidate
+    float Lf;
+};
+
+// The winner of the event search and the data the pivot needs if it is lifted to it.
+struct Hit {
+    double x;
+    unsigned key;       // staged index * 2 + kind (0 hard sphere, 1 tether)
+    double a, b, c;     // FP64 position of the struck bead (rotated frame)
+    int32_t meta, part;
+};
+
+// The single-precision screen of one event search.  For every staged bead the lane holding
+// it computes a float estimate of the bead's x and an interval [lo, hi] that provably holds
+// the exact x of each bead that is a candidate at all (lo = +inf for beads that cannot be).
+// t = min hi and l = min lo over the wavefront: the exact interaction distance x_int lies in
+// [l, t] whenever a candidate exists (x_int = +inf, l = t = +inf otherwise).
+template <int BPL>
+struct Screen {
+    float lo[BPL];
+    float t, l;
+};
+
+template <int BPL, bool WHOLE>
+__device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> &R, const Pivot &pv, int sha, int shb,
+                                       int shc, double sgnd, const ScreenK &K) {
+    const int lane = lane_id();
+    const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
+    const float sgnf = sgnd > 0.0 ? 1.0f : -1.0f;
+    // minima of hi and lo as bit patterns: both are >= 0 (or +inf), where the unsigned order of
+    // the patterns is the order of the numbers
+    constexpr unsigned INFB = 0x7F800000u;
+    unsigned hmin = INFB, lmin = INFB;
+#pragma unroll
+    for (int k = 0; k < BPL; ++k) {
+        const int idx = k * 64 + lane;
+        const bool me = idx == pv.P;
+        const bool partner = (idx == q0) || (idx == q1);
+        float da = R.A[k] - pv.fa;
+        float db = R.B[k] - pv.fb;
+        float dc = R.C[k] - pv.fc;
+        if (WHOLE) {
+            const int ea = (int)((R.META[k] >> sha) & CELL_MASK) - (int)((pv.meta >> sha) & CELL_MASK);
+            const int eb = (int)((R.META[k] >> shb) & CELL_MASK) - (int)((pv.meta >> shb) & CELL_MASK);
+            const int ec = (int)((R.META[k] >> shc) & CELL_MASK) - (int)((pv.meta >> shc) & CELL_MASK);
+            da = da + (ea > 1 ? -K.Lf : (ea < -1 ? K.Lf : 0.0f));
+            db = db + (eb > 1 ? -K.Lf : (eb < -1 ? K.Lf : 0.0f));
+            dc = dc + (ec > 1 ? -K.Lf : (ec < -1 ? K.Lf : 0.0f));
+        }
+        const float p = da * sgnf;
+        const float q = db * db + dc * dc;
+        const bool hs_sure = (p > K.p_sure) && (q < K.in_lo);
+        const bool hs_maybe = (p > -K.p_sure) && (q < K.in_hi);
+        // the estimate follows the hard-sphere formula whenever a contact is possible; a
+        // partner that may or may not be hit gets the interval spanning both formulas
+        const float cc = hs_maybe ? K.sig2f : K.b2f;
+        const float sr = __builtin_amdgcn_sqrtf(fmaxf(cc - q, 0.0f));
+        const float est = fmaxf(hs_maybe ? p - sr : p + sr, 0.0f);
+        float l = est - K.err, hg = est + K.err;
+        const bool amb = partner && hs_maybe && !hs_sure;
+        if (__builtin_expect(__ballot(amb) != 0, 0)) {
+            if (amb) {
+                const float st2 = __builtin_amdgcn_sqrtf(fmaxf(K.b2f - q, 0.0f));
+                const float et = fmaxf(p + st2, 0.0f);
+                l = fminf(l, et - K.err);
+                hg = fmaxf(hg, et + K.err);
+            }
+        }
+        const bool cand = !me && (hs_maybe || partner);
+        // the exact x is >= 0, so lo is clamped there: still a lower bound, and the
+        // membership test lo <= t (t >= 0) is unchanged
+        sc.lo[k] = cand ? fmaxf(l, 0.0f) : __builtin_huge_valf();
+        hmin = umin_(hmin, cand ? __float_as_uint(hg) : INFB);
+        lmin = umin_(lmin, __float_as_uint(sc.lo[k]));
+    }
+    wave_min2_u32(hmin, lmin);
+    sc.t = __uint_as_float(hmin);
+    sc.l = __uint_as_float(lmin);
+}
+
+// Exact first interaction event after the screen: the minimum over all staged beads of
+// (x, staged index, kind), evaluated in FP64 from LDS only for the beads whose interval
+// starts at or below the threshold t (normally one bead).  Their exact minimum x* is
+// certified when x* <= t; otherwise t is raised to x* and the step repeats.  A bead left
+// out has exact x >= lo > t >= x*, so the result is exact.  When a single bead passes,
+// it is evaluated on its own lane and broadcast without a wavefront reduction.
+//
+// Every branch below depends on wavefront-uniform values only (ballots, readlanes and
+// readfirstlane'd flags), so the wavefront never splits: the DPP reductions need all lanes.
+struct Best {
+    double x, A, B, C;
+    unsigned key;
+    int32_t meta, part;
+};
+
+// evaluate in FP64 the beads of this lane that are members (lo <= thr, not yet done).  The
+// first pass has thr = t, a float: lo <= t is then compared in single precision, which is
+// the same comparison.
+template <int BPL, bool FIRST>
+__device__ __forceinline__ void search_pass(const Screen<BPL> &sc, double thr, unsigned &done, Best &b,
+                                            const Stage &st, const Pivot &pv, const double *pA, const double *pB,
+                                            const double *pC, int q0, int q1, int sha, int shb, int shc,
+                                            double sgnd, double sig2, double b2, double L, bool wr) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < BPL; ++k) {
+        const bool mem = FIRST ? sc.lo[k] <= sc.t
+                               : !((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr;
+        if (__ballot(mem)) {
+            if (mem) {
+                const int idx = k * 64 + lane;
+                const double A = pA[idx], B = pB[idx], C = pC[idx];
+                const int32_t m = st.meta[idx];
+                const bool partner = (idx == q0) || (idx == q1);
+                double x;
+                bool hs;
+                const bool ok = (idx != pv.P) &&
+                                (wr ? exact_candidate<true>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner,
+                                                            x, hs)
+                                    : exact_candidate<false>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
+                                                             partner, x, hs));
+                const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
+                if (ok && (x < b.x || (x == b.x && kk < b.key))) {
+                    b.x = x;
+                    b.key = kk;
+                    b.A = A;
+                    b.B = B;
+                    b.C = C;
+                    b.meta = m;
+                    b.part = st.part[idx];
+                }
+            }
+        }
+        if (mem) done |= 1u << k;
+    }
+}
+
+__device__ __forceinline__ void take(Hit &h, const Best &b, int wl) {
+    h.x = rdlane(b.x, wl);
+    h.key = (unsigned)rdlane((int)b.key, wl);
+    h.a = rdlane(b.A, wl);
+    h.b = rdlane(b.B, wl);
+    h.c = rdlane(b.C, wl);
+    h.meta = rdlane((int)b.meta, wl);
+    h.part = rdlane((int)b.part, wl);
+}
+
+template <int BPL>
+__device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, const Pivot &pv, int ax, int sha,
+                                      int shb, int shc, double sgnd, double sig2, double b2, double L, bool wr) {
+    const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
+    const double *pA = st.axis(ax);
+    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
+    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
+    Hit h;
+    h.x = INF;
+    h.key = 0xFFFFFFFFu;
+    h.a = h.b = h.c = 0.0;
+    h.meta = 0;
+    h.part = -1;
+    if (!(sc.l < __builtin_huge_valf())) return h;
+    double thr = (double)sc.t;
+    Best b = {INF, 0.0, 0.0, 0.0, 0xFFFFFFFFu, 0, -1};
+    unsigned done = 0;
+    int nmem = 0;
+#pragma unroll
+    for (int k = 0; k < BPL; ++k) nmem += __popcll(__ballot(sc.lo[k] <= sc.t));
+    search_pass<BPL, true>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
+    if (nmem == 1) {
+        // one bead passed the screen: it set the threshold (its own hi is t), so when it is
+        // a candidate its exact x <= t is the certified minimum
+        const unsigned long long own = __ballot(b.x < INF);
+        if (own) {
+            const int wl = (int)(__ffsll((long long)own) - 1);
+            const double x1 = rdlane(b.x, wl);
+            if (__builtin_amdgcn_readfirstlane((int)(x1 <= thr))) {
+                take(h, b, wl);
+                return h;
+            }
+        }
+    }
+    double xs = wave_min_nonneg_f64(b.x);
+    while (!__builtin_amdgcn_readfirstlane((int)(xs <= thr))) {
+        // the threshold came from a screened bead that is no candidate after all: widen
+        thr = xs;
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < BPL; ++k)
+            more = more || (!((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr);
+        if (!__ballot(more)) break;
+        search_pass<BPL, false>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
+        xs = wave_min_nonneg_f64(b.x);
+    }
+    if (!(xs < INF)) return h;
+    const unsigned long long tie = __ballot(b.x == xs);
+    int wl;
+    if (__popcll(tie) == 1) {
+        wl = (int)(__ffsll((long long)tie) - 1);
+    } else {
+        const unsigned key = wave_min_u32(b.x == xs ? b.key : 0xFFFFFFFFu);
+        wl = (int)((key >> 1) & 63u);
+    }
+    take(h, b, wl);
+    return h;
+}
+
+// The plain FP64 search: every staged bead other than the pivot evaluated exactly, lane by
+// lane in chunks of 64 staged indices, then the wavefront minimum by (x, staged index, kind).
+// A loop over the staging area rather than over register slots, so that its register needs
+// do not grow with the staging capacity.
+__device__ __forceinline__ Hit search_all(const Stage &st, const Pivot &pv, int S, int ax, int sha, int shb, int shc,
+                                          double sgnd, double sig2, double b2, double L, bool wr) {
+    const int lane = lane_id();
+    const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
+    const double *pA = st.axis(ax);
+    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
+    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
+    Best b = {INF, 0.0, 0.0, 0.0, 0xFFFFFFFFu, 0, -1};
+    for (int base = 0; base < S; base += 64) {
+        const int idx = base + lane;
+        if (idx < S && idx != pv.P) {
+            const double A = pA[idx], B = pB[idx], C = pC[idx];
+            const int32_t m = st.meta[idx];
+            const bool partner = (idx == q0) || (idx == q1);
+            double x;
+            bool hs;
+            const bool ok =
+                wr ? exact_candidate<true>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x, hs)
+                   : exact_candidate<false>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x, hs);
+            // a lane's indices increase, so on equal x the earlier bead keeps its place
+            const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
+            if (ok && (x < b.x || (x == b.x && kk < b.key))) {
+                b.x = x;
+                b.key = kk;
+                b.A = A;
+                b.B = B;
+                b.C = C;
+                b.meta = m;
+                b.part = st.part[idx];
+            }
+        }
+    }
+    Hit h;
+    h.x = INF;
+    h.key = 0xFFFFFFFFu;
+    h.a = h.b = h.c = 0.0;
+    h.meta = 0;
+    h.part = -1;
+    const double xs = wave_min_nonneg_f64(b.x);
+    if (!(xs < INF)) return h;
+    const unsigned long long tie = __ballot(b.x == xs);
+    int wl;
+    if (__popcll(tie) == 1) {
+        wl = (int)(__ffsll((long long)tie) - 1);
+    } else {
+        const unsigned key = wave_min_u32(b.x == xs ? b.key : 0xFFFFFFFFu);
+        wl = (int)((key >> 1) & 63u);
+    }
+    take(h, b, wl);
+    return h;
+}
+
+// Select element `slot` (uniform) of a lane's register array.  Written as a masked OR so
+// that the compiler cannot turn it into an indexed load, which would move the array out
+// of VGPRs into scratch memory.
+template <int BPL>
+__device__ __forceinline__ float pick(const float (&V)[BPL], int slot) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < BPL; ++k) acc |= (uint32_t)__float_as_int(V[k]) & (0u - (uint32_t)(slot == k));
+    return __int_as_float((int)acc);
+}
+
+template <int BPL>
+__device__ __forceinline__ void put(float (&V)[BPL], int slot, int owner, float v) {
+    const bool me = lane_id() == owner;
+#pragma unroll
+    for (int k = 0; k < BPL; ++k)
+        if (slot == k && me) V[k] = v;
+}
+
+template <int BPL>
+__device__ __forceinline__ void put(int32_t (&V)[BPL], int slot, int owner, int32_t v) {
+    const bool me = lane_id() == owner;
+#pragma unroll
+    for (int k = 0; k < BPL; ++k)
+        if (slot == k && me) V[k] = v;
+}
+
+__device__ __forceinline__ float fblend(uint32_t m, float x, float y) {
+    return __int_as_float((int)(((uint32_t)__float_as_int(x) & m) | ((uint32_t)__float_as_int(y) & ~m)));
+}
+
+// cyclic change of the frame: (A, B, C) = (r[ax], r[ax+1], r[ax+2]) for the new axis.
+// A bitwise blend rather than two branches, so that the arrays stay in VGPRs.
+template <int BPL, bool WHOLE>
+__device__ __forceinline__ void rotate(Lanes<BPL, WHOLE> &R, int from, int to) {
+    const int r = (to - from + 3) % 3;
+    if (r == 0) return;
+    const uint32_t m = 0u - (uint32_t)(r == 1);
+#pragma unroll
+    for (int k = 0; k < BPL; ++k) {
+        const float a = R.A[k], b = R.B[k], c = R.C[k];
+        R.A[k] = fblend(m, b, c);
+        R.B[k] = fblend(m, c, a);
+        R.C[k] = fblend(m, a, b);
+    }
+}
+
+// Per-wave event counters: lane C_* of one VGPR holds counter C_* (32 bits suffice for
+// one phase of one domain), so that they do not occupy scalar registers.
+struct Tally {
+    uint32_t v;
+    double dsum;
+    __device__ __forceinline__ void inc(int which) { v += (lane_id() == which) ? 1u : 0u; }
+};
+
+struct Frame {
+    int ds[3];      // first cell of the domain per axis
+    int fs[3];      // first cell of the frame (domain plus halo) per axis
+    double O[3];    // lower corner of the frame (screening origin)
+    int S;          // staged beads
+    int dom[3];     // domain coordinates in the domain grid
+    int colour;
+    uint32_t domain;
+};
+
+// screening coordinate of a bead at r in cell c along an axis with frame start fs, origin O
+__device__ __forceinline__ float frame_u(double r, int c, int fs, double L, double O) {
+    const double w = c < fs ? r + L : r;
+    return (float)(w - O);
+}
+
+__device__ __forceinline__ void log_event(const PhaseArgs &a, const Frame &f, long long k, long long step, int p,
+                                          int t, int kind) {
+    if (lane_id() == 0) {
+        const unsigned long long s = atomicAdd(a.log_n, 1ull);
+        if ((long long)s < a.log_cap)
+            a.log[s] = ecmc_event{a.sweep, f.domain, (uint32_t)k, (uint32_t)step, p, t, (uint32_t)kind,
+                                  (uint32_t)f.colour};
+        else
+            atomicOr(a.err, ERR_LOG);
+    }
+}
+
+// A reflection after an earlier one in the same EC.  Between two reflections every move is
+// reversible (a lift is undone by the reverse lift, a stop sends the pivot back), so after
+// the second one the EC runs back to the first and then repeats: whatever is left of x_max
+// only matters modulo twice the length W used between them.  Whole periods are dropped
+// (logged PERIOD); W == 0 means nothing can move and ends the EC (CYCLE, returns true).
+template <bool LOG>
+__device__ __forceinline__ bool repeat_reflection(const PhaseArgs &a, const Frame &f, long long k, long long step,
+                                                  int id, double xref, double &xmax, Tally &t) {
+    const double w = xref - xmax;
+    if (!__builtin_amdgcn_readfirstlane((int)(w > 0.0))) {
+        t.inc(C_CYCLE);
+        if (LOG) log_event(a, f, k, step, id, -1, ECMC_EV_CYCLE);
+        return true;
+    }
+    const double r = fmod(xmax, w + w);
+    if (__builtin_amdgcn_readfirstlane((int)(r < xmax))) {
+        xmax = r;
+        t.inc(C_PERIOD);
+        if (LOG) log_event(a, f, k, step, id, -1, ECMC_EV_PERIOD);
+    }
+    return false;
+}
+
+// ------------------------------------------------------------------ swap move (Sec. II.C)
+__device__ __forceinline__ double min_image(double d, double L, double hL) { return d > hL ? d - L : (d < -hL ? d + L : d); }
+
+// Squared minimum-image distance from u to v, both given in the frame rotated to axis ax
+// (components along ax, ax+1, ax+2), summed over x, y, z in that order.
+__device__ __forceinline__ double dist2_rot(int ax, double ua, double ub, double uc, double va, double vb, double vc,
+                                            double L, double hL) {
+    const double da = min_image(ua - va, L, hL), db = min_image(ub - vb, L, hL), dc = min_image(uc - vc, L, hL);
+    const double qa = da * da, qb = db * db, qc = dc * dc;
+    return ax == 0 ? (qa + qb) + qc : (ax == 1 ? (qc + qa) + qb : (qb + qc) + qa);
+}
+
+// The exchange of pivot p (now at its contact point) and the struck bead j is accepted when
+// every tether of p (measured from j's place) and of j (from p's place) is within b_max: the
+// Metropolis acceptance of a tethered chain, whose energy is 0 or infinite.  Partners are
+// staged indices (0xFFFF: none); the pivot's own LDS entry is stale during an EC, so a
+// partner that is the other bead of the pair is measured at its new place.
+__device__ __forceinline__ bool swap_allowed(const Stage &st, const Pivot &pv, const Hit &hit, int J, int ax,
+                                             double L, double hL, double b2) {
+    const double *pA = st.axis(ax);
+    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
+    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
+    bool ok = true;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int q = (pv.part >> (16 * t)) & 0xFFFF;  // p moves to j's place
+        if (q != 0xFFFF) {
+            const bool qj = q == J;
+            const double va = qj ? pv.a : pA[q], vb = qj ? pv.b : pB[q], vc = qj ? pv.c : pC[q];
+            ok = ok && !(dist2_rot(ax, hit.a, hit.b, hit.c, va, vb, vc, L, hL) > b2);
+        }
+        const int u = (hit.part >> (16 * t)) & 0xFFFF;  // j moves to p's place
+        if (u != 0xFFFF) {
+            const bool up = u == pv.P;
+            const double va = up ? hit.a : pA[u], vb = up ? hit.b : pB[u], vc = up ? hit.c : pC[u];
+            ok = ok && !(dist2_rot(ax, pv.a, pv.b, pv.c, va, vb, vc, L, hL) > b2);
+        }
+    }
+    return __builtin_amdgcn_readfirstlane((int)ok) != 0;
+}
+
+// Write the pivot's position along the axis and its cell word back to LDS, and its
+// screening coordinate to the owner lane.
+template <int BPL, bool WHOLE>
+__device__ __forceinline__ void store_pivot(const Pivot &pv, const Stage &st, double *pA, Lanes<BPL, WHOLE> &R) {
+    if (lane_id() == 0) {
+        pA[pv.P] = pv.a;
+        st.meta[pv.P] = pv.meta;
+    }
+    put(R.A, pv.P >> 6, pv.P & 63, pv.fa);
+    if (WHOLE) put(R.META, pv.P >> 6, pv.P & 63, pv.meta);
+}
+
+// One EC along axis ax (the lanes' frame is already rotated to it), direction sign sgn,
+// from staged pivot P0, x_max = ell.  Returns false if the iteration cap was hit.
+template <int BPL, bool LOG, bool EXACT, bool WHOLE>
+__device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const Stage &st,
+                                       Lanes<lane_slots(BPL, EXACT), WHOLE> &R,
+                                       int P0, int ax, int sgn, bool wr, long long k, const ScreenK &K, Tally &t) {
+    const int n = a.n;
+    const double L = a.L, h = a.h;
+    const int axb = ax == 2 ? 0 : ax + 1, axc = ax == 0 ? 2 : ax - 1;
+    const int sha = ax * CELL_BITS, shb = axb * CELL_BITS, shc = axc * CELL_BITS;
+    const int dsa = f.ds[0] * (ax == 0) + f.ds[1] * (ax == 1) + f.ds[2] * (ax == 2);
+    const int fsa = f.fs[0] * (ax == 0) + f.fs[1] * (ax == 1) + f.fs[2] * (ax == 2);
+    const double Oa = f.O[0] * (ax == 0) + f.O[1] * (ax == 1) + f.O[2] * (ax == 2);
+    double *pA = st.axis(ax);
+    Pivot pv;
+    pv.P = P0;
+    pv.a = pA[P0];
+    pv.b = st.axis(axb)[P0];
+    pv.c = st.axis(axc)[P0];
+    pv.meta = __builtin_amdgcn_readfirstlane(st.meta[P0]);
+    pv.part = __builtin_amdgcn_readfirstlane(st.part[P0]);
+    pv.fa = __int_as_float(rdlane(__float_as_int(pick(R.A, P0 >> 6)), P0 & 63));
+    pv.fb = __int_as_float(rdlane(__float_as_int(pick(R.B, P0 >> 6)), P0 & 63));
+    pv.fc = __int_as_float(rdlane(__float_as_int(pick(R.C, P0 >> 6)), P0 & 63));
+    double xmax = a.ell;
+    long long step = 0;
+    bool reflected = false;  // a reflection happened in this EC ...
+    double xref = 0.0;       // ... with this much displacement left after it
+    unsigned run = 0;      // consecutive zero-length events
+    int saved_p = -1, saved_sgn = 0, saved_c = -1;
+    t.inc(C_EC);
+    for (;;) {
+        if (run > 0) {
+            // zero-length run: the state (pivot, direction, pivot cell) repeating is a cycle
+            const int cc = (pv.meta >> sha) & CELL_MASK;
+            if (pv.P == saved_p && sgn == saved_sgn && cc == saved_c) {
+                store_pivot(pv, st, pA, R);
+                t.inc(C_CYCLE);
+                if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_CYCLE);
+                return true;
+            }
+            if ((run & (run - 1)) == 0) {
+                saved_p = pv.P;
+                saved_sgn = sgn;
+                saved_c = cc;
+            }
+        }
+        if (step >= a.event_cap) {
+            store_pivot(pv, st, pA, R);
+            return false;
+        }
+        ++step;
+        t.inc(C_STEPS);
+        const double sgnd = sgn > 0 ? 1.0 : -1.0;
+        const int c = (pv.meta >> sha) & CELL_MASK;
+        const double r_old = pv.a;
+        double xc = sgn > 0 ? face(c + 1, n, h, L) - r_old : r_old - face(c, n, h, L);
+        if (!(xc > 0.0)) xc = 0.0;
+        Hit hit;
+        if constexpr (EXACT) {
+            hit = search_all(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr);
+        } else {
+            Screen<BPL> sc;
+            screen<BPL, WHOLE>(sc, R, pv, sha, shb, shc, sgnd, K);
+            // the exact interaction distance is at least sc.l: when the end of the EC or the
+            // cell face comes strictly first (end: at or before), no exact search is needed
+            const double lbound = (double)sc.l;
+            const bool skip =
+                __builtin_amdgcn_readfirstlane((int)((xmax <= xc && xmax <= lbound) || xc < lbound)) != 0;
+            if (skip) {
+                hit.x = INF;
+                hit.key = 0xFFFFFFFFu;
+                hit.a = hit.b = hit.c = 0.0;
+                hit.meta = 0;
+                hit.part = -1;
+            } else {
+                hit = search<BPL>(sc, st, pv, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr);
+            }
+        }
+        const double xint = hit.x;
+        const double mlim = xint < xc ? xint : xc;
+        // the event (0 end, 1 interaction, 2 cell face) as a wavefront-uniform value: the
+        // FP64 values compared are the same in every lane, and a uniform branch keeps the
+        // whole step in scalar control flow
+        const int ev = __builtin_amdgcn_readfirstlane(xmax <= mlim ? 0 : (xint <= xc ? 1 : 2));
+        if (ev == 0) {
+            // END: the pivot takes the rest of the displacement
+            pv.a = sgn > 0 ? r_old + xmax : r_old - xmax;
+            pv.fa = frame_u(pv.a, c, fsa, L, Oa);
+            store_pivot(pv, st, pA, R);
+            if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_END);
+            return true;
+        }
+        if (ev == 1) {
+            // interaction event: move to contact / tether limit
+            if (__builtin_amdgcn_readfirstlane((int)(xint > 0.0))) {
+                run = 0;
+                saved_p = -1;
+            } else {
+                ++run;
+            }
+            pv.a = sgn > 0 ? r_old + xint : r_old - xint;
+            pv.fa = frame_u(pv.a, c, fsa, L, Oa);
+            xmax = xmax - xint;
+            const int j = (int)(hit.key >> 1);
+            const int kind = (int)(hit.key & 1u);
+            if (hit.meta & MOTILE_BIT) {
+                // lift: the struck bead continues the chain; accumulate (d_par - x)
+                double da = hit.a - r_old;
+                if (wr) {
+                    const int e = (int)((hit.meta >> sha) & CELL_MASK) - c;
+                    da = da + (e > 1 ? -L : (e < -1 ? L : 0.0));
+                }
+                const double dpar = da * sgnd;
+                t.dsum += dpar - xint;
+                if (a.swap && kind == 0 && swap_allowed(st, pv, hit, j, ax, L, a.halfL, a.b2)) {
+                    // swap (Sec. II.C): p and j exchange places, p goes on from j's; p's
+                    // identity advanced by d_par > 0, so a zero-length run is over
+                    t.inc(C_SWAP);
+                    if (LOG) log_event(a, f, k, step, st.id[pv.P], st.id[j], ECMC_EV_SWAP);
+                    const float ja = __int_as_float(rdlane(__float_as_int(pick(R.A, j >> 6)), j & 63));
+                    const float jb = __int_as_float(rdlane(__float_as_int(pick(R.B, j >> 6)), j & 63));
+                    const float jc = __int_as_float(rdlane(__float_as_int(pick(R.C, j >> 6)), j & 63));
+                    double *pB = st.axis(axb), *pC = st.axis(axc);
+                    if (lane_id() == 0) {
+                        // image counters: p moves by the minimum-image vector to j, j back
+                        const int ip = st.id[pv.P], ij = st.id[j];
+                        const double ra[3] = {hit.a - pv.a, hit.b - pv.b, hit.c - pv.c};
+                        const int gx[3] = {ax, axb, axc};
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const int sh = ra[q] > a.halfL ? -1 : (ra[q] < -a.halfL ? 1 : 0);
+                            if (sh) {
+                                a.img[3 * ip + gx[q]] += sh;
+                                a.img[3 * ij + gx[q]] -= sh;
+                            }
+                        }
+                        pA[j] = pv.a;
+                        pB[j] = pv.b;
+                        pC[j] = pv.c;
+                        st.meta[j] = pv.meta;
+                        pA[pv.P] = hit.a;
+                        pB[pv.P] = hit.b;
+                        pC[pv.P] = hit.c;
+                        st.meta[pv.P] = hit.meta;
+                    }
+                    put(R.A, j >> 6, j & 63, pv.fa);
+                    put(R.B, j >> 6, j & 63, pv.fb);
+                    put(R.C, j >> 6, j & 63, pv.fc);
+                    put(R.A, pv.P >> 6, pv.P & 63, ja);
+                    put(R.B, pv.P >> 6, pv.P & 63, jb);
+                    put(R.C, pv.P >> 6, pv.P & 63, jc);
+                    if (WHOLE) {
+                        put(R.META, j >> 6, j & 63, pv.meta);
+                        put(R.META, pv.P >> 6, pv.P & 63, hit.meta);
+                    }
+                    pv.a = hit.a;
+                    pv.b = hit.b;
+                    pv.c = hit.c;
+                    pv.meta = hit.meta;
+                    pv.fa = ja;
+                    pv.fb = jb;
+                    pv.fc = jc;
+                    run = 0;
+                    saved_p = -1;
+                    continue;
+                }
+                t.inc(kind == 0 ? C_HS_LIFT : C_TETHER_LIFT);
+                if (LOG) log_event(a, f, k, step, st.id[pv.P], st.id[j], kind == 0 ? ECMC_EV_HS_LIFT : ECMC_EV_TETHER_LIFT);
+                store_pivot(pv, st, pA, R);
+                pv.P = j;
+                pv.a = hit.a;
+                pv.b = hit.b;
+                pv.c = hit.c;
+                pv.meta = hit.meta;
+                pv.part = hit.part;
+                pv.fa = __int_as_float(rdlane(__float_as_int(pick(R.A, j >> 6)), j & 63));
+                pv.fb = __int_as_float(rdlane(__float_as_int(pick(R.B, j >> 6)), j & 63));
+                pv.fc = __int_as_float(rdlane(__float_as_int(pick(R.C, j >> 6)), j & 63));
+            } else {
+                t.inc(kind == 0 ? C_HS_REFLECT : C_TETHER_REFLECT);
+                if (LOG)
+                    log_event(a, f, k, step, st.id[pv.P], st.id[j], kind == 0 ? ECMC_EV_HS_REFLECT : ECMC_EV_TETHER_REFLECT);
+                if (reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+                    store_pivot(pv, st, pA, R);
+                    return true;
+                }
+                reflected = true;
+                xref = xmax;
+                sgn = -sgn;
+            }
+            continue;
+        }
+        // cell-face event: the pivot is set onto the face
+        if (__builtin_amdgcn_readfirstlane((int)(xc > 0.0))) {
+            run = 0;
+            saved_p = -1;
+        } else {
+            ++run;
+        }
+        pv.a = sgn > 0 ? face(c + 1, n, h, L) : face(c, n, h, L);
+        xmax = xmax - xc;
+        int nc = c + sgn;
+        int wrapped = 0;
+        if (nc >= n) {
+            nc = 0;
+            wrapped = 1;
+        } else if (nc < 0) {
+            nc = n - 1;
+            wrapped = -1;
+        }
+        const bool inside = a.whole || ((nc - dsa + n) % n) < a.D;
+        if (inside) {
+            pv.meta = (pv.meta & ~(CELL_MASK << sha)) | (nc << sha);
+            if (wrapped > 0) {
+                pv.a = 0.0;
+                if (lane_id() == 0) a.img[3 * st.id[pv.P] + ax] += 1;
+            } else if (wrapped < 0) {
+                pv.a = L;
+                if (lane_id() == 0) a.img[3 * st.id[pv.P] + ax] -= 1;
+            }
+            pv.fa = frame_u(pv.a, nc, fsa, L, Oa);
+            t.inc(C_CROSS);
+        } else {
+            pv.fa = frame_u(pv.a, c, fsa, L, Oa);
+            t.inc(C_WALL);
+            if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_WALL);
+            if (reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+                store_pivot(pv, st, pA, R);
+                return true;
+            }
+            reflected = true;
+            xref = xmax;
+            sgn = -sgn;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ domain frames
+// Domain b of a colour: its first cell per axis (ds), the frame of domain plus one-cell halo
+// (fs, origin O, edge F cells), and whether that frame wraps the box.  The colour of a
+// domain is the parity of its grid coordinates, (d_x & 1) | (d_y & 1) << 1 | (d_z & 1) << 2.
+template <bool WHOLE>
+__device__ __forceinline__ void frame_of(const PhaseArgs &a, int colour, int b, Frame &f, int &F, bool &wraps) {
+    const int n = a.n;
+    int *dom = f.dom;
+    dom[0] = dom[1] = dom[2] = 0;
+    f.domain = 0;
+    f.colour = colour;
+    if (!WHOLE) {
+        const int nd2 = a.nd >> 1;
+        dom[0] = 2 * (b % nd2) + (colour & 1);
+        dom[1] = 2 * ((b / nd2) % nd2) + ((colour >> 1) & 1);
+        dom[2] = 2 * (b / (nd2 * nd2)) + ((colour >> 2) & 1);
+        f.domain = (uint32_t)(dom[0] + a.nd * (dom[1] + a.nd * dom[2]));
+    }
+    F = WHOLE ? n : a.D + 2;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        f.ds[ax] = WHOLE ? 0 : (a.off[ax] + dom[ax] * a.D) % n;
+        f.fs[ax] = WHOLE ? 0 : (f.ds[ax] - 1 + n) % n;
+        f.O[ax] = WHOLE ? 0.0 : face(f.fs[ax], n, a.h, a.L);
+    }
+    wraps = WHOLE || f.fs[0] + F > n || f.fs[1] + F > n || f.fs[2] + F > n;
+}
+
+// Occupancy the register allocation of the phase kernel aims at (waves per SIMD), for the
+// staging tiers of up to 3 beads per lane (the tier that carries almost every domain of a
+// dense melt): 5 waves (96 VGPRs) measured faster than the 4 the compiler picks by itself.
+// A build-time tuning knob; 0 leaves the choice to the compiler.
+#ifndef ECMC_PHASE_WAVES_PER_EU
+#define ECMC_PHASE_WAVES_PER_EU 5
+#endif
+constexpr int phase_waves(int bpl) { return (ECMC_PHASE_WAVES_PER_EU > 0 && bpl <= 3) ? ECMC_PHASE_WAVES_PER_EU : 1; }
+
+// Beads in the frame (domain plus halo) of a domain: the sum of its F^3 cell counts.
+__device__ __forceinline__ int frame_count(const PhaseArgs &a, const Frame &f, int F) {
+    const int n = a.n, lane = lane_id();
+    const int nfc = F * F * F;
+    int S = 0;
+    for (int base = 0; base < nfc; base += 64) {
+        const int c = base + lane;
+        int cnt = 0;
+        if (c < nfc) {
+            const int fx = c % F, fy = (c / F) % F, fz = c / (F * F);
+            cnt = a.ccount[(f.fs[0] + fx) % n + n * ((f.fs[1] + fy) % n + n * ((f.fs[2] + fz) % n))];
+        }
+        S += rdlane(wave_incl_scan(cnt), 63);
+    }
+    return __builtin_amdgcn_readfirstlane(S);
+}
+
+// Where a domain is staged: LDS arrays of the kernel, or a slot of the device workspace
+// for a domain above the LDS capacity.  `cap` is the row length of every array.
+struct StageMem {
+    double *pos;     // three rows of cap doubles; row 2 first holds the unsorted staging lists
+    int32_t *id;     // staged bead ids, ascending
+    int32_t *meta;   // cell words (+ motile bit)
+    int32_t *part;   // tethered partners as staged indices; then the write-back counters
+    int32_t *mot;    // motile staged indices, ascending
+    int cap;
+};
+
+// One domain from its cell lists to the written-back result: stage its S0 beads (the count
+// the caller took, S0 <= min(cap, 64 BPL)), run its K ECs, write back the motile beads and
+// the domain's cell lists, flush the counters.
+template <int BPL, bool LOG, bool EXACT, bool WHOLE>
+__device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F, bool wraps, int S0,
+                                            const StageMem &m) {
+    constexpr int NS = lane_slots(BPL, EXACT);
+    // the loops over a lane's staged beads are unrolled where they fill register slots
+    constexpr int UNR = EXACT ? 1 : BPL;
+    const int lane = lane_id();
+    const int n = a.n;
+    const double L = a.L;
+    const int SM = m.cap;
+    int32_t *t_id = reinterpret_cast<int32_t *>(m.pos + 2 * SM);
+    int32_t *t_meta = t_id + SM;
+    double *const P0r = m.pos, *const P1r = m.pos + SM, *const P2r = m.pos + 2 * SM;
+
+    // ---- stage the frame's beads in cell order, checking the caller's count
+    const int nfc = F * F * F;
+    int S = 0;
+    for (int base = 0; base < nfc; base += 64) {
+        const int c = base + lane;
+        int cnt = 0, flat = 0;
+        int32_t word = 0;
+        if (c < nfc) {
+            const int fx = c % F, fy = (c / F) % F, fz = c / (F * F);
+            const int cx = (f.fs[0] + fx) % n, cy = (f.fs[1] + fy) % n, cz = (f.fs[2] + fz) % n;
+            flat = cx + n * (cy + n * cz);
+            const bool mot = WHOLE || (fx >= 1 && fx <= a.D && fy >= 1 && fy <= a.D && fz >= 1 && fz <= a.D);
+            word = pack_cell(cx, cy, cz) | (mot ? MOTILE_BIT : 0);
+            cnt = a.ccount[flat];
+        }
+        const int incl = wave_incl_scan(cnt);
+        const int excl = incl - cnt;
+        const int tot = rdlane(incl, 63);
+        for (int i = 0; i < cnt; ++i) {
+            const int at = S + excl + i;
+            if (at < S0) {
+                t_id[at] = a.cids[(long long)flat * a.cap + i];
+                t_meta[at] = word;
+            }
+        }
+        S += tot;
+    }
+    if (S != S0) {
+        // the cell lists changed since the count: nothing of this domain is touched
+        if (lane == 0) atomicOr(a.err, ERR_RECOUNT);
+        return;
+    }
+    f.S = S;
+    __syncthreads();
+    // rank sort by bead id
+    for (int e = lane; e < S; e += 64) {
+        const int my = t_id[e];
+        int r = 0;
+        for (int i = 0; i < S; ++i) r += (t_id[i] < my) ? 1 : 0;
+        m.id[r] = my;
+        m.meta[r] = t_meta[e];
+    }
+    __syncthreads();
+
+    // FP64 positions and partners into the staging area; screening copies into the lanes
+    // (empty slots far away, so that they never pass the screen)
+    Lanes<NS, WHOLE> R;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        R.A[k] = R.B[k] = R.C[k] = 1.0e30f;
+        if (WHOLE) R.META[k] = 0;
+    }
+#pragma unroll UNR
+    for (int k = 0; k < BPL; ++k) {
+        const int idx = k * 64 + lane;
+        if (idx < S) {
+            const int id = m.id[idx];
+            const int32_t w = m.meta[idx];
+            const double x = a.px[id], y = a.py[id], z = a.pz[id];
+            P0r[idx] = x;
+            P1r[idx] = y;
+            P2r[idx] = z;
+            if constexpr (!EXACT) {
+                R.A[k] = frame_u(x, cell_of(w, 0), f.fs[0], L, f.O[0]);
+                R.B[k] = frame_u(y, cell_of(w, 1), f.fs[1], L, f.O[1]);
+                R.C[k] = frame_u(z, cell_of(w, 2), f.fs[2], L, f.O[2]);
+                if (WHOLE) R.META[k] = w;
+            }
+            int packed = -1;
+            if (w & MOTILE_BIT) {
+                packed = 0;
+                for (int tt = 0; tt < 2; ++tt) {
+                    const int g = a.part[2 * id + tt];
+                    int found = 0xFFFF;
+                    if (g >= 0) {
+                        int lo = 0, hi = S - 1;
+                        while (lo <= hi) {
+                            const int mid = (lo + hi) >> 1;
+                            const int v = m.id[mid];
+                            if (v == g) {
+                                found = mid;
+                                break;
+                            }
+                            if (v < g) lo = mid + 1;
+                            else hi = mid - 1;
+                        }
+                    }
+                    packed |= found << (16 * tt);
+                }
+            }
+            m.part[idx] = packed;
+        }
+    }
+    // motile list in ascending id
+    int nmot = 0;
+#pragma unroll UNR
+    for (int k = 0; k < BPL; ++k) {
+        const int idx = k * 64 + lane;
+        const bool mt = idx < S && (m.meta[idx] & MOTILE_BIT);
+        const unsigned long long bal = __ballot(mt);
+        if (mt) m.mot[nmot + mbcnt(bal)] = idx;
+        nmot += __popcll(bal);
+    }
+    __syncthreads();
+
+    // ---- ECs
+    const Stage st = {m.pos, SM, m.meta, m.part, m.id};
+    const ScreenK K = {a.sig2f, a.b2f, a.in_lo, a.in_hi, a.p_sure, a.err_f, (float)L};
+    Tally t = {0u, 0.0};
+    bool ok = true;
+    int cur = 0;  // axis the lanes' frame is rotated to
+    for (long long k = 0; k < a.K && nmot > 0 && ok; ++k) {
+        uint32_t ctr[4] = {(uint32_t)k, f.domain, a.sweep, 0u};
+        philox4x32_10(ctr, a.key0, a.key1);
+        const int P0 = __builtin_amdgcn_readfirstlane(m.mot[scale_u32(ctr[0], (uint32_t)nmot)]);
+        const uint32_t dir = scale_u32(ctr[1], 6u);
+        const int ax = __builtin_amdgcn_readfirstlane((int)(dir >> 1));
+        const int sgn = __builtin_amdgcn_readfirstlane((dir & 1u) ? -1 : 1);
+        if constexpr (!EXACT) rotate(R, cur, ax);
+        cur = ax;
+        ok = run_ec<BPL, LOG, EXACT, WHOLE>(a, f, st, R, P0, ax, sgn, wraps, k, K, t);
+    }
+    __syncthreads();
+
+    // ---- write back the motile beads and the domain's cell lists
+    const int ndc = WHOLE ? n * n * n : a.D * a.D * a.D;
+    for (int i = lane; i < ndc; i += 64) m.part[i] = 0;
+    __syncthreads();
+    bool overflow = false;
+#pragma unroll UNR
+    for (int k = 0; k < BPL; ++k) {
+        const int idx = k * 64 + lane;
+        const int32_t w0 = idx < S ? m.meta[idx] : 0;
+        if (idx < S && (w0 & MOTILE_BIT)) {
+            const int id = m.id[idx];
+            a.px[id] = P0r[idx];
+            a.py[id] = P1r[idx];
+            a.pz[id] = P2r[idx];
+            const int32_t w = w0 & ~MOTILE_BIT;
+            a.cellp[id] = w;
+            const int cx = cell_of(w, 0), cy = cell_of(w, 1), cz = cell_of(w, 2);
+            int lc;
+            if (WHOLE) {
+                lc = cx + n * (cy + n * cz);
+            } else {
+                const int tx = (cx - f.ds[0] + n) % n, ty = (cy - f.ds[1] + n) % n, tz = (cz - f.ds[2] + n) % n;
+                lc = tx + a.D * (ty + a.D * tz);
+            }
+            const int slot = atomicAdd(&m.part[lc], 1);
+            if (slot < a.cap) a.cids[(long long)(cx + n * (cy + n * cz)) * a.cap + slot] = id;
+            else overflow = true;
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < ndc; i += 64) {
+        int cx, cy, cz;
+        if (WHOLE) {
+            cx = i % n;
+            cy = (i / n) % n;
+            cz = i / (n * n);
+        } else {
+            cx = (f.ds[0] + i % a.D) % n;
+            cy = (f.ds[1] + (i / a.D) % a.D) % n;
+            cz = (f.ds[2] + i / (a.D * a.D)) % n;
+        }
+        const int v = m.part[i];
+        a.ccount[cx + n * (cy + n * cz)] = v < a.cap ? v : a.cap;
+    }
+    if (__ballot(overflow) && lane == 0) atomicOr(a.err, ERR_CELL);
+    if (lane < NCNT && t.v) atomicAdd(&a.cnt[lane], (unsigned long long)t.v);
+    if (lane == 0) {
+        if (!ok) atomicOr(a.err, ERR_STUCK);
+        if (t.dsum != 0.0) atomicAdd(a.sum_delta, t.dsum);
+    }
+}
+
+}  // namespace
+}  // namespace ecmc

@@ -16,6 +16,7 @@ enum : uint32_t {
     ERR_STUCK = 1u << 2,  // an EC exceeded the per-EC iteration cap
     ERR_LOG = 1u << 3,    // event log full (records dropped; informational)
     ERR_RECOUNT = 1u << 4,  // a domain's cell lists no longer matched its count (internal error)
+    ERR_WAIT = 1u << 5,     // a wait of the dependency-ordered sweep ran out of polls (internal error)
 };
 
 // counter slots in the device counter block
@@ -80,6 +81,14 @@ struct PhaseArgs {
     float sig2f, b2f, in_lo, in_hi, p_sure, err_f;  // single-precision screen constants
     int off[3];
     uint32_t key0, key1, sweep;
+    // dependency-ordered sweep (one launch per sweep)
+    uint32_t *done;            // [nd^3] epoch of the launch that last finished each domain
+    uint32_t *queue;           // [2] next ticket, waves that have left; both 0 between launches
+    uint32_t epoch;            // this launch's stamp, never 0
+    int ndpc;                  // domains per colour, (nd/2)^3
+    double *slow;              // [nslow] staging slots for domains above the LDS capacity
+    uint32_t *slow_lock;       // [nslow] 0 free, 1 taken
+    int nslow, slow_cap;       // slots, beads per slot (0: no slots)
 };
 
 struct ObsArgs {
@@ -98,6 +107,9 @@ struct ObsArgs {
 // launchers (ecmc_kernels.hip)
 hipError_t launch_count(const PhaseArgs &a, int grid, hipStream_t s);
 hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s);
+hipError_t launch_sweep(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s);
+bool sweep_bpl_supported(int bpl);
+constexpr int SLOW_SLOT_BYTES_PER_BEAD = 3 * 8 + 4 * 4;  // staging slot: positions + 4 int32 rows
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
 hipError_t launch_shape(const ObsArgs &a, hipStream_t s);
 bool bpl_supported(int bpl);

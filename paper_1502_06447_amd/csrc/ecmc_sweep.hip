@@ -1,0 +1,178 @@
+// gfx950 kernel of the dependency-ordered sweep: all eight colour phases of a checkerboard
+// sweep in one launch, without a device-wide barrier between the phases.
+//
+// The sweep's result is defined by running the colours 0..7 one after the other, the domains
+// of one colour in any order (they never touch each other's frames).  A domain reads the cells
+// of its frame (its own cells and a one-cell halo, which belongs to the 26 surrounding
+// domains) and writes only its own cells.  Two domains therefore conflict only when they are
+// neighbours in the periodic domain grid, and neighbours always differ in colour.  So a domain
+// may start as soon as its neighbours of earlier colours are finished: by then its frame holds
+// exactly what the colour-by-colour order would give it, and its neighbours of later colours
+// wait for it in turn.
+//
+// Persistent waves take tickets from one counter in colour-major order.  A wave only waits on
+// domains of smaller tickets, which running waves hold and finish without waiting on larger
+// ones, so the waits always end.  As a guard against a broken invariant every wait gives up
+// after a fixed number of polls and flags ERR_WAIT.  Completion is published with an
+// agent-scope release (the per-XCD L2 caches are written back) and observed with an
+// agent-scope acquire.
+//
+// A domain whose frame holds more beads than the LDS staging area is staged in a slot of the
+// device workspace instead and run with the plain FP64 search (identical results).
+#include "ecmc_device.h"
+
+namespace ecmc {
+
+namespace {
+
+// A kernel argument read at its use: the sweep's own arguments are needed only before and
+// after the domain's ECs, and held in scalar registers through them they would push the EC
+// loop's constants out to VGPR lanes (a reload at every step).
+template <class T>
+__device__ __forceinline__ T late(const T &arg) {
+    return *(const volatile T *)&arg;
+}
+
+// polls of one wait before it gives up; a poll sleeps about 8 * 64 cycles, so the limit is
+// about a second, far beyond any real wait (a domain takes well under a millisecond)
+constexpr unsigned WAIT_POLLS = 1u << 20;
+
+// Wait until this launch has finished every neighbour of domain f whose colour comes earlier,
+// then acquire what they wrote.
+__device__ __forceinline__ void wait_for_earlier(const PhaseArgs &a, const Frame &f) {
+    const int lane = lane_id();
+    const int nd = a.nd;
+    const uint32_t *done = a.done;
+    const uint32_t epoch = a.epoch;
+    bool need = false;
+    int nb = 0;
+    if (lane < 27 && lane != 13) {
+        const int ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
+        // a step of one domain along an axis flips that axis' parity bit (nd is even)
+        const int col = f.colour ^ ((ox != 0) | ((oy != 0) << 1) | ((oz != 0) << 2));
+        need = col < f.colour;
+        nb = (f.dom[0] + ox + nd) % nd + nd * ((f.dom[1] + oy + nd) % nd + nd * ((f.dom[2] + oz + nd) % nd));
+    }
+    for (unsigned polls = 0;; ++polls) {
+        need = need && __hip_atomic_load(&done[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch;
+        if (!__ballot(need)) break;
+        if (polls >= WAIT_POLLS) {
+            if (lane == 0) atomicOr(a.err, ERR_WAIT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// A free staging slot, searched from `start`; -1 (and ERR_WAIT) if none came free in time.
+// Called after the dependency wait: a wave holding a slot never waits on another domain, so
+// every slot is given back.
+__device__ __forceinline__ int take_slot(const PhaseArgs &a, uint32_t start) {
+    int got = -1;
+    if (lane_id() == 0) {
+        for (unsigned polls = 0; got < 0; ++polls) {
+            const int nslow = a.nslow;
+            uint32_t *lock = a.slow_lock;
+            for (int i = 0; i < nslow && got < 0; ++i) {
+                const int s = (int)((start + (uint32_t)i) % (uint32_t)nslow);
+                if (atomicCAS(&lock[s], 0u, 1u) == 0u) got = s;
+            }
+            if (got >= 0) break;
+            if (polls >= WAIT_POLLS) {
+                atomicOr(a.err, ERR_WAIT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(got);
+}
+
+template <int BPL, bool LOG, bool EXACT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(BPL)))) void k_sweep(const PhaseArgs a) {
+    constexpr int SMAX = 64 * BPL;
+    __shared__ double s_pos[3][SMAX];
+    __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[SMAX];
+    const int lane = lane_id();
+    // one ticket per workgroup, taken when the workgroup runs: ticket order, not launch order,
+    // is the order of the waits
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(&a.queue[0], 1u);
+    t = __builtin_amdgcn_readfirstlane(t);
+    const uint32_t ndpc = (uint32_t)a.ndpc;
+    Frame f;
+    int F;
+    bool wraps;
+    frame_of<false>(a, (int)(t / ndpc), (int)(t % ndpc), f, F, wraps);
+    wait_for_earlier(a, f);
+    const int S = frame_count(a, f, F);
+    int slot = -1;
+    if (S <= SMAX) {
+        const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
+        domain_body<BPL, LOG, EXACT, false>(a, f, F, wraps, S, m);
+    } else if (S <= a.slow_cap) {
+        slot = take_slot(a, t);
+        if (slot >= 0) {
+            // slot layout: three rows of positions, then id, meta, part, mot rows
+            const int cap = a.slow_cap;
+            double *base = a.slow + (size_t)slot * (size_t)cap * (SLOW_SLOT_BYTES_PER_BEAD / 8);
+            int32_t *ib = reinterpret_cast<int32_t *>(base + 3 * (size_t)cap);
+            const StageMem m = {base, ib, ib + cap, ib + 2 * cap, ib + 3 * cap, cap};
+            domain_body<16, LOG, true, false>(a, f, F, wraps, S, m);
+        }
+    } else if (lane == 0) {
+        atomicOr(a.err, ERR_STAGE);
+    }
+    // publish: every write of this domain is visible device-wide before its stamp
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) {
+        __hip_atomic_store(&late(a.done)[f.domain], late(a.epoch), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (slot >= 0)
+            __hip_atomic_store(&late(a.slow_lock)[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the last workgroup to finish resets the ticket counter for the next launch
+        uint32_t *q = late(a.queue);
+        const uint32_t left = atomicAdd(&q[1], 1u);
+        if (left == gridDim.x - 1) {
+            __hip_atomic_store(&q[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&q[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <int BPL, bool LOG, bool EXACT>
+hipError_t launch_sweep_v(const PhaseArgs &a, int *grid, hipStream_t s) {
+    const int g = 8 * a.ndpc;  // one workgroup per domain of the sweep
+    *grid = g;
+    hipLaunchKernelGGL((k_sweep<BPL, LOG, EXACT>), dim3(g), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int BPL>
+hipError_t launch_sweep_b(const PhaseArgs &a, bool log, int *grid, hipStream_t s) {
+    if (log) return a.exact_search ? launch_sweep_v<BPL, true, true>(a, grid, s) : launch_sweep_v<BPL, true, false>(a, grid, s);
+    return a.exact_search ? launch_sweep_v<BPL, false, true>(a, grid, s) : launch_sweep_v<BPL, false, false>(a, grid, s);
+}
+
+}  // namespace
+
+bool sweep_bpl_supported(int bpl) {
+    switch (bpl) {
+        case 1: case 2: case 3: case 4: case 6: case 8: return true;
+        default: return false;
+    }
+}
+
+hipError_t launch_sweep(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s) {
+    switch (bpl) {
+        case 1: return launch_sweep_b<1>(a, log, grid, s);
+        case 2: return launch_sweep_b<2>(a, log, grid, s);
+        case 3: return launch_sweep_b<3>(a, log, grid, s);
+        case 4: return launch_sweep_b<4>(a, log, grid, s);
+        case 6: return launch_sweep_b<6>(a, log, grid, s);
+        case 8: return launch_sweep_b<8>(a, log, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ecmc

@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("ECMC_LIB") or os.path.join(_HERE, "libecmc.so")
 OK, E_ARG, E_OVERLAP, E_TETHER, E_BOX, E_CELL_OVERFLOW, E_STUCK, E_DEVICE, E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC_FP64, PREC_MIXED = 0, 1
 TILING_WHOLE, TILING_CHECKER = 0, 1
+SCHED_SWEEP, SCHED_PHASES = 0, 1
 EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END, EV_PERIOD, EV_CYCLE, EV_SWAP = range(9)
 
 EVENT_DTYPE = np.dtype([
@@ -39,6 +40,7 @@ class ecmc_options(ctypes.Structure):
         ("event_log_capacity", ctypes.c_int64),
         ("time_kernels", ctypes.c_int32),
         ("swap_moves", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
@@ -177,6 +179,7 @@ class Options:
     time_kernels: bool = False
     precision: int = PREC_MIXED
     swap_moves: bool = False
+    schedule: int = SCHED_SWEEP
 
 
 class Melt:
@@ -197,6 +200,7 @@ class Melt:
         opt.event_log_capacity = o.event_log_capacity
         opt.time_kernels = 1 if o.time_kernels else 0
         opt.swap_moves = 1 if o.swap_moves else 0
+        opt.schedule = o.schedule
         pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
         nbytes = ecmc_workspace_size(L, sigma, b_max, pos.shape[0], opt)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)

@@ -58,6 +58,26 @@ def test_workspace_size_and_geometry_errors():
     with pytest.raises(ecmc.EcmcError) as e:
         ecmc.ecmc_workspace_size(20.0, 1.0, 1.4, 10, o)
     assert e.value.code == ecmc.E_ARG
+    o = ecmc.ecmc_default_options()
+    o.schedule = 2                                               # neither SWEEP nor PHASES
+    with pytest.raises(ecmc.EcmcError) as e:
+        ecmc.ecmc_workspace_size(20.0, 1.0, 1.4, 10, o)
+    assert e.value.code == ecmc.E_ARG
+
+
+def test_sweep_schedule_reserves_staging_slots():
+    """The one-launch sweep stages the rare domains above the LDS capacity in workspace slots
+    (512 of them at the 1,048,576-bead melt, each for a full frame of 4^3 cells x 16 beads,
+    40 bytes a bead); by phases, or with a fixed staging capacity, there are none."""
+    o = ecmc.ecmc_default_options()
+    sweep = ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
+    o.schedule = ecmc.SCHED_PHASES
+    phases = ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
+    assert sweep - phases >= 512 * 1024 * 40 and sweep - phases < 512 * 1024 * 40 + 4 * 76 ** 3
+    o.schedule = ecmc.SCHED_SWEEP
+    o.stage_capacity = 192
+    fixed = ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
+    assert fixed - phases < 4096
 
 
 def _init_status(pos, bonds, L=10.0, tiling=ecmc.TILING_WHOLE, workspace=True):

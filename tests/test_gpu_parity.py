@@ -81,11 +81,14 @@ def test_whole_box_c1_event_sequence_bit_exact(melt_c1, exact):
     print(f"{n} events, max |dr| {dp}")
 
 
-@pytest.mark.parametrize("exact", [False, True])
-def test_checkerboard_c1_event_sequence_bit_exact(melt_c1, exact):
+@pytest.mark.parametrize("exact,sched", [(False, ecmc.SCHED_SWEEP), (True, ecmc.SCHED_SWEEP),
+                                         (False, ecmc.SCHED_PHASES)])
+def test_checkerboard_c1_event_sequence_bit_exact(melt_c1, exact, sched):
     """Checkerboard decomposition on the 16 x 16 melt (n = 4, D = 2: one domain per colour):
-    walls, immotile reflections, every domain frame wrapping the periodic box."""
-    p, g, o = _pair(melt_c1, ecmc.TILING_CHECKER, D=2, n_cells=4, precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
+    walls, immotile reflections, every domain frame wrapping the periodic box; one launch per
+    sweep (each domain waits for its neighbours of earlier colours) and one per phase."""
+    p, g, o = _pair(melt_c1, ecmc.TILING_CHECKER, D=2, n_cells=4, precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED,
+                    schedule=sched)
     for s in range(4):
         p.sweep(256, 10.0, 70 + s)
     n, _ = _compare(g, o)
@@ -110,15 +113,53 @@ def melt_c2():
     return inputs.lattice_chains(500, 32, 0.45, seed=2)
 
 
-@pytest.mark.parametrize("D,n_cells,exact", [(2, 16, False), (3, 18, False), (3, 18, True)])
-def test_c2_dense_melt_bit_exact(melt_c2, D, n_cells, exact):
+@pytest.mark.parametrize("D,n_cells,exact,sched", [(2, 16, False, ecmc.SCHED_SWEEP), (2, 16, False, ecmc.SCHED_PHASES),
+                                                   (3, 18, False, ecmc.SCHED_SWEEP), (3, 18, True, ecmc.SCHED_SWEEP),
+                                                   (3, 18, False, ecmc.SCHED_PHASES)])
+def test_c2_dense_melt_bit_exact(melt_c2, D, n_cells, exact, sched):
     """500 x 32 melt at eta = 0.45 (n = 16, D = 2: 64 domains per colour; n = 18, D = 3: 27),
-    2 sweeps of 16,000 ECs with ell = 20 sigma."""
-    p, g, o = _pair(melt_c2, ecmc.TILING_CHECKER, D=D, n_cells=n_cells, log=40_000_000, precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
+    2 sweeps of 16,000 ECs with ell = 20 sigma, by both schedules."""
+    p, g, o = _pair(melt_c2, ecmc.TILING_CHECKER, D=D, n_cells=n_cells, log=40_000_000,
+                    precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED, schedule=sched)
     for s in range(2):
         p.sweep(16000, 20.0, 5 + s)
     n, _ = _compare(g, o)
     assert n > 250_000
+
+
+def _clustered(melt, grow):
+    """The chains of `melt` that do not cross its periodic boundary, unchanged, in a box `grow`
+    times wider: a dense region next to an empty one, so that domain frames hold very
+    different bead counts (the densest far above what the mean density asks for)."""
+    L, n_per = melt.L, melt.n_per
+    ch = melt.positions.reshape(melt.n_poly, n_per, 3)
+    keep = np.all(np.abs(np.diff(ch, axis=1)) < 0.5 * L, axis=(1, 2))
+    m = int(keep.sum())
+    i = np.arange(m * n_per, dtype=np.int32).reshape(m, n_per)
+    bonds = np.stack([i[:, :-1].ravel(), i[:, 1:].ravel()], axis=1).astype(np.int32)
+    return inputs.Melt(L=L * grow, positions=ch[keep].reshape(-1, 3).copy(), bonds=bonds, sigma=melt.sigma,
+                       b_max=melt.b_max, n_poly=m, n_per=n_per)
+
+
+@pytest.mark.parametrize("sched", [ecmc.SCHED_SWEEP, ecmc.SCHED_PHASES])
+def test_clustered_melt_large_frames_bit_exact(melt_c2, sched):
+    """The 500 x 32 melt (eta = 0.45) in a box 1.35 times wider (n = 24, D = 2): the staging
+    area is sized for the mean density, so the dense domains (about 180 beads in a frame)
+    overflow it and run from workspace slots (one launch per sweep) or from the larger
+    staging tiers (by phases); event sequence and state as in the oracle."""
+    m = _clustered(melt_c2, 1.35)
+    frame = 64 * m.n_beads / 24 ** 3
+    p, g, o = _pair(m, ecmc.TILING_CHECKER, D=2, n_cells=24, log=40_000_000, schedule=sched)
+    # the densest 4^3-cell frames hold more than twice the mean
+    cells = np.floor(m.positions / g.h).astype(int) % 24
+    dense = np.zeros((24, 24, 24), int)
+    np.add.at(dense, (cells[:, 0], cells[:, 1], cells[:, 2]), 1)
+    win = sum(np.roll(dense, (-a, -b, -c), axis=(0, 1, 2)) for a in range(4) for b in range(4) for c in range(4))
+    assert win.max() > 2 * frame > 100
+    for s in range(2):
+        p.sweep(m.n_beads, 20.0, 41 + s)
+    n, _ = _compare(g, o)
+    assert n > 100_000
 
 
 def test_swap_moves_c2_dense_melt_bit_exact(melt_c2):
@@ -248,6 +289,29 @@ def test_c3_full_size_sampled_domains(melt_c3, swap):
     c, _ = o.counters()
     assert c[oracle.C_EC] == 20 * len(np.unique(did[np.isin(did, pick)]))
     assert (g.counters()["swap"] > 0) == swap   # over the whole phase (rarely accepted from a lattice start)
+
+
+def test_c3_schedules_agree_at_full_size(melt_c3):
+    """At 1,048,576 beads (6,859 domains per colour, a few hundred of them above the LDS
+    staging area) two sweeps in one launch each and two sweeps by colour phases end in the
+    same state bit for bit: positions, cells, images and every counter."""
+    m = melt_c3
+    runs = []
+    for sched in (ecmc.SCHED_SWEEP, ecmc.SCHED_PHASES):
+        g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, schedule=sched))
+        for s in range(2):
+            g.sweep(m.n_beads, 20.0, 300 + s)
+        g.synchronize()
+        runs.append((g.positions(), g.cells(), g.images(), g.counters()))
+        g.close()
+    (p0, c0, i0, k0), (p1, c1, i1, k1) = runs
+    assert np.array_equal(p0, p1) and np.array_equal(c0, c1) and np.array_equal(i0, i1)
+    for k in k0:
+        if k == "sum_delta":
+            assert k0[k] == pytest.approx(k1[k], rel=1e-9)
+        else:
+            assert k0[k] == k1[k], k
+    assert k0["ec"] > 2_000_000 and k0["error_flags"] == 0
 
 
 def test_c3_invariants_after_full_sweeps(melt_c3):
