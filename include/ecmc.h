@@ -99,7 +99,8 @@ typedef struct {
                                    size up and 1024 beads (by phases); > 0 = LDS staging of
                                    this capacity only, a larger domain is
                                    ECMC_E_CELL_OVERFLOW; at most 1024                       */
-    int64_t event_cap;          /* loop iterations allowed per EC; 0 = 10^7                 */
+    int64_t event_cap;          /* loop iterations allowed per EC; 0 = 10^7 (at most
+                                   2^31 - 1 are honoured)                                   */
     int64_t event_log_capacity; /* event records kept; 0 = no log (the fast path)           */
     int32_t time_kernels;       /* nonzero: time every sweep launch (or colour phase, by
                                    phases) with HIP events                                  */
@@ -130,10 +131,35 @@ typedef struct {
 } ecmc_counters;
 
 typedef struct {
-    uint32_t sweep, domain, ec, step;
-    int32_t pivot, target;
+    uint32_t sweep, domain, ec, step;   /* domain: index among all domains of the context
+                                           (melt by melt; a single melt: its domain grid) */
+    int32_t pivot, target;              /* bead indices among all beads of the context     */
     uint32_t kind, colour;
 } ecmc_event;
+
+/* One melt of a batch (ecmc_init_batch).  Every melt is a periodic cube of its own; melts
+ * never interact.  They share sigma, l_max and the options. */
+typedef struct {
+    double box;                 /* edge L of the melt's cube                                */
+    int64_t n_beads;
+    const double *positions;    /* host [n_beads][3]                                        */
+    int64_t n_bonds;
+    const int32_t *bonds;       /* host [n_bonds][2], bead indices within this melt         */
+    int32_t n_cells;            /* cells per axis; 0 = automatic                            */
+    int32_t domain_cells;       /* D; 0 = automatic: D = 2, n the largest multiple of 4
+                                   with L/n > l_max (or, with n_cells set, the smallest
+                                   D >= 2 that divides n with n/D even)                     */
+} ecmc_melt_desc;
+
+/* Where a melt of a context lives: its beads, polymers and domains are consecutive ranges
+ * of every per-bead, per-polymer and per-domain output, in melt order. */
+typedef struct {
+    double box, cell_size;
+    int64_t first_bead, n_beads;
+    int64_t first_polymer, n_polymers;
+    int64_t first_domain, n_domains;
+    int32_t n_cells, domain_cells;
+} ecmc_melt_info;
 
 /* Fills *opt with the defaults (screened precision, checkerboard, D = 2, automatic sizes). */
 void ecmc_default_options(ecmc_options *opt);
@@ -142,6 +168,11 @@ void ecmc_default_options(ecmc_options *opt);
  * with the given options (workspace fields are ignored).  Errors as ecmc_init. */
 ecmc_status ecmc_workspace_size(double box, double sigma, double l_max, int64_t n_beads,
                                 const ecmc_options *opt, size_t *bytes);
+
+/* Bytes of device workspace ecmc_init_batch needs for these melts (positions and bonds are
+ * not read; n_beads and n_bonds are). */
+ecmc_status ecmc_workspace_size_batch(int32_t n_melts, const ecmc_melt_desc *melts, double sigma,
+                                      double l_max, const ecmc_options *opt, size_t *bytes);
 
 /* Creates a context.  positions: host [n_beads][3] doubles, wrapped into [0, box) and
  * binned into closed cells [k h, (k+1) h]; bonds: host [n_bonds][2] bead indices forming
@@ -152,14 +183,29 @@ ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, in
                       const double *positions, int64_t n_bonds, const int32_t *bonds,
                       const ecmc_options *opt);
 
+/* Creates a context holding n_melts independent melts (the batched form): each validated,
+ * binned and decomposed as by ecmc_init in its own box, with its own cell grid and domain
+ * edge; all of them sweep together in one launch per sweep.  Needs the checkerboard tiling
+ * and the dependency-ordered schedule.  Melt m draws from random stream m (see ecmc_sweep);
+ * a context of one melt behaves exactly as one from ecmc_init. */
+ecmc_status ecmc_init_batch(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *melts,
+                            double sigma, double l_max, const ecmc_options *opt);
+
 /* One sweep (Sec. II.A: the decomposition is redrawn every sweep): a partition offset,
  * then the 8 colour phases in order; every non-empty active domain runs
- * K = ceil(n_chains / n_domains) ECs of length ell (whole-box tiling: n_chains ECs).
- * Random numbers: Philox4x32-10 keyed by seed, counter (k, domain, sweep, 0) for the
- * pivot and direction of EC k, (0, 0, sweep, 1) for the offsets.  Asynchronous. */
+ * K = ceil(n_chains / n_domains) ECs of length ell, n_domains counted over all melts
+ * (whole-box tiling: n_chains ECs; K above 2^31 - 1 is ECMC_E_ARG).
+ * Random numbers: Philox4x32-10 keyed by seed; melt m draws the pivot and direction of
+ * EC k of a domain from counter (k, domain, sweep, 2 m) and its offsets from
+ * (0, 0, sweep, 2 m + 1), domain being the index in the melt's own domain grid.
+ * sweep is the context's sweep counter, kept in device memory and advanced by every
+ * sweep on the stream.  Asynchronous, and free of host synchronisation and memory
+ * operations, so that a sequence of sweeps can be captured into a hipGraph on a
+ * capturing stream and replayed: each replay moves the sweep counter on. */
 ecmc_status ecmc_sweep(ecmc_ctx *ctx, int64_t n_chains, double ell, uint64_t seed);
 
-/* As ecmc_sweep, running only the colour phases whose bit is set in colour_mask. */
+/* As ecmc_sweep, running only the colour phases whose bit is set in colour_mask (single
+ * melts only; a mask other than 0xFF runs the phases one launch set at a time). */
 ecmc_status ecmc_sweep_colours(ecmc_ctx *ctx, int64_t n_chains, double ell, uint64_t seed,
                                uint32_t colour_mask);
 
@@ -205,10 +251,13 @@ ecmc_status ecmc_set_state(ecmc_ctx *ctx, const double *positions, const int32_t
  * number (needs time_kernels).  Synchronises. */
 ecmc_status ecmc_kernel_time(ecmc_ctx *ctx, double *ms, int64_t *launches);
 
+/* The sweep counter (read from the device: synchronises). */
 uint32_t ecmc_sweep_counter(const ecmc_ctx *ctx);
 int32_t ecmc_n_cells(const ecmc_ctx *ctx);
 double ecmc_cell_size(const ecmc_ctx *ctx);
 int32_t ecmc_stage_capacity(const ecmc_ctx *ctx);
+int32_t ecmc_n_melts(const ecmc_ctx *ctx);
+ecmc_status ecmc_get_melt_info(const ecmc_ctx *ctx, int32_t melt, ecmc_melt_info *out);
 
 void ecmc_destroy(ecmc_ctx *ctx);
 const char *ecmc_status_str(ecmc_status s);

@@ -55,6 +55,8 @@ def lib():
         L.orc_destroy.argtypes = [vp]
         L.orc_set_options.argtypes = [vp, i64, ctypes.c_int]
         L.orc_set_swap.argtypes = [vp, ctypes.c_int]
+        L.orc_set_stream.argtypes = [vp, u32]
+        L.orc_set_stream.restype = ctypes.c_int
         L.orc_set_log.argtypes = [vp, vp, i64]
         L.orc_log_count.argtypes = [vp]
         L.orc_log_count.restype = i64
@@ -159,6 +161,11 @@ class Oracle:
     def set_swap(self, on: bool = True):
         """Swap moves at hard-sphere contacts (Sec. II.C) for the following ECs."""
         lib().orc_set_swap(self._h, 1 if on else 0)
+
+    def set_stream(self, m: int):
+        """Random stream m: the draws of melt m of a batch (Philox counter word 3 = 2 m, 2 m + 1)."""
+        if lib().orc_set_stream(self._h, int(m)) != 0:
+            raise ValueError(f"stream index {m} out of range")
 
     def enable_log(self, capacity: int):
         self._log = np.zeros(int(capacity), dtype=EVENT_DTYPE)

@@ -40,7 +40,8 @@
  *    repeats forever with nothing moving; it is detected (Brent's cycle search over the
  *    run) and ends the EC;
  *  - random numbers: Philox4x32-10 keyed by the 64-bit seed; EC draws use counter
- *    (k, domain, sweep, 0), the partition offsets use (0, 0, sweep, 1);
+ *    (k, domain, sweep, 2 m), the partition offsets use (0, 0, sweep, 2 m + 1), with the
+ *    stream index m = 0 unless set (m numbers a melt of a batch run side by side);
  *  - swap moves (Sec. II.C, optional): proposed at every hard-sphere contact with a motile
  *    bead; accepted iff all tethers of both beads are within b_max after the exchange
  *    (squared minimum-image lengths, summed over x, y, z, compared with b_max^2).
@@ -69,6 +70,7 @@ struct orc_sys {
     int64_t event_cap;
     int check;
     int swap;          /* swap moves at hard-sphere contacts (Sec. II.C) */
+    uint32_t stream;   /* random stream index m (counter word 3 = 2 m, 2 m + 1) */
     orc_event *log;
     int64_t log_cap, log_n;
     uint64_t cnt[ORC_NCNT];
@@ -347,6 +349,12 @@ int orc_set_options(orc_sys *s, int64_t event_cap, int check) {
 
 int orc_set_swap(orc_sys *s, int on) {
     s->swap = on ? 1 : 0;
+    return ORC_OK;
+}
+
+int orc_set_stream(orc_sys *s, uint32_t m) {
+    if (m > 0x7FFFFFFFu) return ORC_E_ARG;
+    s->stream = m;
     return ORC_OK;
 }
 
@@ -798,7 +806,7 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
         dm.D = 1;
         for (int64_t i = 0; i < s->nb; ++i) mot[i] = (int32_t)i;
         for (int64_t k = 0; k < n_ec && st == ORC_OK; ++k) {
-            const uint32_t ctr[4] = {(uint32_t)k, 0u, sweep, 0u};
+            const uint32_t ctr[4] = {(uint32_t)k, 0u, sweep, 2u * s->stream};
             uint32_t u[4];
             orc_philox4x32_10(ctr, key, u);
             const int32_t p = mot[below(u[0], (uint32_t)s->nb)];
@@ -818,7 +826,7 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
         dm.tiled = 1;
         dm.D = D;
         {
-            const uint32_t ctr[4] = {0u, 0u, sweep, 1u};
+            const uint32_t ctr[4] = {0u, 0u, sweep, 2u * s->stream + 1u};
             uint32_t u[4];
             orc_philox4x32_10(ctr, key, u);
             for (int a = 0; a < 3; ++a) dm.off[a] = (int)below(u[a], (uint32_t)D);
@@ -850,7 +858,7 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
                         if (m == 0) continue;
                         qsort(mot, (size_t)m, sizeof(int32_t), cmp_i32);
                         for (int64_t k = 0; k < K && st == ORC_OK; ++k) {
-                            const uint32_t ctr[4] = {(uint32_t)k, dm.domain, sweep, 0u};
+                            const uint32_t ctr[4] = {(uint32_t)k, dm.domain, sweep, 2u * s->stream};
                             uint32_t u[4];
                             orc_philox4x32_10(ctr, key, u);
                             const int32_t p = mot[below(u[0], (uint32_t)m)];

@@ -82,6 +82,10 @@ int orc_set_options(orc_sys *s, int64_t event_cap, int check);
 
 /* Swap moves (Sec. II.C) on (1) or off (0, the default) for the following ECs. */
 int orc_set_swap(orc_sys *s, int on);
+
+/* Random stream index m (default 0): the Philox counters of the following sweeps end in 2 m
+ * (EC draws) and 2 m + 1 (partition offsets), the streams of melt m of a batch. */
+int orc_set_stream(orc_sys *s, uint32_t m);
 int orc_set_log(orc_sys *s, orc_event *buf, int64_t cap);
 int64_t orc_log_count(const orc_sys *s);
 

@@ -1,5 +1,9 @@
 // Host side of the C ABI declared in include/ecmc.h: validation of the start
-// configuration, cell binning, workspace layout, launches of the gfx950 kernels.
+// configurations, cell binning, workspace layout, launches of the gfx950 kernels.
+//
+// A context holds one melt or a batch of independent melts.  Their beads, polymers, cells
+// and domains are consecutive ranges of shared arrays, in melt order; a per-melt table on
+// the device gives each melt's box, cell grid, domain grid and ranges.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,15 +25,39 @@ constexpr int DEFAULT_CAP = 16;
 constexpr int MAX_BINS = 1024;
 constexpr int SLOW_SLOTS = 512;  // workspace staging slots of the dependency-ordered sweep
 
+// ---------------------------------------------------------------- plan
+struct MeltPlan {
+    double L = 0, h = 0;
+    int n = 0, D = 1, nd = 1, ndpc = 0;
+    int64_t nb = 0, bead0 = 0, poly0 = 0, npoly = 0;
+    int64_t cell0 = 0, dom0 = 0;
+    int tick0 = 0;
+    float in_lo = 0, in_hi = 0, p_sure = 0, err_f = 0;  // screen constants
+};
+
+struct Plan {
+    std::vector<MeltPlan> melts;
+    bool whole = false;
+    int64_t nb = 0, cells = 0, domains = 0;
+    int tickets = 0;       // domains per colour, summed over the melts
+    int bpl = 0;           // beads per lane of the first staging tier
+    int stage = 0;
+    int bpl2 = 0;          // second tier for the rare domains above 64 * bpl (by phases; 0 = none)
+    int bpl3 = 0;          // third tier above 64 * bpl2 (0 = none)
+    bool sweep = false;    // one dependency-ordered launch per sweep
+    int nslow = 0;         // its workspace staging slots for domains above 64 * bpl
+    int slow_cap = 0;      // beads per slot
+};
+
 struct Layout {
-    size_t px, py, pz, cellp, img, part, ccount, cids, dstage, done, queue, slow_lock, slow, porder, pstart, r2, rg2,
-        mid, shape, hist, cnt, dsum, err, log_n, log;
+    size_t px, py, pz, cellp, img, part, ccount, cids, dstage, done, queue, dstate, slow_lock, slow, melts, porder,
+        pstart, polyL, r2, rg2, mid, shape, hist, cnt, dsum, err, log_n, log;
     size_t total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap, int nslow, int slow_cap) {
+Layout make_layout(const Plan &p, int64_t npoly_max, int cap, int64_t log_cap) {
     Layout l{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -37,7 +65,7 @@ Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap, int nslow, int s
         o = align256(o + bytes);
         return at;
     };
-    const size_t nc = (size_t)n * n * n;
+    const size_t nb = (size_t)p.nb, nc = (size_t)p.cells, np = (size_t)npoly_max;
     l.px = take(8 * nb);
     l.py = take(8 * nb);
     l.pz = take(8 * nb);
@@ -46,17 +74,20 @@ Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap, int nslow, int s
     l.part = take(8 * nb);
     l.ccount = take(4 * nc);
     l.cids = take(4 * nc * cap);
-    l.dstage = take(4 * (nc / 8 + 1));  // one count per domain of a colour phase (at most n^3 / 64)
-    l.done = take(4 * (nc / 8 + 1));    // one stamp per domain (D >= 2: at most n^3 / 8)
+    l.dstage = take(4 * (nc / 8 + 1));  // one count per domain of a colour phase (single melt)
+    l.done = take(4 * (size_t)(p.domains + 1));
     l.queue = take(8);
-    l.slow_lock = take(4 * (size_t)std::max(nslow, 0));
-    l.slow = take((size_t)std::max(nslow, 0) * (size_t)std::max(slow_cap, 0) * SLOW_SLOT_BYTES_PER_BEAD);
+    l.dstate = take(8);
+    l.slow_lock = take(4 * (size_t)std::max(p.nslow, 0));
+    l.slow = take((size_t)std::max(p.nslow, 0) * (size_t)std::max(p.slow_cap, 0) * SLOW_SLOT_BYTES_PER_BEAD);
+    l.melts = take(sizeof(MeltDev) * p.melts.size());
     l.porder = take(4 * nb);
-    l.pstart = take(4 * (nb + 1));
-    l.r2 = take(8 * nb);
-    l.rg2 = take(8 * nb);
-    l.mid = take(24 * nb);
-    l.shape = take(96 * nb);  // gyration tensor, eigenvalues, centre of mass: 12 doubles per polymer
+    l.pstart = take(4 * (np + 1));
+    l.polyL = take(8 * np);
+    l.r2 = take(8 * np);
+    l.rg2 = take(8 * np);
+    l.mid = take(24 * np);
+    l.shape = take(96 * np);  // gyration tensor, eigenvalues, centre of mass: 12 doubles per polymer
     l.hist = take(8 * MAX_BINS);
     l.cnt = take(8 * NCNT);
     l.dsum = take(8);
@@ -67,35 +98,20 @@ Layout make_layout(int64_t nb, int n, int cap, int64_t log_cap, int nslow, int s
     return l;
 }
 
-struct Geometry {
-    int n = 0;
-    double h = 0;
-    int D = 1;
-    int nd = 1;
-    int bpl = 0;     // beads per lane of the first staging tier
-    int stage = 0;
-    int bpl2 = 0;    // second tier for the rare domains above 64 * bpl (0 = none)
-    int bpl3 = 0;    // third tier above 64 * bpl2 (0 = none)
-    bool sweep = false;  // one dependency-ordered launch per sweep
-    int nslow = 0;       // its workspace staging slots for domains above 64 * bpl
-    int slow_cap = 0;    // beads per slot
-};
-
 }  // namespace
 
 struct ecmc_ctx {
     ecmc_options opt;
     hipStream_t stream = nullptr;
-    hipStream_t side = nullptr;       // second stream for the larger staging tiers
+    hipStream_t side = nullptr;       // second stream for the larger staging tiers (by phases)
     hipEvent_t fork = nullptr, join = nullptr;
-    double L = 0, sigma = 0, lmax = 0, sig2 = 0, b2 = 0;
+    double sigma = 0, lmax = 0, sig2 = 0, b2 = 0;
     int64_t nb = 0, npoly = 0;
-    Geometry g;
+    Plan p;
     int cap = DEFAULT_CAP;
     Layout lay{};
     char *ws = nullptr;
-    uint32_t sweep_ctr = 0;
-    uint32_t epoch = 0;               // stamp of the last dependency-ordered launch
+    uint32_t sweep_ctr = 0;           // host count of sweeps (the device holds the authoritative one)
     std::string err;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;
     template <class T>
@@ -123,53 +139,139 @@ ecmc_status fail(ecmc_ctx *c, ecmc_status s, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(ctx, ECMC_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-// ---------------------------------------------------------------- geometry
-ecmc_status geometry(double L, double sigma, double lmax, int64_t nb, const ecmc_options &o, Geometry &g,
-                     ecmc_ctx *c) {
-    if (!(std::isfinite(L) && L > 0 && std::isfinite(sigma) && sigma > 0 && std::isfinite(lmax) && lmax >= sigma))
+// Cells and domains of one melt.  n_req = 0: the largest n with L/n > l_max.  D_req = 0
+// (checkerboard): D = 2, with n the largest multiple of 4 below that bound unless n_req fixes
+// it (then the smallest D >= 2 that fits).
+ecmc_status plan_melt(double L, int64_t nb, double lmax, int n_req, int D_req, int tiling, MeltPlan &mp,
+                      ecmc_ctx *c, int m) {
+    if (!(std::isfinite(L) && L > 0)) return fail(c, ECMC_E_ARG, "melt %d: need a finite box > 0", m);
+    if (nb < 1 || nb > 0x7fffffffLL)
+        return fail(c, ECMC_E_ARG, "melt %d: bead count %lld out of range", m, (long long)nb);
+    int nmax = (int)std::min(std::floor(L / lmax), (double)MAX_CELLS_PER_AXIS);
+    while (nmax > 0 && !(L / nmax > lmax)) --nmax;
+    int n = n_req > 0 ? n_req : nmax;
+    int D = D_req;
+    if (tiling == ECMC_TILING_CHECKER && D_req == 0) {
+        if (n_req > 0) {
+            for (D = 2; D <= n && !(n % D == 0 && (n / D) % 2 == 0); ++D) {
+            }
+            if (D > n) return fail(c, ECMC_E_BOX, "melt %d: no domain edge D >= 2 with n/D even (n = %d)", m, n);
+        } else {
+            D = 2;
+            n = nmax - nmax % 4;
+        }
+    }
+    if (n < 4 || n > MAX_CELLS_PER_AXIS || !(L / n > lmax))
+        return fail(c, ECMC_E_BOX, "cells per axis n = %d: need 4 <= n <= %d and L/n > l_max (melt %d)", n,
+                    MAX_CELLS_PER_AXIS, m);
+    mp.L = L;
+    mp.n = n;
+    mp.h = L / n;
+    mp.nb = nb;
+    if (tiling == ECMC_TILING_WHOLE) {
+        mp.D = n;
+        mp.nd = 1;
+        if (nb > MAX_STAGE) return fail(c, ECMC_E_ARG, "whole-box tiling holds at most %d beads", MAX_STAGE);
+        if ((int64_t)n * n * n > 64 * 16)
+            return fail(c, ECMC_E_BOX, "whole-box tiling needs n^3 <= 1024 cells (n = %d)", n);
+    } else if (tiling == ECMC_TILING_CHECKER) {
+        // D >= 2: the integer offset drawn from [0, D) is what moves the partition between
+        // sweeps; with D = 1 it is always 0 and every bead stays in its cell for good.
+        if (D < 2 || n % D != 0 || (n / D) % 2 != 0)
+            return fail(c, ECMC_E_BOX, "checkerboard needs D >= 2, n %% D == 0 and n/D even (melt %d: n = %d, D = %d)",
+                        m, n, D);
+        mp.D = D;
+        mp.nd = n / D;
+        mp.ndpc = (mp.nd / 2) * (mp.nd / 2) * (mp.nd / 2);
+    } else {
+        return fail(c, ECMC_E_ARG, "unknown tiling %d", tiling);
+    }
+    return ECMC_OK;
+}
+
+// Single-precision screen constants of a melt (see screen() in the kernels).  Screening
+// coordinates are frame coordinates rounded once to float, so every float displacement is
+// within delta = 6 u X of the FP64 one (u = 2^-24, X the largest coordinate or displacement:
+// the frame edge, or L for the whole box).  For |d_perp| <= b the float d_perp^2 (a product
+// and one fused multiply-add, at most 3 u b^2 of rounding) is then within
+// m = 4 b delta + 2 delta^2 + 8 u b^2 of the FP64 value, the argument of the square root
+// within m + 4 u b^2, the square root within the square root of that (the ill-conditioned
+// grazing case), and the estimate of x within delta + sqrt(m + 4 u b^2) + 4 u b + u (X + b).
+// The interval half-width is twice that.
+void screen_constants(MeltPlan &mp, double sigma, double lmax, bool whole) {
+    const double u = std::ldexp(1.0, -24);
+    const double bm = std::max(sigma, lmax);
+    const double X = whole ? mp.L : (mp.D + 2) * mp.h;
+    const double delta = 6.0 * u * X + 1e-12 * mp.L;
+    const double m = 4.0 * bm * delta + 2.0 * delta * delta + 8.0 * u * bm * bm;
+    const double err = 2.0 * (delta + std::sqrt(m + 4.0 * u * bm * bm) + 4.0 * u * bm + u * (X + bm));
+    const float inf = __builtin_huge_valf();
+    mp.p_sure = std::nextafter((float)delta, inf);
+    mp.in_lo = std::nextafter((float)(sigma * sigma - m), 0.0f);
+    mp.in_hi = std::nextafter((float)(sigma * sigma + m), inf);
+    mp.err_f = std::nextafter((float)err, inf);
+}
+
+struct MeltIn {
+    double box;
+    int64_t nb;
+    int n_cells, domain_cells;
+};
+
+ecmc_status plan(const std::vector<MeltIn> &in, double sigma, double lmax, const ecmc_options &o, Plan &p,
+                 ecmc_ctx *c) {
+    if (!(std::isfinite(sigma) && sigma > 0 && std::isfinite(lmax) && lmax >= sigma))
         return fail(c, ECMC_E_ARG, "need finite box > 0, sigma > 0, l_max >= sigma");
-    if (nb < 1 || nb > 0x7fffffffLL) return fail(c, ECMC_E_ARG, "bead count %lld out of range", (long long)nb);
     if (o.precision != ECMC_PREC_FP64 && o.precision != ECMC_PREC_MIXED)
         return fail(c, ECMC_E_ARG, "precision must be ECMC_PREC_FP64 or ECMC_PREC_MIXED (got %d)", o.precision);
     if (o.schedule != ECMC_SCHED_SWEEP && o.schedule != ECMC_SCHED_PHASES)
         return fail(c, ECMC_E_ARG, "schedule must be ECMC_SCHED_SWEEP or ECMC_SCHED_PHASES (got %d)", o.schedule);
-    int n = o.n_cells;
-    if (n == 0) {
-        n = (int)std::floor(L / lmax);
-        while (n > 0 && !(L / n > lmax)) --n;
-    }
-    if (n < 4 || n > MAX_CELLS_PER_AXIS || !(L / n > lmax))
-        return fail(c, ECMC_E_BOX, "cells per axis n = %d: need 4 <= n <= %d and L/n > l_max", n, MAX_CELLS_PER_AXIS);
-    g.n = n;
-    g.h = L / n;
-    if (o.tiling == ECMC_TILING_WHOLE) {
-        g.D = n;
-        g.nd = 1;
-        g.stage = (int)std::min<int64_t>(nb, MAX_STAGE + 1);
-        if (nb > MAX_STAGE) return fail(c, ECMC_E_ARG, "whole-box tiling holds at most %d beads", MAX_STAGE);
-        if ((int64_t)n * n * n > 64 * 16)
-            return fail(c, ECMC_E_BOX, "whole-box tiling needs n^3 <= 1024 cells (n = %d)", n);
-    } else if (o.tiling == ECMC_TILING_CHECKER) {
-        const int D = o.domain_cells;
-        // D >= 2: the integer offset drawn from [0, D) is what moves the partition between
-        // sweeps; with D = 1 it is always 0 and every bead stays in its cell for good.
-        if (D < 2 || n % D != 0 || (n / D) % 2 != 0)
-            return fail(c, ECMC_E_BOX, "checkerboard needs D >= 2, n %% D == 0 and n/D even (n = %d, D = %d)", n, D);
-        g.D = D;
-        g.nd = n / D;
-        if (o.stage_capacity > 0) {
-            g.stage = o.stage_capacity;
-        } else {
-            // first tier sized for the typical domain; the few above it go to a second launch
-            const double mean = std::pow((double)(D + 2), 3) * (double)nb / ((double)n * n * n);
-            g.stage = (int)std::ceil(mean + 3.0 * std::sqrt(mean) + 2.0);
-            g.bpl2 = 16;
+    if (in.empty()) return fail(c, ECMC_E_ARG, "no melts");
+    const bool batch = in.size() > 1;
+    if (batch && o.tiling != ECMC_TILING_CHECKER)
+        return fail(c, ECMC_E_ARG, "a batch of melts needs the checkerboard tiling");
+    if (batch && o.schedule != ECMC_SCHED_SWEEP)
+        return fail(c, ECMC_E_ARG, "a batch of melts runs with the dependency-ordered sweep (ECMC_SCHED_SWEEP)");
+    p = Plan{};
+    p.whole = o.tiling == ECMC_TILING_WHOLE;
+    const int cap = o.cell_capacity > 0 ? o.cell_capacity : DEFAULT_CAP;
+    double worst = 0;  // largest typical frame
+    int64_t most = 0;  // largest possible frame
+    for (size_t m = 0; m < in.size(); ++m) {
+        MeltPlan mp;
+        ecmc_status st = plan_melt(in[m].box, in[m].nb, lmax, in[m].n_cells, in[m].domain_cells, o.tiling, mp, c,
+                                   (int)m);
+        if (st) return st;
+        screen_constants(mp, sigma, lmax, p.whole);
+        mp.bead0 = p.nb;
+        mp.cell0 = p.cells;
+        mp.dom0 = p.domains;
+        mp.tick0 = p.tickets;
+        p.nb += mp.nb;
+        p.cells += (int64_t)mp.n * mp.n * mp.n;
+        p.domains += p.whole ? 1 : (int64_t)mp.nd * mp.nd * mp.nd;
+        if ((int64_t)p.tickets + mp.ndpc > 0x7fffffffLL / 8) return fail(c, ECMC_E_ARG, "too many domains");
+        p.tickets += mp.ndpc;
+        if (!p.whole) {
+            const double f = std::pow((double)(mp.D + 2), 3);
+            worst = std::max(worst, f * (double)mp.nb / ((double)mp.n * mp.n * mp.n));
+            most = std::max(most, (int64_t)(mp.D + 2) * (mp.D + 2) * (mp.D + 2) * cap);
         }
-    } else {
-        return fail(c, ECMC_E_ARG, "unknown tiling %d", o.tiling);
+        p.melts.push_back(mp);
     }
-    if (o.tiling == ECMC_TILING_WHOLE && o.stage_capacity > 0) g.stage = std::max(g.stage, o.stage_capacity);
-    int bpl = (g.stage + 63) / 64;
+    if (p.nb > 0x7fffffffLL) return fail(c, ECMC_E_ARG, "at most 2^31 - 1 beads in all");
+    // staging capacity
+    if (p.whole) {
+        p.stage = (int)std::min<int64_t>(p.melts[0].nb, MAX_STAGE + 1);
+        if (o.stage_capacity > 0) p.stage = std::max(p.stage, o.stage_capacity);
+    } else if (o.stage_capacity > 0) {
+        p.stage = o.stage_capacity;
+    } else {
+        // first tier sized for the typical domain; the few above it are staged elsewhere
+        p.stage = (int)std::ceil(worst + 3.0 * std::sqrt(worst) + 2.0);
+        p.bpl2 = 16;
+    }
+    int bpl = (p.stage + 63) / 64;
     static const int ok[] = {1, 2, 3, 4, 6, 8, 12, 16};
     int pick = 0;
     for (int v : ok)
@@ -177,31 +279,29 @@ ecmc_status geometry(double L, double sigma, double lmax, int64_t nb, const ecmc
             pick = v;
             break;
         }
-    if (!pick) return fail(c, ECMC_E_ARG, "staging capacity %d exceeds %d", g.stage, MAX_STAGE);
-    const int ndc = o.tiling == ECMC_TILING_WHOLE ? n * n * n : g.D * g.D * g.D;
-    while (pick < 16 && ndc > 64 * pick) pick = *std::find_if(std::begin(ok), std::end(ok), [&](int v) { return v > pick; });
+    if (!pick) return fail(c, ECMC_E_ARG, "staging capacity %d exceeds %d", p.stage, MAX_STAGE);
+    int ndc = 0;
+    for (const MeltPlan &mp : p.melts) ndc = std::max(ndc, p.whole ? mp.n * mp.n * mp.n : mp.D * mp.D * mp.D);
+    while (pick < 16 && ndc > 64 * pick)
+        pick = *std::find_if(std::begin(ok), std::end(ok), [&](int v) { return v > pick; });
     if (ndc > 64 * pick) return fail(c, ECMC_E_BOX, "a domain of %d cells exceeds the staging area", ndc);
-    g.bpl = pick;
-    if (g.bpl2) {
-        // tier 2 one step above tier 1, tier 3 the full 16 beads per lane
-        const int* nxt = std::find_if(std::begin(ok), std::end(ok), [&](int v) { return v > pick; });
-        g.bpl2 = nxt == std::end(ok) ? 0 : *nxt;
-        g.bpl3 = (g.bpl2 && g.bpl2 < 16) ? 16 : 0;
+    p.bpl = pick;
+    if (p.bpl2) {
+        // by phases: tier 2 one step above tier 1, tier 3 the full 16 beads per lane
+        const int *nxt = std::find_if(std::begin(ok), std::end(ok), [&](int v) { return v > pick; });
+        p.bpl2 = nxt == std::end(ok) ? 0 : *nxt;
+        p.bpl3 = (p.bpl2 && p.bpl2 < 16) ? 16 : 0;
     }
-    if (o.tiling == ECMC_TILING_CHECKER && o.schedule == ECMC_SCHED_SWEEP && sweep_bpl_supported(g.bpl)) {
-        g.sweep = true;
-        if (g.bpl2) {
+    if (!p.whole && o.schedule == ECMC_SCHED_SWEEP && sweep_bpl_supported(p.bpl)) {
+        p.sweep = true;
+        if (p.bpl2 && most > 64 * p.bpl) {
             // automatic capacity: the domains above the LDS staging area go to workspace slots
             // that hold any frame up to the staging limit
-            const int cap = o.cell_capacity > 0 ? o.cell_capacity : DEFAULT_CAP;
-            const int64_t most = (int64_t)(g.D + 2) * (g.D + 2) * (g.D + 2) * cap;
-            if (most > 64 * g.bpl) {
-                const int64_t ndpc = (int64_t)(g.nd / 2) * (g.nd / 2) * (g.nd / 2);
-                g.slow_cap = (int)std::min<int64_t>(most, MAX_STAGE);
-                g.nslow = (int)std::min<int64_t>(ndpc, SLOW_SLOTS);
-            }
+            p.slow_cap = (int)std::min<int64_t>(most, MAX_STAGE);
+            p.nslow = (int)std::min<int64_t>(p.tickets, SLOW_SLOTS);
         }
     }
+    if (batch && !p.sweep) return fail(c, ECMC_E_ARG, "a batch of melts needs a staging capacity of at most 512 beads");
     return ECMC_OK;
 }
 
@@ -229,78 +329,84 @@ double min_image(double d, double L) {
 struct HostState {
     std::vector<double> px, py, pz;
     std::vector<int32_t> cellp, img, part, ccount, cids, porder, pstart;
+    std::vector<double> polyL;
     std::vector<int32_t> cx, cy, cz;
 };
 
-// partners, chain order, validation of bonds
-ecmc_status build_topology(ecmc_ctx *c, int64_t nb, int64_t n_bonds, const int32_t *bonds, HostState &hs) {
-    hs.part.assign(2 * nb, -1);
+// partners, chain order and validation of the bonds of melt m (bead indices local to it)
+ecmc_status build_topology(ecmc_ctx *c, int m, int64_t n_bonds, const int32_t *bonds, HostState &hs) {
+    MeltPlan &mp = c->p.melts[m];
+    const int64_t nb = mp.nb, b0 = mp.bead0;
+    int32_t *part = hs.part.data() + 2 * b0;
     for (int64_t b = 0; b < n_bonds; ++b) {
         const int32_t i = bonds[2 * b], j = bonds[2 * b + 1];
-        if (i < 0 || j < 0 || i >= nb || j >= nb || i == j) return fail(c, ECMC_E_ARG, "bond %lld invalid", (long long)b);
-        if (hs.part[2 * i] == j || hs.part[2 * i + 1] == j)
-            return fail(c, ECMC_E_ARG, "duplicate bond %d-%d", i, j);
-        int32_t *si = hs.part[2 * i] < 0 ? &hs.part[2 * i] : (hs.part[2 * i + 1] < 0 ? &hs.part[2 * i + 1] : nullptr);
-        int32_t *sj = hs.part[2 * j] < 0 ? &hs.part[2 * j] : (hs.part[2 * j + 1] < 0 ? &hs.part[2 * j + 1] : nullptr);
-        if (!si || !sj) return fail(c, ECMC_E_ARG, "bead with more than two bonds (bond %lld)", (long long)b);
-        *si = j;
-        *sj = i;
+        if (i < 0 || j < 0 || i >= nb || j >= nb || i == j)
+            return fail(c, ECMC_E_ARG, "melt %d: bond %lld invalid", m, (long long)b);
+        const int32_t gi = (int32_t)(b0 + i), gj = (int32_t)(b0 + j);
+        if (part[2 * i] == gj || part[2 * i + 1] == gj) return fail(c, ECMC_E_ARG, "melt %d: duplicate bond %d-%d", m, i, j);
+        int32_t *si = part[2 * i] < 0 ? &part[2 * i] : (part[2 * i + 1] < 0 ? &part[2 * i + 1] : nullptr);
+        int32_t *sj = part[2 * j] < 0 ? &part[2 * j] : (part[2 * j + 1] < 0 ? &part[2 * j + 1] : nullptr);
+        if (!si || !sj)
+            return fail(c, ECMC_E_ARG, "melt %d: bead with more than two bonds (bond %lld)", m, (long long)b);
+        *si = gj;
+        *sj = gi;
     }
     std::vector<char> seen(nb, 0);
-    hs.porder.clear();
-    hs.pstart.clear();
+    const size_t before = hs.porder.size();
+    mp.poly0 = (int64_t)hs.pstart.size();
     for (int64_t i = 0; i < nb; ++i) {
-        const int deg = (hs.part[2 * i] >= 0) + (hs.part[2 * i + 1] >= 0);
+        const int deg = (part[2 * i] >= 0) + (part[2 * i + 1] >= 0);
         if (seen[i] || deg > 1) continue;
         hs.pstart.push_back((int32_t)hs.porder.size());
-        int32_t prev = -1, cur = (int32_t)i;
+        hs.polyL.push_back(mp.L);
+        int32_t prev = -1, cur = (int32_t)(b0 + i);
         while (cur >= 0) {
-            seen[cur] = 1;
+            seen[cur - b0] = 1;
             hs.porder.push_back(cur);
-            int32_t nx = hs.part[2 * cur] != prev ? hs.part[2 * cur] : hs.part[2 * cur + 1];
+            const int32_t *pc = hs.part.data() + 2 * (size_t)cur;
+            int32_t nx = pc[0] != prev ? pc[0] : pc[1];
             if (nx == prev) nx = -1;
             prev = cur;
             cur = nx;
         }
     }
-    if ((int64_t)hs.porder.size() != nb) return fail(c, ECMC_E_ARG, "bond list contains a ring");
-    c->npoly = (int64_t)hs.pstart.size();
-    hs.pstart.push_back((int32_t)nb);
+    if ((int64_t)(hs.porder.size() - before) != nb) return fail(c, ECMC_E_ARG, "melt %d: bond list contains a ring", m);
+    mp.npoly = (int64_t)hs.pstart.size() - mp.poly0;
     return ECMC_OK;
 }
 
-// cell lists from the per-bead cells; overlap and tether checks
-ecmc_status build_cells(ecmc_ctx *c, HostState &hs, bool validate) {
-    const int n = c->g.n;
-    const int64_t nb = c->nb;
-    const size_t nc = (size_t)n * n * n;
-    hs.ccount.assign(nc, 0);
-    hs.cids.assign(nc * c->cap, -1);
-    hs.cellp.resize(nb);
-    for (int64_t i = 0; i < nb; ++i) {
+// cell lists of melt m from the per-bead cells; overlap and tether checks
+ecmc_status build_cells(ecmc_ctx *c, int m, HostState &hs, bool validate) {
+    const MeltPlan &mp = c->p.melts[m];
+    const int n = mp.n;
+    const int64_t b0 = mp.bead0, b1 = mp.bead0 + mp.nb;
+    int32_t *ccount = hs.ccount.data() + mp.cell0;
+    int32_t *cids = hs.cids.data() + mp.cell0 * c->cap;
+    for (int64_t i = b0; i < b1; ++i) {
         const size_t f = (size_t)hs.cx[i] + n * ((size_t)hs.cy[i] + n * (size_t)hs.cz[i]);
-        if (hs.ccount[f] >= c->cap)
-            return fail(c, ECMC_E_CELL_OVERFLOW, "cell %zu holds more than %d beads", f, c->cap);
-        hs.cids[f * c->cap + hs.ccount[f]++] = (int32_t)i;
+        if (ccount[f] >= c->cap)
+            return fail(c, ECMC_E_CELL_OVERFLOW, "melt %d: cell %zu holds more than %d beads", m, f, c->cap);
+        cids[f * c->cap + ccount[f]++] = (int32_t)i;
         hs.cellp[i] = pack_cell(hs.cx[i], hs.cy[i], hs.cz[i]);
     }
     if (!validate) return ECMC_OK;
-    const double L = c->L;
+    const double L = mp.L;
     const double lim_ov = c->sig2 * (1.0 - 2e-12);
-    for (int64_t i = 0; i < nb; ++i) {
+    for (int64_t i = b0; i < b1; ++i) {
         for (int dz = -1; dz <= 1; ++dz)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int ax = (hs.cx[i] + dx + n) % n, ay = (hs.cy[i] + dy + n) % n, az = (hs.cz[i] + dz + n) % n;
                     const size_t f = (size_t)ax + n * ((size_t)ay + n * (size_t)az);
-                    for (int t = 0; t < hs.ccount[f]; ++t) {
-                        const int32_t j = hs.cids[f * c->cap + t];
+                    for (int t = 0; t < ccount[f]; ++t) {
+                        const int32_t j = cids[f * c->cap + t];
                         if (j <= i) continue;
                         const double ex = min_image(hs.px[j] - hs.px[i], L);
                         const double ey = min_image(hs.py[j] - hs.py[i], L);
                         const double ez = min_image(hs.pz[j] - hs.pz[i], L);
                         if (ex * ex + ey * ey + ez * ez < lim_ov)
-                            return fail(c, ECMC_E_OVERLAP, "beads %lld and %d overlap", (long long)i, j);
+                            return fail(c, ECMC_E_OVERLAP, "melt %d: beads %lld and %lld overlap", m, (long long)(i - b0),
+                                        (long long)(j - b0));
                     }
                 }
         for (int t = 0; t < 2; ++t) {
@@ -310,7 +416,8 @@ ecmc_status build_cells(ecmc_ctx *c, HostState &hs, bool validate) {
             const double ey = min_image(hs.py[j] - hs.py[i], L);
             const double ez = min_image(hs.pz[j] - hs.pz[i], L);
             if (ex * ex + ey * ey + ez * ez > c->b2 * (1.0 + 2e-12))
-                return fail(c, ECMC_E_TETHER, "bond %lld-%d longer than l_max", (long long)i, j);
+                return fail(c, ECMC_E_TETHER, "melt %d: bond %lld-%lld longer than l_max", m, (long long)(i - b0),
+                            (long long)(j - b0));
         }
     }
     return ECMC_OK;
@@ -319,7 +426,7 @@ ecmc_status build_cells(ecmc_ctx *c, HostState &hs, bool validate) {
 ecmc_status upload(ecmc_ctx *c, const HostState &hs, bool topology) {
     hipStream_t s = c->stream;
     const int64_t nb = c->nb;
-    const size_t nc = (size_t)c->g.n * c->g.n * c->g.n;
+    const size_t nc = (size_t)c->p.cells;
     HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.px, hs.px.data(), 8 * nb, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.py, hs.py.data(), 8 * nb, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.pz, hs.pz.data(), 8 * nb, hipMemcpyHostToDevice, s));
@@ -327,19 +434,40 @@ ecmc_status upload(ecmc_ctx *c, const HostState &hs, bool topology) {
     HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.img, hs.img.data(), 12 * nb, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.ccount, hs.ccount.data(), 4 * nc, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.cids, hs.cids.data(), 4 * nc * c->cap, hipMemcpyHostToDevice, s));
+    std::vector<MeltDev> md;
     if (topology) {
+        md.resize(c->p.melts.size());
+        for (size_t m = 0; m < md.size(); ++m) {
+            const MeltPlan &mp = c->p.melts[m];
+            MeltDev &d = md[m];
+            d.L = mp.L;
+            d.h = mp.h;
+            d.halfL = 0.5 * mp.L;
+            d.in_lo = mp.in_lo;
+            d.in_hi = mp.in_hi;
+            d.p_sure = mp.p_sure;
+            d.err_f = mp.err_f;
+            d.n = mp.n;
+            d.D = mp.D;
+            d.nd = mp.nd;
+            d.ndpc = mp.ndpc;
+            d.tick0 = mp.tick0;
+            d.dom0 = (int)mp.dom0;
+            d.cell0 = mp.cell0;
+        }
+        HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.melts, md.data(), sizeof(MeltDev) * md.size(), hipMemcpyHostToDevice, s));
         HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.part, hs.part.data(), 8 * nb, hipMemcpyHostToDevice, s));
         HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.porder, hs.porder.data(), 4 * nb, hipMemcpyHostToDevice, s));
-        HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.pstart, hs.pstart.data(), 4 * (c->npoly + 1), hipMemcpyHostToDevice,
-                                 s));
+        HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.pstart, hs.pstart.data(), 4 * (c->npoly + 1), hipMemcpyHostToDevice, s));
+        HIP_OK(c, hipMemcpyAsync(c->ws + c->lay.polyL, hs.polyL.data(), 8 * c->npoly, hipMemcpyHostToDevice, s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.cnt, 0, 8 * NCNT, s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.dsum, 0, 8, s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.err, 0, 4, s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.log_n, 0, 8, s));
-        const size_t nc8 = nc / 8 + 1;
-        HIP_OK(c, hipMemsetAsync(c->ws + c->lay.done, 0, 4 * nc8, s));
+        HIP_OK(c, hipMemsetAsync(c->ws + c->lay.done, 0, 4 * (size_t)(c->p.domains + 1), s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.queue, 0, 8, s));
-        if (c->g.nslow > 0) HIP_OK(c, hipMemsetAsync(c->ws + c->lay.slow_lock, 0, 4 * (size_t)c->g.nslow, s));
+        HIP_OK(c, hipMemsetAsync(c->ws + c->lay.dstate, 0, 8, s));
+        if (c->p.nslow > 0) HIP_OK(c, hipMemsetAsync(c->ws + c->lay.slow_lock, 0, 4 * (size_t)c->p.nslow, s));
     }
     HIP_OK(c, hipStreamSynchronize(s));
     return ECMC_OK;
@@ -349,12 +477,118 @@ ecmc_status check_device(ecmc_ctx *c) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
     uint32_t e = 0;
     HIP_OK(c, hipMemcpy(&e, c->ws + c->lay.err, 4, hipMemcpyDeviceToHost));
-    if (e & ERR_STAGE) return fail(c, ECMC_E_CELL_OVERFLOW, "a domain exceeded the staging capacity %d", c->g.stage);
+    if (e & ERR_STAGE) return fail(c, ECMC_E_CELL_OVERFLOW, "a domain exceeded the staging capacity %d", c->p.stage);
     if (e & ERR_CELL) return fail(c, ECMC_E_CELL_OVERFLOW, "a cell exceeded its capacity %d", c->cap);
     if (e & ERR_STUCK) return fail(c, ECMC_E_STUCK, "an EC exceeded %lld iterations", (long long)c->opt.event_cap);
     if (e & ERR_RECOUNT) return fail(c, ECMC_E_DEVICE, "a domain's cell lists changed between its count and its staging");
     if (e & ERR_WAIT) return fail(c, ECMC_E_DEVICE, "a wait of the dependency-ordered sweep ran out of polls");
     return ECMC_OK;
+}
+
+std::vector<MeltIn> melt_inputs(int32_t n_melts, const ecmc_melt_desc *melts) {
+    std::vector<MeltIn> in((size_t)std::max(n_melts, 0));
+    for (int32_t m = 0; m < n_melts; ++m)
+        in[m] = {melts[m].box, melts[m].n_beads, melts[m].n_cells, melts[m].domain_cells};
+    return in;
+}
+
+// polymers of a melt: n_beads - n_bonds for linear chains (checked at init)
+int64_t polymers(int32_t n_melts, const ecmc_melt_desc *melts) {
+    int64_t np = 0;
+    for (int32_t m = 0; m < n_melts; ++m) np += std::max<int64_t>(melts[m].n_beads - melts[m].n_bonds, 1);
+    return np;
+}
+
+ecmc_status init_impl(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *melts, double sigma, double l_max,
+                      const ecmc_options *opt, int64_t npoly_layout) {
+    if (!out) return fail(nullptr, ECMC_E_ARG, "null output pointer");
+    *out = nullptr;
+    if (!opt || !melts || n_melts < 1) return fail(nullptr, ECMC_E_ARG, "null argument or no melts");
+    for (int32_t m = 0; m < n_melts; ++m)
+        if (!melts[m].positions || melts[m].n_bonds < 0 || (melts[m].n_bonds > 0 && !melts[m].bonds))
+            return fail(nullptr, ECMC_E_ARG, "melt %d: null argument", m);
+    ecmc_ctx *c = new ecmc_ctx();
+    c->opt = *opt;
+    if (c->opt.event_cap <= 0) c->opt.event_cap = DEFAULT_EVENT_CAP;
+    c->stream = (hipStream_t)opt->stream;
+    c->sigma = sigma;
+    c->lmax = l_max;
+    c->sig2 = sigma * sigma;
+    c->b2 = l_max * l_max;
+    c->cap = opt->cell_capacity > 0 ? opt->cell_capacity : DEFAULT_CAP;
+    auto bail = [&](ecmc_status s) {
+        g_err = c->err;
+        ecmc_destroy(c);
+        return s;
+    };
+    ecmc_status st = plan(melt_inputs(n_melts, melts), sigma, l_max, *opt, c->p, c);
+    if (st) return bail(st);
+    c->nb = c->p.nb;
+    c->lay = make_layout(c->p, npoly_layout, c->cap, opt->event_log_capacity);
+    if (!opt->workspace || opt->workspace_bytes < c->lay.total || ((uintptr_t)opt->workspace & 255))
+        return bail(fail(c, ECMC_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)", c->lay.total,
+                         opt->workspace_bytes));
+    c->ws = (char *)opt->workspace;
+    if (c->p.bpl2) {
+        // by phases (also for a sweep-capable melt when only some colours run)
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(c, ECMC_E_DEVICE, "creating the second stream failed"));
+    }
+
+    HostState hs;
+    const int64_t nb = c->nb;
+    hs.px.resize(nb);
+    hs.py.resize(nb);
+    hs.pz.resize(nb);
+    hs.cx.resize(nb);
+    hs.cy.resize(nb);
+    hs.cz.resize(nb);
+    hs.img.assign(3 * nb, 0);
+    hs.part.assign(2 * nb, -1);
+    hs.cellp.resize(nb);
+    hs.ccount.assign((size_t)c->p.cells, 0);
+    hs.cids.assign((size_t)c->p.cells * c->cap, -1);
+    for (int32_t m = 0; m < n_melts; ++m) {
+        const MeltPlan &mp = c->p.melts[m];
+        for (int64_t i = 0; i < mp.nb; ++i) {
+            double w[3];
+            for (int a = 0; a < 3; ++a) {
+                const double v = melts[m].positions[3 * i + a];
+                if (!std::isfinite(v)) return bail(fail(c, ECMC_E_ARG, "melt %d: position %lld is not finite", m, (long long)i));
+                w[a] = wrap_coord(v, mp.L);
+            }
+            const int64_t g = mp.bead0 + i;
+            hs.px[g] = w[0];
+            hs.py[g] = w[1];
+            hs.pz[g] = w[2];
+            hs.cx[g] = bin_coord(w[0], mp.n, mp.h, mp.L);
+            hs.cy[g] = bin_coord(w[1], mp.n, mp.h, mp.L);
+            hs.cz[g] = bin_coord(w[2], mp.n, mp.h, mp.L);
+        }
+        if ((st = build_topology(c, m, melts[m].n_bonds, melts[m].bonds, hs))) return bail(st);
+        if ((st = build_cells(c, m, hs, true))) return bail(st);
+    }
+    c->npoly = (int64_t)hs.pstart.size();
+    if (c->npoly > npoly_layout) return bail(fail(c, ECMC_E_ARG, "more polymers than the layout holds"));
+    hs.pstart.push_back((int32_t)nb);
+    if ((st = upload(c, hs, true))) return bail(st);
+    *out = c;
+    return ECMC_OK;
+}
+
+ecmc_melt_desc single_melt(double box, int64_t n_beads, const double *positions, int64_t n_bonds,
+                           const int32_t *bonds, const ecmc_options &o) {
+    ecmc_melt_desc d{};
+    d.box = box;
+    d.n_beads = n_beads;
+    d.positions = positions;
+    d.n_bonds = n_bonds;
+    d.bonds = bonds;
+    d.n_cells = o.n_cells;
+    d.domain_cells = o.tiling == ECMC_TILING_CHECKER ? o.domain_cells : 0;
+    return d;
 }
 
 }  // namespace
@@ -368,84 +602,50 @@ void ecmc_default_options(ecmc_options *o) {
     o->domain_cells = 2;
 }
 
+ecmc_status ecmc_workspace_size_batch(int32_t n_melts, const ecmc_melt_desc *melts, double sigma, double l_max,
+                                      const ecmc_options *opt, size_t *bytes) {
+    if (!opt || !bytes || !melts || n_melts < 1) return fail(nullptr, ECMC_E_ARG, "null argument or no melts");
+    Plan p;
+    ecmc_status st = plan(melt_inputs(n_melts, melts), sigma, l_max, *opt, p, nullptr);
+    if (st) return st;
+    const int cap = opt->cell_capacity > 0 ? opt->cell_capacity : DEFAULT_CAP;
+    *bytes = make_layout(p, polymers(n_melts, melts), cap, opt->event_log_capacity).total;
+    return ECMC_OK;
+}
+
 ecmc_status ecmc_workspace_size(double box, double sigma, double l_max, int64_t n_beads, const ecmc_options *opt,
                                 size_t *bytes) {
     if (!opt || !bytes) return fail(nullptr, ECMC_E_ARG, "null argument");
-    Geometry g;
-    ecmc_status st = geometry(box, sigma, l_max, n_beads, *opt, g, nullptr);
+    // bonds are not known here: room for up to one polymer per bead
+    const ecmc_melt_desc d = single_melt(box, n_beads, nullptr, 0, nullptr, *opt);
+    Plan p;
+    ecmc_status st = plan(melt_inputs(1, &d), sigma, l_max, *opt, p, nullptr);
     if (st) return st;
     const int cap = opt->cell_capacity > 0 ? opt->cell_capacity : DEFAULT_CAP;
-    *bytes = make_layout(n_beads, g.n, cap, opt->event_log_capacity, g.nslow, g.slow_cap).total;
+    *bytes = make_layout(p, std::max<int64_t>(n_beads, 1), cap, opt->event_log_capacity).total;
     return ECMC_OK;
 }
 
 ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, int64_t n_beads,
                       const double *positions, int64_t n_bonds, const int32_t *bonds, const ecmc_options *opt) {
-    if (!out) return fail(nullptr, ECMC_E_ARG, "null output pointer");
-    *out = nullptr;
-    if (!opt || !positions || n_bonds < 0 || (n_bonds > 0 && !bonds)) return fail(nullptr, ECMC_E_ARG, "null argument");
-    ecmc_ctx *c = new ecmc_ctx();
-    c->opt = *opt;
-    if (c->opt.event_cap <= 0) c->opt.event_cap = DEFAULT_EVENT_CAP;
-    c->stream = (hipStream_t)opt->stream;
-    c->L = box;
-    c->sigma = sigma;
-    c->lmax = l_max;
-    c->sig2 = sigma * sigma;
-    c->b2 = l_max * l_max;
-    c->nb = n_beads;
-    c->cap = opt->cell_capacity > 0 ? opt->cell_capacity : DEFAULT_CAP;
-    auto bail = [&](ecmc_status s) {
-        g_err = c->err;
-        ecmc_destroy(c);
-        return s;
-    };
-    ecmc_status st = geometry(box, sigma, l_max, n_beads, *opt, c->g, c);
-    if (st) return bail(st);
-    c->lay = make_layout(n_beads, c->g.n, c->cap, opt->event_log_capacity, c->g.nslow, c->g.slow_cap);
-    if (!opt->workspace || opt->workspace_bytes < c->lay.total || ((uintptr_t)opt->workspace & 255))
-        return bail(fail(c, ECMC_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)", c->lay.total,
-                         opt->workspace_bytes));
-    c->ws = (char *)opt->workspace;
-    if (c->g.bpl2) {
-        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess)
-            return bail(fail(c, ECMC_E_DEVICE, "creating the second stream failed"));
-    }
+    if (!opt) return fail(nullptr, ECMC_E_ARG, "null argument");
+    const ecmc_melt_desc d = single_melt(box, n_beads, positions, n_bonds, bonds, *opt);
+    // the layout ecmc_workspace_size promised: room for one polymer per bead
+    return init_impl(out, 1, &d, sigma, l_max, opt, std::max<int64_t>(n_beads, 1));
+}
 
-    HostState hs;
-    hs.px.resize(n_beads);
-    hs.py.resize(n_beads);
-    hs.pz.resize(n_beads);
-    hs.cx.resize(n_beads);
-    hs.cy.resize(n_beads);
-    hs.cz.resize(n_beads);
-    hs.img.assign(3 * n_beads, 0);
-    for (int64_t i = 0; i < n_beads; ++i) {
-        double w[3];
-        for (int a = 0; a < 3; ++a) {
-            const double v = positions[3 * i + a];
-            if (!std::isfinite(v)) return bail(fail(c, ECMC_E_ARG, "position %lld is not finite", (long long)i));
-            w[a] = wrap_coord(v, box);
-        }
-        hs.px[i] = w[0];
-        hs.py[i] = w[1];
-        hs.pz[i] = w[2];
-        hs.cx[i] = bin_coord(w[0], c->g.n, c->g.h, box);
-        hs.cy[i] = bin_coord(w[1], c->g.n, c->g.h, box);
-        hs.cz[i] = bin_coord(w[2], c->g.n, c->g.h, box);
-    }
-    if ((st = build_topology(c, n_beads, n_bonds, bonds, hs))) return bail(st);
-    if ((st = build_cells(c, hs, true))) return bail(st);
-    if ((st = upload(c, hs, true))) return bail(st);
-    *out = c;
-    return ECMC_OK;
+ecmc_status ecmc_init_batch(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *melts, double sigma,
+                            double l_max, const ecmc_options *opt) {
+    if (!melts || n_melts < 1) return fail(nullptr, ECMC_E_ARG, "null argument or no melts");
+    return init_impl(out, n_melts, melts, sigma, l_max, opt, polymers(n_melts, melts));
 }
 
 ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed, uint32_t colour_mask) {
     if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
     if (n_chains < 0 || !std::isfinite(ell) || !(ell >= 0)) return fail(c, ECMC_E_ARG, "need n_chains >= 0, ell >= 0");
+    const bool batch = c->p.melts.size() > 1;
+    if (batch && (colour_mask & 0xFFu) != 0xFFu) return fail(c, ECMC_E_ARG, "a batch of melts sweeps all eight colours");
+    const MeltPlan &m0 = c->p.melts[0];
     PhaseArgs a{};
     a.px = c->dev<double>(c->lay.px);
     a.py = c->dev<double>(c->lay.py);
@@ -458,138 +658,123 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     a.dstage = c->dev<int32_t>(c->lay.dstage);
     a.done = c->dev<uint32_t>(c->lay.done);
     a.queue = c->dev<uint32_t>(c->lay.queue);
+    a.dstate = c->dev<uint32_t>(c->lay.dstate);
+    a.melts = c->dev<MeltDev>(c->lay.melts);
+    a.n_melts = (int)c->p.melts.size();
+    a.tickets = c->p.tickets;
     a.slow = c->dev<double>(c->lay.slow);
     a.slow_lock = c->dev<uint32_t>(c->lay.slow_lock);
-    a.nslow = c->g.nslow;
-    a.slow_cap = c->g.nslow > 0 ? c->g.slow_cap : 0;
+    a.nslow = c->p.nslow;
+    a.slow_cap = c->p.nslow > 0 ? c->p.slow_cap : 0;
     a.cnt = c->dev<unsigned long long>(c->lay.cnt);
     a.sum_delta = c->dev<double>(c->lay.dsum);
     a.err = c->dev<unsigned int>(c->lay.err);
     a.log = c->opt.event_log_capacity > 0 ? c->dev<ecmc_event>(c->lay.log) : nullptr;
     a.log_n = c->dev<unsigned long long>(c->lay.log_n);
     a.log_cap = c->opt.event_log_capacity;
-    a.L = c->L;
-    a.h = c->g.h;
+    // melt 0's geometry: the phase kernels run a single melt; the sweep kernel takes every
+    // melt's own from the table
+    a.L = m0.L;
+    a.h = m0.h;
+    a.halfL = 0.5 * m0.L;
+    a.n = m0.n;
+    a.D = m0.D;
+    a.nd = m0.nd;
+    a.ndpc = m0.ndpc;
+    a.in_lo = m0.in_lo;
+    a.in_hi = m0.in_hi;
+    a.p_sure = m0.p_sure;
+    a.err_f = m0.err_f;
     a.sig2 = c->sig2;
     a.b2 = c->b2;
+    a.sig2f = (float)c->sig2;
+    a.b2f = (float)c->b2;
     a.ell = ell;
-    a.event_cap = c->opt.event_cap;
-    a.n = c->g.n;
-    a.D = c->g.D;
-    a.nd = c->g.nd;
+    a.event_cap = (int)std::min<int64_t>(c->opt.event_cap, INT32_MAX);
     a.cap = c->cap;
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
-    a.sweep = c->sweep_ctr;
+    a.stream = 0;
     a.exact_search = c->opt.precision == ECMC_PREC_FP64 ? 1 : 0;
     a.swap = c->opt.swap_moves ? 1 : 0;
-    a.halfL = 0.5 * c->L;
-    {
-        // Single-precision screen (see screen() in the kernels).  Screening coordinates are frame
-        // coordinates rounded once to float, so every float displacement is within
-        // delta = 6 u X of the FP64 one (u = 2^-24, X the largest coordinate or displacement:
-        // the frame edge, or L for the whole box).  For |d_perp| <= b the float d_perp^2 is
-        // then within m = 4 b delta + 2 delta^2 + 8 u b^2 of the FP64 value, the argument of
-        // the square root within m + 4 u b^2, the square root within the square root of that
-        // (the ill-conditioned grazing case), and the estimate of x within
-        // delta + sqrt(m + 4 u b^2) + 4 u b + u (X + b).  The interval half-width is twice that.
-        const double u = std::ldexp(1.0, -24);
-        const double bm = std::max(c->sigma, c->lmax);
-        const bool whole = c->opt.tiling == ECMC_TILING_WHOLE;
-        const double X = whole ? c->L : (c->g.D + 2) * c->g.h;
-        const double delta = 6.0 * u * X + 1e-12 * c->L;
-        const double m = 4.0 * bm * delta + 2.0 * delta * delta + 8.0 * u * bm * bm;
-        const double err = 2.0 * (delta + std::sqrt(m + 4.0 * u * bm * bm) + 4.0 * u * bm + u * (X + bm));
-        const float inf = __builtin_huge_valf();
-        a.p_sure = std::nextafter((float)delta, inf);
-        a.in_lo = std::nextafter((float)(c->sig2 - m), 0.0f);
-        a.in_hi = std::nextafter((float)(c->sig2 + m), inf);
-        a.err_f = std::nextafter((float)err, inf);
-        a.sig2f = (float)c->sig2;
-        a.b2f = (float)c->b2;
-    }
     const bool log = c->opt.event_log_capacity > 0;
-    auto launch = [&](int grid) -> ecmc_status {
+    auto timed = [&](auto body) -> ecmc_status {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->opt.time_kernels) {
             HIP_OK(c, hipEventCreate(&e0));
             HIP_OK(c, hipEventCreate(&e1));
             HIP_OK(c, hipEventRecord(e0, c->stream));
         }
-        // every domain's bead count first, on the main stream: the tier launches pick their
-        // domains by it and never recount (a count taken while another tier rewrites a
-        // domain's cell lists could be half-updated and claim that domain twice)
-        HIP_OK(c, launch_count(a, grid, c->stream));
-        // the tiers take disjoint sets of domains of one colour, which never interact: the
-        // larger (rarer) tiers run on a second stream concurrently with the first
-        if (c->g.bpl2) {
-            HIP_OK(c, hipEventRecord(c->fork, c->stream));
-            HIP_OK(c, hipStreamWaitEvent(c->side, c->fork, 0));
-            PhaseArgs b = a;
-            b.stage_lo = 64 * c->g.bpl;
-            b.stage_hi = c->g.bpl3 ? 64 * c->g.bpl2 : 0x7fffffff;
-            HIP_OK(c, launch_phase(b, c->g.bpl2, log, grid, c->side));
-            if (c->g.bpl3) {
-                b.stage_lo = 64 * c->g.bpl2;
-                b.stage_hi = 0x7fffffff;
-                HIP_OK(c, launch_phase(b, c->g.bpl3, log, grid, c->side));
-            }
-            HIP_OK(c, hipEventRecord(c->join, c->side));
-        }
-        a.stage_lo = 0;
-        a.stage_hi = c->g.bpl2 ? 64 * c->g.bpl : 0x7fffffff;
-        HIP_OK(c, launch_phase(a, c->g.bpl, log, grid, c->stream));
-        if (c->g.bpl2) HIP_OK(c, hipStreamWaitEvent(c->stream, c->join, 0));
+        ecmc_status st = body();
+        if (st) return st;
         if (c->opt.time_kernels) {
             HIP_OK(c, hipEventRecord(e1, c->stream));
             c->timing.emplace_back(e0, e1);
         }
         return ECMC_OK;
     };
+    auto phase = [&](int grid) -> ecmc_status {
+        return timed([&]() -> ecmc_status {
+            // every domain's bead count first, on the main stream: the tier launches pick their
+            // domains by it and never recount (a count taken while another tier rewrites a
+            // domain's cell lists could be half-updated and claim that domain twice)
+            HIP_OK(c, launch_count(a, grid, c->stream));
+            // the tiers take disjoint sets of domains of one colour, which never interact: the
+            // larger (rarer) tiers run on a second stream concurrently with the first
+            if (c->p.bpl2) {
+                HIP_OK(c, hipEventRecord(c->fork, c->stream));
+                HIP_OK(c, hipStreamWaitEvent(c->side, c->fork, 0));
+                PhaseArgs b = a;
+                b.stage_lo = 64 * c->p.bpl;
+                b.stage_hi = c->p.bpl3 ? 64 * c->p.bpl2 : 0x7fffffff;
+                HIP_OK(c, launch_phase(b, c->p.bpl2, log, grid, c->side));
+                if (c->p.bpl3) {
+                    b.stage_lo = 64 * c->p.bpl2;
+                    b.stage_hi = 0x7fffffff;
+                    HIP_OK(c, launch_phase(b, c->p.bpl3, log, grid, c->side));
+                }
+                HIP_OK(c, hipEventRecord(c->join, c->side));
+            }
+            a.stage_lo = 0;
+            a.stage_hi = c->p.bpl2 ? 64 * c->p.bpl : 0x7fffffff;
+            HIP_OK(c, launch_phase(a, c->p.bpl, log, grid, c->stream));
+            if (c->p.bpl2) HIP_OK(c, hipStreamWaitEvent(c->stream, c->join, 0));
+            return ECMC_OK;
+        });
+    };
     ecmc_status st = ECMC_OK;
-    if (c->opt.tiling == ECMC_TILING_WHOLE) {
+    if (c->p.whole) {
         a.whole = 1;
-        a.K = n_chains;
+        if (n_chains > INT32_MAX) return fail(c, ECMC_E_ARG, "at most %d ECs per domain and sweep", INT32_MAX);
+        a.K = (int)n_chains;
         a.colour = 0;
-        if (n_chains > 0 && (colour_mask & 1u)) st = launch(1);
+        if (n_chains > 0 && (colour_mask & 1u)) st = phase(1);
     } else {
         a.whole = 0;
-        const int64_t nd = c->g.nd;
-        const int64_t ndom = nd * nd * nd;
-        a.K = (n_chains + ndom - 1) / ndom;
-        uint32_t ctr[4] = {0u, 0u, c->sweep_ctr, 1u};
-        philox4x32_10(ctr, a.key0, a.key1);
-        for (int ax = 0; ax < 3; ++ax) a.off[ax] = (int)scale_u32(ctr[ax], (uint32_t)c->g.D);
-        const int grid = (int)((nd / 2) * (nd / 2) * (nd / 2));
-        if (c->g.sweep && (colour_mask & 0xFFu) == 0xFFu) {
-            // all eight colours in one dependency-ordered launch
-            if (a.K > 0) {
-                if (++c->epoch == 0) ++c->epoch;
-                a.epoch = c->epoch;
-                a.ndpc = grid;
-                hipEvent_t e0 = nullptr, e1 = nullptr;
-                if (c->opt.time_kernels) {
-                    HIP_OK(c, hipEventCreate(&e0));
-                    HIP_OK(c, hipEventCreate(&e1));
-                    HIP_OK(c, hipEventRecord(e0, c->stream));
-                }
+        const int64_t K = (n_chains + c->p.domains - 1) / c->p.domains;
+        if (K > INT32_MAX) return fail(c, ECMC_E_ARG, "at most %d ECs per domain and sweep", INT32_MAX);
+        a.K = (int)K;
+        if (c->p.sweep && (colour_mask & 0xFFu) == 0xFFu && a.K > 0) {
+            // all eight colours of every melt in one dependency-ordered launch, which also
+            // advances the device-side sweep counter
+            st = timed([&]() -> ecmc_status {
                 int waves = 0;
-                HIP_OK(c, launch_sweep(a, c->g.bpl, log, &waves, c->stream));
-                if (c->opt.time_kernels) {
-                    HIP_OK(c, hipEventRecord(e1, c->stream));
-                    c->timing.emplace_back(e0, e1);
-                }
-            }
-        } else {
-            for (int colour = 0; colour < 8 && st == ECMC_OK && a.K > 0; ++colour) {
-                if (!((colour_mask >> colour) & 1u)) continue;
-                a.colour = colour;
-                st = launch(grid);
-            }
+                HIP_OK(c, launch_sweep(a, c->p.bpl, log, &waves, c->stream));
+                return ECMC_OK;
+            });
+            if (st == ECMC_OK) c->sweep_ctr++;
+            return st;
+        }
+        for (int colour = 0; colour < 8 && st == ECMC_OK && a.K > 0; ++colour) {
+            if (!((colour_mask >> colour) & 1u)) continue;
+            a.colour = colour;
+            st = phase(m0.ndpc);
         }
     }
+    if (st) return st;
+    HIP_OK(c, launch_advance(a, c->stream));
     c->sweep_ctr++;
-    return st;
+    return ECMC_OK;
 }
 
 ecmc_status ecmc_sweep(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed) {
@@ -601,12 +786,10 @@ ecmc_status ecmc_synchronize(ecmc_ctx *c) {
     return check_device(c);
 }
 
-ecmc_status ecmc_observables(ecmc_ctx *c, int32_t nbins, double *r2, double *rg2, int64_t *hist, double *mid,
-                             int64_t *n_poly) {
-    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
-    if (nbins <= 0 || nbins > MAX_BINS) return fail(c, ECMC_E_ARG, "nbins must be in [1, %d]", MAX_BINS);
-    if (n_poly) *n_poly = c->npoly;
-    HIP_OK(c, hipMemsetAsync(c->ws + c->lay.hist, 0, 8 * nbins, c->stream));
+}  // extern "C"
+
+namespace {
+ObsArgs obs_args(ecmc_ctx *c) {
     ObsArgs o{};
     o.px = c->dev<double>(c->lay.px);
     o.py = c->dev<double>(c->lay.py);
@@ -614,11 +797,23 @@ ecmc_status ecmc_observables(ecmc_ctx *c, int32_t nbins, double *r2, double *rg2
     o.img = c->dev<int32_t>(c->lay.img);
     o.porder = c->dev<int32_t>(c->lay.porder);
     o.pstart = c->dev<int32_t>(c->lay.pstart);
+    o.polyL = c->dev<double>(c->lay.polyL);
     o.npoly = c->npoly;
-    o.L = c->L;
-    o.halfL = 0.5 * c->L;
     o.sigma = c->sigma;
     o.bmax = c->lmax;
+    return o;
+}
+}  // namespace
+
+extern "C" {
+
+ecmc_status ecmc_observables(ecmc_ctx *c, int32_t nbins, double *r2, double *rg2, int64_t *hist, double *mid,
+                             int64_t *n_poly) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    if (nbins <= 0 || nbins > MAX_BINS) return fail(c, ECMC_E_ARG, "nbins must be in [1, %d]", MAX_BINS);
+    if (n_poly) *n_poly = c->npoly;
+    HIP_OK(c, hipMemsetAsync(c->ws + c->lay.hist, 0, 8 * nbins, c->stream));
+    ObsArgs o = obs_args(c);
     o.nbins = nbins;
     o.r2 = c->dev<double>(c->lay.r2);
     o.rg2 = c->dev<double>(c->lay.rg2);
@@ -637,16 +832,7 @@ ecmc_status ecmc_observables(ecmc_ctx *c, int32_t nbins, double *r2, double *rg2
 ecmc_status ecmc_shape(ecmc_ctx *c, double *gyr, double *eig, double *com, int64_t *n_poly) {
     if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
     if (n_poly) *n_poly = c->npoly;
-    ObsArgs o{};
-    o.px = c->dev<double>(c->lay.px);
-    o.py = c->dev<double>(c->lay.py);
-    o.pz = c->dev<double>(c->lay.pz);
-    o.img = c->dev<int32_t>(c->lay.img);
-    o.porder = c->dev<int32_t>(c->lay.porder);
-    o.pstart = c->dev<int32_t>(c->lay.pstart);
-    o.npoly = c->npoly;
-    o.L = c->L;
-    o.halfL = 0.5 * c->L;
+    ObsArgs o = obs_args(c);
     o.gyr = c->dev<double>(c->lay.shape);
     o.eig = o.gyr + 6 * c->npoly;
     o.com = o.eig + 3 * c->npoly;
@@ -732,8 +918,7 @@ ecmc_status ecmc_get_event_log(ecmc_ctx *c, ecmc_event *out, int64_t capacity, i
     if (n_total) *n_total = (int64_t)n;
     const int64_t have = std::min<int64_t>((int64_t)n, c->opt.event_log_capacity);
     const int64_t take = std::min<int64_t>(have, capacity);
-    if (out && take > 0)
-        HIP_OK(c, hipMemcpy(out, c->ws + c->lay.log, sizeof(ecmc_event) * take, hipMemcpyDeviceToHost));
+    if (out && take > 0) HIP_OK(c, hipMemcpy(out, c->ws + c->lay.log, sizeof(ecmc_event) * take, hipMemcpyDeviceToHost));
     return ECMC_OK;
 }
 
@@ -750,33 +935,41 @@ ecmc_status ecmc_set_state(ecmc_ctx *c, const double *pos, const int32_t *cells,
     HIP_OK(c, hipStreamSynchronize(c->stream));
     HostState hs;
     const int64_t nb = c->nb;
-    const int n = c->g.n;
-    const double h = c->g.h, L = c->L;
     hs.px.resize(nb);
     hs.py.resize(nb);
     hs.pz.resize(nb);
     hs.cx.resize(nb);
     hs.cy.resize(nb);
     hs.cz.resize(nb);
+    hs.cellp.resize(nb);
     hs.img.assign(images, images + 3 * nb);
-    auto bnd = [&](int k) { return k < n ? (double)k * h : L; };
-    for (int64_t i = 0; i < nb; ++i) {
-        for (int a = 0; a < 3; ++a) {
-            const int cc = cells[3 * i + a];
-            const double v = pos[3 * i + a];
-            if (cc < 0 || cc >= n || !(v >= bnd(cc) - 1e-12 && v <= bnd(cc + 1) + 1e-12))
-                return fail(c, ECMC_E_ARG, "bead %lld: coordinate outside its cell", (long long)i);
+    hs.ccount.assign((size_t)c->p.cells, 0);
+    hs.cids.assign((size_t)c->p.cells * c->cap, -1);
+    for (size_t m = 0; m < c->p.melts.size(); ++m) {
+        const MeltPlan &mp = c->p.melts[m];
+        const int n = mp.n;
+        const double h = mp.h, L = mp.L;
+        auto bnd = [&](int k) { return k < n ? (double)k * h : L; };
+        for (int64_t i = mp.bead0; i < mp.bead0 + mp.nb; ++i) {
+            for (int a = 0; a < 3; ++a) {
+                const int cc = cells[3 * i + a];
+                const double v = pos[3 * i + a];
+                if (cc < 0 || cc >= n || !(v >= bnd(cc) - 1e-12 && v <= bnd(cc + 1) + 1e-12))
+                    return fail(c, ECMC_E_ARG, "bead %lld: coordinate outside its cell", (long long)i);
+            }
+            hs.px[i] = pos[3 * i];
+            hs.py[i] = pos[3 * i + 1];
+            hs.pz[i] = pos[3 * i + 2];
+            hs.cx[i] = cells[3 * i];
+            hs.cy[i] = cells[3 * i + 1];
+            hs.cz[i] = cells[3 * i + 2];
         }
-        hs.px[i] = pos[3 * i];
-        hs.py[i] = pos[3 * i + 1];
-        hs.pz[i] = pos[3 * i + 2];
-        hs.cx[i] = cells[3 * i];
-        hs.cy[i] = cells[3 * i + 1];
-        hs.cz[i] = cells[3 * i + 2];
+        ecmc_status st = build_cells(c, (int)m, hs, false);
+        if (st) return st;
     }
-    ecmc_status st = build_cells(c, hs, false);
+    ecmc_status st = upload(c, hs, false);
     if (st) return st;
-    if ((st = upload(c, hs, false))) return st;
+    HIP_OK(c, hipMemcpy(c->ws + c->lay.dstate, &sweep_counter, 4, hipMemcpyHostToDevice));
     c->sweep_ctr = sweep_counter;
     return ECMC_OK;
 }
@@ -798,11 +991,41 @@ ecmc_status ecmc_kernel_time(ecmc_ctx *c, double *ms, int64_t *launches) {
     return ECMC_OK;
 }
 
-uint32_t ecmc_sweep_counter(const ecmc_ctx *c) { return c ? c->sweep_ctr : 0; }
-int32_t ecmc_n_cells(const ecmc_ctx *c) { return c ? c->g.n : 0; }
-double ecmc_cell_size(const ecmc_ctx *c) { return c ? c->g.h : 0.0; }
+uint32_t ecmc_sweep_counter(const ecmc_ctx *c) {
+    if (!c) return 0;
+    // the device holds the count: a replayed graph of sweeps advances it without the host
+    uint32_t v = c->sweep_ctr;
+    if (hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(&v, c->ws + c->lay.dstate, 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return c->sweep_ctr;
+    return v;
+}
+
+int32_t ecmc_n_cells(const ecmc_ctx *c) { return c ? c->p.melts[0].n : 0; }
+double ecmc_cell_size(const ecmc_ctx *c) { return c ? c->p.melts[0].h : 0.0; }
 int32_t ecmc_stage_capacity(const ecmc_ctx *c) {
-    return c ? 64 * (c->g.bpl3 ? c->g.bpl3 : (c->g.bpl2 ? c->g.bpl2 : c->g.bpl)) : 0;
+    if (!c) return 0;
+    if (c->p.sweep) return std::max(64 * c->p.bpl, c->p.nslow > 0 ? c->p.slow_cap : 0);
+    return 64 * (c->p.bpl3 ? c->p.bpl3 : (c->p.bpl2 ? c->p.bpl2 : c->p.bpl));
+}
+int32_t ecmc_n_melts(const ecmc_ctx *c) { return c ? (int32_t)c->p.melts.size() : 0; }
+
+ecmc_status ecmc_get_melt_info(const ecmc_ctx *c, int32_t m, ecmc_melt_info *out) {
+    if (!c || !out) return fail(nullptr, ECMC_E_ARG, "null argument");
+    if (m < 0 || m >= (int32_t)c->p.melts.size()) return fail(nullptr, ECMC_E_ARG, "melt %d out of range", m);
+    const MeltPlan &mp = c->p.melts[m];
+    std::memset(out, 0, sizeof *out);
+    out->box = mp.L;
+    out->cell_size = mp.h;
+    out->first_bead = mp.bead0;
+    out->n_beads = mp.nb;
+    out->first_polymer = mp.poly0;
+    out->n_polymers = mp.npoly;
+    out->first_domain = mp.dom0;
+    out->n_domains = (int64_t)mp.nd * mp.nd * mp.nd;
+    out->n_cells = mp.n;
+    out->domain_cells = mp.D;
+    return ECMC_OK;
 }
 
 void ecmc_destroy(ecmc_ctx *c) {

@@ -32,6 +32,15 @@ constexpr double INF = __builtin_huge_val();
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// A kernel argument read again where it is used.  Arguments needed only before and after the
+// EC loop (the staging and write-back pointers, the sweep's own state) would otherwise stay
+// in scalar registers through the loop and push its constants out to VGPR lanes, to be
+// reloaded at every step.
+template <class T>
+__device__ __forceinline__ T late(const T &arg) {
+    return *(const volatile T *)&arg;
+}
+
 __device__ __forceinline__ double rdlane(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -161,6 +170,25 @@ struct Stage {
     __device__ __forceinline__ double *axis(int ax) const { return pos + ax * stride; }
 };
 
+// Correctly rounded square root of an x that is 0 or at least 2^-767 (every argument here:
+// a difference of squares of lengths near sigma, or 0 after the clamp).  A hardware estimate
+// of 1/sqrt(x) refined by coupled Newton steps on g ~ sqrt(x) and h ~ 1/(2 sqrt(x)), with a
+// final residual correction (Markstein); the general square root adds a rescaling for
+// x < 2^-767 and a fix-up for 0 and infinity around the same steps, which for these
+// arguments change nothing: the results are the same bits.
+__device__ __forceinline__ double sqrt_nonneg(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    return x > 0.0 ? g : 0.0;
+}
+
 // Exact FP64 candidate of one staged bead: displacement from the pivot (periodic shift
 // from the cell-index difference, added after the subtraction), d_par and d_perp^2, then
 //   hard sphere, if d_par > 0 and d_perp^2 < sigma^2:  x = d_par - sqrt(sigma^2 - d_perp^2)
@@ -189,7 +217,7 @@ __device__ __forceinline__ bool exact_candidate(double A, double B, double C, in
     hs = (dpar > 0.0) && (dperp2 < sig2);
     double arg = (hs ? sig2 : b2) - dperp2;
     if (!(arg > 0.0)) arg = 0.0;
-    const double sq = __builtin_sqrt(arg);
+    const double sq = sqrt_nonneg(arg);
     double v = hs ? dpar - sq : dpar + sq;
     if (!(v > 0.0)) v = 0.0;
     x = v;
@@ -227,7 +255,6 @@ struct Screen {
 template <int BPL, bool WHOLE>
 __device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> &R, const Pivot &pv, int sha, int shb,
                                        int shc, double sgnd, const ScreenK &K) {
-    const int lane = lane_id();
     const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
     const float sgnf = sgnd > 0.0 ? 1.0f : -1.0f;
     // minima of hi and lo as bit patterns: both are >= 0 (or +inf), where the unsigned order of
@@ -236,9 +263,10 @@ __device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> 
     unsigned hmin = INFB, lmin = INFB;
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
-        const int idx = k * 64 + lane;
-        const bool me = idx == pv.P;
-        const bool partner = (idx == q0) || (idx == q1);
+        // the lanes of this slot holding the pivot and its partners, as scalar lane masks
+        const unsigned long long mme = (pv.P >> 6) == k ? 1ull << (pv.P & 63) : 0ull;
+        const unsigned long long mpart =
+            ((q0 >> 6) == k ? 1ull << (q0 & 63) : 0ull) | ((q1 >> 6) == k ? 1ull << (q1 & 63) : 0ull);
         float da = R.A[k] - pv.fa;
         float db = R.B[k] - pv.fb;
         float dc = R.C[k] - pv.fc;
@@ -251,28 +279,32 @@ __device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> 
             dc = dc + (ec > 1 ? -K.Lf : (ec < -1 ? K.Lf : 0.0f));
         }
         const float p = da * sgnf;
-        const float q = db * db + dc * dc;
-        const bool hs_sure = (p > K.p_sure) && (q < K.in_lo);
-        const bool hs_maybe = (p > -K.p_sure) && (q < K.in_hi);
+        // one rounding fewer than db * db + dc * dc, so within the same error bound
+        const float q = __builtin_fmaf(db, db, dc * dc);
+        // lane masks (one ballot per comparison, combined in scalar registers): a hard-sphere
+        // contact surely / possibly ahead
+        const unsigned long long m_sure = __ballot(p > K.p_sure) & __ballot(q < K.in_lo);
+        const unsigned long long m_maybe = __ballot(p > -K.p_sure) & __ballot(q < K.in_hi);
+        const bool hs_maybe = __builtin_amdgcn_inverse_ballot_w64(m_maybe);
         // the estimate follows the hard-sphere formula whenever a contact is possible; a
-        // partner that may or may not be hit gets the interval spanning both formulas
-        const float cc = hs_maybe ? K.sig2f : K.b2f;
-        const float sr = __builtin_amdgcn_sqrtf(fmaxf(cc - q, 0.0f));
+        // partner that may or may not be hit gets the interval spanning both formulas.  The
+        // exact x is >= 0, so lo is clamped there: still a lower bound, and the membership
+        // test lo <= t (t >= 0) is unchanged.
+        const float sr = __builtin_amdgcn_sqrtf(fmaxf(hs_maybe ? K.sig2f - q : K.b2f - q, 0.0f));
         const float est = fmaxf(hs_maybe ? p - sr : p + sr, 0.0f);
-        float l = est - K.err, hg = est + K.err;
-        const bool amb = partner && hs_maybe && !hs_sure;
-        if (__builtin_expect(__ballot(amb) != 0, 0)) {
-            if (amb) {
+        float l = fmaxf(est - K.err, 0.0f), hg = est + K.err;
+        const unsigned long long m_amb = mpart & m_maybe & ~m_sure;
+        if (__builtin_expect(m_amb != 0, 0)) {
+            if (__builtin_amdgcn_inverse_ballot_w64(m_amb)) {
                 const float st2 = __builtin_amdgcn_sqrtf(fmaxf(K.b2f - q, 0.0f));
                 const float et = fmaxf(p + st2, 0.0f);
-                l = fminf(l, et - K.err);
+                l = fminf(l, fmaxf(et - K.err, 0.0f));
                 hg = fmaxf(hg, et + K.err);
             }
         }
-        const bool cand = !me && (hs_maybe || partner);
-        // the exact x is >= 0, so lo is clamped there: still a lower bound, and the
-        // membership test lo <= t (t >= 0) is unchanged
-        sc.lo[k] = cand ? fmaxf(l, 0.0f) : __builtin_huge_valf();
+        // candidates: possible contacts and the partners, never the pivot itself
+        const bool cand = __builtin_amdgcn_inverse_ballot_w64(~mme & (m_maybe | mpart));
+        sc.lo[k] = cand ? l : __builtin_huge_valf();
         hmin = umin_(hmin, cand ? __float_as_uint(hg) : INFB);
         lmin = umin_(lmin, __float_as_uint(sc.lo[k]));
     }
@@ -363,7 +395,9 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
     h.part = -1;
     if (!(sc.l < __builtin_huge_valf())) return h;
     double thr = (double)sc.t;
-    Best b = {INF, 0.0, 0.0, 0.0, 0xFFFFFFFFu, 0, -1};
+    Best b;  // the position, cell word and partners are read only after a candidate is stored
+    b.x = INF;
+    b.key = 0xFFFFFFFFu;
     unsigned done = 0;
     int nmem = 0;
 #pragma unroll
@@ -418,7 +452,9 @@ __device__ __forceinline__ Hit search_all(const Stage &st, const Pivot &pv, int 
     const double *pA = st.axis(ax);
     const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
     const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
-    Best b = {INF, 0.0, 0.0, 0.0, 0xFFFFFFFFu, 0, -1};
+    Best b;  // the position, cell word and partners are read only after a candidate is stored
+    b.x = INF;
+    b.key = 0xFFFFFFFFu;
     for (int base = 0; base < S; base += 64) {
         const int idx = base + lane;
         if (idx < S && idx != pv.P) {
@@ -525,7 +561,8 @@ struct Frame {
     int S;          // staged beads
     int dom[3];     // domain coordinates in the domain grid
     int colour;
-    uint32_t domain;
+    uint32_t domain;   // index in the melt's domain grid (the random-number counter)
+    uint32_t gdomain;  // index among all domains of a batch (the event log)
 };
 
 // screening coordinate of a bead at r in cell c along an axis with frame start fs, origin O
@@ -534,12 +571,12 @@ __device__ __forceinline__ float frame_u(double r, int c, int fs, double L, doub
     return (float)(w - O);
 }
 
-__device__ __forceinline__ void log_event(const PhaseArgs &a, const Frame &f, long long k, long long step, int p,
+__device__ __forceinline__ void log_event(const PhaseArgs &a, const Frame &f, int k, int step, int p,
                                           int t, int kind) {
     if (lane_id() == 0) {
         const unsigned long long s = atomicAdd(a.log_n, 1ull);
         if ((long long)s < a.log_cap)
-            a.log[s] = ecmc_event{a.sweep, f.domain, (uint32_t)k, (uint32_t)step, p, t, (uint32_t)kind,
+            a.log[s] = ecmc_event{a.sweep, f.gdomain, (uint32_t)k, (uint32_t)step, p, t, (uint32_t)kind,
                                   (uint32_t)f.colour};
         else
             atomicOr(a.err, ERR_LOG);
@@ -552,7 +589,7 @@ __device__ __forceinline__ void log_event(const PhaseArgs &a, const Frame &f, lo
 // only matters modulo twice the length W used between them.  Whole periods are dropped
 // (logged PERIOD); W == 0 means nothing can move and ends the EC (CYCLE, returns true).
 template <bool LOG>
-__device__ __forceinline__ bool repeat_reflection(const PhaseArgs &a, const Frame &f, long long k, long long step,
+__device__ __forceinline__ bool repeat_reflection(const PhaseArgs &a, const Frame &f, int k, int step,
                                                   int id, double xref, double &xmax, Tally &t) {
     const double w = xref - xmax;
     if (!__builtin_amdgcn_readfirstlane((int)(w > 0.0))) {
@@ -627,7 +664,7 @@ __device__ __forceinline__ void store_pivot(const Pivot &pv, const Stage &st, do
 template <int BPL, bool LOG, bool EXACT, bool WHOLE>
 __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const Stage &st,
                                        Lanes<lane_slots(BPL, EXACT), WHOLE> &R,
-                                       int P0, int ax, int sgn, bool wr, long long k, const ScreenK &K, Tally &t) {
+                                       int P0, int ax, int sgn, bool wr, int k, const ScreenK &K, Tally &t) {
     const int n = a.n;
     const double L = a.L, h = a.h;
     const int axb = ax == 2 ? 0 : ax + 1, axc = ax == 0 ? 2 : ax - 1;
@@ -647,7 +684,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
     pv.fb = __int_as_float(rdlane(__float_as_int(pick(R.B, P0 >> 6)), P0 & 63));
     pv.fc = __int_as_float(rdlane(__float_as_int(pick(R.C, P0 >> 6)), P0 & 63));
     double xmax = a.ell;
-    long long step = 0;
+    int step = 0;
     bool reflected = false;  // a reflection happened in this EC ...
     double xref = 0.0;       // ... with this much displacement left after it
     unsigned run = 0;      // consecutive zero-length events
@@ -833,7 +870,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
             nc = n - 1;
             wrapped = -1;
         }
-        const bool inside = a.whole || ((nc - dsa + n) % n) < a.D;
+        const bool inside = WHOLE || ((nc - dsa + n) % n) < a.D;
         if (inside) {
             pv.meta = (pv.meta & ~(CELL_MASK << sha)) | (nc << sha);
             if (wrapped > 0) {
@@ -865,7 +902,8 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
 // (fs, origin O, edge F cells), and whether that frame wraps the box.  The colour of a
 // domain is the parity of its grid coordinates, (d_x & 1) | (d_y & 1) << 1 | (d_z & 1) << 2.
 template <bool WHOLE>
-__device__ __forceinline__ void frame_of(const PhaseArgs &a, int colour, int b, Frame &f, int &F, bool &wraps) {
+__device__ __forceinline__ void frame_of(const PhaseArgs &a, int colour, int b, const int off[3], int dom0, Frame &f,
+                                         int &F, bool &wraps) {
     const int n = a.n;
     int *dom = f.dom;
     dom[0] = dom[1] = dom[2] = 0;
@@ -878,10 +916,11 @@ __device__ __forceinline__ void frame_of(const PhaseArgs &a, int colour, int b, 
         dom[2] = 2 * (b / (nd2 * nd2)) + ((colour >> 2) & 1);
         f.domain = (uint32_t)(dom[0] + a.nd * (dom[1] + a.nd * dom[2]));
     }
+    f.gdomain = (uint32_t)dom0 + f.domain;
     F = WHOLE ? n : a.D + 2;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        f.ds[ax] = WHOLE ? 0 : (a.off[ax] + dom[ax] * a.D) % n;
+        f.ds[ax] = WHOLE ? 0 : (off[ax] + dom[ax] * a.D) % n;
         f.fs[ax] = WHOLE ? 0 : (f.ds[ax] - 1 + n) % n;
         f.O[ax] = WHOLE ? 0.0 : face(f.fs[ax], n, a.h, a.L);
     }
@@ -896,6 +935,17 @@ __device__ __forceinline__ void frame_of(const PhaseArgs &a, int colour, int b, 
 #define ECMC_PHASE_WAVES_PER_EU 5
 #endif
 constexpr int phase_waves(int bpl) { return (ECMC_PHASE_WAVES_PER_EU > 0 && bpl <= 3) ? ECMC_PHASE_WAVES_PER_EU : 1; }
+
+// The partition offsets of a sweep (Sec. II.A: the decomposition moves every sweep): one
+// integer per axis, uniform in [0, D), from the Philox counter (0, 0, sweep, 2 stream + 1).
+__device__ __forceinline__ void partition_offsets(const PhaseArgs &a, int D, uint32_t sweep, uint32_t stream,
+                                                  int off[3]) {
+    uint32_t ctr[4] = {0u, 0u, sweep, 2u * stream + 1u};
+    philox4x32_10(ctr, a.key0, a.key1);
+    off[0] = (int)scale_u32(ctr[0], (uint32_t)D);
+    off[1] = (int)scale_u32(ctr[1], (uint32_t)D);
+    off[2] = (int)scale_u32(ctr[2], (uint32_t)D);
+}
 
 // Beads in the frame (domain plus halo) of a domain: the sum of its F^3 cell counts.
 __device__ __forceinline__ int frame_count(const PhaseArgs &a, const Frame &f, int F) {
@@ -1053,8 +1103,8 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
     Tally t = {0u, 0.0};
     bool ok = true;
     int cur = 0;  // axis the lanes' frame is rotated to
-    for (long long k = 0; k < a.K && nmot > 0 && ok; ++k) {
-        uint32_t ctr[4] = {(uint32_t)k, f.domain, a.sweep, 0u};
+    for (int k = 0; k < a.K && nmot > 0 && ok; ++k) {
+        uint32_t ctr[4] = {(uint32_t)k, f.domain, a.sweep, 2u * a.stream};
         philox4x32_10(ctr, a.key0, a.key1);
         const int P0 = __builtin_amdgcn_readfirstlane(m.mot[scale_u32(ctr[0], (uint32_t)nmot)]);
         const uint32_t dir = scale_u32(ctr[1], 6u);
@@ -1077,11 +1127,11 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
         const int32_t w0 = idx < S ? m.meta[idx] : 0;
         if (idx < S && (w0 & MOTILE_BIT)) {
             const int id = m.id[idx];
-            a.px[id] = P0r[idx];
-            a.py[id] = P1r[idx];
-            a.pz[id] = P2r[idx];
+            late(a.px)[id] = P0r[idx];
+            late(a.py)[id] = P1r[idx];
+            late(a.pz)[id] = P2r[idx];
             const int32_t w = w0 & ~MOTILE_BIT;
-            a.cellp[id] = w;
+            late(a.cellp)[id] = w;
             const int cx = cell_of(w, 0), cy = cell_of(w, 1), cz = cell_of(w, 2);
             int lc;
             if (WHOLE) {
@@ -1091,7 +1141,7 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
                 lc = tx + a.D * (ty + a.D * tz);
             }
             const int slot = atomicAdd(&m.part[lc], 1);
-            if (slot < a.cap) a.cids[(long long)(cx + n * (cy + n * cz)) * a.cap + slot] = id;
+            if (slot < a.cap) late(a.cids)[(long long)(cx + n * (cy + n * cz)) * a.cap + slot] = id;
             else overflow = true;
         }
     }
@@ -1108,13 +1158,13 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
             cz = (f.ds[2] + i / (a.D * a.D)) % n;
         }
         const int v = m.part[i];
-        a.ccount[cx + n * (cy + n * cz)] = v < a.cap ? v : a.cap;
+        late(a.ccount)[cx + n * (cy + n * cz)] = v < a.cap ? v : a.cap;
     }
-    if (__ballot(overflow) && lane == 0) atomicOr(a.err, ERR_CELL);
-    if (lane < NCNT && t.v) atomicAdd(&a.cnt[lane], (unsigned long long)t.v);
+    if (__ballot(overflow) && lane == 0) atomicOr(late(a.err), ERR_CELL);
+    if (lane < NCNT && t.v) atomicAdd(&late(a.cnt)[lane], (unsigned long long)t.v);
     if (lane == 0) {
-        if (!ok) atomicOr(a.err, ERR_STUCK);
-        if (t.dsum != 0.0) atomicAdd(a.sum_delta, t.dsum);
+        if (!ok) atomicOr(late(a.err), ERR_STUCK);
+        if (t.dsum != 0.0) atomicAdd(late(a.sum_delta), t.dsum);
     }
 }
 

@@ -58,6 +58,18 @@ __host__ __device__ inline uint32_t scale_u32(uint32_t u, uint32_t m) {
     return (uint32_t)(((uint64_t)u * m) >> 32);
 }
 
+// Per-melt constants of a batch of independent melts (one device table entry per melt; a
+// single melt is a batch of one).  The melts' beads, cells and domain stamps are consecutive
+// ranges of the shared arrays.
+struct MeltDev {
+    double L, h, halfL;
+    float in_lo, in_hi, p_sure, err_f;  // single-precision screen constants (depend on the frame edge)
+    int n, D, nd, ndpc;                 // cells per axis, domain edge, domains per axis and per colour
+    int tick0;                          // first ticket of the melt within a colour
+    int dom0;                           // first domain stamp of the melt
+    long long cell0;                    // first cell of the melt
+};
+
 struct PhaseArgs {
     double *px, *py, *pz;      // [n] positions
     int32_t *cellp;            // [n] packed cell words (motile bit clear)
@@ -73,19 +85,24 @@ struct PhaseArgs {
     unsigned long long *log_n;
     long long log_cap;
     double L, h, sig2, b2, ell, halfL;
-    long long K, event_cap;
+    int K, event_cap;          // ECs per domain; loop iterations allowed per EC
     int n, D, nd, cap, whole, colour;
     int stage_lo, stage_hi;    // this launch takes the domains staging S beads, stage_lo < S <= stage_hi
     int exact_search;          // 1: evaluate every staged bead in FP64 (reference search)
     int swap;                  // 1: swap moves at hard-sphere contacts with motile beads
     float sig2f, b2f, in_lo, in_hi, p_sure, err_f;  // single-precision screen constants
-    int off[3];
+    int off[3];                // partition offsets (drawn on the device from the sweep counter)
     uint32_t key0, key1, sweep;
+    uint32_t stream;           // random stream of the melt (Philox counter word 3 = 2 stream)
+    uint32_t *dstate;          // [2] sweep counter, stamp of the last dependency-ordered launch
     // dependency-ordered sweep (one launch per sweep)
-    uint32_t *done;            // [nd^3] epoch of the launch that last finished each domain
-    uint32_t *queue;           // [2] next ticket, waves that have left; both 0 between launches
+    uint32_t *done;            // [total domains] stamp of the launch that last finished each domain
+    uint32_t *queue;           // [2] next ticket, workgroups that have left; both 0 between launches
     uint32_t epoch;            // this launch's stamp, never 0
     int ndpc;                  // domains per colour, (nd/2)^3
+    const MeltDev *melts;      // [n_melts]
+    int n_melts;
+    int tickets;               // tickets per colour: domains per colour summed over the melts
     double *slow;              // [nslow] staging slots for domains above the LDS capacity
     uint32_t *slow_lock;       // [nslow] 0 free, 1 taken
     int nslow, slow_cap;       // slots, beads per slot (0: no slots)
@@ -97,7 +114,8 @@ struct ObsArgs {
     const int32_t *porder;     // [n] beads in chain order
     const int32_t *pstart;     // [npoly + 1]
     int64_t npoly;
-    double L, halfL, sigma, bmax;
+    const double *polyL;       // [npoly] box edge of each polymer's melt
+    double sigma, bmax;
     int nbins;
     double *r2, *rg2, *mid;    // [npoly], [npoly], [3 npoly]
     double *gyr, *eig, *com;   // shape: [6 npoly], [3 npoly], [3 npoly]
@@ -106,6 +124,7 @@ struct ObsArgs {
 
 // launchers (ecmc_kernels.hip)
 hipError_t launch_count(const PhaseArgs &a, int grid, hipStream_t s);
+hipError_t launch_advance(const PhaseArgs &a, hipStream_t s);
 hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s);
 hipError_t launch_sweep(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s);
 bool sweep_bpl_supported(int bpl);

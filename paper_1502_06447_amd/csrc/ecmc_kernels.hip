@@ -10,12 +10,20 @@ namespace {
 // the phase's tier launches start: they run concurrently and pick their domains by it.
 template <bool WHOLE>
 __global__ __launch_bounds__(64) void k_count(const PhaseArgs a) {
+    int off[3];
+    partition_offsets(a, a.D, a.dstate[0], 0u, off);
     Frame f;
     int F;
     bool wraps;
-    frame_of<WHOLE>(a, a.colour, blockIdx.x, f, F, wraps);
+    frame_of<WHOLE>(a, a.colour, blockIdx.x, off, 0, f, F, wraps);
     const int S = frame_count(a, f, F);
     if (lane_id() == 0) a.dstage[blockIdx.x] = S;
+}
+
+// The end of a sweep by colour phases: the sweep counter (in device memory, where the
+// dependency-ordered sweep advances it too) moves on.
+__global__ void k_advance(const PhaseArgs a) {
+    if (threadIdx.x == 0) a.dstate[0] += 1u;
 }
 
 // ------------------------------------------------------------------ phase kernel
@@ -26,10 +34,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
     constexpr int SMAX = 64 * BPL;
     __shared__ double s_pos[3][SMAX];
     __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[SMAX];
+    // this sweep's number and partition, from the device-side sweep counter
+    PhaseArgs b = a;
+    b.sweep = a.dstate[0];
+    int off[3];
+    partition_offsets(b, b.D, b.sweep, 0u, off);
     Frame f;
     int F;
     bool wraps;
-    frame_of<WHOLE>(a, a.colour, blockIdx.x, f, F, wraps);
+    frame_of<WHOLE>(b, b.colour, blockIdx.x, off, 0, f, F, wraps);
     // The count comes from k_count, taken before any tier of this phase ran: a block of
     // another tier may be rewriting this domain's cell lists, so a count read here could be
     // a half-updated one.  A domain outside this launch's tier belongs to another launch.
@@ -40,7 +53,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
         return;
     }
     const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
-    domain_body<BPL, LOG, EXACT, WHOLE>(a, f, F, wraps, S0, m);
+    domain_body<BPL, LOG, EXACT, WHOLE>(b, f, F, wraps, S0, m);
 }
 
 // ------------------------------------------------------------------ observables
@@ -80,8 +93,10 @@ __global__ __launch_bounds__(64 * OBS_WAVES) void k_observables(const ObsArgs a)
     const int w = (int)threadIdx.x >> 6;
     for (int i = (int)threadIdx.x; i < a.nbins; i += 64 * OBS_WAVES) s_hist[i] = 0u;
     __syncthreads();
-    auto mi = [&](double d) { return d > a.halfL ? d - a.L : (d < -a.halfL ? d + a.L : d); };
     for (int64_t q = (int64_t)blockIdx.x * OBS_WAVES + w; q < a.npoly; q += (int64_t)gridDim.x * OBS_WAVES) {
+        // the box of this polymer's melt
+        const double L = a.polyL[q], halfL = 0.5 * L;
+        auto mi = [&](double d) { return d > halfL ? d - L : (d < -halfL ? d + L : d); };
         const int64_t s = a.pstart[q];
         const int N = (int)(a.pstart[q + 1] - s);
         double c0 = 0.0, c1 = 0.0, c2 = 0.0;  // u of the last bead of the previous chunk
@@ -108,9 +123,9 @@ __global__ __launch_bounds__(64 * OBS_WAVES) void k_observables(const ObsArgs a)
                     }
                 }
                 if (t == N / 2) {
-                    a.mid[3 * q + 0] = a.px[ib] + (double)a.img[3 * ib + 0] * a.L;
-                    a.mid[3 * q + 1] = a.py[ib] + (double)a.img[3 * ib + 1] * a.L;
-                    a.mid[3 * q + 2] = a.pz[ib] + (double)a.img[3 * ib + 2] * a.L;
+                    a.mid[3 * q + 0] = a.px[ib] + (double)a.img[3 * ib + 0] * L;
+                    a.mid[3 * q + 1] = a.py[ib] + (double)a.img[3 * ib + 1] * L;
+                    a.mid[3 * q + 2] = a.pz[ib] + (double)a.img[3 * ib + 2] * L;
                 }
             }
             const double u0 = c0 + wave_scan_f64(d0);
@@ -185,8 +200,10 @@ __device__ void sym3_eigenvalues(const double g[6], double e[3]) {
 __global__ __launch_bounds__(64 * OBS_WAVES) void k_shape(const ObsArgs a) {
     const int lane = lane_id();
     const int w = (int)threadIdx.x >> 6;
-    auto mi = [&](double d) { return d > a.halfL ? d - a.L : (d < -a.halfL ? d + a.L : d); };
     for (int64_t q = (int64_t)blockIdx.x * OBS_WAVES + w; q < a.npoly; q += (int64_t)gridDim.x * OBS_WAVES) {
+        // the box of this polymer's melt
+        const double L = a.polyL[q], halfL = 0.5 * L;
+        auto mi = [&](double d) { return d > halfL ? d - L : (d < -halfL ? d + L : d); };
         const int64_t s = a.pstart[q];
         const int N = (int)(a.pstart[q + 1] - s);
         double c0 = 0.0, c1 = 0.0, c2 = 0.0;
@@ -235,9 +252,9 @@ __global__ __launch_bounds__(64 * OBS_WAVES) void k_shape(const ObsArgs a) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) a.eig[3 * q + k] = e[k];
             const int i0 = a.porder[s];
-            a.com[3 * q + 0] = a.px[i0] + (double)a.img[3 * i0 + 0] * a.L + m0;
-            a.com[3 * q + 1] = a.py[i0] + (double)a.img[3 * i0 + 1] * a.L + m1;
-            a.com[3 * q + 2] = a.pz[i0] + (double)a.img[3 * i0 + 2] * a.L + m2;
+            a.com[3 * q + 0] = a.px[i0] + (double)a.img[3 * i0 + 0] * L + m0;
+            a.com[3 * q + 1] = a.py[i0] + (double)a.img[3 * i0 + 1] * L + m1;
+            a.com[3 * q + 2] = a.pz[i0] + (double)a.img[3 * i0 + 2] * L + m2;
         }
     }
 }
@@ -279,6 +296,11 @@ hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStre
         case 16: return launch_bpl<16>(a, log, grid, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_advance(const PhaseArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_count(const PhaseArgs &a, int grid, hipStream_t s) {

@@ -25,14 +25,6 @@ namespace ecmc {
 
 namespace {
 
-// A kernel argument read at its use: the sweep's own arguments are needed only before and
-// after the domain's ECs, and held in scalar registers through them they would push the EC
-// loop's constants out to VGPR lanes (a reload at every step).
-template <class T>
-__device__ __forceinline__ T late(const T &arg) {
-    return *(const volatile T *)&arg;
-}
-
 // polls of one wait before it gives up; a poll sleeps about 8 * 64 cycles, so the limit is
 // about a second, far beyond any real wait (a domain takes well under a millisecond)
 constexpr unsigned WAIT_POLLS = 1u << 20;
@@ -42,7 +34,7 @@ constexpr unsigned WAIT_POLLS = 1u << 20;
 __device__ __forceinline__ void wait_for_earlier(const PhaseArgs &a, const Frame &f) {
     const int lane = lane_id();
     const int nd = a.nd;
-    const uint32_t *done = a.done;
+    const uint32_t *done = a.done;  // the melt's stamps
     const uint32_t epoch = a.epoch;
     bool need = false;
     int nb = 0;
@@ -89,6 +81,18 @@ __device__ __forceinline__ int take_slot(const PhaseArgs &a, uint32_t start) {
     return __builtin_amdgcn_readfirstlane(got);
 }
 
+// The melt of ticket r (its index within a colour): the last melt whose first ticket is at
+// or below r.
+__device__ __forceinline__ int melt_of(const PhaseArgs &a, int r) {
+    int lo = 0, hi = a.n_melts - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.melts[mid].tick0 <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int BPL, bool LOG, bool EXACT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(BPL)))) void k_sweep(const PhaseArgs a) {
     constexpr int SMAX = 64 * BPL;
@@ -96,21 +100,45 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
     __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[SMAX];
     const int lane = lane_id();
     // one ticket per workgroup, taken when the workgroup runs: ticket order, not launch order,
-    // is the order of the waits
+    // is the order of the waits.  Tickets run colour by colour, melt by melt within a colour.
     uint32_t t = 0;
     if (lane == 0) t = atomicAdd(&a.queue[0], 1u);
     t = __builtin_amdgcn_readfirstlane(t);
-    const uint32_t ndpc = (uint32_t)a.ndpc;
+    const int colour = (int)(t / (uint32_t)a.tickets);
+    const int r = (int)(t % (uint32_t)a.tickets);
+    const int mi = melt_of(a, r);
+    const MeltDev &M = a.melts[mi];
+    // the melt's view of the arguments; the sweep number and this launch's stamp come from
+    // device memory, so that a replayed graph of sweep launches moves on by itself
+    PhaseArgs b = a;
+    b.L = M.L;
+    b.h = M.h;
+    b.halfL = M.halfL;
+    b.in_lo = M.in_lo;
+    b.in_hi = M.in_hi;
+    b.p_sure = M.p_sure;
+    b.err_f = M.err_f;
+    b.n = M.n;
+    b.D = M.D;
+    b.nd = M.nd;
+    b.ccount = a.ccount + M.cell0;
+    b.cids = a.cids + M.cell0 * a.cap;
+    b.done = a.done + M.dom0;
+    b.sweep = a.dstate[0];
+    b.epoch = a.dstate[1] + 1u;
+    b.stream = (uint32_t)mi;
+    int off[3];
+    partition_offsets(b, b.D, b.sweep, b.stream, off);
     Frame f;
     int F;
     bool wraps;
-    frame_of<false>(a, (int)(t / ndpc), (int)(t % ndpc), f, F, wraps);
-    wait_for_earlier(a, f);
-    const int S = frame_count(a, f, F);
+    frame_of<false>(b, colour, r - M.tick0, off, M.dom0, f, F, wraps);
+    wait_for_earlier(b, f);
+    const int S = frame_count(b, f, F);
     int slot = -1;
     if (S <= SMAX) {
         const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
-        domain_body<BPL, LOG, EXACT, false>(a, f, F, wraps, S, m);
+        domain_body<BPL, LOG, EXACT, false>(b, f, F, wraps, S, m);
     } else if (S <= a.slow_cap) {
         slot = take_slot(a, t);
         if (slot >= 0) {
@@ -119,30 +147,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
             double *base = a.slow + (size_t)slot * (size_t)cap * (SLOW_SLOT_BYTES_PER_BEAD / 8);
             int32_t *ib = reinterpret_cast<int32_t *>(base + 3 * (size_t)cap);
             const StageMem m = {base, ib, ib + cap, ib + 2 * cap, ib + 3 * cap, cap};
-            domain_body<16, LOG, true, false>(a, f, F, wraps, S, m);
+            domain_body<16, LOG, true, false>(b, f, F, wraps, S, m);
         }
     } else if (lane == 0) {
         atomicOr(a.err, ERR_STAGE);
     }
-    // publish: every write of this domain is visible device-wide before its stamp
+    // publish: every write of this domain is visible device-wide before its stamp (the stamp
+    // and the arrays are read again here rather than held through the ECs)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0) {
-        __hip_atomic_store(&late(a.done)[f.domain], late(a.epoch), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t *st = late(a.dstate);
+        __hip_atomic_store(&late(a.done)[f.gdomain], st[1] + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (slot >= 0)
             __hip_atomic_store(&late(a.slow_lock)[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // the last workgroup to finish resets the ticket counter for the next launch
+        // the last workgroup to finish resets the ticket counter and advances the sweep
+        // counter and the stamp for the next launch
         uint32_t *q = late(a.queue);
         const uint32_t left = atomicAdd(&q[1], 1u);
         if (left == gridDim.x - 1) {
             __hip_atomic_store(&q[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&q[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st[0], st[0] + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st[1], st[1] + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
 
 template <int BPL, bool LOG, bool EXACT>
 hipError_t launch_sweep_v(const PhaseArgs &a, int *grid, hipStream_t s) {
-    const int g = 8 * a.ndpc;  // one workgroup per domain of the sweep
+    const int g = 8 * a.tickets;  // one workgroup per domain of the sweep
     *grid = g;
     hipLaunchKernelGGL((k_sweep<BPL, LOG, EXACT>), dim3(g), dim3(64), 0, s, a);
     return hipGetLastError();

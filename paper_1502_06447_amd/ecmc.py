@@ -47,6 +47,31 @@ class ecmc_options(ctypes.Structure):
     ]
 
 
+class ecmc_melt_desc(ctypes.Structure):
+    _fields_ = [
+        ("box", ctypes.c_double),
+        ("n_beads", ctypes.c_int64),
+        ("positions", ctypes.c_void_p),
+        ("n_bonds", ctypes.c_int64),
+        ("bonds", ctypes.c_void_p),
+        ("n_cells", ctypes.c_int32),
+        ("domain_cells", ctypes.c_int32),
+    ]
+
+
+class ecmc_melt_info(ctypes.Structure):
+    _fields_ = [
+        ("box", ctypes.c_double), ("cell_size", ctypes.c_double),
+        ("first_bead", ctypes.c_int64), ("n_beads", ctypes.c_int64),
+        ("first_polymer", ctypes.c_int64), ("n_polymers", ctypes.c_int64),
+        ("first_domain", ctypes.c_int64), ("n_domains", ctypes.c_int64),
+        ("n_cells", ctypes.c_int32), ("domain_cells", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ecmc_counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("hs_lift", "tether_lift", "hs_reflect", "tether_reflect", "wall", "cross", "ec", "steps",
@@ -71,6 +96,7 @@ EXPORTS = (
     "ecmc_get_counters", "ecmc_reset_counters", "ecmc_get_event_log", "ecmc_clear_event_log",
     "ecmc_set_state", "ecmc_kernel_time", "ecmc_sweep_counter", "ecmc_n_cells", "ecmc_cell_size",
     "ecmc_stage_capacity", "ecmc_destroy", "ecmc_status_str", "ecmc_last_error",
+    "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
 )
 
 
@@ -81,6 +107,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() (no CPU fallback exists)")
+    # torch's HIP runtime is loaded first: the library's shares the process with it, and the
+    # other order leaves the library without a device
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, vp = ctypes.POINTER, ctypes.c_void_p
     i32, i64, u32, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
@@ -108,6 +137,10 @@ def lib():
         "ecmc_n_cells": (i32, [vp]),
         "ecmc_cell_size": (dbl, [vp]),
         "ecmc_stage_capacity": (i32, [vp]),
+        "ecmc_workspace_size_batch": (st, [i32, P(ecmc_melt_desc), dbl, dbl, opt_p, P(ctypes.c_size_t)]),
+        "ecmc_init_batch": (st, [P(vp), i32, P(ecmc_melt_desc), dbl, dbl, opt_p]),
+        "ecmc_n_melts": (i32, [vp]),
+        "ecmc_get_melt_info": (st, [vp, i32, P(ecmc_melt_info)]),
         "ecmc_destroy": (None, [vp]),
         "ecmc_status_str": (ctypes.c_char_p, [st]),
         "ecmc_last_error": (ctypes.c_char_p, [vp]),
@@ -149,6 +182,41 @@ def ecmc_init(box, sigma, l_max, positions, bonds, opt: ecmc_options):
     return h
 
 
+def _melt_descs(melts, n_cells=None, domain_cells=None):
+    """ecmc_melt_desc array for inputs.Melt-like objects; the returned arrays must outlive the call."""
+    keep = []
+    descs = (ecmc_melt_desc * len(melts))()
+    for i, m in enumerate(melts):
+        pos = np.ascontiguousarray(m.positions, dtype=np.float64).reshape(-1, 3)
+        bnd = np.ascontiguousarray(m.bonds, dtype=np.int32).reshape(-1, 2)
+        keep += [pos, bnd]
+        descs[i].box = float(m.L)
+        descs[i].n_beads = pos.shape[0]
+        descs[i].positions = pos.ctypes.data
+        descs[i].n_bonds = bnd.shape[0]
+        descs[i].bonds = bnd.ctypes.data if bnd.size else None
+        descs[i].n_cells = int(n_cells[i]) if n_cells is not None else 0
+        descs[i].domain_cells = int(domain_cells[i]) if domain_cells is not None else 0
+    return descs, keep
+
+
+def ecmc_workspace_size_batch(melts, sigma: float, l_max: float, opt: ecmc_options, n_cells=None,
+                              domain_cells=None) -> int:
+    descs, keep = _melt_descs(melts, n_cells, domain_cells)
+    n = ctypes.c_size_t()
+    _check(lib().ecmc_workspace_size_batch(len(melts), descs, sigma, l_max, ctypes.byref(opt), ctypes.byref(n)),
+           "ecmc_workspace_size_batch")
+    return n.value
+
+
+def ecmc_init_batch(melts, sigma: float, l_max: float, opt: ecmc_options, n_cells=None, domain_cells=None):
+    descs, keep = _melt_descs(melts, n_cells, domain_cells)
+    h = ctypes.c_void_p()
+    _check(lib().ecmc_init_batch(ctypes.byref(h), len(melts), descs, sigma, l_max, ctypes.byref(opt)),
+           "ecmc_init_batch")
+    return h
+
+
 def ecmc_sweep(ctx, n_chains: int, ell: float, seed: int):
     _check(lib().ecmc_sweep(ctx, int(n_chains), float(ell), int(seed) & 0xFFFFFFFFFFFFFFFF), "ecmc_sweep", ctx)
 
@@ -182,41 +250,75 @@ class Options:
     schedule: int = SCHED_SWEEP
 
 
+def _native_options(o: "Options") -> ecmc_options:
+    opt = ecmc_default_options()
+    opt.precision = o.precision
+    opt.tiling = o.tiling
+    opt.domain_cells = o.domain_cells
+    opt.n_cells = o.n_cells
+    opt.cell_capacity = o.cell_capacity
+    opt.stage_capacity = o.stage_capacity
+    opt.event_cap = o.event_cap
+    opt.event_log_capacity = o.event_log_capacity
+    opt.time_kernels = 1 if o.time_kernels else 0
+    opt.swap_moves = 1 if o.swap_moves else 0
+    opt.schedule = o.schedule
+    return opt
+
+
 class Melt:
-    """A melt resident on the GPU: the context plus its torch-owned workspace."""
+    """A melt (or a batch of independent melts) resident on the GPU: the context plus its
+    torch-owned workspace."""
 
     def __init__(self, L: float, sigma: float, b_max: float, positions, bonds, options: Options | None = None,
                  device: str = "cuda", stream=None):
-        import torch
-        o = options or Options()
-        opt = ecmc_default_options()
-        opt.precision = o.precision
-        opt.tiling = o.tiling
-        opt.domain_cells = o.domain_cells
-        opt.n_cells = o.n_cells
-        opt.cell_capacity = o.cell_capacity
-        opt.stage_capacity = o.stage_capacity
-        opt.event_cap = o.event_cap
-        opt.event_log_capacity = o.event_log_capacity
-        opt.time_kernels = 1 if o.time_kernels else 0
-        opt.swap_moves = 1 if o.swap_moves else 0
-        opt.schedule = o.schedule
+        opt = _native_options(options or Options())
         pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
-        nbytes = ecmc_workspace_size(L, sigma, b_max, pos.shape[0], opt)
+        self._attach(opt, ecmc_workspace_size(L, sigma, b_max, pos.shape[0], opt), device, stream, options)
+        self.L, self.sigma, self.b_max = float(L), float(sigma), float(b_max)
+        self.n_beads = pos.shape[0]
+        self.ctx = ecmc_init(L, sigma, b_max, pos, bonds, opt)
+        # linear chains (the library rejects anything else): one polymer per bead minus bonds
+        self.n_poly = self.n_beads - int(np.asarray(bonds).reshape(-1, 2).shape[0])
+
+    def _attach(self, opt, nbytes, device, stream, options):
+        import torch
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
-        opt.workspace = aligned
+        opt.workspace = (base + 255) & ~255
         opt.workspace_bytes = nbytes
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         opt.stream = self.stream.cuda_stream
         self.opt = opt
-        self.L, self.sigma, self.b_max = float(L), float(sigma), float(b_max)
-        self.n_beads = pos.shape[0]
-        self.log_capacity = int(o.event_log_capacity)
-        self.ctx = ecmc_init(L, sigma, b_max, pos, bonds, opt)
-        # linear chains (the library rejects anything else): one polymer per bead minus bonds
-        self.n_poly = self.n_beads - int(np.asarray(bonds).reshape(-1, 2).shape[0])
+        self.log_capacity = int((options or Options()).event_log_capacity)
+
+    @classmethod
+    def from_batch(cls, melts, options: Options | None = None, n_cells=None, domain_cells=None, device: str = "cuda",
+                   stream=None):
+        """Independent melts (inputs.Melt-like: L, positions, bonds, sigma, b_max) in one context:
+        they sweep together in one launch per sweep.  Per-bead and per-polymer results are the
+        melts' own, concatenated in melt order (see melt_info)."""
+        o = options or Options()
+        opt = _native_options(o)
+        sigma, b_max = float(melts[0].sigma), float(melts[0].b_max)
+        if any(float(m.sigma) != sigma or float(m.b_max) != b_max for m in melts):
+            raise ValueError("the melts of a batch share sigma and b_max")
+        self = cls.__new__(cls)
+        self._attach(opt, ecmc_workspace_size_batch(melts, sigma, b_max, opt, n_cells, domain_cells), device, stream, o)
+        self.L, self.sigma, self.b_max = None, sigma, b_max
+        self.n_beads = sum(int(np.asarray(m.positions).reshape(-1, 3).shape[0]) for m in melts)
+        self.ctx = ecmc_init_batch(melts, sigma, b_max, opt, n_cells, domain_cells)
+        self.n_poly = sum(self.melt_info(i)["n_polymers"] for i in range(len(melts)))
+        return self
+
+    @property
+    def n_melts(self) -> int:
+        return lib().ecmc_n_melts(self.ctx)
+
+    def melt_info(self, m: int) -> dict:
+        info = ecmc_melt_info()
+        _check(lib().ecmc_get_melt_info(self.ctx, int(m), ctypes.byref(info)), "ecmc_get_melt_info", self.ctx)
+        return info.as_dict()
 
     @classmethod
     def from_melt(cls, melt, options: Options | None = None, **kw):

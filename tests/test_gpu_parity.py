@@ -377,3 +377,97 @@ def test_gpu_dimer_bond_length_distribution(tiling, D, L):
         r[k] = np.linalg.norm(d)
     cdf = lambda x: np.clip((x ** 3 - 1.0) / (1.4 ** 3 - 1.0), 0, 1)
     assert stats.kstest(r[::5], cdf).pvalue > 1e-3
+
+
+# ---------------------------------------------------------------- batches of independent melts
+@pytest.fixture(scope="module")
+def small_batch():
+    """Four melts of the batched workload's kinds (N from 16 to 64, 1,000 to 3,000 beads,
+    eta from 0.35 to 0.45), each in its own box."""
+    return inputs.batch_melts(4, 11, n_choices=(16, 32, 64), beads_range=(1000, 3000))
+
+
+def _split_log(log, info):
+    sel = (log["domain"] >= info["first_domain"]) & (log["domain"] < info["first_domain"] + info["n_domains"])
+    part = log[sel].copy()
+    part["domain"] -= info["first_domain"]
+    for k in ("pivot", "target"):
+        ok = part[k] >= 0
+        part[k][ok] -= info["first_bead"]
+    return part
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_batch_every_melt_matches_the_oracle(small_batch, exact):
+    """A batch sweeps all its melts in one launch; melt m draws from random stream m.  Replayed
+    alone in the oracle (stream m, the batch's ECs per domain), every melt must give the same
+    event sequence, positions, cells and images; the counters add up over the melts."""
+    melts = small_batch
+    g = ecmc.Melt.from_batch(melts, ecmc.Options(event_log_capacity=20_000_000,
+                                                 precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED))
+    assert g.n_melts == len(melts)
+    infos = [g.melt_info(m) for m in range(len(melts))]
+    total_domains = sum(i["n_domains"] for i in infos)
+    n_ec = g.n_beads
+    K = -(-n_ec // total_domains)
+    for s in range(2):
+        g.sweep(n_ec, 20.0, 61 + s)
+    g.synchronize()
+    log = g.event_log()
+    pos, cells, img = g.positions(), g.cells(), g.images()
+    tot = np.zeros(oracle.NCNT, dtype=np.uint64)
+    for m, (melt, info) in enumerate(zip(melts, infos)):
+        o = oracle.Oracle.from_melt(melt, n_cells=info["n_cells"])
+        o.set_stream(m)
+        o.enable_log(10_000_000)
+        for s in range(2):
+            o.sweep(K * info["n_domains"], 20.0, 61 + s, tiling=1, D=info["domain_cells"])
+        lg = _sorted(_split_log(log, info))
+        lo = _sorted(o.event_log())
+        assert len(lg) == len(lo) and np.array_equal(lg, lo), f"melt {m}: logs differ ({len(lg)} vs {len(lo)})"
+        b0, nb = info["first_bead"], info["n_beads"]
+        assert np.array_equal(pos[b0:b0 + nb], o.positions()), m
+        assert np.array_equal(cells[b0:b0 + nb], o.cells()), m
+        assert np.array_equal(img[b0:b0 + nb], o.images()), m
+        tot += np.asarray(o.counters()[0], dtype=np.uint64)
+    cg = g.counters()
+    assert cg["hs_lift"] == tot[oracle.C_HS_LIFT] and cg["ec"] == tot[oracle.C_EC] and cg["steps"] == tot[oracle.C_STEPS]
+    assert len(log) > 100_000
+
+
+def test_batch_of_one_is_the_single_melt(melt_c2):
+    """A batch holding one melt sweeps exactly as the single-melt context."""
+    a = ecmc.Melt.from_melt(melt_c2, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=16))
+    b = ecmc.Melt.from_batch([melt_c2], ecmc.Options(), n_cells=[16], domain_cells=[2])
+    for s in range(3):
+        a.sweep(16000, 20.0, 91 + s)
+        b.sweep(16000, 20.0, 91 + s)
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.images(), b.images())
+    assert a.sweep_counter == b.sweep_counter == 3
+
+
+def test_graph_of_sweeps_replays_like_eager_sweeps(small_batch):
+    """Three sweeps captured into a HIP graph on the context's stream, replayed twice with
+    eager work and synchronisation in between: after each replay the state equals three more
+    eager sweeps of a twin context (the sweep counter and stamps advance on the device)."""
+    import torch
+    s = torch.cuda.Stream()
+    g = ecmc.Melt.from_batch(small_batch, ecmc.Options(), stream=s)
+    e = ecmc.Melt.from_batch(small_batch, ecmc.Options())
+    n_ec = g.n_beads
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=s):
+        for _ in range(3):
+            g.sweep(n_ec, 20.0, 5)
+    for rep in range(2):
+        graph.replay()
+        for _ in range(3):
+            e.sweep(n_ec, 20.0, 5)
+        torch.cuda.synchronize()
+        assert g.sweep_counter == e.sweep_counter == 3 * (rep + 1)
+        assert np.array_equal(g.positions(), e.positions()), rep
+        assert np.array_equal(g.cells(), e.cells()), rep
+        ce, cg = e.counters(), g.counters()
+        assert all(ce[k] == cg[k] for k in ("hs_lift", "hs_reflect", "ec", "steps", "cross", "wall")), rep
