@@ -63,6 +63,10 @@ WORKLOADS = {
     "c3": dict(M=16384, N=64, eta=0.45, ell=20.0, D=2, label="16384 chains x 64 beads (1,048,576), eta=0.45"),
     "c2": dict(M=500, N=32, eta=0.45, ell=20.0, D=3, label="500 chains x 32 beads (16,000), eta=0.45"),
     "c5": dict(M=2048, N=512, eta=0.45, ell=20.0, D=2, label="2048 chains x 512 beads (1,048,576), eta=0.45"),
+    # the batched form: independent melts, N uniform in {16, ..., 256}, 2k-64k beads each,
+    # eta uniform in [0.35, 0.45]; one tuned launch per sweep, sweeps replayed from a HIP graph
+    "c4": dict(melts=256, ell=20.0, label="256 independent melts, N in {16,32,64,128,256}, 2,048-65,536 beads "
+                                         "each, eta in [0.35, 0.45]"),
 }
 
 
@@ -137,6 +141,151 @@ def precision_check(melt, w, sweeps: int, swap: bool = False) -> dict:
             "sum_delta_rel_diff": float(abs(cm["sum_delta"] - cf["sum_delta"]) / max(abs(cf["sum_delta"]), 1e-300))}
 
 
+def batch_precision_check(melts, opts, nc, dc, ell: float, sweeps: int) -> dict:
+    """Both precisions from the same start through the same sweeps of the whole batch."""
+    import numpy as np
+    from paper_1502_06447_amd import ecmc
+    nb = sum(m.n_beads for m in melts)
+    res = {}
+    for name, prec in (("mixed", ecmc.PREC_MIXED), ("fp64", ecmc.PREC_FP64)):
+        o = ecmc.Options(**{**opts.__dict__, "precision": prec})
+        g = ecmc.Melt.from_batch(melts, o, n_cells=nc, domain_cells=dc)
+        for i in range(sweeps):
+            g.sweep(nb, ell, 7000 + i)
+        g.synchronize()
+        res[name] = (g.positions(), g.counters())
+        g.close()
+    (pm, cm), (pf, cf) = res["mixed"], res["fp64"]
+    return {"sweeps": sweeps, "beads": int(nb), "positions_identical": bool(np.array_equal(pm, pf)),
+            "max_position_drift": float(np.abs(pm - pf).max()),
+            "event_counts_identical": all(cm[k] == cf[k] for k in cm if k not in ("error_flags", "sum_delta"))}
+
+
+def batch_cpu_baseline(melt, ell: float, D: int, n_cells: int, seconds: float) -> dict:
+    """The CPU oracle (serial, one core) on one melt of the batch, same schedule rules."""
+    import oracle
+    o = oracle.Oracle.from_melt(melt, n_cells=n_cells)
+    o.sweep(melt.n_beads, ell, 100, tiling=1, D=D)
+    c0, _ = o.counters()
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < seconds:
+        o.sweep(melt.n_beads, ell, 200 + k, tiling=1, D=D)
+        k += 1
+    dt = time.perf_counter() - t0
+    c1, _ = o.counters()
+    ev = int(sum(c1[i] - c0[i] for i in (oracle.C_HS_LIFT, oracle.C_TETHER_LIFT, oracle.C_HS_REFLECT,
+                                          oracle.C_TETHER_REFLECT, oracle.C_SWAP)))
+    return {"value": ev / dt, "unit": "collision events/s", "cores": 1, "kind": "oracle",
+            "sample": f"melt 0 of the batch ({melt.n_beads} beads, N={melt.n_per}, eta={melt.eta:.3f}), "
+                      f"{n_cells}^3 cells, D={D}: {k} sweeps after 1 warm-up sweep, {dt:.1f} s, single thread",
+            "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
+
+
+def main_batch(args):
+    """The batched workload: tuned geometry and staging, K sweeps captured into one HIP graph
+    (the sweep loop), replayed once in the timed region after W eager warm-up sweeps."""
+    import numpy as np
+    import torch
+    from paper_1502_06447_amd import ecmc, inputs
+
+    w = WORKLOADS["c4"]
+    torch.cuda.set_device(0)
+    melts = inputs.batch_melts(w["melts"], args.seed)
+    nb = sum(m.n_beads for m in melts)
+    ell = w["ell"]
+    prec = ecmc.PREC_MIXED if args.precision == "mixed" else ecmc.PREC_FP64
+    opts = ecmc.Options(precision=prec, swap_moves=args.swap)
+    tune = None
+    nc = dc = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        nc, dc, tune = ecmc.ecmc_tune_batch(melts, 1.0, 1.4, ecmc._native_options(opts), nb, ell, trial_sweeps=2)
+        tune["seconds"] = time.perf_counter() - t0
+        opts.stage_tier = tune["stage_tier"]
+        print(f"# tuned: stage tier {tune['stage_tier']}, policy {tune['policy']}, {tune['candidates']} candidates, "
+              f"{tune['seconds']:.1f} s", file=sys.stderr, flush=True)
+    stream = torch.cuda.Stream()
+    g = ecmc.Melt.from_batch(melts, opts, n_cells=nc, domain_cells=dc, stream=stream)
+    infos = [g.melt_info(m) for m in range(g.n_melts)]
+    cells = sum(i["n_cells"] ** 3 for i in infos)
+    print(f"# c4: {len(melts)} melts, {nb} beads, {cells} cells, staging {g.stage_capacity}", file=sys.stderr,
+          flush=True)
+    for i in range(args.warmup):
+        g.sweep(nb, ell, 1000 + i)
+        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    g.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        for i in range(args.steps):
+            g.sweep(nb, ell, 1000 + args.warmup + i)
+    torch.cuda.synchronize()
+    c0 = g.counters()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    c1 = g.counters()
+    g.synchronize()
+    kernel_s = e0.elapsed_time(e1) / 1e3
+    d = {k: c1[k] - c0[k] for k in c1 if k not in ("error_flags",)}
+    events = d["hs_lift"] + d["tether_lift"] + d["hs_reflect"] + d["tether_reflect"] + d["swap"]
+    ecs = d["ec"]
+    value = events / dt
+    # algorithmic bytes per event at the bead-weighted mean occupancy of a cell
+    occ = sum(i["n_beads"] * (i["n_beads"] / i["n_cells"] ** 3) for i in infos) / nb
+    B = bytes_per_event(occ)
+    achieved = events * B / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    out = {
+        "metric": "collision events/s",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"c4: {w['label']}, ell={ell} sigma, checkerboard (tuned per melt), FP64 results "
+                        f"({args.precision} event search), sweep loop replayed from one HIP graph",
+            "melts": len(melts), "beads": nb, "cells": cells, "precision": args.precision,
+            "swap_moves": bool(args.swap), "stage_capacity": g.stage_capacity, "parallelism": "single GPU",
+            "domain_cells_used": sorted(set(i["domain_cells"] for i in infos)),
+        },
+        "tune": tune,
+        "bead_sweeps_per_s": ecs / dt,
+        "events_per_ec": events / max(ecs, 1),
+        "counters": {k: int(v) if isinstance(v, int) else v for k, v in d.items()},
+        "kernel_ms_per_step": kernel_s * 1e3 / args.steps,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_event": B,
+            "note": "algorithmic bytes (18-cell forward cell-list scan per collision event, bead-weighted mean "
+                    "cell occupancy) over the HIP-event time of the graph replay",
+        },
+    }
+    if not args.no_precision_check:
+        out["precision_check"] = batch_precision_check(melts, opts, nc, dc, ell, sweeps=2)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batch_cpu_baseline(melts[0], ell, infos[0]["domain_cells"], infos[0]["n_cells"],
+                                                 seconds=args.cpu_seconds)
+        out["cpu_baseline"]["vs_gpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +301,7 @@ def main():
                     help="skip the untimed comparison of the two precisions after the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner (automatic geometry and staging)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device once (a plain copy kernel of known size, "
                          "the scale for hardware byte counters)")
@@ -160,6 +310,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU run is not part of this build",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c4":
+        return main_batch(args)
 
     import numpy as np
     import torch

@@ -113,6 +113,10 @@ typedef struct {
                                    ECMC_SCHED_PHASES: one launch set per colour phase. A
                                    colour_mask other than all eight colours, or a staging
                                    capacity above 512 beads, always runs by phases          */
+    int32_t stage_tier;         /* with stage_capacity = 0: beads of the LDS staging tier
+                                   (a multiple of 64 up to 512; 0 = sized for the typical
+                                   domain); larger domains are staged as for the automatic
+                                   capacity.  The knob ecmc_tune_batch sets                */
     void *workspace;            /* device memory owned by the caller (256-byte aligned)     */
     size_t workspace_bytes;
     void *stream;               /* hipStream_t for every launch and copy; NULL = default    */
@@ -190,6 +194,31 @@ ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, in
  * a context of one melt behaves exactly as one from ecmc_init. */
 ecmc_status ecmc_init_batch(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *melts,
                             double sigma, double l_max, const ecmc_options *opt);
+
+/* The autotuner of the batched form.  Candidates: the LDS staging tier (64, 128, 192, 256,
+ * 384 or 512 beads per domain frame, from the smallest that holds the typical frame) and
+ * two domain policies per melt: 0 = D = 2 on the largest multiple of 4 cells per axis, 1 =
+ * the (n, D) of smallest typical frame among n from that multiple up to the largest n
+ * (n/D even).  Each candidate is initialised in opt->workspace (scratch; it must hold
+ * ecmc_tune_workspace_size bytes) and timed over trial_sweeps sweeps of n_chains ECs of
+ * length ell after one untimed sweep; the fastest in ECs per second is returned:
+ * n_cells and domain_cells per melt (for ecmc_melt_desc) and the staging tier (for
+ * ecmc_options.stage_tier).  Synchronises; the caller's melts are only read. */
+typedef struct {
+    int32_t stage_tier;
+    int32_t policy;
+    double ms_per_sweep;        /* of the fastest candidate                                 */
+    double ecs_per_s;
+    int32_t candidates;         /* candidates timed                                         */
+    int32_t pad;
+} ecmc_tune_result;
+
+ecmc_status ecmc_tune_workspace_size(int32_t n_melts, const ecmc_melt_desc *melts, double sigma,
+                                     double l_max, const ecmc_options *opt, size_t *bytes);
+ecmc_status ecmc_tune_batch(int32_t n_melts, const ecmc_melt_desc *melts, double sigma, double l_max,
+                            const ecmc_options *opt, int64_t n_chains, double ell,
+                            int32_t trial_sweeps, int32_t *n_cells_out, int32_t *domain_cells_out,
+                            ecmc_tune_result *best);
 
 /* One sweep (Sec. II.A: the decomposition is redrawn every sweep): a partition offset,
  * then the 8 colour phases in order; every non-empty active domain runs

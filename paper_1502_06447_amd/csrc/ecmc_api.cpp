@@ -267,8 +267,11 @@ ecmc_status plan(const std::vector<MeltIn> &in, double sigma, double lmax, const
     } else if (o.stage_capacity > 0) {
         p.stage = o.stage_capacity;
     } else {
-        // first tier sized for the typical domain; the few above it are staged elsewhere
-        p.stage = (int)std::ceil(worst + 3.0 * std::sqrt(worst) + 2.0);
+        // first tier sized for the typical domain (or as asked); the few above it are staged
+        // elsewhere
+        if (o.stage_tier < 0 || o.stage_tier > 512 || o.stage_tier % 64 != 0)
+            return fail(c, ECMC_E_ARG, "stage_tier must be 0 or a multiple of 64 up to 512 (got %d)", o.stage_tier);
+        p.stage = o.stage_tier > 0 ? o.stage_tier : (int)std::ceil(worst + 3.0 * std::sqrt(worst) + 2.0);
         p.bpl2 = 16;
     }
     int bpl = (p.stage + 63) / 64;
@@ -1062,5 +1065,183 @@ const char *ecmc_status_str(ecmc_status s) {
 }
 
 const char *ecmc_last_error(const ecmc_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+
+// Cells and domain edge of a melt under a tuning policy: 0 = D = 2 on the largest multiple
+// of 4 cells per axis; 1 = the smallest typical frame (D + 2)^3 nb / n^3 among n from that
+// multiple up to the largest n and every D >= 2 with n/D even.
+bool policy_geometry(double L, int64_t nb, double lmax, int policy, int &n_out, int &D_out) {
+    int nmax = (int)std::min(std::floor(L / lmax), (double)MAX_CELLS_PER_AXIS);
+    while (nmax > 0 && !(L / nmax > lmax)) --nmax;
+    const int n4 = nmax - nmax % 4;
+    if (n4 < 4) return false;
+    n_out = n4;
+    D_out = 2;
+    if (policy == 0) return true;
+    double best = std::pow(4.0, 3) * (double)nb / std::pow((double)n4, 3);
+    for (int n = n4; n <= nmax; ++n)
+        for (int D = 2; D <= n; ++D) {
+            if (n % D != 0 || (n / D) % 2 != 0) continue;
+            const double frame = std::pow((double)(D + 2), 3) * (double)nb / std::pow((double)n, 3);
+            if (frame < best) {
+                best = frame;
+                n_out = n;
+                D_out = D;
+            }
+        }
+    return true;
+}
+
+ecmc_status policy_descs(int32_t n_melts, const ecmc_melt_desc *melts, double lmax, int policy,
+                         std::vector<ecmc_melt_desc> &out) {
+    out.assign(melts, melts + n_melts);
+    for (int32_t m = 0; m < n_melts; ++m) {
+        int n = 0, D = 0;
+        if (!policy_geometry(melts[m].box, melts[m].n_beads, lmax, policy, n, D))
+            return fail(nullptr, ECMC_E_BOX, "melt %d: box too small for a checkerboard of 2-cell domains", m);
+        out[m].n_cells = n;
+        out[m].domain_cells = D;
+    }
+    return ECMC_OK;
+}
+
+// Staging tiers worth timing: from the smallest one holding the typical frame of the median
+// bead (the frame of its melt) up to four tiers; the domains above a tier are staged in
+// workspace slots, so a tier below the largest melts' frames trades their speed for that of
+// the rest.
+std::vector<int> tier_candidates(double typical) {
+    static const int tiers[] = {64, 128, 192, 256, 384, 512};
+    std::vector<int> out;
+    for (int t : tiers)
+        if (t >= typical && out.size() < 4) out.push_back(t);
+    if (out.empty()) out.push_back(512);
+    return out;
+}
+
+double typical_frame(const std::vector<ecmc_melt_desc> &d) {
+    // the typical frame (mean plus three standard deviations of a Poisson count) of the melt
+    // holding the median bead
+    std::vector<std::pair<double, int64_t>> f;
+    int64_t total = 0;
+    for (const ecmc_melt_desc &m : d) {
+        const double mean = std::pow((double)(m.domain_cells + 2), 3) * (double)m.n_beads / std::pow((double)m.n_cells, 3);
+        f.emplace_back(mean + 3.0 * std::sqrt(mean), m.n_beads);
+        total += m.n_beads;
+    }
+    std::sort(f.begin(), f.end());
+    int64_t acc = 0;
+    for (const auto &x : f) {
+        acc += x.second;
+        if (2 * acc >= total) return x.first;
+    }
+    return f.back().first;
+}
+
+}  // namespace
+
+extern "C" {
+
+ecmc_status ecmc_tune_workspace_size(int32_t n_melts, const ecmc_melt_desc *melts, double sigma, double l_max,
+                                     const ecmc_options *opt, size_t *bytes) {
+    if (!opt || !bytes || !melts || n_melts < 1) return fail(nullptr, ECMC_E_ARG, "null argument or no melts");
+    size_t most = 0;
+    for (int policy = 0; policy < 2; ++policy) {
+        std::vector<ecmc_melt_desc> d;
+        ecmc_status st = policy_descs(n_melts, melts, l_max, policy, d);
+        if (st) return st;
+        ecmc_options o = *opt;
+        o.tiling = ECMC_TILING_CHECKER;
+        o.schedule = ECMC_SCHED_SWEEP;
+        o.stage_capacity = 0;
+        o.stage_tier = tier_candidates(typical_frame(d)).front();
+        o.event_log_capacity = 0;
+        size_t b = 0;
+        if ((st = ecmc_workspace_size_batch(n_melts, d.data(), sigma, l_max, &o, &b))) return st;
+        most = std::max(most, b);
+    }
+    *bytes = most;
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_tune_batch(int32_t n_melts, const ecmc_melt_desc *melts, double sigma, double l_max,
+                            const ecmc_options *opt, int64_t n_chains, double ell, int32_t trial_sweeps,
+                            int32_t *n_cells_out, int32_t *domain_cells_out, ecmc_tune_result *best) {
+    if (!opt || !melts || n_melts < 1 || !n_cells_out || !domain_cells_out || !best || trial_sweeps < 1)
+        return fail(nullptr, ECMC_E_ARG, "null argument, no melts or no trial sweeps");
+    std::memset(best, 0, sizeof *best);
+    double best_rate = -1.0;
+    std::vector<ecmc_melt_desc> chosen;
+    for (int policy = 0; policy < 2; ++policy) {
+        std::vector<ecmc_melt_desc> d;
+        ecmc_status st = policy_descs(n_melts, melts, l_max, policy, d);
+        if (st) return st;
+        if (policy == 1 && !chosen.empty()) {
+            bool same = true;
+            std::vector<ecmc_melt_desc> d0;
+            (void)policy_descs(n_melts, melts, l_max, 0, d0);
+            for (int32_t m = 0; m < n_melts && same; ++m)
+                same = d0[m].n_cells == d[m].n_cells && d0[m].domain_cells == d[m].domain_cells;
+            if (same) continue;  // the policies agree on every melt: nothing new to time
+        }
+        const std::vector<int> tiers = tier_candidates(typical_frame(d));
+        ecmc_options o = *opt;
+        o.tiling = ECMC_TILING_CHECKER;
+        o.schedule = ECMC_SCHED_SWEEP;
+        o.stage_capacity = 0;
+        o.stage_tier = tiers.front();
+        o.event_log_capacity = 0;
+        o.time_kernels = 0;
+        ecmc_ctx *c = nullptr;
+        if ((st = ecmc_init_batch(&c, n_melts, d.data(), sigma, l_max, &o))) return st;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        auto done = [&](ecmc_status s) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            ecmc_destroy(c);
+            return s;
+        };
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return done(fail(nullptr, ECMC_E_DEVICE, "creating timing events failed"));
+        for (int tier : tiers) {
+            // the staging tier only changes which kernel runs: the layout (with its workspace
+            // slots for the larger domains) is the one of the smallest tier
+            const int bpl = tier / 64;
+            if (!sweep_bpl_supported(bpl)) continue;
+            c->p.bpl = bpl;
+            if ((st = ecmc_sweep(c, n_chains, ell, 0x5EEDu + (uint64_t)tier))) return done(st);
+            ecmc_counters k0{}, k1{};
+            if ((st = ecmc_get_counters(c, &k0))) return done(st);
+            if (hipEventRecord(e0, c->stream) != hipSuccess) return done(fail(nullptr, ECMC_E_DEVICE, "event record failed"));
+            for (int t = 0; t < trial_sweeps; ++t)
+                if ((st = ecmc_sweep(c, n_chains, ell, 0x5EEDu + (uint64_t)(tier + t + 1)))) return done(st);
+            if (hipEventRecord(e1, c->stream) != hipSuccess) return done(fail(nullptr, ECMC_E_DEVICE, "event record failed"));
+            if ((st = check_device(c))) return done(st);
+            if ((st = ecmc_get_counters(c, &k1))) return done(st);
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return done(fail(nullptr, ECMC_E_DEVICE, "event timing failed"));
+            const double rate = ms > 0 ? (double)(k1.ec - k0.ec) / (ms * 1e-3) : 0.0;
+            best->candidates++;
+            if (rate > best_rate) {
+                best_rate = rate;
+                best->stage_tier = tier;
+                best->policy = policy;
+                best->ms_per_sweep = ms / trial_sweeps;
+                best->ecs_per_s = rate;
+                chosen = d;
+            }
+        }
+        (void)done(ECMC_OK);
+    }
+    if (chosen.empty()) return fail(nullptr, ECMC_E_ARG, "no candidate configuration could be timed");
+    for (int32_t m = 0; m < n_melts; ++m) {
+        n_cells_out[m] = chosen[m].n_cells;
+        domain_cells_out[m] = chosen[m].domain_cells;
+    }
+    return ECMC_OK;
+}
 
 }  // extern "C"

@@ -41,6 +41,7 @@ class ecmc_options(ctypes.Structure):
         ("time_kernels", ctypes.c_int32),
         ("swap_moves", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
+        ("stage_tier", ctypes.c_int32),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
@@ -72,6 +73,14 @@ class ecmc_melt_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ecmc_tune_result(ctypes.Structure):
+    _fields_ = [("stage_tier", ctypes.c_int32), ("policy", ctypes.c_int32), ("ms_per_sweep", ctypes.c_double),
+                ("ecs_per_s", ctypes.c_double), ("candidates", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 class ecmc_counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("hs_lift", "tether_lift", "hs_reflect", "tether_reflect", "wall", "cross", "ec", "steps",
@@ -97,6 +106,7 @@ EXPORTS = (
     "ecmc_set_state", "ecmc_kernel_time", "ecmc_sweep_counter", "ecmc_n_cells", "ecmc_cell_size",
     "ecmc_stage_capacity", "ecmc_destroy", "ecmc_status_str", "ecmc_last_error",
     "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
+    "ecmc_tune_workspace_size", "ecmc_tune_batch",
 )
 
 
@@ -141,6 +151,9 @@ def lib():
         "ecmc_init_batch": (st, [P(vp), i32, P(ecmc_melt_desc), dbl, dbl, opt_p]),
         "ecmc_n_melts": (i32, [vp]),
         "ecmc_get_melt_info": (st, [vp, i32, P(ecmc_melt_info)]),
+        "ecmc_tune_workspace_size": (st, [i32, P(ecmc_melt_desc), dbl, dbl, opt_p, P(ctypes.c_size_t)]),
+        "ecmc_tune_batch": (st, [i32, P(ecmc_melt_desc), dbl, dbl, opt_p, i64, dbl, i32, P(i32), P(i32),
+                                 P(ecmc_tune_result)]),
         "ecmc_destroy": (None, [vp]),
         "ecmc_status_str": (ctypes.c_char_p, [st]),
         "ecmc_last_error": (ctypes.c_char_p, [vp]),
@@ -217,6 +230,29 @@ def ecmc_init_batch(melts, sigma: float, l_max: float, opt: ecmc_options, n_cell
     return h
 
 
+def ecmc_tune_batch(melts, sigma: float, l_max: float, opt: ecmc_options, n_chains: int, ell: float,
+                    trial_sweeps: int = 2, device: str = "cuda"):
+    """Run the library's autotuner on a scratch workspace (a torch tensor freed on return).
+    Returns (n_cells, domain_cells, result): per-melt geometry and the chosen staging tier."""
+    import torch
+    descs, keep = _melt_descs(melts)
+    n = ctypes.c_size_t()
+    _check(lib().ecmc_tune_workspace_size(len(melts), descs, sigma, l_max, ctypes.byref(opt), ctypes.byref(n)),
+           "ecmc_tune_workspace_size")
+    scratch = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+    o = ecmc_options.from_buffer_copy(opt)
+    o.workspace = (scratch.data_ptr() + 255) & ~255
+    o.workspace_bytes = n.value
+    nc = (ctypes.c_int32 * len(melts))()
+    dc = (ctypes.c_int32 * len(melts))()
+    res = ecmc_tune_result()
+    _check(lib().ecmc_tune_batch(len(melts), descs, sigma, l_max, ctypes.byref(o), int(n_chains), float(ell),
+                                 int(trial_sweeps), nc, dc, ctypes.byref(res)), "ecmc_tune_batch")
+    torch.cuda.synchronize()
+    del scratch
+    return list(nc), list(dc), res.as_dict()
+
+
 def ecmc_sweep(ctx, n_chains: int, ell: float, seed: int):
     _check(lib().ecmc_sweep(ctx, int(n_chains), float(ell), int(seed) & 0xFFFFFFFFFFFFFFFF), "ecmc_sweep", ctx)
 
@@ -248,6 +284,7 @@ class Options:
     precision: int = PREC_MIXED
     swap_moves: bool = False
     schedule: int = SCHED_SWEEP
+    stage_tier: int = 0
 
 
 def _native_options(o: "Options") -> ecmc_options:
@@ -263,6 +300,7 @@ def _native_options(o: "Options") -> ecmc_options:
     opt.time_kernels = 1 if o.time_kernels else 0
     opt.swap_moves = 1 if o.swap_moves else 0
     opt.schedule = o.schedule
+    opt.stage_tier = o.stage_tier
     return opt
 
 

@@ -471,3 +471,20 @@ def test_graph_of_sweeps_replays_like_eager_sweeps(small_batch):
         assert np.array_equal(g.cells(), e.cells()), rep
         ce, cg = e.counters(), g.counters()
         assert all(ce[k] == cg[k] for k in ("hs_lift", "hs_reflect", "ec", "steps", "cross", "wall")), rep
+
+
+def test_autotuner_returns_a_configuration_that_runs(small_batch):
+    """The autotuner times its candidates on a scratch workspace and returns per-melt cells and
+    domain edges and a staging tier that a batch context accepts and sweeps with."""
+    melts = small_batch
+    nb = sum(m.n_beads for m in melts)
+    opts = ecmc.Options()
+    nc, dc, res = ecmc.ecmc_tune_batch(melts, 1.0, 1.4, ecmc._native_options(opts), nb, 20.0, trial_sweeps=1)
+    assert res["candidates"] >= 1 and res["ecs_per_s"] > 0 and res["stage_tier"] in (64, 128, 192, 256, 384, 512)
+    for m, n, D in zip(melts, nc, dc):
+        assert n >= 4 and D >= 2 and n % D == 0 and (n // D) % 2 == 0 and m.L / n > 1.4
+    opts.stage_tier = res["stage_tier"]
+    g = ecmc.Melt.from_batch(melts, opts, n_cells=nc, domain_cells=dc)
+    g.sweep(nb, 20.0, 3)
+    g.synchronize()
+    assert g.counters()["ec"] > 0
