@@ -38,14 +38,22 @@ def bytes_per_event(beads_per_cell: float) -> float:
     return 18 * beads_per_cell * 28 + 18 * 4 + 3 * 28 + 24
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ecmc_phase_c3_1M_fp64_hbm_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1502_06447_amd", "csrc", "ecmc_kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ecmc_sweep_c3_1M_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1502_06447_amd", "csrc", f)
+                  for f in ("ecmc_device.h", "ecmc_internal.h", "ecmc_kernels.hip", "ecmc_sweep.hip")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
-    """HBM bytes per colour phase from the committed FETCH_SIZE / WRITE_SIZE summary, or None
-    when there is none or the kernel source has changed since the counters were taken."""
-    import hashlib
+    """HBM bytes per sweep launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None
+    when there is none or the kernel sources have changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     fields = {}
@@ -53,10 +61,9 @@ def measured_traffic():
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].strip().split(": ", 1)
             fields[k.strip("`")] = v.strip().strip("`")
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != src or "hbm_bytes_per_phase" not in fields:
+    if fields.get("kernel_source_sha256") != kernel_source_hash() or "hbm_bytes_per_launch" not in fields:
         return None
-    return float(fields["hbm_bytes_per_phase"])
+    return float(fields["hbm_bytes_per_launch"])
 
 
 WORKLOADS = {
@@ -362,10 +369,9 @@ def main():
     ecs = d["ec"]
     value = events / dt
     B = bytes_per_event(beads_per_cell)
-    sweeps = launches  # one timing pair per colour phase
-    kernel_s = kms / 1e3
+    kernel_s = kms / 1e3  # HIP events around each sweep launch (or colour phase, by phases)
     achieved = events * B / kernel_s / 1e9 if kernel_s > 0 else 0.0
-    traffic = measured_traffic() if args.workload == "c3" and not args.swap else None
+    traffic = measured_traffic() if args.workload == "c3" and not args.swap and args.precision == "mixed" else None
     out = {
         "metric": "collision events/s",
         "value": value,
@@ -391,7 +397,7 @@ def main():
         "events_per_ec": events / max(ecs, 1),
         "counters": {k: int(v) if isinstance(v, int) else v for k, v in d.items()},
         "kernel_ms_per_step": kms / args.steps,
-        "phase_launches": launches,
+        "timed_launches": launches,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -399,9 +405,11 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "algorithmic_bytes_per_launch": events * B / max(launches, 1),
             "bytes_per_event": B,
-            "note": "algorithmic bytes (18-cell forward cell-list scan per collision event) over the "
-                    "HIP-event time of the phase kernels",
+            "note": "achieved: algorithmic bytes (18-cell forward cell-list scan per collision event) over the "
+                    "HIP-event time of the sweep launches (one dependency-ordered kernel per sweep); traffic: "
+                    "measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated by a copy)",
         },
     }
     out["roofline"]["measured_copy_GBps"] = copy_bandwidth()

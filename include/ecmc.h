@@ -196,7 +196,8 @@ ecmc_status ecmc_init_batch(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_des
                             double sigma, double l_max, const ecmc_options *opt);
 
 /* The autotuner of the batched form.  Candidates: the LDS staging tier (64, 128, 192, 256,
- * 384 or 512 beads per domain frame, from the smallest that holds the typical frame) and
+ * 384 or 512 beads per domain frame: up to four, from the smallest that holds the mean frame
+ * of the melt holding the median bead; larger frames go to workspace slots) and
  * two domain policies per melt: 0 = D = 2 on the largest multiple of 4 cells per axis, 1 =
  * the (n, D) of smallest typical frame among n from that multiple up to the largest n
  * (n/D even).  Each candidate is initialised in opt->workspace (scratch; it must hold

@@ -1109,7 +1109,7 @@ ecmc_status policy_descs(int32_t n_melts, const ecmc_melt_desc *melts, double lm
     return ECMC_OK;
 }
 
-// Staging tiers worth timing: from the smallest one holding the typical frame of the median
+// Staging tiers worth timing: from the smallest one holding the mean frame of the median
 // bead (the frame of its melt) up to four tiers; the domains above a tier are staged in
 // workspace slots, so a tier below the largest melts' frames trades their speed for that of
 // the rest.
@@ -1123,13 +1123,12 @@ std::vector<int> tier_candidates(double typical) {
 }
 
 double typical_frame(const std::vector<ecmc_melt_desc> &d) {
-    // the typical frame (mean plus three standard deviations of a Poisson count) of the melt
-    // holding the median bead
+    // the mean frame of the melt holding the median bead
     std::vector<std::pair<double, int64_t>> f;
     int64_t total = 0;
     for (const ecmc_melt_desc &m : d) {
         const double mean = std::pow((double)(m.domain_cells + 2), 3) * (double)m.n_beads / std::pow((double)m.n_cells, 3);
-        f.emplace_back(mean + 3.0 * std::sqrt(mean), m.n_beads);
+        f.emplace_back(mean, m.n_beads);
         total += m.n_beads;
     }
     std::sort(f.begin(), f.end());
