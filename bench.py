@@ -15,8 +15,12 @@ event at the algorithmic bytes of a cell-list search over the 18-cell forward
 neighbourhood (1,384 B at this density, FP64) against 8 TB/s of HBM; the kernel
 itself keeps each domain in registers, so its measured HBM traffic is far below.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c5] [--precision mixed|fp64]
-       [--swap]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c5|c4] [--precision mixed|fp64]
+       [--swap] [--springs K [--spring-cap B]]
+
+--springs K bonds the same chains by harmonic springs (k/2)(b - sigma)^2 of constant K (Eq. (2);
+the paper's melts use K = 30), capped at B sigma (default 1.8, which cuts off a Boltzmann weight
+of 3e-5 of a free bond); the cells then have edge > B.
 """
 from __future__ import annotations
 
@@ -40,7 +44,8 @@ def bytes_per_event(beads_per_cell: float) -> float:
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ecmc_sweep_c3_1M_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1502_06447_amd", "csrc", f)
-                  for f in ("ecmc_device.h", "ecmc_internal.h", "ecmc_kernels.hip", "ecmc_sweep.hip")]
+                  for f in ("ecmc_device.h", "ecmc_internal.h", "ecmc_kernels.hip", "ecmc_phase.hip",
+                            "ecmc_sweep.hip")]
 
 
 def kernel_source_hash() -> str:
@@ -77,15 +82,21 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False) -> dict:
+def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False, spring_k: float = 0.0,
+                 b_max: float = 1.4) -> dict:
     """The CPU oracle (serial, one core) on a bounded sample of the same workload: an
-    independent 64 x 64 melt at the same packing fraction, ell and domain size."""
+    independent 64 x 64 melt at the same packing fraction, ell, domain size and bonds."""
     import oracle
     from paper_1502_06447_amd import inputs
 
-    m = inputs.lattice_chains(64, 64, w["eta"], seed=seed)
-    o = oracle.Oracle.from_melt(m)
+    m = inputs.lattice_chains(64, 64, w["eta"], seed=seed, b_max=b_max)
+    # the largest cell grid with edge > b_max that the checkerboard of D^3-cell domains tiles
+    n = int(m.L // b_max)
+    while n > 0 and (m.L / n <= b_max or n % w["D"] or (n // w["D"]) % 2):
+        n -= 1
+    o = oracle.Oracle.from_melt(m, n_cells=n)
     o.set_swap(swap)
+    o.set_spring(spring_k)
     for s in range(2):  # melt the lattice like the GPU warm-up does
         o.sweep(m.n_beads, w["ell"], 100 + s, tiling=1, D=w["D"])
     c0, _ = o.counters()
@@ -99,7 +110,8 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False) ->
     ev = int(sum(c1[i] - c0[i] for i in (oracle.C_HS_LIFT, oracle.C_TETHER_LIFT, oracle.C_HS_REFLECT,
                                           oracle.C_TETHER_REFLECT, oracle.C_SWAP)))
     return {"value": ev / dt, "unit": "collision events/s", "cores": 1, "kind": "oracle",
-            "sample": f"64 x 64 beads (4,096), eta={w['eta']}, ell={w['ell']}, D={w['D']}: {k} sweeps "
+            "sample": f"64 x 64 beads (4,096), eta={w['eta']}, ell={w['ell']}, D={w['D']}, {n}^3 cells"
+                      + (f", springs k={spring_k} capped at {b_max}" if spring_k else "") + f": {k} sweeps "
                       f"after 2 warm-up sweeps, {dt:.1f} s, single thread",
             "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
 
@@ -125,7 +137,7 @@ def copy_bandwidth(gib: int = 2, reps: int = 5) -> float:
     return 2.0 * n / best / 1e9
 
 
-def precision_check(melt, w, sweeps: int, swap: bool = False) -> dict:
+def precision_check(melt, w, sweeps: int, swap: bool = False, spring_k: float = 0.0) -> dict:
     """Both precisions from the same start through the same sweeps (untimed): the screened
     kernel must reproduce the plain FP64 kernel bit for bit."""
     import numpy as np
@@ -133,7 +145,7 @@ def precision_check(melt, w, sweeps: int, swap: bool = False) -> dict:
     res = {}
     for name, prec in (("mixed", ecmc.PREC_MIXED), ("fp64", ecmc.PREC_FP64)):
         g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], precision=prec,
-                                                   swap_moves=swap))
+                                                   swap_moves=swap, spring_k=spring_k))
         for i in range(sweeps):
             g.sweep(melt.n_beads, w["ell"], 7000 + i)
         g.synchronize()
@@ -304,6 +316,10 @@ def main():
                     help="mixed: single-precision screen + FP64 evaluation (default); fp64: every staged "
                          "bead evaluated in FP64 at every event (the plain kernel); identical results")
     ap.add_argument("--swap", action="store_true", help="swap moves at hard-sphere contacts (Sec. II.C)")
+    ap.add_argument("--springs", type=float, default=0.0, metavar="K",
+                    help="bonds as harmonic springs of constant K (Eq. (2), k_B T / sigma^2); 0 = tethers")
+    ap.add_argument("--spring-cap", type=float, default=1.8, metavar="B",
+                    help="with --springs: bond length cap in sigma (cells get an edge > B)")
     ap.add_argument("--no-precision-check", action="store_true",
                     help="skip the untimed comparison of the two precisions after the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -318,7 +334,11 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "c4":
+        if args.springs:
+            print("--springs is not offered for the batched workload", file=sys.stderr)
+            sys.exit(2)
         return main_batch(args)
+    b_max = args.spring_cap if args.springs else 1.4
 
     import numpy as np
     import torch
@@ -335,10 +355,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         print(f"# copy probe: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
-    melt = inputs.lattice_chains(w["M"], w["N"], w["eta"], seed=args.seed)
+    melt = inputs.lattice_chains(w["M"], w["N"], w["eta"], seed=args.seed, b_max=b_max)
     prec = ecmc.PREC_MIXED if args.precision == "mixed" else ecmc.PREC_FP64
     g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], time_kernels=True,
-                                               precision=prec, swap_moves=args.swap))
+                                               precision=prec, swap_moves=args.swap, spring_k=args.springs))
     nb = melt.n_beads
     n = g.n_cells
     beads_per_cell = nb / n ** 3
@@ -371,7 +391,8 @@ def main():
     B = bytes_per_event(beads_per_cell)
     kernel_s = kms / 1e3  # HIP events around each sweep launch (or colour phase, by phases)
     achieved = events * B / kernel_s / 1e9 if kernel_s > 0 else 0.0
-    traffic = measured_traffic() if args.workload == "c3" and not args.swap and args.precision == "mixed" else None
+    traffic = (measured_traffic() if args.workload == "c3" and not args.swap and not args.springs
+               and args.precision == "mixed" else None)
     out = {
         "metric": "collision events/s",
         "value": value,
@@ -388,8 +409,10 @@ def main():
         "config": {
             "workload": f"{args.workload}: {w['label']}, ell={w['ell']} sigma, checkerboard D={w['D']}, "
                         f"{n}^3 cells, FP64 results ({args.precision} event search)"
-                        + (", swap moves" if args.swap else ""),
+                        + (", swap moves" if args.swap else "")
+                        + (f", harmonic springs k={args.springs} capped at {b_max} sigma" if args.springs else ""),
             "precision": args.precision, "swap_moves": bool(args.swap),
+            "bonds": (f"spring k={args.springs}, cap {b_max} sigma" if args.springs else "tether 1.4 sigma"),
             "beads": nb, "chains": w["M"], "beads_per_chain": w["N"], "eta": w["eta"], "ell": w["ell"],
             "domain_cells": w["D"], "cells_per_axis": n, "parallelism": "single GPU",
         },
@@ -414,9 +437,10 @@ def main():
     }
     out["roofline"]["measured_copy_GBps"] = copy_bandwidth()
     if not args.no_precision_check:
-        out["precision_check"] = precision_check(melt, w, sweeps=2, swap=args.swap)
+        out["precision_check"] = precision_check(melt, w, sweeps=2, swap=args.swap, spring_k=args.springs)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds, swap=args.swap)
+        out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds, swap=args.swap, spring_k=args.springs,
+                                           b_max=b_max)
         out["cpu_baseline"]["vs_gpu"] = value / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
 

@@ -117,6 +117,12 @@ typedef struct {
                                    (a multiple of 64 up to 512; 0 = sized for the typical
                                    domain); larger domains are staged as for the automatic
                                    capacity.  The knob ecmc_tune_batch sets                */
+    double spring_k;            /* 0 (default): bonds are tethers of length at most l_max.
+                                   > 0: harmonic springs (k/2)(b - sigma)^2 of this constant
+                                   (Eq. (2), in k_B T / sigma^2, within [1e-6, 1e12]), still
+                                   capped at l_max; each step draws one energy per bond of
+                                   the pivot, and whole periods after a reflection are not
+                                   dropped.  Not combined with swap_moves                  */
     void *workspace;            /* device memory owned by the caller (256-byte aligned)     */
     size_t workspace_bytes;
     void *stream;               /* hipStream_t for every launch and copy; NULL = default    */
@@ -259,6 +265,35 @@ ecmc_status ecmc_observables(ecmc_ctx *ctx, int32_t nbins, double *r2, double *r
  * N (tr G 1 - G), eigenvalues N (tr G - l_i)), and the centre of mass in image-unwrapped
  * coordinates com [3].  Host outputs of n_poly entries (any may be NULL).  Synchronises. */
 ecmc_status ecmc_shape(ecmc_ctx *ctx, double *gyr, double *eig, double *com, int64_t *n_poly);
+
+/* Snapshot for the mean-square displacements g1 and g2 (Sec. IV.A): per polymer the middle bead
+ * floor(N/2) and the centre of mass, both image-unwrapped (as ecmc_observables and ecmc_shape
+ * give them), written as snap [n_poly][6] (x, y, z of the bead, then of the centre) to DEVICE
+ * memory owned by the caller (8-byte aligned).  Queued on the context's stream; does not
+ * synchronise, so a run can record snapshots between sweeps without host copies. */
+ecmc_status ecmc_snapshot(ecmc_ctx *ctx, double *snap_device);
+
+/* g1 and g2 (Sec. IV.A) of a series of T snapshots [T][n_poly][6] in DEVICE memory (as written
+ * by ecmc_snapshot, equally spaced in time), averaged over the polymers and over every time
+ * origin: for each lag d = 0..T-1,
+ *   g1(d) = < |r_mid(t + d) - r_mid(t)|^2 >,  g2(d) = < |(r_mid - R_cm)(t + d) - (r_mid - R_cm)(t)|^2 >,
+ * written to out_device [2][T] (g1, then g2; 0 at d = 0), DEVICE memory of the caller.  Queued on
+ * the context's stream; does not synchronise.  T in [1, 2^31 - 1]. */
+ecmc_status ecmc_msd(ecmc_ctx *ctx, const double *snaps_device, int64_t T, double *out_device);
+
+/* End-to-end distance distribution W(R) (appendix): over all polymers, the number with
+ * |R| in [k w, (k + 1) w), w = r_max / nbins, k = 0..nbins-1; |R| >= r_max is counted in the
+ * last bin.  |R| = sqrt(R^2) with R^2 as ecmc_observables computes it.  Host hist [nbins],
+ * nbins in [1, 1024].  Synchronises. */
+ecmc_status ecmc_end_to_end_histogram(ecmc_ctx *ctx, int32_t nbins, double r_max, int64_t *hist);
+
+/* Pair counts behind the pair correlation g(r): the pairs i < j of one melt (summed over the
+ * melts of a batch) whose minimum-image distance r is below r_max, binned by
+ * floor(r / r_max * nbins) (clamped to nbins - 1).  r_max may not exceed the smallest cell
+ * edge (the pairs are found through the cell lists); g(r) follows by dividing by the ideal-gas
+ * counts N (N - 1) / 2 * 4 pi (r_hi^3 - r_lo^3) / (3 V) of each bin.  Host hist [nbins], nbins
+ * in [1, 1024].  Synchronises. */
+ecmc_status ecmc_pair_histogram(ecmc_ctx *ctx, int32_t nbins, double r_max, int64_t *hist);
 
 /* Host copies of the state: positions [n][3], cell indices [n][3], image counters [n][3]. */
 ecmc_status ecmc_get_positions(ecmc_ctx *ctx, double *out);

@@ -55,6 +55,13 @@ def lib():
         L.orc_destroy.argtypes = [vp]
         L.orc_set_options.argtypes = [vp, i64, ctypes.c_int]
         L.orc_set_swap.argtypes = [vp, ctypes.c_int]
+        L.orc_set_swap.restype = ctypes.c_int
+        L.orc_set_spring.argtypes = [vp, dbl]
+        L.orc_set_spring.restype = ctypes.c_int
+        L.orc_bond_x.argtypes = [vp, dbl, dbl, dbl]
+        L.orc_bond_x.restype = dbl
+        L.orc_ln.argtypes = [dbl]
+        L.orc_ln.restype = dbl
         L.orc_set_stream.argtypes = [vp, u32]
         L.orc_set_stream.restype = ctypes.c_int
         L.orc_set_log.argtypes = [vp, vp, i64]
@@ -67,6 +74,10 @@ def lib():
         L.orc_next_event.argtypes = [vp, i32, ctypes.c_int, ctypes.c_int, P(dbl), P(i32), P(ctypes.c_int), P(dbl)]
         L.orc_run_ec.argtypes = [vp, i32, ctypes.c_int, dbl]
         L.orc_observables.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, P(i64)]
+        L.orc_pair_histogram.argtypes = [vp, ctypes.c_int, dbl, vp]
+        L.orc_pair_histogram.restype = ctypes.c_int
+        L.orc_end_to_end_histogram.argtypes = [vp, ctypes.c_int, dbl, vp]
+        L.orc_end_to_end_histogram.restype = ctypes.c_int
         L.orc_gyration.argtypes = [vp, i64, vp]
         L.orc_gyration.restype = None
         L.orc_shape.argtypes = [vp, vp, vp]
@@ -93,6 +104,11 @@ class OracleError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__(f"{what}: oracle status {code}")
         self.code = code
+
+
+def ln(u: float) -> float:
+    """The oracle's natural logarithm (the one the spring draws use)."""
+    return lib().orc_ln(float(u))
 
 
 def philox4x32_10(ctr, key) -> np.ndarray:
@@ -160,7 +176,18 @@ class Oracle:
 
     def set_swap(self, on: bool = True):
         """Swap moves at hard-sphere contacts (Sec. II.C) for the following ECs."""
-        lib().orc_set_swap(self._h, 1 if on else 0)
+        if lib().orc_set_swap(self._h, 1 if on else 0) != OK:
+            raise ValueError("swap moves cannot be combined with springs")
+
+    def set_spring(self, k: float):
+        """Bonds as harmonic springs of constant k (Eq. (2), k_B T / sigma^2), capped at b_max;
+        k = 0 gives tethers."""
+        if lib().orc_set_spring(self._h, float(k)) != OK:
+            raise ValueError(f"spring constant {k!r} refused")
+
+    def bond_x(self, dpar: float, dperp2: float, g: float) -> float:
+        """Bond candidate for a partner at (d_par, d_perp^2); g = 2 dE / k, or < 0 for the tether."""
+        return lib().orc_bond_x(self._h, float(dpar), float(dperp2), float(g))
 
     def set_stream(self, m: int):
         """Random stream m: the draws of melt m of a batch (Philox counter word 3 = 2 m, 2 m + 1)."""
@@ -238,6 +265,27 @@ class Oracle:
         if st != OK:
             raise OracleError(st, "orc_set_state")
 
+    def pair_histogram(self, nbins: int, r_max: float) -> np.ndarray:
+        """Pair counts (i < j, minimum image, r < r_max) in nbins bins of width r_max / nbins."""
+        h = np.zeros(int(nbins), dtype=np.int64)
+        st = lib().orc_pair_histogram(self._h, int(nbins), float(r_max), h.ctypes.data)
+        if st != OK:
+            raise OracleError(st, "orc_pair_histogram")
+        return h
+
+    def end_to_end_histogram(self, nbins: int, r_max: float) -> np.ndarray:
+        """W(R): polymers per bin of |R| (width r_max / nbins; |R| >= r_max in the last bin)."""
+        h = np.zeros(int(nbins), dtype=np.int64)
+        st = lib().orc_end_to_end_histogram(self._h, int(nbins), float(r_max), h.ctypes.data)
+        if st != OK:
+            raise OracleError(st, "orc_end_to_end_histogram")
+        return h
+
+    def snapshot(self) -> np.ndarray:
+        """Per polymer: the middle bead floor(N/2) and the centre of mass, both image-unwrapped,
+        as [n_poly, 6] (the quantities whose displacements g1 and g2 of Sec. IV.A average)."""
+        return np.concatenate([self.observables(nbins=1)["mid"], self.shape()["com"]], axis=1)
+
     def observables(self, nbins: int = 20):
         n_poly = ctypes.c_int64()
         lib().orc_observables(self._h, 0, None, None, None, None, ctypes.byref(n_poly))
@@ -288,3 +336,21 @@ def shape_descriptors(eig) -> dict:
             "r_132": float((I[..., 0] - I[..., 1] + I[..., 2]).mean() / tr.mean()),
             "r_231": float((-I[..., 0] + I[..., 1] + I[..., 2]).mean() / tr.mean()),
             "solc": float((4 * b ** 2 + 3 * c ** 2).mean() / tr.mean() ** 2)}
+
+
+def msd_series(snaps) -> tuple[np.ndarray, np.ndarray]:
+    """Mean-square displacements of Sec. IV.A from a time series of snapshots [T, n_poly, 6]
+    (middle bead r_{N/2}, centre of mass R, both unwrapped), averaged over polymers and over
+    every time origin t: for each lag d = 0..T-1,
+      g1(d) = < |r_{N/2}(t + d) - r_{N/2}(t)|^2 >,
+      g2(d) = < |(r_{N/2} - R)(t + d) - (r_{N/2} - R)(t)|^2 >."""
+    s = np.asarray(snaps, dtype=np.float64)
+    T = s.shape[0]
+    mid = s[:, :, 0:3]
+    rel = s[:, :, 0:3] - s[:, :, 3:6]
+    g1 = np.zeros(T)
+    g2 = np.zeros(T)
+    for d in range(1, T):
+        g1[d] = np.mean(np.sum((mid[d:] - mid[:-d]) ** 2, axis=2))
+        g2[d] = np.mean(np.sum((rel[d:] - rel[:-d]) ** 2, axis=2))
+    return g1, g2

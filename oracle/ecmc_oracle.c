@@ -8,7 +8,8 @@
  *
  * Model (Sec. II): hard spheres of diameter sigma between ALL bead pairs (Eq. (1)),
  * bonded neighbours joined by tethers of maximal length b_max (the tether variant
- * stated after Eq. (2)), periodic cube of edge L.
+ * stated after Eq. (2)) or, optionally, by harmonic springs (k/2)(b - sigma)^2 (Eq. (2)),
+ * periodic cube of edge L.
  *
  * EC move (Sec. II, steps 1-4, and the generalisation to several interaction
  * partners that follows them): a pivot bead and a direction v = s e_a are drawn,
@@ -44,7 +45,16 @@
  *    stream index m = 0 unless set (m numbers a melt of a batch run side by side);
  *  - swap moves (Sec. II.C, optional): proposed at every hard-sphere contact with a motile
  *    bead; accepted iff all tethers of both beads are within b_max after the exchange
- *    (squared minimum-image lengths, summed over x, y, z, compared with b_max^2).
+ *    (squared minimum-image lengths, summed over x, y, z, compared with b_max^2);
+ *  - springs (optional, Eq. (2) with the EC rule for pair potentials of Sec. II): at every
+ *    step each bond of the pivot gets a fresh energy dE = -ln u, u uniform in (0, 1] (by the
+ *    memorylessness of the exponential law this equals one draw per event); the bond is also
+ *    capped at b_max, a tether, so that every partner lies within one cell.  The draws of step
+ *    j of EC k use the counter (j, k, domain, sweep) under a second key, words 0-1 of the
+ *    draw at counter (2^32-1, 2^32-1, m, 0x53505247) under the seed's key; partner slot t
+ *    takes words 2t (low 21 bits dropped) and 2t+1.  A spring EC does not retrace its path
+ *    after a reflection, so the periodic reduction is off; swap moves are not combined with
+ *    springs.
  */
 #include "ecmc_oracle.h"
 
@@ -70,6 +80,8 @@ struct orc_sys {
     int64_t event_cap;
     int check;
     int swap;          /* swap moves at hard-sphere contacts (Sec. II.C) */
+    int spring;        /* bonds are harmonic springs capped at b_max (Eq. (2)) */
+    double spring_k, two_over_k;
     uint32_t stream;   /* random stream index m (counter word 3 = 2 m, 2 m + 1) */
     orc_event *log;
     int64_t log_cap, log_n;
@@ -348,7 +360,16 @@ int orc_set_options(orc_sys *s, int64_t event_cap, int check) {
 }
 
 int orc_set_swap(orc_sys *s, int on) {
+    if (on && s->spring) return ORC_E_ARG;
     s->swap = on ? 1 : 0;
+    return ORC_OK;
+}
+
+int orc_set_spring(orc_sys *s, double k) {
+    if (!(k >= 0.0) || !isfinite(k) || (k > 0.0 && s->swap)) return ORC_E_ARG;
+    s->spring = k > 0.0;
+    s->spring_k = k;
+    s->two_over_k = k > 0.0 ? 2.0 / k : 0.0;
     return ORC_OK;
 }
 
@@ -374,6 +395,7 @@ typedef struct {
     int off[3];     /* partition offset (cells) */
     int dom[3];     /* active domain coordinates */
     uint32_t sweep, domain, colour, ec;
+    uint32_t skey[2]; /* key of the spring energy draws */
 } orc_dom;
 
 static int dom_coord(const orc_sys *s, const orc_dom *dm, int c, int a) {
@@ -444,6 +466,57 @@ static double tether_candidate(const orc_sys *s, double dpar, double dperp2) {
     return v;
 }
 
+/* Natural logarithm of a finite u > 0, written out so that its bits can be reproduced
+ * elsewhere from the same steps: u = f 2^e with f in [sqrt(1/2), sqrt(2)); with
+ * z = (f - 1)/(f + 1), ln f = 2 artanh z = 2 z (1 + z^2/3 + z^4/5 + ... + z^22/23), the
+ * bracket by Horner's rule (|z| <= 0.1716, so the first term left out is below 2^-60 of
+ * it); ln u = e ln 2 + ln f. */
+double orc_ln(double u) {
+    int e;
+    double f = frexp(u, &e); /* u = f 2^e, f in [1/2, 1) */
+    if (f < 0.70710678118654752440) {
+        f = f + f;
+        e = e - 1;
+    }
+    const double z = (f - 1.0) / (f + 1.0);
+    const double z2 = z * z;
+    double sum = 1.0 / 23.0;
+    for (int n = 10; n >= 0; --n) sum = 1.0 / (double)(2 * n + 1) + z2 * sum;
+    return (double)e * 0.69314718055994530942 + (z + z) * sum;
+}
+
+/* The two energies of one step (one per bond slot of the pivot), as dE * 2/k. */
+static void spring_terms(const orc_sys *s, const orc_dom *dm, uint32_t step, double g[2]) {
+    const uint32_t ctr[4] = {step, dm->ec, dm->domain, dm->sweep};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, dm->skey, w);
+    for (int t = 0; t < 2; ++t) {
+        const uint64_t bits = ((uint64_t)w[2 * t + 1] << 21) | (uint64_t)(w[2 * t] >> 11);
+        const double u = (double)(bits + 1u) * 0x1p-53; /* in (0, 1] */
+        g[t] = -orc_ln(u) * s->two_over_k;
+    }
+}
+
+/* Bond candidate.  Tether: as above.  Spring (Eq. (2)): along the path the bond first
+ * shortens (no energy needed) until the pivot passes the partner's foot on its line, then
+ * lengthens.  From the shortest length still ahead, b0 = d_perp if d_par > 0, else the
+ * present length, the drawn energy is used up where (k/2)(b - sigma)^2 has grown by dE:
+ * b_end = sigma + sqrt((b0 - sigma)^2 + 2 dE/k), capped at b_max, reached after
+ * x = d_par + sqrt(b_end^2 - d_perp^2).  g = 2 dE / k; g < 0 selects the tether. */
+double orc_bond_x(const orc_sys *s, double dpar, double dperp2, double g) {
+    if (!(g >= 0.0)) return tether_candidate(s, dpar, dperp2);
+    const double b0 = sqrt(dpar > 0.0 ? dperp2 : dpar * dpar + dperp2);
+    const double e = b0 - s->sigma;
+    const double be = s->sigma + sqrt(e * e + g);
+    double be2 = be * be;
+    if (be2 > s->b2) be2 = s->b2;
+    double q = be2 - dperp2;
+    if (!(q > 0.0)) q = 0.0;
+    double x = dpar + sqrt(q);
+    if (!(x > 0.0)) x = 0.0;
+    return x;
+}
+
 typedef struct {
     double x;
     int32_t j;
@@ -462,7 +535,7 @@ static void consider(orc_best *b, double x, int32_t j, int kind, double dpar) {
 
 /* Minimum over all interaction partners of the pivot (Sec. II): every bead in the 27
  * cells around the pivot's cell (hard spheres) and its tethered partners (tethers). */
-static orc_best scan_partners(const orc_sys *s, int32_t p, int axis, int sgn) {
+static orc_best scan_partners(const orc_sys *s, int32_t p, int axis, int sgn, const double *g) {
     orc_best best = {INFINITY, 0x7fffffff, 0, 0.0};
     const int32_t *cp = s->cell + 3 * p;
     const int n = s->n;
@@ -496,13 +569,13 @@ static orc_best scan_partners(const orc_sys *s, int32_t p, int axis, int sgn) {
         }
         double dpar, dperp2;
         geom(s, p, q, w, axis, sgn, &dpar, &dperp2);
-        consider(&best, tether_candidate(s, dpar, dperp2), q, 1, dpar);
+        consider(&best, orc_bond_x(s, dpar, dperp2, g ? g[t] : -1.0), q, 1, dpar);
     }
     return best;
 }
 
 /* Brute force over every bead with the minimum-image convention (self-check). */
-static orc_best brute_partners(const orc_sys *s, int32_t p, int axis, int sgn) {
+static orc_best brute_partners(const orc_sys *s, int32_t p, int axis, int sgn, const double *g) {
     orc_best best = {INFINITY, 0x7fffffff, 0, 0.0};
     for (int64_t j = 0; j < s->nb; ++j) {
         if (j == p) continue;
@@ -513,8 +586,8 @@ static orc_best brute_partners(const orc_sys *s, int32_t p, int axis, int sgn) {
         const double dperp2 = d[b] * d[b] + d[c] * d[c];
         double x;
         if (hs_candidate(s, dpar, dperp2, &x)) consider(&best, x, (int32_t)j, 0, dpar);
-        if (s->nbr[2 * p] == j || s->nbr[2 * p + 1] == j)
-            consider(&best, tether_candidate(s, dpar, dperp2), (int32_t)j, 1, dpar);
+        for (int t = 0; t < 2; ++t)
+            if (s->nbr[2 * p + t] == j) consider(&best, orc_bond_x(s, dpar, dperp2, g ? g[t] : -1.0), (int32_t)j, 1, dpar);
     }
     return best;
 }
@@ -530,7 +603,7 @@ static double x_cell_of(const orc_sys *s, int32_t p, int axis, int sgn) {
 int orc_next_event(const orc_sys *s, int32_t p, int axis, int sgn, double *x, int32_t *j,
                    int *kind, double *x_cell) {
     if (p < 0 || p >= s->nb || axis < 0 || axis > 2 || (sgn != 1 && sgn != -1)) return ORC_E_ARG;
-    const orc_best b = scan_partners(s, p, axis, sgn);
+    const orc_best b = scan_partners(s, p, axis, sgn, NULL);
     *x = b.x;
     *j = b.x < INFINITY ? b.j : -1;
     *kind = b.kind;
@@ -662,10 +735,12 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
         if ((int64_t)step >= s->event_cap) return ORC_E_STUCK;
         step++;
         s->cnt[ORC_C_STEPS]++;
-        const orc_best b = scan_partners(s, p, axis, sgn);
+        double g[2];
+        if (s->spring) spring_terms(s, dm, step, g);
+        const orc_best b = scan_partners(s, p, axis, sgn, s->spring ? g : NULL);
         const double xc = x_cell_of(s, p, axis, sgn);
         if (s->check >= 2) {
-            const orc_best bf = brute_partners(s, p, axis, sgn);
+            const orc_best bf = brute_partners(s, p, axis, sgn, s->spring ? g : NULL);
             if (b.x <= xc) {
                 if (!(bf.x == b.x && bf.j == b.j && bf.kind == b.kind)) return ORC_E_CHECK;
             } else if (!(bf.x > xc)) {
@@ -711,7 +786,7 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
             } else {
                 log_event(s, dm, step, p, b.j, b.kind == 0 ? ORC_EV_HS_REFLECT : ORC_EV_TETHER_REFLECT);
                 s->cnt[b.kind == 0 ? ORC_C_HS_REFLECT : ORC_C_TETHER_REFLECT]++;
-                if (reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+                if (!s->spring && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
                 reflected = 1;
                 xref = xmax;
                 sgn = -sgn;
@@ -755,7 +830,7 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
         } else {
             log_event(s, dm, step, p, -1, ORC_EV_WALL);
             s->cnt[ORC_C_WALL]++;
-            if (reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+            if (!s->spring && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
             reflected = 1;
             xref = xmax;
             sgn = -sgn;
@@ -800,6 +875,13 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
     orc_dom dm;
     memset(&dm, 0, sizeof dm);
     dm.sweep = sweep;
+    {
+        const uint32_t ctr[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, s->stream, 0x53505247u};
+        uint32_t u[4];
+        orc_philox4x32_10(ctr, key, u);
+        dm.skey[0] = u[0];
+        dm.skey[1] = u[1];
+    }
     if (tiling == 0) {
         /* one domain: the whole box */
         dm.tiled = 0;
@@ -987,6 +1069,48 @@ int orc_observables(const orc_sys *s, int nbins, double *r2, double *rg2, int64_
             for (int k = 0; k < 3; ++k) mid[3 * q + k] = s->r[3 * im + k] + (double)s->img[3 * im + k] * s->L;
         }
     }
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- pair distances */
+/* Histogram of the distances of all bead pairs i < j closer than r_max (minimum image, by brute
+ * force over every pair), bin floor(r / r_max * nbins) (clamped to nbins - 1): the pair counts
+ * behind g(r).  Displacements are taken as (r_j - r_i) and then shifted by the box edge, the
+ * squared length summed over x, y, z in that order. */
+int orc_pair_histogram(const orc_sys *s, int nbins, double rmax, int64_t *hist) {
+    if (nbins < 1 || !(rmax > 0.0) || !(rmax <= s->halfL)) return ORC_E_ARG;
+    for (int k = 0; k < nbins; ++k) hist[k] = 0;
+    for (int64_t i = 0; i < s->nb; ++i)
+        for (int64_t j = i + 1; j < s->nb; ++j) {
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = mi(s, s->r[3 * j + a] - s->r[3 * i + a]);
+            const double q0 = d[0] * d[0];
+            const double q1 = d[1] * d[1];
+            const double q2 = d[2] * d[2];
+            const double r = sqrt((q0 + q1) + q2);
+            if (!(r < rmax)) continue;
+            int bin = (int)floor(r / rmax * (double)nbins);
+            if (bin > nbins - 1) bin = nbins - 1;
+            hist[bin]++;
+        }
+    return ORC_OK;
+}
+
+/* End-to-end distance distribution W(R) (appendix, end-to-end distance distribution): the
+ * histogram over polymers of |R| = sqrt(R^2), R^2 as orc_observables computes it, bin
+ * floor(|R| / r_max * nbins), values at or above r_max in the last bin. */
+int orc_end_to_end_histogram(const orc_sys *s, int nbins, double rmax, int64_t *hist) {
+    if (nbins < 1 || !(rmax > 0.0)) return ORC_E_ARG;
+    double *r2 = (double *)malloc(sizeof(double) * (size_t)(s->npoly > 0 ? s->npoly : 1));
+    if (!r2) return ORC_E_ARG;
+    orc_observables(s, 0, r2, NULL, NULL, NULL, NULL);
+    for (int k = 0; k < nbins; ++k) hist[k] = 0;
+    for (int64_t q = 0; q < s->npoly; ++q) {
+        int bin = (int)floor(sqrt(r2[q]) / rmax * (double)nbins);
+        if (bin > nbins - 1) bin = nbins - 1;
+        hist[bin]++;
+    }
+    free(r2);
     return ORC_OK;
 }
 

@@ -80,8 +80,15 @@ void orc_destroy(orc_sys *s);
  * check: 0 none; 1 invariants after every event; 2 also brute-force next-event search. */
 int orc_set_options(orc_sys *s, int64_t event_cap, int check);
 
-/* Swap moves (Sec. II.C) on (1) or off (0, the default) for the following ECs. */
+/* Swap moves (Sec. II.C) on (1) or off (0, the default) for the following ECs.  Refused
+ * (ORC_E_ARG) while springs are on. */
 int orc_set_swap(orc_sys *s, int on);
+
+/* Bonds as harmonic springs (k/2)(b - sigma)^2 of spring constant k > 0 (Eq. (2), in units
+ * of k_B T / sigma^2), still capped at b_max; k = 0 (the default) gives tethers.  Refused
+ * (ORC_E_ARG) for k < 0, a non-finite k, or while swap moves are on.  A single EC of
+ * orc_run_ec draws its energies with key (0, 0) and EC, domain and sweep 0. */
+int orc_set_spring(orc_sys *s, double k);
 
 /* Random stream index m (default 0): the Philox counters of the following sweeps end in 2 m
  * (EC draws) and 2 m + 1 (partition offsets), the streams of melt m of a batch. */
@@ -118,6 +125,14 @@ int orc_shape(const orc_sys *s, double *gyr, double *com);
 int orc_observables(const orc_sys *s, int nbins, double *r2, double *rg2, int64_t *hist,
                     double *mid, int64_t *n_poly);
 
+/* Pair counts behind g(r): every pair i < j with minimum-image distance r < r_max (r_max at most
+ * L/2), binned by floor(r / r_max * nbins) (clamped to nbins - 1).  Brute force over all pairs. */
+int orc_pair_histogram(const orc_sys *s, int nbins, double rmax, int64_t *hist);
+
+/* End-to-end distance distribution W(R): histogram over polymers of |R|, bins of width
+ * r_max / nbins from 0, values at or above r_max counted in the last bin. */
+int orc_end_to_end_histogram(const orc_sys *s, int nbins, double rmax, int64_t *hist);
+
 int64_t orc_n_beads(const orc_sys *s);
 int orc_n_cells(const orc_sys *s);
 double orc_cell_size(const orc_sys *s);
@@ -128,6 +143,14 @@ void orc_get_images(const orc_sys *s, int32_t *out);
 void orc_counters(const orc_sys *s, uint64_t *cnt, double *sum_delta);
 int orc_set_state(orc_sys *s, const double *pos, const int32_t *cells, const int32_t *img,
                   uint32_t sweep_ctr);
+
+/* Bond candidate of a partner at (d_par, d_perp^2) from the pivot: the tether formula for
+ * g < 0, else the spring formula with g = 2 dE / k (see the readings in the source). */
+double orc_bond_x(const orc_sys *s, double dpar, double dperp2, double g);
+
+/* Natural logarithm as the spring draws evaluate it (reduction to [sqrt(1/2), sqrt(2)) and
+ * the artanh series); within a few ulp of the libm value. */
+double orc_ln(double u);
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

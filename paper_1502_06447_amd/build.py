@@ -14,7 +14,11 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libecmc.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("ecmc_kernels.hip", "ecmc_sweep.hip", "ecmc_api.cpp")]
+# (source, extra macros, object tag): the phase and sweep kernels are built a second time for
+# harmonic springs
+SOURCES = [(os.path.join(CSRC, f), d, t) for f, d, t in (
+    ("ecmc_kernels.hip", (), ""), ("ecmc_phase.hip", (), ""), ("ecmc_phase.hip", ("ECMC_SPRING_TU=1",), ".spring"),
+    ("ecmc_sweep.hip", (), ""), ("ecmc_sweep.hip", ("ECMC_SPRING_TU=1",), ".spring"), ("ecmc_api.cpp", (), ""))]
 HEADERS = [os.path.join(CSRC, f) for f in ("ecmc_device.h", "ecmc_internal.h")]
 ARCH = os.environ.get("ECMC_OFFLOAD_ARCH", "gfx950")
 
@@ -36,11 +40,11 @@ def build(verbose: bool = False, out: str = LIB, defines: tuple = ()) -> str:
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument",
              "-I", os.path.join(ROOT, "include")] + [f"-D{d}" for d in defines]
-    objs = [out + "." + os.path.basename(src) + ".o" for src in SOURCES]
+    objs = [out + "." + os.path.basename(src) + tag + ".o" for src, _, tag in SOURCES]
 
     def compile_one(src_obj):
-        src, obj = src_obj
-        cmd = [hipcc()] + flags + ["-c", "-o", obj, "-x", "hip", src]
+        (src, extra, _), obj = src_obj
+        cmd = [hipcc()] + flags + [f"-D{d}" for d in extra] + ["-c", "-o", obj, "-x", "hip", src]
         if verbose:
             print(" ".join(cmd), flush=True)
         return subprocess.run(cmd).returncode

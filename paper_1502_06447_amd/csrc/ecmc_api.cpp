@@ -226,6 +226,9 @@ ecmc_status plan(const std::vector<MeltIn> &in, double sigma, double lmax, const
         return fail(c, ECMC_E_ARG, "precision must be ECMC_PREC_FP64 or ECMC_PREC_MIXED (got %d)", o.precision);
     if (o.schedule != ECMC_SCHED_SWEEP && o.schedule != ECMC_SCHED_PHASES)
         return fail(c, ECMC_E_ARG, "schedule must be ECMC_SCHED_SWEEP or ECMC_SCHED_PHASES (got %d)", o.schedule);
+    if (!(o.spring_k == 0.0 || (o.spring_k >= 1e-6 && o.spring_k <= 1e12)))
+        return fail(c, ECMC_E_ARG, "spring_k must be 0 (tethers) or in [1e-6, 1e12] (got %g)", o.spring_k);
+    if (o.spring_k > 0.0 && o.swap_moves) return fail(c, ECMC_E_ARG, "swap moves cannot be combined with springs");
     if (in.empty()) return fail(c, ECMC_E_ARG, "no melts");
     const bool batch = in.size() > 1;
     if (batch && o.tiling != ECMC_TILING_CHECKER)
@@ -700,7 +703,13 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     a.stream = 0;
     a.exact_search = c->opt.precision == ECMC_PREC_FP64 ? 1 : 0;
     a.swap = c->opt.swap_moves ? 1 : 0;
+    a.two_over_k = c->opt.spring_k > 0.0 ? 2.0 / c->opt.spring_k : 0.0;
+    a.sigma = c->sigma;
+    const bool spring = c->opt.spring_k > 0.0;
     const bool log = c->opt.event_log_capacity > 0;
+    auto phase_launch = [&](const PhaseArgs &pa, int bpl, int grid, hipStream_t s) {
+        return spring ? launch_phase_spring(pa, bpl, log, grid, s) : launch_phase(pa, bpl, log, grid, s);
+    };
     auto timed = [&](auto body) -> ecmc_status {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->opt.time_kernels) {
@@ -730,17 +739,17 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
                 PhaseArgs b = a;
                 b.stage_lo = 64 * c->p.bpl;
                 b.stage_hi = c->p.bpl3 ? 64 * c->p.bpl2 : 0x7fffffff;
-                HIP_OK(c, launch_phase(b, c->p.bpl2, log, grid, c->side));
+                HIP_OK(c, phase_launch(b, c->p.bpl2, grid, c->side));
                 if (c->p.bpl3) {
                     b.stage_lo = 64 * c->p.bpl2;
                     b.stage_hi = 0x7fffffff;
-                    HIP_OK(c, launch_phase(b, c->p.bpl3, log, grid, c->side));
+                    HIP_OK(c, phase_launch(b, c->p.bpl3, grid, c->side));
                 }
                 HIP_OK(c, hipEventRecord(c->join, c->side));
             }
             a.stage_lo = 0;
             a.stage_hi = c->p.bpl2 ? 64 * c->p.bpl : 0x7fffffff;
-            HIP_OK(c, launch_phase(a, c->p.bpl, log, grid, c->stream));
+            HIP_OK(c, phase_launch(a, c->p.bpl, grid, c->stream));
             if (c->p.bpl2) HIP_OK(c, hipStreamWaitEvent(c->stream, c->join, 0));
             return ECMC_OK;
         });
@@ -762,7 +771,8 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
             // advances the device-side sweep counter
             st = timed([&]() -> ecmc_status {
                 int waves = 0;
-                HIP_OK(c, launch_sweep(a, c->p.bpl, log, &waves, c->stream));
+                HIP_OK(c, spring ? launch_sweep_spring(a, c->p.bpl, log, &waves, c->stream)
+                                 : launch_sweep(a, c->p.bpl, log, &waves, c->stream));
                 return ECMC_OK;
             });
             if (st == ECMC_OK) c->sweep_ctr++;
@@ -845,6 +855,75 @@ ecmc_status ecmc_shape(ecmc_ctx *c, double *gyr, double *eig, double *com, int64
     if (gyr) HIP_OK(c, hipMemcpy(gyr, o.gyr, 48 * c->npoly, hipMemcpyDeviceToHost));
     if (eig) HIP_OK(c, hipMemcpy(eig, o.eig, 24 * c->npoly, hipMemcpyDeviceToHost));
     if (com) HIP_OK(c, hipMemcpy(com, o.com, 24 * c->npoly, hipMemcpyDeviceToHost));
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_snapshot(ecmc_ctx *c, double *snap) {
+    if (!c || !snap) return fail(c, ECMC_E_ARG, "null argument");
+    if (reinterpret_cast<uintptr_t>(snap) % 8) return fail(c, ECMC_E_ARG, "snapshot buffer not 8-byte aligned");
+    ObsArgs o = obs_args(c);
+    o.gyr = c->dev<double>(c->lay.shape);
+    o.eig = o.gyr + 6 * c->npoly;
+    o.com = o.eig + 3 * c->npoly;
+    o.snap = snap;
+    HIP_OK(c, launch_shape(o, c->stream));
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_msd(ecmc_ctx *c, const double *snaps, int64_t T, double *out) {
+    if (!c || !snaps || !out) return fail(c, ECMC_E_ARG, "null argument");
+    if (T < 1 || T > 0x7fffffff) return fail(c, ECMC_E_ARG, "T must be in [1, 2^31 - 1] (got %lld)", (long long)T);
+    HIP_OK(c, launch_msd(snaps, T, c->npoly, out, c->stream));
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_end_to_end_histogram(ecmc_ctx *c, int32_t nbins, double r_max, int64_t *hist) {
+    if (!c || !hist) return fail(c, ECMC_E_ARG, "null argument");
+    if (nbins <= 0 || nbins > MAX_BINS) return fail(c, ECMC_E_ARG, "nbins must be in [1, %d]", MAX_BINS);
+    if (!(r_max > 0.0) || !std::isfinite(r_max)) return fail(c, ECMC_E_ARG, "r_max must be finite and > 0");
+    // the bond histogram's buffer holds the counts (a context's calls do not overlap)
+    HIP_OK(c, hipMemsetAsync(c->ws + c->lay.hist, 0, 8 * nbins, c->stream));
+    ObsArgs o = obs_args(c);
+    o.nbins = 1;
+    o.r2 = c->dev<double>(c->lay.r2);
+    o.rg2 = c->dev<double>(c->lay.rg2);
+    o.mid = c->dev<double>(c->lay.mid);
+    o.hist = nullptr;
+    o.rhist = c->dev<unsigned long long>(c->lay.hist);
+    o.rbins = nbins;
+    o.rmax = r_max;
+    HIP_OK(c, launch_observables(o, c->stream));
+    ecmc_status st = check_device(c);
+    if (st) return st;
+    HIP_OK(c, hipMemcpy(hist, o.rhist, 8 * nbins, hipMemcpyDeviceToHost));
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_pair_histogram(ecmc_ctx *c, int32_t nbins, double r_max, int64_t *hist) {
+    if (!c || !hist) return fail(c, ECMC_E_ARG, "null argument");
+    if (nbins <= 0 || nbins > MAX_BINS) return fail(c, ECMC_E_ARG, "nbins must be in [1, %d]", MAX_BINS);
+    double hmin = INFINITY;
+    for (const MeltPlan &mp : c->p.melts) hmin = std::min(hmin, mp.h);
+    if (!(r_max > 0.0) || !(r_max <= hmin))
+        return fail(c, ECMC_E_ARG, "r_max must be in (0, %g], the smallest cell edge (got %g)", hmin, r_max);
+    HIP_OK(c, hipMemsetAsync(c->ws + c->lay.hist, 0, 8 * nbins, c->stream));
+    PairArgs a{};
+    a.px = c->dev<double>(c->lay.px);
+    a.py = c->dev<double>(c->lay.py);
+    a.pz = c->dev<double>(c->lay.pz);
+    a.ccount = c->dev<int32_t>(c->lay.ccount);
+    a.cids = c->dev<int32_t>(c->lay.cids);
+    a.cap = c->cap;
+    a.melts = c->dev<MeltDev>(c->lay.melts);
+    a.n_melts = (int)c->p.melts.size();
+    a.cells = c->p.cells;
+    a.nbins = nbins;
+    a.rmax = r_max;
+    a.hist = c->dev<unsigned long long>(c->lay.hist);
+    HIP_OK(c, launch_pairs(a, c->stream));
+    ecmc_status st = check_device(c);
+    if (st) return st;
+    HIP_OK(c, hipMemcpy(hist, a.hist, 8 * nbins, hipMemcpyDeviceToHost));
     return ECMC_OK;
 }
 

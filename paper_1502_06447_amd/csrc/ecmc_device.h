@@ -195,10 +195,19 @@ __device__ __forceinline__ double sqrt_nonneg(double x) {
 //   tether, for a partner of the pivot that is not hit:  x = d_par + sqrt(max(b^2 - d_perp^2, 0))
 // (for a partner that is hit the contact always comes first: x_hs <= d_par <= x_tether),
 // clamped at 0.  Returns whether the bead is a candidate at all.
-template <bool WRAP>
+//
+// Springs (Eq. (2), SPRING): a partner that is not hit takes the tether formula with b^2
+// replaced by the square of the bond length at which the drawn energy dE is used up, capped
+// at b^2.  The bond shortens at no cost until the pivot passes the partner's foot on its
+// line and lengthens after it; from the shortest length still ahead, b0 = d_perp if
+// d_par > 0 and the present length otherwise, (k/2)(b - sigma)^2 grows by dE at
+// b_end = sigma + sqrt((b0 - sigma)^2 + g) with g = 2 dE / k.  The general correctly
+// rounded square root is used there: its arguments are not bounded away from 0.
+template <bool WRAP, bool SPRING = false>
 __device__ __forceinline__ bool exact_candidate(double A, double B, double C, int32_t meta, const Pivot &pv, int sha,
                                                 int shb, int shc, double sgnd, double sig2, double b2, double L,
-                                                bool partner, double &x, bool &hs) {
+                                                bool partner, double &x, bool &hs, double gterm = 0.0,
+                                                double sigma = 0.0) {
     double da = A - pv.a;
     double db = B - pv.b;
     double dc = C - pv.c;
@@ -215,7 +224,15 @@ __device__ __forceinline__ bool exact_candidate(double A, double B, double C, in
     const double pc = dc * dc;
     const double dperp2 = pb + pc;
     hs = (dpar > 0.0) && (dperp2 < sig2);
-    double arg = (hs ? sig2 : b2) - dperp2;
+    double bb2 = b2;
+    if (SPRING && partner && !hs) {
+        const double b0 = __builtin_sqrt(dpar > 0.0 ? dperp2 : dpar * dpar + dperp2);
+        const double e = b0 - sigma;
+        const double be = sigma + __builtin_sqrt(e * e + gterm);
+        const double be2 = be * be;
+        bb2 = be2 > b2 ? b2 : be2;
+    }
+    double arg = (hs ? sig2 : bb2) - dperp2;
     if (!(arg > 0.0)) arg = 0.0;
     const double sq = sqrt_nonneg(arg);
     double v = hs ? dpar - sq : dpar + sq;
@@ -252,7 +269,7 @@ struct Screen {
     float t, l;
 };
 
-template <int BPL, bool WHOLE>
+template <int BPL, bool WHOLE, bool SPRING = false>
 __device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> &R, const Pivot &pv, int sha, int shb,
                                        int shc, double sgnd, const ScreenK &K) {
     const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
@@ -302,6 +319,12 @@ __device__ __forceinline__ void screen(Screen<BPL> &sc, const Lanes<BPL, WHOLE> 
                 hg = fmaxf(hg, et + K.err);
             }
         }
+        if constexpr (SPRING) {
+            // a spring partner not hit has d_par <= x <= x_tether (its bond length at the event
+            // is at most b_max and at least the shortest one ahead): the tether estimate stays
+            // an upper bound, and the float d_par (within K.err of the exact one) a lower one
+            if (__builtin_amdgcn_inverse_ballot_w64(mpart)) l = fminf(l, fmaxf(p - K.err, 0.0f));
+        }
         // candidates: possible contacts and the partners, never the pivot itself
         const bool cand = __builtin_amdgcn_inverse_ballot_w64(~mme & (m_maybe | mpart));
         sc.lo[k] = cand ? l : __builtin_huge_valf();
@@ -331,11 +354,12 @@ struct Best {
 // evaluate in FP64 the beads of this lane that are members (lo <= thr, not yet done).  The
 // first pass has thr = t, a float: lo <= t is then compared in single precision, which is
 // the same comparison.
-template <int BPL, bool FIRST>
+template <int BPL, bool FIRST, bool SPRING = false>
 __device__ __forceinline__ void search_pass(const Screen<BPL> &sc, double thr, unsigned &done, Best &b,
                                             const Stage &st, const Pivot &pv, const double *pA, const double *pB,
                                             const double *pC, int q0, int q1, int sha, int shb, int shc,
-                                            double sgnd, double sig2, double b2, double L, bool wr) {
+                                            double sgnd, double sig2, double b2, double L, bool wr,
+                                            double g0 = 0.0, double g1 = 0.0, double sigma = 0.0) {
     const int lane = lane_id();
 #pragma unroll
     for (int k = 0; k < BPL; ++k) {
@@ -347,13 +371,14 @@ __device__ __forceinline__ void search_pass(const Screen<BPL> &sc, double thr, u
                 const double A = pA[idx], B = pB[idx], C = pC[idx];
                 const int32_t m = st.meta[idx];
                 const bool partner = (idx == q0) || (idx == q1);
+                const double gt = idx == q0 ? g0 : g1;
                 double x;
                 bool hs;
                 const bool ok = (idx != pv.P) &&
-                                (wr ? exact_candidate<true>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner,
-                                                            x, hs)
-                                    : exact_candidate<false>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
-                                                             partner, x, hs));
+                                (wr ? exact_candidate<true, SPRING>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
+                                                                    partner, x, hs, gt, sigma)
+                                    : exact_candidate<false, SPRING>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L,
+                                                                     partner, x, hs, gt, sigma));
                 const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
                 if (ok && (x < b.x || (x == b.x && kk < b.key))) {
                     b.x = x;
@@ -380,9 +405,10 @@ __device__ __forceinline__ void take(Hit &h, const Best &b, int wl) {
     h.part = rdlane((int)b.part, wl);
 }
 
-template <int BPL>
+template <int BPL, bool SPRING = false>
 __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, const Pivot &pv, int ax, int sha,
-                                      int shb, int shc, double sgnd, double sig2, double b2, double L, bool wr) {
+                                      int shb, int shc, double sgnd, double sig2, double b2, double L, bool wr,
+                                      double g0 = 0.0, double g1 = 0.0, double sigma = 0.0) {
     const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
     const double *pA = st.axis(ax);
     const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
@@ -402,7 +428,8 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
     int nmem = 0;
 #pragma unroll
     for (int k = 0; k < BPL; ++k) nmem += __popcll(__ballot(sc.lo[k] <= sc.t));
-    search_pass<BPL, true>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
+    search_pass<BPL, true, SPRING>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr,
+                                   g0, g1, sigma);
     if (nmem == 1) {
         // one bead passed the screen: it set the threshold (its own hi is t), so when it is
         // a candidate its exact x <= t is the certified minimum
@@ -425,7 +452,8 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
         for (int k = 0; k < BPL; ++k)
             more = more || (!((done >> k) & 1u) && sc.lo[k] < __builtin_huge_valf() && (double)sc.lo[k] <= thr);
         if (!__ballot(more)) break;
-        search_pass<BPL, false>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2, L, wr);
+        search_pass<BPL, false, SPRING>(sc, thr, done, b, st, pv, pA, pB, pC, q0, q1, sha, shb, shc, sgnd, sig2, b2,
+                                        L, wr, g0, g1, sigma);
         xs = wave_min_nonneg_f64(b.x);
     }
     if (!(xs < INF)) return h;
@@ -445,8 +473,10 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
 // lane in chunks of 64 staged indices, then the wavefront minimum by (x, staged index, kind).
 // A loop over the staging area rather than over register slots, so that its register needs
 // do not grow with the staging capacity.
+template <bool SPRING = false>
 __device__ __forceinline__ Hit search_all(const Stage &st, const Pivot &pv, int S, int ax, int sha, int shb, int shc,
-                                          double sgnd, double sig2, double b2, double L, bool wr) {
+                                          double sgnd, double sig2, double b2, double L, bool wr, double g0 = 0.0,
+                                          double g1 = 0.0, double sigma = 0.0) {
     const int lane = lane_id();
     const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
     const double *pA = st.axis(ax);
@@ -461,11 +491,14 @@ __device__ __forceinline__ Hit search_all(const Stage &st, const Pivot &pv, int 
             const double A = pA[idx], B = pB[idx], C = pC[idx];
             const int32_t m = st.meta[idx];
             const bool partner = (idx == q0) || (idx == q1);
+            const double gt = idx == q0 ? g0 : g1;
             double x;
             bool hs;
             const bool ok =
-                wr ? exact_candidate<true>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x, hs)
-                   : exact_candidate<false>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x, hs);
+                wr ? exact_candidate<true, SPRING>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x, hs,
+                                                   gt, sigma)
+                   : exact_candidate<false, SPRING>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x, hs,
+                                                    gt, sigma);
             // a lane's indices increase, so on equal x the earlier bead keeps its place
             const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
             if (ok && (x < b.x || (x == b.x && kk < b.key))) {
@@ -583,6 +616,50 @@ __device__ __forceinline__ void log_event(const PhaseArgs &a, const Frame &f, in
     }
 }
 
+// ------------------------------------------------------------------ spring energies
+// Natural logarithm of u > 0 by fixed steps, so that every IEEE binary64 evaluation of them
+// gives the same bits: u = f 2^e with f in [sqrt(1/2), sqrt(2)); z = (f - 1)/(f + 1);
+// ln f = 2 artanh z = 2 z (1 + z^2/3 + z^4/5 + ... + z^22/23) by Horner's rule (|z| <= 0.1716:
+// the first term left out is below 2^-60 of the bracket); ln u = e ln 2 + ln f.
+__device__ __forceinline__ double ln_artanh(double u) {
+    int e;
+    double f = frexp(u, &e);  // f in [1/2, 1)
+    if (f < 0.70710678118654752440) {
+        f = f + f;
+        e = e - 1;
+    }
+    const double z = (f - 1.0) / (f + 1.0);
+    const double z2 = z * z;
+    double s = 1.0 / 23.0;
+#pragma unroll
+    for (int n = 10; n >= 0; --n) s = 1.0 / (double)(2 * n + 1) + z2 * s;
+    return (double)e * 0.69314718055994530942 + (z + z) * s;
+}
+
+// Key of the spring energy draws of random stream `stream`: words 0-1 of the Philox draw at
+// counter (2^32 - 1, 2^32 - 1, stream, 0x53505247), a counter the EC and offset draws never use.
+__device__ __forceinline__ void spring_key(const PhaseArgs &a, uint32_t stream, uint32_t &k0, uint32_t &k1) {
+    uint32_t c[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, stream, 0x53505247u};
+    philox4x32_10(c, a.key0, a.key1);
+    k0 = c[0];
+    k1 = c[1];
+}
+
+// The energies of step `step` of EC k of a domain, one per bond slot of the pivot, as
+// g = 2 dE / k with dE = -ln u, u uniform in (0, 1] from 53 bits of the Philox draw at
+// counter (step, k, domain, sweep) under the spring key: slot t takes words 2t (its upper 21
+// bits) and 2t + 1.  A fresh draw per step is exact for an exponential energy budget, which
+// has no memory.
+__device__ __forceinline__ void spring_terms(const PhaseArgs &a, const Frame &f, int k, int step, uint32_t sk0,
+                                             uint32_t sk1, double &g0, double &g1) {
+    uint32_t c[4] = {(uint32_t)step, (uint32_t)k, f.domain, a.sweep};
+    philox4x32_10(c, sk0, sk1);
+    const unsigned long long m0 = ((unsigned long long)c[1] << 21) | (unsigned long long)(c[0] >> 11);
+    const unsigned long long m1 = ((unsigned long long)c[3] << 21) | (unsigned long long)(c[2] >> 11);
+    g0 = -ln_artanh((double)(m0 + 1ull) * 0x1p-53) * a.two_over_k;
+    g1 = -ln_artanh((double)(m1 + 1ull) * 0x1p-53) * a.two_over_k;
+}
+
 // A reflection after an earlier one in the same EC.  Between two reflections every move is
 // reversible (a lift is undone by the reverse lift, a stop sends the pivot back), so after
 // the second one the EC runs back to the first and then repeats: whatever is left of x_max
@@ -661,10 +738,15 @@ __device__ __forceinline__ void store_pivot(const Pivot &pv, const Stage &st, do
 
 // One EC along axis ax (the lanes' frame is already rotated to it), direction sign sgn,
 // from staged pivot P0, x_max = ell.  Returns false if the iteration cap was hit.
-template <int BPL, bool LOG, bool EXACT, bool WHOLE>
+//
+// With springs (SPRING) the bond energies of every step are drawn from the key (sk0, sk1), and
+// an EC never retraces its path after a reflection (its draws differ), so whole periods are
+// not dropped.
+template <int BPL, bool LOG, bool EXACT, bool WHOLE, bool SPRING = false>
 __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const Stage &st,
                                        Lanes<lane_slots(BPL, EXACT), WHOLE> &R,
-                                       int P0, int ax, int sgn, bool wr, int k, const ScreenK &K, Tally &t) {
+                                       int P0, int ax, int sgn, bool wr, int k, const ScreenK &K, Tally &t,
+                                       uint32_t sk0 = 0u, uint32_t sk1 = 0u) {
     const int n = a.n;
     const double L = a.L, h = a.h;
     const int axb = ax == 2 ? 0 : ax + 1, axc = ax == 0 ? 2 : ax - 1;
@@ -719,10 +801,12 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
         if (!(xc > 0.0)) xc = 0.0;
         Hit hit;
         if constexpr (EXACT) {
-            hit = search_all(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr);
+            double g0 = 0.0, g1 = 0.0;
+            if constexpr (SPRING) spring_terms(a, f, k, step, sk0, sk1, g0, g1);
+            hit = search_all<SPRING>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, g0, g1, a.sigma);
         } else {
             Screen<BPL> sc;
-            screen<BPL, WHOLE>(sc, R, pv, sha, shb, shc, sgnd, K);
+            screen<BPL, WHOLE, SPRING>(sc, R, pv, sha, shb, shc, sgnd, K);
             // the exact interaction distance is at least sc.l: when the end of the EC or the
             // cell face comes strictly first (end: at or before), no exact search is needed
             const double lbound = (double)sc.l;
@@ -735,7 +819,9 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
                 hit.meta = 0;
                 hit.part = -1;
             } else {
-                hit = search<BPL>(sc, st, pv, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr);
+                double g0 = 0.0, g1 = 0.0;
+                if constexpr (SPRING) spring_terms(a, f, k, step, sk0, sk1, g0, g1);
+                hit = search<BPL, SPRING>(sc, st, pv, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, g0, g1, a.sigma);
             }
         }
         const double xint = hit.x;
@@ -842,7 +928,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
                 t.inc(kind == 0 ? C_HS_REFLECT : C_TETHER_REFLECT);
                 if (LOG)
                     log_event(a, f, k, step, st.id[pv.P], st.id[j], kind == 0 ? ECMC_EV_HS_REFLECT : ECMC_EV_TETHER_REFLECT);
-                if (reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+                if (!SPRING && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
                     store_pivot(pv, st, pA, R);
                     return true;
                 }
@@ -886,7 +972,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
             pv.fa = frame_u(pv.a, c, fsa, L, Oa);
             t.inc(C_WALL);
             if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_WALL);
-            if (reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+            if (!SPRING && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
                 store_pivot(pv, st, pA, R);
                 return true;
             }
@@ -978,7 +1064,7 @@ struct StageMem {
 // One domain from its cell lists to the written-back result: stage its S0 beads (the count
 // the caller took, S0 <= min(cap, 64 BPL)), run its K ECs, write back the motile beads and
 // the domain's cell lists, flush the counters.
-template <int BPL, bool LOG, bool EXACT, bool WHOLE>
+template <int BPL, bool LOG, bool EXACT, bool WHOLE, bool SPRING = false>
 __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F, bool wraps, int S0,
                                             const StageMem &m) {
     constexpr int NS = lane_slots(BPL, EXACT);
@@ -1103,6 +1189,8 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
     Tally t = {0u, 0.0};
     bool ok = true;
     int cur = 0;  // axis the lanes' frame is rotated to
+    uint32_t sk0 = 0u, sk1 = 0u;
+    if constexpr (SPRING) spring_key(a, a.stream, sk0, sk1);
     for (int k = 0; k < a.K && nmot > 0 && ok; ++k) {
         uint32_t ctr[4] = {(uint32_t)k, f.domain, a.sweep, 2u * a.stream};
         philox4x32_10(ctr, a.key0, a.key1);
@@ -1112,7 +1200,7 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
         const int sgn = __builtin_amdgcn_readfirstlane((dir & 1u) ? -1 : 1);
         if constexpr (!EXACT) rotate(R, cur, ax);
         cur = ax;
-        ok = run_ec<BPL, LOG, EXACT, WHOLE>(a, f, st, R, P0, ax, sgn, wraps, k, K, t);
+        ok = run_ec<BPL, LOG, EXACT, WHOLE, SPRING>(a, f, st, R, P0, ax, sgn, wraps, k, K, t, sk0, sk1);
     }
     __syncthreads();
 

@@ -106,6 +106,8 @@ struct PhaseArgs {
     double *slow;              // [nslow] staging slots for domains above the LDS capacity
     uint32_t *slow_lock;       // [nslow] 0 free, 1 taken
     int nslow, slow_cap;       // slots, beads per slot (0: no slots)
+    // harmonic springs (Eq. (2)): 2 / k, 0 for tethers; sigma for the spring formula
+    double two_over_k, sigma;
 };
 
 struct ObsArgs {
@@ -120,17 +122,39 @@ struct ObsArgs {
     double *r2, *rg2, *mid;    // [npoly], [npoly], [3 npoly]
     double *gyr, *eig, *com;   // shape: [6 npoly], [3 npoly], [3 npoly]
     unsigned long long *hist;  // [nbins]
+    double *snap;              // [6 npoly] middle bead and centre of mass, unwrapped (or null)
+    unsigned long long *rhist; // [rbins] end-to-end distance histogram (or null)
+    int rbins;
+    double rmax;
+};
+
+// Pair counts behind g(r): every pair of one melt closer than rmax (at most a cell edge).
+struct PairArgs {
+    const double *px, *py, *pz;
+    const int32_t *ccount, *cids;
+    int cap;
+    const MeltDev *melts;
+    int n_melts;
+    long long cells;           // cells of all melts
+    int nbins;
+    double rmax;
+    unsigned long long *hist;  // [nbins]
 };
 
 // launchers (ecmc_kernels.hip)
 hipError_t launch_count(const PhaseArgs &a, int grid, hipStream_t s);
 hipError_t launch_advance(const PhaseArgs &a, hipStream_t s);
+// the phase and sweep kernels are built twice, for tethers and for springs (_spring)
 hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s);
+hipError_t launch_phase_spring(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s);
 hipError_t launch_sweep(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s);
+hipError_t launch_sweep_spring(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s);
 bool sweep_bpl_supported(int bpl);
 constexpr int SLOW_SLOT_BYTES_PER_BEAD = 3 * 8 + 4 * 4;  // staging slot: positions + 4 int32 rows
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
 hipError_t launch_shape(const ObsArgs &a, hipStream_t s);
+hipError_t launch_pairs(const PairArgs &a, hipStream_t s);
+hipError_t launch_msd(const double *snaps, int64_t T, int64_t npoly, double *out, hipStream_t s);
 bool bpl_supported(int bpl);
 
 }  // namespace ecmc

@@ -1,5 +1,6 @@
-// gfx950 kernels of the colour-phase schedule (one launch set per colour phase), the
-// observables and the shape analysis.  The device code of the EC move is in ecmc_device.h.
+// gfx950 kernels around the colour-phase schedule (the per-phase bead counts, the sweep
+// counter), the observables and the shape analysis.  The device code of the EC move is in
+// ecmc_device.h, the phase kernel itself in ecmc_phase.hip.
 #include "ecmc_device.h"
 
 namespace ecmc {
@@ -24,36 +25,6 @@ __global__ __launch_bounds__(64) void k_count(const PhaseArgs a) {
 // dependency-ordered sweep advances it too) moves on.
 __global__ void k_advance(const PhaseArgs a) {
     if (threadIdx.x == 0) a.dstate[0] += 1u;
-}
-
-// ------------------------------------------------------------------ phase kernel
-// One colour phase: one wavefront per domain of the colour, for the domains whose bead count
-// (from k_count) falls in this launch's staging tier (stage_lo, stage_hi].
-template <int BPL, bool LOG, bool EXACT, bool WHOLE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(BPL)))) void k_phase(const PhaseArgs a) {
-    constexpr int SMAX = 64 * BPL;
-    __shared__ double s_pos[3][SMAX];
-    __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[SMAX];
-    // this sweep's number and partition, from the device-side sweep counter
-    PhaseArgs b = a;
-    b.sweep = a.dstate[0];
-    int off[3];
-    partition_offsets(b, b.D, b.sweep, 0u, off);
-    Frame f;
-    int F;
-    bool wraps;
-    frame_of<WHOLE>(b, b.colour, blockIdx.x, off, 0, f, F, wraps);
-    // The count comes from k_count, taken before any tier of this phase ran: a block of
-    // another tier may be rewriting this domain's cell lists, so a count read here could be
-    // a half-updated one.  A domain outside this launch's tier belongs to another launch.
-    const int S0 = __builtin_amdgcn_readfirstlane(a.dstage[blockIdx.x]);
-    if (S0 <= a.stage_lo || S0 > a.stage_hi) return;
-    if (S0 > SMAX) {
-        if (lane_id() == 0) atomicOr(a.err, ERR_STAGE);
-        return;
-    }
-    const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
-    domain_body<BPL, LOG, EXACT, WHOLE>(b, f, F, wraps, S0, m);
 }
 
 // ------------------------------------------------------------------ observables
@@ -157,6 +128,12 @@ __global__ __launch_bounds__(64 * OBS_WAVES) void k_observables(const ObsArgs a)
             const double g1 = m1 * m1;
             const double g2 = m2 * m2;
             a.rg2[q] = qq - ((g0 + g1) + g2);
+            if (a.rhist) {
+                // W(R): |R| binned from 0 in rbins bins of width rmax / rbins, the rest in the last
+                int bin = (int)__builtin_floor(__builtin_sqrt(a.r2[q]) / a.rmax * (double)a.rbins);
+                if (bin > a.rbins - 1) bin = a.rbins - 1;
+                atomicAdd(&a.rhist[bin], 1ull);
+            }
         }
     }
     __syncthreads();
@@ -217,6 +194,13 @@ __global__ __launch_bounds__(64 * OBS_WAVES) void k_shape(const ObsArgs a) {
                 d1 = mi(a.py[ib] - a.py[ia]);
                 d2 = mi(a.pz[ib] - a.pz[ia]);
             }
+            if (a.snap && t == N / 2) {
+                // the middle bead, unwrapped with its image counters (as the observables do)
+                const int ib = a.porder[s + t];
+                a.snap[6 * q + 0] = a.px[ib] + (double)a.img[3 * ib + 0] * L;
+                a.snap[6 * q + 1] = a.py[ib] + (double)a.img[3 * ib + 1] * L;
+                a.snap[6 * q + 2] = a.pz[ib] + (double)a.img[3 * ib + 2] * L;
+            }
             const double u0 = c0 + wave_scan_f64(d0);
             const double u1 = c1 + wave_scan_f64(d1);
             const double u2 = c2 + wave_scan_f64(d2);
@@ -255,7 +239,112 @@ __global__ __launch_bounds__(64 * OBS_WAVES) void k_shape(const ObsArgs a) {
             a.com[3 * q + 0] = a.px[i0] + (double)a.img[3 * i0 + 0] * L + m0;
             a.com[3 * q + 1] = a.py[i0] + (double)a.img[3 * i0 + 1] * L + m1;
             a.com[3 * q + 2] = a.pz[i0] + (double)a.img[3 * i0 + 2] * L + m2;
+            if (a.snap) {
+                a.snap[6 * q + 3] = a.com[3 * q + 0];
+                a.snap[6 * q + 4] = a.com[3 * q + 1];
+                a.snap[6 * q + 5] = a.com[3 * q + 2];
+            }
         }
+    }
+}
+
+// ------------------------------------------------------------------ pair distances
+// Pair counts behind g(r): one thread per cell (all melts' cells in one grid).  Each bead of the
+// cell meets the beads of the 27 cells around it (n >= 4, so these are distinct) with a larger
+// id: every pair closer than rmax <= the cell edge lies in neighbouring cells and is met once.
+// The displacement is (r_j - r_i) plus the box edge where the neighbour cell wraps, which is
+// the minimum image for such pairs; bins are counted in LDS, one global add per bin and block.
+constexpr int PAIR_THREADS = 256;
+
+__global__ __launch_bounds__(PAIR_THREADS) void k_pairs(const PairArgs a) {
+    __shared__ unsigned s_hist[OBS_MAX_BINS];
+    for (int i = (int)threadIdx.x; i < a.nbins; i += PAIR_THREADS) s_hist[i] = 0u;
+    __syncthreads();
+    const double r2max = a.rmax * a.rmax;
+    for (long long c = (long long)blockIdx.x * PAIR_THREADS + threadIdx.x; c < a.cells;
+         c += (long long)gridDim.x * PAIR_THREADS) {
+        int lo = 0, hi = a.n_melts - 1;  // the melt of cell c: the last whose first cell is <= c
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.melts[mid].cell0 <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        const MeltDev &M = a.melts[lo];
+        const int n = M.n;
+        const double L = M.L;
+        const int lc = (int)(c - M.cell0);
+        const int cx = lc % n, cy = (lc / n) % n, cz = lc / (n * n);
+        const int ni = a.ccount[c];
+        for (int ii = 0; ii < ni; ++ii) {
+            const int i = a.cids[c * a.cap + ii];
+            const double xi = a.px[i], yi = a.py[i], zi = a.pz[i];
+            for (int nb = 0; nb < 27; ++nb) {
+                const int rx = cx + nb % 3 - 1, ry = cy + (nb / 3) % 3 - 1, rz = cz + nb / 9 - 1;
+                const double sx = rx < 0 ? -L : (rx >= n ? L : 0.0);
+                const double sy = ry < 0 ? -L : (ry >= n ? L : 0.0);
+                const double sz = rz < 0 ? -L : (rz >= n ? L : 0.0);
+                const long long cn = M.cell0 + (rx + n) % n + n * ((ry + n) % n + n * ((rz + n) % n));
+                const int nj = a.ccount[cn];
+                for (int jj = 0; jj < nj; ++jj) {
+                    const int j = a.cids[cn * a.cap + jj];
+                    if (j <= i) continue;
+                    const double d0 = (a.px[j] - xi) + sx;
+                    const double d1 = (a.py[j] - yi) + sy;
+                    const double d2 = (a.pz[j] - zi) + sz;
+                    const double q0 = d0 * d0;
+                    const double q1 = d1 * d1;
+                    const double q2 = d2 * d2;
+                    const double dd = (q0 + q1) + q2;
+                    if (!(dd < r2max * 1.0000001)) continue;  // cheap pre-test; the exact one below
+                    const double r = __builtin_sqrt(dd);
+                    if (!(r < a.rmax)) continue;
+                    int bin = (int)__builtin_floor(r / a.rmax * (double)a.nbins);
+                    if (bin > a.nbins - 1) bin = a.nbins - 1;
+                    atomicAdd(&s_hist[bin], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < a.nbins; i += PAIR_THREADS)
+        if (s_hist[i]) atomicAdd(&a.hist[i], (unsigned long long)s_hist[i]);
+}
+
+// ------------------------------------------------------------------ mean-square displacements
+// g1 and g2 of Sec. IV.A from T snapshots [T][P][6] (middle bead, centre of mass): one block
+// per lag d, its threads over the (T - d) P pairs of snapshots d apart, summed in FP64 and
+// reduced in a fixed tree; out[d] = g1(d), out[T + d] = g2(d) (0 at d = 0).
+constexpr int MSD_THREADS = 256;
+
+__global__ __launch_bounds__(MSD_THREADS) void k_msd(const double *snaps, long long T, long long P, double *out) {
+    __shared__ double s1[MSD_THREADS], s2[MSD_THREADS];
+    const long long d = blockIdx.x;
+    double a1 = 0.0, a2 = 0.0;
+    const long long m = d > 0 ? (T - d) * P : 0;
+    for (long long k = threadIdx.x; k < m; k += MSD_THREADS) {
+        const double *u = snaps + 6 * k;            // snapshot t, polymer q (k = t P + q)
+        const double *v = snaps + 6 * (k + d * P);  // snapshot t + d, same polymer
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const double x = v[e] - u[e];
+            const double y = (v[e] - v[3 + e]) - (u[e] - u[3 + e]);
+            a1 += x * x;
+            a2 += y * y;
+        }
+    }
+    s1[threadIdx.x] = a1;
+    s2[threadIdx.x] = a2;
+    __syncthreads();
+    for (int w = MSD_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+            s2[threadIdx.x] += s2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[d] = m > 0 ? s1[0] / (double)m : 0.0;
+        out[T + d] = m > 0 ? s2[0] / (double)m : 0.0;
     }
 }
 
@@ -265,36 +354,6 @@ bool bpl_supported(int bpl) {
     switch (bpl) {
         case 1: case 2: case 3: case 4: case 6: case 8: case 12: case 16: return true;
         default: return false;
-    }
-}
-
-// EXACT: the plain FP64 search (every staged bead evaluated at every event); otherwise the
-// single-precision screen with FP64 evaluation of the beads that can come first.
-template <int BPL, bool WHOLE>
-static hipError_t launch_bpl(const PhaseArgs &a, bool log, int grid, hipStream_t s) {
-    if (log && a.exact_search) hipLaunchKernelGGL((k_phase<BPL, true, true, WHOLE>), dim3(grid), dim3(64), 0, s, a);
-    else if (log) hipLaunchKernelGGL((k_phase<BPL, true, false, WHOLE>), dim3(grid), dim3(64), 0, s, a);
-    else if (a.exact_search) hipLaunchKernelGGL((k_phase<BPL, false, true, WHOLE>), dim3(grid), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((k_phase<BPL, false, false, WHOLE>), dim3(grid), dim3(64), 0, s, a);
-    return hipGetLastError();
-}
-
-template <int BPL>
-static hipError_t launch_bpl(const PhaseArgs &a, bool log, int grid, hipStream_t s) {
-    return a.whole ? launch_bpl<BPL, true>(a, log, grid, s) : launch_bpl<BPL, false>(a, log, grid, s);
-}
-
-hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s) {
-    switch (bpl) {
-        case 1: return launch_bpl<1>(a, log, grid, s);
-        case 2: return launch_bpl<2>(a, log, grid, s);
-        case 3: return launch_bpl<3>(a, log, grid, s);
-        case 4: return launch_bpl<4>(a, log, grid, s);
-        case 6: return launch_bpl<6>(a, log, grid, s);
-        case 8: return launch_bpl<8>(a, log, grid, s);
-        case 12: return launch_bpl<12>(a, log, grid, s);
-        case 16: return launch_bpl<16>(a, log, grid, s);
-        default: return hipErrorInvalidValue;
     }
 }
 
@@ -314,6 +373,22 @@ hipError_t launch_shape(const ObsArgs &a, hipStream_t s) {
     int64_t grid = (a.npoly + OBS_WAVES - 1) / OBS_WAVES;
     if (grid > 16384) grid = 16384;
     hipLaunchKernelGGL(k_shape, dim3((unsigned)grid), dim3(64 * OBS_WAVES), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(const PairArgs &a, hipStream_t s) {
+    if (a.cells <= 0) return hipSuccess;
+    if (a.nbins < 1 || a.nbins > OBS_MAX_BINS) return hipErrorInvalidValue;
+    long long grid = (a.cells + PAIR_THREADS - 1) / PAIR_THREADS;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_pairs, dim3((unsigned)grid), dim3(PAIR_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_msd(const double *snaps, int64_t T, int64_t npoly, double *out, hipStream_t s) {
+    if (T <= 0) return hipSuccess;
+    if (T > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_msd, dim3((unsigned)T), dim3(MSD_THREADS), 0, s, snaps, (long long)T, (long long)npoly, out);
     return hipGetLastError();
 }
 

@@ -21,9 +21,23 @@
 // device workspace instead and run with the plain FP64 search (identical results).
 #include "ecmc_device.h"
 
+// Built twice: for tethers, and with ECMC_SPRING_TU=1 for harmonic springs (Eq. (2)).
+#ifndef ECMC_SPRING_TU
+#define ECMC_SPRING_TU 0
+#endif
+#if ECMC_SPRING_TU
+#define K_SWEEP k_sweep_spring
+#define SWEEP_LAUNCHER launch_sweep_spring
+#else
+#define K_SWEEP k_sweep
+#define SWEEP_LAUNCHER launch_sweep
+#endif
+
 namespace ecmc {
 
 namespace {
+
+constexpr bool SPRING = ECMC_SPRING_TU != 0;
 
 // polls of one wait before it gives up; a poll sleeps about 8 * 64 cycles, so the limit is
 // about a second, far beyond any real wait (a domain takes well under a millisecond)
@@ -94,7 +108,7 @@ __device__ __forceinline__ int melt_of(const PhaseArgs &a, int r) {
 }
 
 template <int BPL, bool LOG, bool EXACT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(BPL)))) void k_sweep(const PhaseArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(BPL)))) void K_SWEEP(const PhaseArgs a) {
     constexpr int SMAX = 64 * BPL;
     __shared__ double s_pos[3][SMAX];
     __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[SMAX];
@@ -138,7 +152,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
     int slot = -1;
     if (S <= SMAX) {
         const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
-        domain_body<BPL, LOG, EXACT, false>(b, f, F, wraps, S, m);
+        domain_body<BPL, LOG, EXACT, false, SPRING>(b, f, F, wraps, S, m);
     } else if (S <= a.slow_cap) {
         slot = take_slot(a, t);
         if (slot >= 0) {
@@ -147,7 +161,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
             double *base = a.slow + (size_t)slot * (size_t)cap * (SLOW_SLOT_BYTES_PER_BEAD / 8);
             int32_t *ib = reinterpret_cast<int32_t *>(base + 3 * (size_t)cap);
             const StageMem m = {base, ib, ib + cap, ib + 2 * cap, ib + 3 * cap, cap};
-            domain_body<16, LOG, true, false>(b, f, F, wraps, S, m);
+            domain_body<16, LOG, true, false, SPRING>(b, f, F, wraps, S, m);
         }
     } else if (lane == 0) {
         atomicOr(a.err, ERR_STAGE);
@@ -177,7 +191,7 @@ template <int BPL, bool LOG, bool EXACT>
 hipError_t launch_sweep_v(const PhaseArgs &a, int *grid, hipStream_t s) {
     const int g = 8 * a.tickets;  // one workgroup per domain of the sweep
     *grid = g;
-    hipLaunchKernelGGL((k_sweep<BPL, LOG, EXACT>), dim3(g), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((K_SWEEP<BPL, LOG, EXACT>), dim3(g), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -189,14 +203,16 @@ hipError_t launch_sweep_b(const PhaseArgs &a, bool log, int *grid, hipStream_t s
 
 }  // namespace
 
+#if !ECMC_SPRING_TU
 bool sweep_bpl_supported(int bpl) {
     switch (bpl) {
         case 1: case 2: case 3: case 4: case 6: case 8: return true;
         default: return false;
     }
 }
+#endif
 
-hipError_t launch_sweep(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s) {
+hipError_t SWEEP_LAUNCHER(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s) {
     switch (bpl) {
         case 1: return launch_sweep_b<1>(a, log, grid, s);
         case 2: return launch_sweep_b<2>(a, log, grid, s);

@@ -42,6 +42,7 @@ class ecmc_options(ctypes.Structure):
         ("swap_moves", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
         ("stage_tier", ctypes.c_int32),
+        ("spring_k", ctypes.c_double),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
@@ -106,7 +107,8 @@ EXPORTS = (
     "ecmc_set_state", "ecmc_kernel_time", "ecmc_sweep_counter", "ecmc_n_cells", "ecmc_cell_size",
     "ecmc_stage_capacity", "ecmc_destroy", "ecmc_status_str", "ecmc_last_error",
     "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
-    "ecmc_tune_workspace_size", "ecmc_tune_batch",
+    "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
+    "ecmc_pair_histogram",
 )
 
 
@@ -134,6 +136,10 @@ def lib():
         "ecmc_synchronize": (st, [vp]),
         "ecmc_observables": (st, [vp, i32, vp, vp, vp, vp, P(i64)]),
         "ecmc_shape": (st, [vp, vp, vp, vp, P(i64)]),
+        "ecmc_snapshot": (st, [vp, vp]),
+        "ecmc_msd": (st, [vp, vp, i64, vp]),
+        "ecmc_end_to_end_histogram": (st, [vp, i32, dbl, vp]),
+        "ecmc_pair_histogram": (st, [vp, i32, dbl, vp]),
         "ecmc_get_positions": (st, [vp, vp]),
         "ecmc_get_cells": (st, [vp, vp]),
         "ecmc_get_images": (st, [vp, vp]),
@@ -285,6 +291,7 @@ class Options:
     swap_moves: bool = False
     schedule: int = SCHED_SWEEP
     stage_tier: int = 0
+    spring_k: float = 0.0  # > 0: harmonic springs of this constant, capped at l_max
 
 
 def _native_options(o: "Options") -> ecmc_options:
@@ -301,6 +308,7 @@ def _native_options(o: "Options") -> ecmc_options:
     opt.swap_moves = 1 if o.swap_moves else 0
     opt.schedule = o.schedule
     opt.stage_tier = o.stage_tier
+    opt.spring_k = float(o.spring_k)
     return opt
 
 
@@ -461,6 +469,45 @@ class Melt:
         assert n_poly.value == M
         return {"r2": r2, "rg2": rg2, "hist": hist, "mid": mid, "n_poly": M}
 
+    def snapshot(self, out=None):
+        """Middle bead and centre of mass of every polymer, image-unwrapped, as a device tensor
+        [M, 6] (queued on the melt's stream, no synchronisation): one time point for g1 and g2."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_poly, 6), dtype=torch.float64, device=self.workspace.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != 6 * self.n_poly:
+            raise ValueError("snapshot buffer must be a contiguous float64 tensor of n_poly x 6")
+        _check(lib().ecmc_snapshot(self.ctx, out.data_ptr()), "ecmc_snapshot", self.ctx)
+        return out
+
+    def msd(self, snaps) -> tuple:
+        """g1 and g2 (Sec. IV.A) for lags 0..T-1 from a device tensor of snapshots [T, M, 6],
+        averaged over polymers and time origins, computed on the GPU; numpy arrays."""
+        import torch
+        if snaps.dtype != torch.float64 or not snaps.is_contiguous() or snaps.dim() != 3 \
+                or snaps.shape[1] != self.n_poly or snaps.shape[2] != 6:
+            raise ValueError("snapshots must be a contiguous float64 tensor [T, n_poly, 6]")
+        T = snaps.shape[0]
+        out = torch.empty(2 * T, dtype=torch.float64, device=snaps.device)
+        _check(lib().ecmc_msd(self.ctx, snaps.data_ptr(), T, out.data_ptr()), "ecmc_msd", self.ctx)
+        self.synchronize()
+        o = out.cpu().numpy()
+        return o[:T].copy(), o[T:].copy()
+
+    def end_to_end_histogram(self, nbins: int, r_max: float) -> np.ndarray:
+        """W(R): polymers per bin of |R| (width r_max / nbins; |R| >= r_max in the last bin)."""
+        h = np.zeros(int(nbins), dtype=np.int64)
+        _check(lib().ecmc_end_to_end_histogram(self.ctx, int(nbins), float(r_max), h.ctypes.data),
+               "ecmc_end_to_end_histogram", self.ctx)
+        return h
+
+    def pair_histogram(self, nbins: int, r_max: float) -> np.ndarray:
+        """Pair counts behind g(r): pairs i < j of a melt with r < r_max (<= the cell edge)."""
+        h = np.zeros(int(nbins), dtype=np.int64)
+        _check(lib().ecmc_pair_histogram(self.ctx, int(nbins), float(r_max), h.ctypes.data), "ecmc_pair_histogram",
+               self.ctx)
+        return h
+
     def shape(self) -> dict:
         """Per polymer: gyration tensor [M, 6] (xx, yy, zz, xy, xz, yz), its eigenvalues [M, 3]
         (descending) and the image-unwrapped centre of mass [M, 3], computed on the GPU."""
@@ -493,3 +540,12 @@ def shape_descriptors(eig) -> dict:
     return {"kappa2": float(np.mean(4.0 * (1.0 - 3.0 * pair / tr ** 2))),
             "r_123": float(np.mean(i1 + i2 - i3) / mt), "r_132": float(np.mean(i1 - i2 + i3) / mt),
             "r_231": float(np.mean(-i1 + i2 + i3) / mt), "solc": float(np.mean(4 * b * b + 3 * c * c) / mt ** 2)}
+
+
+def pair_correlation(hist, r_max: float, n_beads: int, volume: float) -> np.ndarray:
+    """g(r) of one melt from its pair counts: each bin divided by the ideal-gas count
+    N (N - 1) / 2 * (4 pi / 3) (r_hi^3 - r_lo^3) / V."""
+    h = np.asarray(hist, dtype=np.float64)
+    edges = np.linspace(0.0, r_max, len(h) + 1)
+    shell = 4.0 * np.pi / 3.0 * (edges[1:] ** 3 - edges[:-1] ** 3)
+    return h / (0.5 * n_beads * (n_beads - 1) * shell / volume)

@@ -20,7 +20,7 @@ MUTANTS = {
     "perp_drop": ("*dperp2 = pb + pc;", "*dperp2 = pb;"),
     "wrap_sign": ("if (w[a] > 0) d[a] = d[a] + s->L;", "if (w[a] > 0) d[a] = d[a] - s->L;"),
     "dpar_sign": ("*dpar = sgn > 0 ? d[axis] : -d[axis];", "*dpar = d[axis];"),
-    "no_tether": ("consider(&best, tether_candidate(s, dpar, dperp2), q, 1, dpar);\n    }\n    return best;",
+    "no_tether": ("consider(&best, orc_bond_x(s, dpar, dperp2, g ? g[t] : -1.0), q, 1, dpar);\n    }\n    return best;",
                   "}\n    return best;"),
     "delta_sign": ("s->sum_delta += b.dpar - b.x;", "s->sum_delta += b.dpar + b.x;"),
     "no_reflect": ("sgn = -sgn;\n            }\n            continue;", "p = b.j;\n            }\n            continue;"),
@@ -33,11 +33,29 @@ MUTANTS = {
     "period_half": ("const double r = fmod(*xmax, W + W);", "const double r = fmod(*xmax, W);"),
     "swap_skip_j": ("        if (u >= 0 && dist2(s, rp, u == p ? rj : &s->r[3 * u]) > s->b2) return 0;\n", ""),
     "swap_image_sign": ("        s->img[3 * p + a] += sh;", "        s->img[3 * p + a] -= sh;"),
+    "spring_b0_present": ("sqrt(dpar > 0.0 ? dperp2 : dpar * dpar + dperp2)", "sqrt(dpar * dpar + dperp2)"),
+    "spring_energy_sign": ("sqrt(e * e + g)", "sqrt(fabs(e * e - g))"),
+    "spring_no_cap": ("    if (be2 > s->b2) be2 = s->b2;\n", ""),
+    "spring_half_energy": ("g[t] = -orc_ln(u) * s->two_over_k;", "g[t] = -orc_ln(u) * s->two_over_k * 0.5;"),
+    "spring_stale_draw": ("const uint32_t ctr[4] = {step, dm->ec, dm->domain, dm->sweep};",
+                          "const uint32_t ctr[4] = {0u, dm->ec, dm->domain, dm->sweep};"),
+    "ln_series_short": ("for (int n = 10; n >= 0; --n)", "for (int n = 8; n >= 0; --n)"),
+    "ln_reduction": ("if (f < 0.70710678118654752440) {", "if (f < 0.5) {"),
+    "pair_drop_z": ("const double r = sqrt((q0 + q1) + q2);", "const double r = sqrt(q0 + q1);"),
+    "pair_twice": ("for (int64_t j = i + 1; j < s->nb; ++j) {",
+                   "for (int64_t j = 0; j < s->nb; ++j) {\n            if (j == i) continue;"),
+    "pair_no_image": ("for (int a = 0; a < 3; ++a) d[a] = mi(s, s->r[3 * j + a] - s->r[3 * i + a]);\n            const double q0",
+                      "for (int a = 0; a < 3; ++a) d[a] = s->r[3 * j + a] - s->r[3 * i + a];\n            const double q0"),
+    "e2e_squared": ("floor(sqrt(r2[q]) / rmax * (double)nbins)", "floor(r2[q] / rmax * (double)nbins)"),
     # equivalent mutants: no observable difference is expected
     # (W = 0 means every event between the two reflections had zero length, so the zero-length
     # cycle search ends the same EC a few steps later with the same positions)
     "period_no_cycle (equivalent)": ("if (!(W > 0.0)) {", "if (W < 0.0) {"),
     "tie_kind (equivalent)": ("(j == b->j && kind < b->kind)", "(j == b->j && kind > b->kind)"),
+    # (the two energies of a step are independent uniforms: which bond takes which changes
+    # trajectories, which the GPU parity tests see, but no distribution)
+    "spring_slot_swap (equivalent)": ("consider(&best, orc_bond_x(s, dpar, dperp2, g ? g[t] : -1.0), q, 1, dpar);",
+                                      "consider(&best, orc_bond_x(s, dpar, dperp2, g ? g[1 - t] : -1.0), q, 1, dpar);"),
     "face_add (rounding only)": ("*ra = sgn > 0 ? s->bnd[c + 1] : s->bnd[c];", "*ra = sgn > 0 ? *ra + xc : *ra - xc;"),
 }
 

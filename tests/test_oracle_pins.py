@@ -723,3 +723,288 @@ def test_shape_of_a_melt_is_consistent_with_rg2(melt_c1):
         u = np.concatenate([(p[ids[0]] + img[ids[0]] * m.L)[None, :], p[ids[0]] + img[ids[0]] * m.L + np.cumsum(d, 0)])
         assert np.allclose(sh["com"][q], u.mean(axis=0), atol=1e-10)
         assert np.allclose(sh["gyr"][q], oracle.gyration(u), atol=1e-10)
+
+
+# ------------------------------------------------------------------ springs (Eq. (2))
+def test_ln_matches_libm_within_two_ulp():
+    """The logarithm of the spring draws against libm: within 2 ulp over (0, 1], exact at 1
+    and at powers of two up to the rounding of e ln 2, and around the reduction boundaries
+    (f near sqrt(1/2), where the series converges slowest)."""
+    rng = np.random.default_rng(17)
+    u = np.concatenate([rng.uniform(size=20000), 2.0 ** rng.uniform(-53, 0, size=20000),
+                        np.sqrt(0.5) * 2.0 ** -np.arange(0, 40) * (1 + 1e-15),
+                        np.sqrt(0.5) * 2.0 ** -np.arange(0, 40) * (1 - 1e-15),
+                        [1.0, 0.5, 2.0 ** -53, 1 - 2.0 ** -53, 0.75, 0.9999999]])
+    u = u[(u > 0) & (u <= 1)]
+    mine = np.array([oracle.ln(x) for x in u])
+    ref = np.log(u)
+    ulp = np.spacing(np.abs(ref))
+    err = np.abs(mine - ref)
+    ok = (err <= 2 * ulp) | (ref == 0.0) & (mine == 0.0)
+    assert ok.all(), (u[~ok][:5], mine[~ok][:5], ref[~ok][:5])
+    assert oracle.ln(1.0) == 0.0
+    assert oracle.ln(0.5) == -math.log(2.0)
+
+
+def _bond_x_numeric(dpar, dperp2, dE, k, sigma, b_max):
+    """The spring event from the energy itself, by root finding: moving the pivot by s along
+    v, the bond length is b(s) = |d - s v|; the energy used is the sum of the increases of
+    U(b) = (k/2)(b - sigma)^2 along the way.  U has one minimum on the path (where b is
+    shortest), so the energy used is U(s) - min over [0, s] of U, and the event is where it
+    first reaches dE, or where b reaches b_max, whichever comes first."""
+    from scipy import optimize
+    b = lambda s: math.sqrt((dpar - s) ** 2 + dperp2)
+    U = lambda s: 0.5 * k * (b(s) - sigma) ** 2
+    s_min = max(dpar, 0.0)  # b is shortest at the foot of the partner, or now if it is behind
+    used = lambda s: U(s) - U(s_min)
+    hi = s_min + 1.0
+    while used(hi) < dE and b(hi) < b_max:
+        hi = hi * 2 + 1
+    s_e = optimize.brentq(lambda s: used(s) - dE, s_min, hi, xtol=1e-14) if used(hi) >= dE else math.inf
+    s_c = optimize.brentq(lambda s: b(s) - b_max, s_min, hi, xtol=1e-14) if b(hi) >= b_max else math.inf
+    return min(s_e, s_c)
+
+
+def test_spring_bond_candidate_matches_energy_root():
+    """The closed form of the spring candidate against the root of its energy balance, for
+    partners ahead and behind, near and far from the line of motion, small and large drawn
+    energies (the largest reach the cap b_max, where the tether formula takes over)."""
+    k, sigma, b_max = 30.0, 1.0, 2.0
+    o = oracle.Oracle(20.0, sigma, b_max, [[5, 5, 5], [6.2, 5, 5]], [[0, 1]])
+    o.set_spring(k)
+    rng = np.random.default_rng(3)
+    n = 0
+    while n < 400:
+        d = rng.normal(size=3)
+        d *= rng.uniform(sigma, b_max) / np.linalg.norm(d)
+        dpar, dperp2 = d[0], d[1] ** 2 + d[2] ** 2
+        if dpar > 0 and dperp2 < sigma ** 2:
+            continue  # a partner that is hit: the contact comes first, the spring never counts
+        dE = -math.log(rng.uniform()) * rng.choice([0.01, 1.0, 5.0])
+        x = o.bond_x(dpar, dperp2, 2.0 * dE / k)
+        ref = _bond_x_numeric(dpar, dperp2, dE, k, sigma, b_max)
+        assert abs(x - ref) < 1e-9 * max(1.0, ref), (d, dE, x, ref)
+        n += 1
+    # g < 0 is the tether, and an unbounded energy meets the cap exactly there
+    assert o.bond_x(0.3, 0.5, -1.0) == o.bond_x(0.3, 0.5, 1e300)
+    assert abs(o.bond_x(0.3, 0.5, -1.0) - (0.3 + math.sqrt(4.0 - 0.5))) < 1e-15
+    # no energy: the event is where the bond starts to lengthen (the partner's foot or now)
+    assert o.bond_x(0.7, 1.44, 0.0) == 0.7 and abs(o.bond_x(-0.4, 1.44, 0.0)) < 1e-15
+
+
+def _spring_dimer_cdf(k, sigma, b_max):
+    from scipy import integrate
+    w = lambda r: r * r * math.exp(-0.5 * k * (r - sigma) ** 2)
+    Z = integrate.quad(w, sigma, b_max, epsabs=0, epsrel=1e-12)[0]
+    return lambda x: np.array([integrate.quad(w, sigma, min(max(v, sigma), b_max), epsabs=0,
+                                              epsrel=1e-10)[0] / Z for v in np.atleast_1d(x)])
+
+
+def _spring_dimer_samples(tiling, D, L, n_samples, seed, k, b_max, ell=5.3, per=3, burn_in=300):
+    m = inputs.dimer(L, seed=seed, b_max=b_max)
+    o = oracle.Oracle.from_melt(m)
+    o.set_spring(k)
+    for j in range(burn_in):
+        o.sweep(per, ell, seed * 1000003 + n_samples + j, tiling=tiling, D=D)
+    out = np.empty(n_samples)
+    for j in range(n_samples):
+        o.sweep(per, ell, seed * 1000003 + j, tiling=tiling, D=D)
+        p = o.positions()
+        d = p[1] - p[0]
+        d -= L * np.round(d / L)
+        out[j] = np.linalg.norm(d)
+    return out, o
+
+
+@pytest.mark.parametrize("tiling,D,L,k,b_max", [(0, 1, 10.0, 30.0, 2.0), (1, 2, 10.0, 30.0, 2.0),
+                                                (0, 1, 10.0, 8.0, 1.6)])
+def test_spring_dimer_bond_length_distribution(tiling, D, L, k, b_max):
+    """An isolated dimer bonded by a spring samples p(r) ~ r^2 exp(-k (r - sigma)^2 / 2) on
+    [sigma, b_max] (Eq. (2), hard core below sigma, cap at b_max).  At k sigma^2 = 30 and a
+    cap of 2 sigma (which removes a weight below 2e-7) the mean is 1.16763 sigma; at k = 8 with
+    a cap of 1.6 sigma the cap is active.  Whole box and checkerboard (walls, reflections at
+    immotile partners)."""
+    from scipy import stats
+    r, o = _spring_dimer_samples(tiling, D, L, 12000, seed=21 + D + tiling + int(k), k=k, b_max=b_max)
+    assert r.min() >= 1.0 - 1e-10 and r.max() <= b_max + 1e-10
+    cdf = _spring_dimer_cdf(k, 1.0, b_max)
+    ks = stats.kstest(r[::5], cdf)
+    assert ks.pvalue > 1e-3, ks
+    from scipy import integrate
+    w = lambda x: x * x * math.exp(-0.5 * k * (x - 1.0) ** 2)
+    mean_exact = integrate.quad(lambda x: x * w(x), 1, b_max)[0] / integrate.quad(w, 1, b_max)[0]
+    if k == 30.0:
+        assert abs(mean_exact - 1.16763) < 1e-5
+    blocks = r.reshape(120, 100).mean(axis=1)
+    assert abs(r.mean() - mean_exact) < 5 * blocks.std() / math.sqrt(len(blocks))
+    c, _ = o.counters()
+    assert c[oracle.C_PERIOD] == 0  # the periodic reduction is off for springs
+    if tiling:
+        assert c[oracle.C_TETHER_REFLECT] > 0 and c[oracle.C_WALL] > 0
+
+
+def _direct_spring_chain_samples(rng, N, n, k, sigma=1.0, b_max=2.0):
+    """Exact Boltzmann sampling of an isolated spring chain: bond lengths from
+    r^2 exp(-k (r - sigma)^2 / 2) on [sigma, b_max] by inverting a tabulated CDF, uniform
+    directions, rejection if any non-bonded pair is closer than sigma."""
+    grid = np.linspace(sigma, b_max, 200001)
+    w = grid ** 2 * np.exp(-0.5 * k * (grid - sigma) ** 2)
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (w[1:] + w[:-1]) * np.diff(grid))])
+    cdf /= cdf[-1]
+    out = []
+    while len(out) < n:
+        m = 4 * (n - len(out)) + 16
+        r = np.interp(rng.uniform(size=(m, N - 1)), cdf, grid)
+        v = rng.normal(size=(m, N - 1, 3))
+        v /= np.linalg.norm(v, axis=2)[:, :, None]
+        x = np.concatenate([np.zeros((m, 1, 3)), np.cumsum(r[:, :, None] * v, axis=1)], axis=1)
+        d = np.linalg.norm(x[:, :, None, :] - x[:, None, :, :], axis=3)
+        ok = np.ones(m, dtype=bool)
+        for i in range(N):
+            for j in range(i + 2, N):
+                ok &= d[:, i, j] >= sigma
+        out.extend(list(x[ok]))
+    return np.array(out[:n])
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_short_spring_chain_matches_direct_sampler(N):
+    """<R^2>, <R_g^2> and the distribution of |r_1 - r_3| of an isolated spring chain (k sigma^2
+    = 10, so that bonds stretch visibly) sampled by ECs against direct Boltzmann sampling.
+    Middle beads have two springs, each with its own energy draw."""
+    from scipy import stats
+    k = 10.0
+    rng = np.random.default_rng(200 + N)
+    ref = _direct_spring_chain_samples(rng, N, 20000, k)
+    L = 20.0
+    m = inputs.isolated_chain(N, L, seed=N, b_max=2.0)
+    o = oracle.Oracle.from_melt(m)
+    o.set_spring(k)
+    samples = []
+    for j in range(5000):
+        o.sweep(2 * N, 4.1, 9000 + j)
+        p = o.positions()
+        x = p - p[0]
+        x -= L * np.round(x / L)
+        samples.append(x)
+    ec = np.array(samples)
+    R2e, Rg2e, r13e = _shape(ec)
+    R2r, Rg2r, r13r = _shape(ref)
+    for a, bb in ((R2e, R2r), (Rg2e, Rg2r)):
+        err = math.sqrt(4 * a.var() / len(a) + bb.var() / len(bb))
+        assert abs(a.mean() - bb.mean()) < 4 * err, (a.mean(), bb.mean(), err)
+    assert stats.ks_2samp(r13e[::2], r13r).pvalue > 1e-3
+
+
+def test_spring_option_errors():
+    """Negative or non-finite spring constants are refused, and so is the combination with
+    swap moves, in either order."""
+    o = oracle.Oracle(20.0, 1.0, 2.0, [[5, 5, 5], [6.2, 5, 5]], [[0, 1]])
+    for bad in (-1.0, math.inf, math.nan):
+        with pytest.raises(ValueError):
+            o.set_spring(bad)
+    o.set_spring(30.0)
+    with pytest.raises(ValueError):
+        o.set_swap(True)
+    o.set_spring(0.0)
+    o.set_swap(True)
+    with pytest.raises(ValueError):
+        o.set_spring(30.0)
+
+
+# ------------------------------------------------------------------ analysis: g(r), W(R), g1, g2
+def _sc_lattice(n_l, a):
+    g = np.arange(n_l) * a + 0.5 * a
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
+def test_pair_histogram_of_a_simple_cubic_lattice():
+    """Pair counts of a simple cubic lattice (6^3 sites, spacing a = 1.23, periodic): every site
+    has 6 neighbours at a, 12 at a sqrt 2, 8 at a sqrt 3, 6 at 2a and 24 at a sqrt 5, so the
+    pair counts are 216 x (6, 12, 8, 6, 24) / 2 in the bins of those distances and 0 elsewhere
+    below r_max = 2.9 (a sqrt 6 = 3.01 lies beyond)."""
+    a, n_l = 1.23, 6
+    pos = _sc_lattice(n_l, a)
+    o = oracle.Oracle(n_l * a, 1.0, 1.4, pos, np.zeros((0, 2), dtype=np.int32))
+    h = o.pair_histogram(29, 2.9)
+    want = np.zeros(29, dtype=np.int64)
+    for dist, z in ((a, 6), (a * math.sqrt(2), 12), (a * math.sqrt(3), 8), (2 * a, 6), (a * math.sqrt(5), 24)):
+        want[int(dist / 0.1)] += 216 * z // 2
+    assert np.array_equal(h, want), (h, want)
+    with pytest.raises(oracle.OracleError):
+        o.pair_histogram(10, n_l * a)  # beyond L/2 the minimum image is not the only pair
+
+
+def test_pair_histogram_of_a_hard_sphere_melt(melt_c1):
+    """In any valid melt no pair is closer than sigma, and the counts up to r_max add up to the
+    number of pairs within r_max found by a direct numpy computation."""
+    m = melt_c1
+    o = oracle.Oracle.from_melt(m)
+    h = o.pair_histogram(30, 3.0)
+    assert h[:10].sum() == 0  # bins below sigma = 1 (width 0.1)
+    p = m.positions
+    d = p[None, :, :] - p[:, None, :]
+    d -= m.L * np.round(d / m.L)
+    r = np.sqrt((d ** 2).sum(axis=2))
+    iu = np.triu_indices(len(p), 1)
+    assert h.sum() == np.count_nonzero(r[iu] < 3.0)
+
+
+def test_end_to_end_histogram_of_rods():
+    """Straight chains: |R| = (N - 1) b exactly, so all polymers of one length fall in one bin;
+    two lengths give two bins; a bound below the longest puts those in the last bin."""
+    b = 1.1
+    pos, bonds = [], []
+    k = 0
+    for c, N in enumerate([4] * 5 + [7] * 3):
+        for t in range(N):
+            pos.append([1.0 + t * b, 2.0 + 1.5 * c, 3.0])
+            if t:
+                bonds.append([k - 1, k])
+            k += 1
+    o = oracle.Oracle(20.0, 1.0, 1.4, np.array(pos), np.array(bonds))
+    h = o.end_to_end_histogram(10, 10.0)
+    want = np.zeros(10, dtype=np.int64)
+    want[int(3 * b)] = 5
+    want[int(6 * b)] = 3
+    assert np.array_equal(h, want)
+    h = o.end_to_end_histogram(4, 4.0)
+    assert h[3] == 5 + 3 and h.sum() == 8
+
+
+def _msd_loops(s):
+    T, P = s.shape[0], s.shape[1]
+    g1, g2 = [0.0] * T, [0.0] * T
+    for d in range(1, T):
+        a1 = a2 = 0.0
+        for t in range(T - d):
+            for q in range(P):
+                for k in range(3):
+                    a1 += (s[t + d, q, k] - s[t, q, k]) ** 2
+                    a2 += ((s[t + d, q, k] - s[t + d, q, 3 + k]) - (s[t, q, k] - s[t, q, 3 + k])) ** 2
+        g1[d] = a1 / ((T - d) * P)
+        g2[d] = a2 / ((T - d) * P)
+    return np.array(g1), np.array(g2)
+
+
+def test_msd_series_closed_forms_and_brute_force():
+    """g1 and g2 of Sec. IV.A: against plain loops on a small random series; a melt drifting
+    rigidly with velocity v has g1(d) = |v|^2 d^2 and g2 = 0; a middle bead that alternates
+    between two places relative to a fixed centre of mass has g2 = |w|^2 at odd lags, 0 at
+    even ones."""
+    rng = np.random.default_rng(4)
+    s = rng.normal(size=(7, 5, 6))
+    g1, g2 = oracle.msd_series(s)
+    r1, r2 = _msd_loops(s)
+    assert np.allclose(g1, r1, rtol=1e-13, atol=0) and np.allclose(g2, r2, rtol=1e-13, atol=0)
+    T, v = 9, np.array([0.3, -0.2, 0.6])
+    base = rng.normal(size=(4, 6))
+    drift = np.stack([base + np.concatenate([v, v]) * t for t in range(T)])
+    g1, g2 = oracle.msd_series(drift)
+    d = np.arange(T)
+    assert np.allclose(g1, (v @ v) * d ** 2, rtol=1e-12, atol=1e-12) and np.allclose(g2, 0, atol=1e-24)
+    w = np.array([0.5, 0.0, -1.0])
+    alt = np.stack([np.concatenate([base[:, :3] + (t % 2) * w, base[:, 3:]], axis=1) for t in range(T)])
+    g1, g2 = oracle.msd_series(alt)
+    assert np.allclose(g2[1::2], w @ w, rtol=1e-12) and np.allclose(g2[2::2], 0, atol=1e-24)
