@@ -117,6 +117,10 @@ typedef struct {
                                    (a multiple of 64 up to 512; 0 = sized for the typical
                                    domain); larger domains are staged as for the automatic
                                    capacity.  The knob ecmc_tune_batch sets                */
+    int32_t overlapping_start;  /* nonzero: hard-sphere overlaps in the start are accepted (the
+                                   phantom start of the push-off, ecmc_pushoff); tethers only,
+                                   no swap moves.  Plain sweeps on an overlapping state are the
+                                   caller's responsibility                                 */
     double spring_k;            /* 0 (default): bonds are tethers of length at most l_max.
                                    > 0: harmonic springs (k/2)(b - sigma)^2 of this constant
                                    (Eq. (2), in k_B T / sigma^2, within [1e-6, 1e12]), still
@@ -265,6 +269,27 @@ ecmc_status ecmc_observables(ecmc_ctx *ctx, int32_t nbins, double *r2, double *r
  * N (tr G 1 - G), eigenvalues N (tr G - l_i)), and the centre of mass in image-unwrapped
  * coordinates com [3].  Host outputs of n_poly entries (any may be NULL).  Synchronises. */
 ecmc_status ecmc_shape(ecmc_ctx *ctx, double *gyr, double *eig, double *com, int64_t *n_poly);
+
+/* Push-off of an overlapping start (Sec. II.B; the context made with overlapping_start): one
+ * sweep at working diameter d in (0, sigma] in which a pair closer than d (squared distance
+ * below d^2 (1 - 1e-9)) is no hard-sphere event for either bead, and every EC starts at a
+ * motile bead that overlaps some bead (the k-th draw of a domain picks among them in ascending
+ * id; a domain with none runs no EC).  The plain FP64 search, one dependency-ordered launch
+ * (tethered chains, checkerboard, all colours).  Asynchronous like ecmc_sweep. */
+ecmc_status ecmc_pushoff_sweep(ecmc_ctx *ctx, int64_t n_chains, double ell, uint64_t seed, double diameter);
+
+/* Pairs (summed over the melts) closer than d: squared distance below d^2 (1 - 1e-9), d in
+ * (0, sigma].  Synchronises. */
+ecmc_status ecmc_count_overlaps(ecmc_ctx *ctx, double diameter, int64_t *n);
+
+/* The slow push-off (Sec. II.B): working diameters d_s = d_start + (sigma - d_start) s / stages,
+ * s = 1..stages (the last exactly sigma); at each, push-off sweeps of n_beads ECs of length ell
+ * (seeds seed, seed + 1, ... over the whole run) until no pair is closer than d_s or max_sweeps
+ * sweeps have run.  Stops early at a stage that keeps overlaps.  Reports the sweeps run and the
+ * overlaps left at the last diameter reached (0 when the state is a valid start at sigma).
+ * Synchronises. */
+ecmc_status ecmc_pushoff(ecmc_ctx *ctx, double d_start, int32_t stages, double ell, uint64_t seed,
+                         int64_t max_sweeps, int64_t *sweeps_done, int64_t *overlaps_left);
 
 /* Snapshot for the mean-square displacements g1 and g2 (Sec. IV.A): per polymer the middle bead
  * floor(N/2) and the centre of mass, both image-unwrapped (as ecmc_observables and ecmc_shape

@@ -52,6 +52,12 @@ def lib():
         i64, i32, u32, u64, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
         L.orc_create.argtypes = [P(vp), dbl, dbl, dbl, ctypes.c_int, i64, vp, i64, vp]
         L.orc_create.restype = ctypes.c_int
+        L.orc_create_overlapping.argtypes = [P(vp), dbl, dbl, dbl, ctypes.c_int, i64, vp, i64, vp]
+        L.orc_create_overlapping.restype = ctypes.c_int
+        L.orc_set_pushoff.argtypes = [vp, dbl]
+        L.orc_set_pushoff.restype = ctypes.c_int
+        L.orc_count_overlaps.argtypes = [vp, dbl]
+        L.orc_count_overlaps.restype = i64
         L.orc_destroy.argtypes = [vp]
         L.orc_set_options.argtypes = [vp, i64, ctypes.c_int]
         L.orc_set_swap.argtypes = [vp, ctypes.c_int]
@@ -123,13 +129,14 @@ class Oracle:
     """One melt held by the CPU oracle."""
 
     def __init__(self, L: float, sigma: float, b_max: float, positions, bonds, n_cells: int = 0,
-                 event_cap: int = 0, check: int = 0):
+                 event_cap: int = 0, check: int = 0, overlapping: bool = False):
         self._pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
         self._bonds = np.ascontiguousarray(bonds, dtype=np.int32).reshape(-1, 2)
         h = ctypes.c_void_p()
-        st = lib().orc_create(ctypes.byref(h), float(L), float(sigma), float(b_max), int(n_cells),
-                              self._pos.shape[0], self._pos.ctypes.data, self._bonds.shape[0],
-                              self._bonds.ctypes.data if self._bonds.size else None)
+        create = lib().orc_create_overlapping if overlapping else lib().orc_create
+        st = create(ctypes.byref(h), float(L), float(sigma), float(b_max), int(n_cells),
+                    self._pos.shape[0], self._pos.ctypes.data, self._bonds.shape[0],
+                    self._bonds.ctypes.data if self._bonds.size else None)
         if st != OK:
             raise OracleError(st, "orc_create")
         self._h = h
@@ -178,6 +185,15 @@ class Oracle:
         """Swap moves at hard-sphere contacts (Sec. II.C) for the following ECs."""
         if lib().orc_set_swap(self._h, 1 if on else 0) != OK:
             raise ValueError("swap moves cannot be combined with springs")
+
+    def set_pushoff(self, d: float):
+        """Push-off (Sec. II.B) at working diameter d for the following sweeps (d = 0: off)."""
+        if lib().orc_set_pushoff(self._h, float(d)) != OK:
+            raise ValueError(f"push-off diameter {d!r} refused")
+
+    def count_overlaps(self, d: float) -> int:
+        """Pairs closer than d (squared distance below d^2 (1 - 1e-9))."""
+        return int(lib().orc_count_overlaps(self._h, float(d)))
 
     def set_spring(self, k: float):
         """Bonds as harmonic springs of constant k (Eq. (2), k_B T / sigma^2), capped at b_max;

@@ -54,7 +54,14 @@
  *    draw at counter (2^32-1, 2^32-1, m, 0x53505247) under the seed's key; partner slot t
  *    takes words 2t (low 21 bits dropped) and 2t+1.  A spring EC does not retrace its path
  *    after a reflection, so the periodic reduction is off; swap moves are not combined with
- *    springs.
+ *    springs;
+ *  - push-off (Sec. II.B, optional): hard spheres of a working diameter d <= sigma; a pair is
+ *    overlapping when its squared distance is below d^2 (1 - 1e-9) (the margin keeps pairs left
+ *    in contact by an earlier event, up to rounding, as obstacles); an overlapping pair is no
+ *    hard-sphere event for either bead, and every EC starts from a motile bead that overlaps
+ *    some bead (the k-th draw picks among them in ascending id; a domain with none runs no
+ *    EC); the periodic reduction is off (a pair that stops overlapping no longer lets the
+ *    pivot through on the way back).
  */
 #include "ecmc_oracle.h"
 
@@ -81,6 +88,8 @@ struct orc_sys {
     int check;
     int swap;          /* swap moves at hard-sphere contacts (Sec. II.C) */
     int spring;        /* bonds are harmonic springs capped at b_max (Eq. (2)) */
+    int push;          /* push-off: overlapping pairs ignored, ECs start at overlapping beads */
+    double ov2;        /* squared overlap distance of the push-off: d^2 (1 - 1e-9) */
     double spring_k, two_over_k;
     uint32_t stream;   /* random stream index m (counter word 3 = 2 m, 2 m + 1) */
     orc_event *log;
@@ -204,8 +213,8 @@ static int rebuild_cells(orc_sys *s) {
 }
 
 /* ---------------------------------------------------------------- create */
-int orc_create(orc_sys **out, double L, double sigma, double bmax, int n_cells, int64_t n_beads,
-               const double *pos, int64_t n_bonds, const int32_t *bonds) {
+static int create_impl(orc_sys **out, double L, double sigma, double bmax, int n_cells, int64_t n_beads,
+                       const double *pos, int64_t n_bonds, const int32_t *bonds, int check_overlaps) {
     *out = NULL;
     if (!(isfinite(L) && L > 0 && isfinite(sigma) && sigma > 0 && isfinite(bmax) && bmax >= sigma))
         return ORC_E_ARG;
@@ -329,7 +338,7 @@ int orc_create(orc_sys **out, double L, double sigma, double bmax, int n_cells, 
                             const double d = mi(s, s->r[3 * j + a] - s->r[3 * i + a]);
                             d2 += d * d;
                         }
-                        if (d2 < lim_ov) {
+                        if (check_overlaps && d2 < lim_ov) {
                             free_sys(s);
                             return ORC_E_OVERLAP;
                         }
@@ -353,6 +362,29 @@ int orc_create(orc_sys **out, double L, double sigma, double bmax, int n_cells, 
     return ORC_OK;
 }
 
+int orc_create(orc_sys **out, double L, double sigma, double bmax, int n_cells, int64_t n_beads,
+               const double *pos, int64_t n_bonds, const int32_t *bonds) {
+    return create_impl(out, L, sigma, bmax, n_cells, n_beads, pos, n_bonds, bonds, 1);
+}
+
+int orc_create_overlapping(orc_sys **out, double L, double sigma, double bmax, int n_cells, int64_t n_beads,
+                           const double *pos, int64_t n_bonds, const int32_t *bonds) {
+    return create_impl(out, L, sigma, bmax, n_cells, n_beads, pos, n_bonds, bonds, 0);
+}
+
+int orc_set_pushoff(orc_sys *s, double d) {
+    if (d == 0.0) {
+        s->push = 0;
+        s->sig2 = s->sigma * s->sigma;
+        return ORC_OK;
+    }
+    if (!(d > 0.0) || !(d <= s->sigma) || s->spring || s->swap) return ORC_E_ARG;
+    s->push = 1;
+    s->sig2 = d * d;
+    s->ov2 = s->sig2 * (1.0 - 1e-9);
+    return ORC_OK;
+}
+
 int orc_set_options(orc_sys *s, int64_t event_cap, int check) {
     s->event_cap = event_cap > 0 ? event_cap : ORC_DEFAULT_EVENT_CAP;
     s->check = check;
@@ -360,13 +392,13 @@ int orc_set_options(orc_sys *s, int64_t event_cap, int check) {
 }
 
 int orc_set_swap(orc_sys *s, int on) {
-    if (on && s->spring) return ORC_E_ARG;
+    if (on && (s->spring || s->push)) return ORC_E_ARG;
     s->swap = on ? 1 : 0;
     return ORC_OK;
 }
 
 int orc_set_spring(orc_sys *s, double k) {
-    if (!(k >= 0.0) || !isfinite(k) || (k > 0.0 && s->swap)) return ORC_E_ARG;
+    if (!(k >= 0.0) || !isfinite(k) || (k > 0.0 && (s->swap || s->push))) return ORC_E_ARG;
     s->spring = k > 0.0;
     s->spring_k = k;
     s->two_over_k = k > 0.0 ? 2.0 / k : 0.0;
@@ -450,6 +482,7 @@ static void geom(const orc_sys *s, int32_t p, int32_t j, const int w[3], int axi
  * the line of motion.  Returns 0 if j is never hit. */
 static int hs_candidate(const orc_sys *s, double dpar, double dperp2, double *x) {
     if (!(dpar > 0.0 && dperp2 < s->sig2)) return 0;
+    if (s->push && dpar * dpar + dperp2 < s->ov2) return 0; /* push-off: an overlapping pair */
     double v = dpar - sqrt(s->sig2 - dperp2);
     if (!(v > 0.0)) v = 0.0;
     *x = v;
@@ -622,7 +655,7 @@ static int check_pivot(const orc_sys *s, int32_t p) {
             const double d = mi(s, s->r[3 * j + a] - s->r[3 * p + a]);
             d2 += d * d;
         }
-        if (d2 < s->sig2 * (1.0 - tol)) return ORC_E_CHECK;
+        if (!s->push && d2 < s->sig2 * (1.0 - tol)) return ORC_E_CHECK;
         if ((s->nbr[2 * p] == j || s->nbr[2 * p + 1] == j) && d2 > s->b2 * (1.0 + tol)) return ORC_E_CHECK;
     }
     for (int a = 0; a < 3; ++a) {
@@ -786,7 +819,7 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
             } else {
                 log_event(s, dm, step, p, b.j, b.kind == 0 ? ORC_EV_HS_REFLECT : ORC_EV_TETHER_REFLECT);
                 s->cnt[b.kind == 0 ? ORC_C_HS_REFLECT : ORC_C_TETHER_REFLECT]++;
-                if (!s->spring && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+                if (!s->spring && !s->push && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
                 reflected = 1;
                 xref = xmax;
                 sgn = -sgn;
@@ -830,7 +863,7 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
         } else {
             log_event(s, dm, step, p, -1, ORC_EV_WALL);
             s->cnt[ORC_C_WALL]++;
-            if (!s->spring && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+            if (!s->spring && !s->push && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
             reflected = 1;
             xref = xmax;
             sgn = -sgn;
@@ -852,6 +885,54 @@ static int cmp_i32(const void *a, const void *b) {
     return (x > y) - (x < y);
 }
 
+/* ---------------------------------------------------------------- push-off */
+/* Whether bead i overlaps any other bead at the push-off diameter (minimum image, every bead of
+ * the 27 cells around it, squared distance summed over x, y, z in that order). */
+static int overlaps_any(const orc_sys *s, int32_t i) {
+    const int n = s->n;
+    const int32_t *ci = s->cell + 3 * i;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int c = cidx(s, (ci[0] + dx + n) % n, (ci[1] + dy + n) % n, (ci[2] + dz + n) % n);
+                for (int t = 0; t < s->ccount[c]; ++t) {
+                    const int32_t j = s->clist[c][t];
+                    if (j == i) continue;
+                    double q[3];
+                    for (int a = 0; a < 3; ++a) {
+                        const double d = mi(s, s->r[3 * j + a] - s->r[3 * i + a]);
+                        q[a] = d * d;
+                    }
+                    if ((q[0] + q[1]) + q[2] < s->ov2) return 1;
+                }
+            }
+    return 0;
+}
+
+int64_t orc_count_overlaps(const orc_sys *s, double d) {
+    const double lim = d * d * (1.0 - 1e-9);
+    int64_t k = 0;
+    for (int64_t i = 0; i < s->nb; ++i)
+        for (int64_t j = i + 1; j < s->nb; ++j) {
+            double q = 0;
+            for (int a = 0; a < 3; ++a) {
+                const double v = mi(s, s->r[3 * j + a] - s->r[3 * i + a]);
+                q += v * v;
+            }
+            if (q < lim) ++k;
+        }
+    return k;
+}
+
+/* The EC starts of the push-off: the beads of list[0..m) that overlap some bead, in the same
+ * order, written to out; returns how many.  Without push-off every bead of the list. */
+static int64_t start_beads(const orc_sys *s, const int32_t *list, int64_t m, int32_t *out) {
+    int64_t k = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (!s->push || overlaps_any(s, list[i])) out[k++] = list[i];
+    return k;
+}
+
 /* ---------------------------------------------------------------- sweep */
 static int in_list(const uint32_t *list, int64_t n, uint32_t v) {
     int64_t lo = 0, hi = n - 1;
@@ -870,7 +951,12 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     const uint32_t sweep = s->sweep_ctr;
     int32_t *mot = (int32_t *)malloc(sizeof(int32_t) * (size_t)s->nb);
-    if (!mot) return ORC_E_ARG;
+    int32_t *starts = (int32_t *)malloc(sizeof(int32_t) * (size_t)s->nb);
+    if (!mot || !starts) {
+        free(mot);
+        free(starts);
+        return ORC_E_ARG;
+    }
     int st = ORC_OK;
     orc_dom dm;
     memset(&dm, 0, sizeof dm);
@@ -888,10 +974,12 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
         dm.D = 1;
         for (int64_t i = 0; i < s->nb; ++i) mot[i] = (int32_t)i;
         for (int64_t k = 0; k < n_ec && st == ORC_OK; ++k) {
+            const int64_t ms = start_beads(s, mot, s->nb, starts);
+            if (ms == 0) break;
             const uint32_t ctr[4] = {(uint32_t)k, 0u, sweep, 2u * s->stream};
             uint32_t u[4];
             orc_philox4x32_10(ctr, key, u);
-            const int32_t p = mot[below(u[0], (uint32_t)s->nb)];
+            const int32_t p = starts[below(u[0], (uint32_t)ms)];
             const uint32_t dir = below(u[1], 6);
             dm.ec = (uint32_t)k;
             st = run_ec(s, &dm, p, (int)(dir >> 1), (dir & 1) ? -1 : 1, ell);
@@ -940,10 +1028,12 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
                         if (m == 0) continue;
                         qsort(mot, (size_t)m, sizeof(int32_t), cmp_i32);
                         for (int64_t k = 0; k < K && st == ORC_OK; ++k) {
+                            const int64_t ms = start_beads(s, mot, m, starts);
+                            if (ms == 0) break;
                             const uint32_t ctr[4] = {(uint32_t)k, dm.domain, sweep, 2u * s->stream};
                             uint32_t u[4];
                             orc_philox4x32_10(ctr, key, u);
-                            const int32_t p = mot[below(u[0], (uint32_t)m)];
+                            const int32_t p = starts[below(u[0], (uint32_t)ms)];
                             const uint32_t dir = below(u[1], 6);
                             dm.ec = (uint32_t)k;
                             st = run_ec(s, &dm, p, (int)(dir >> 1), (dir & 1) ? -1 : 1, ell);
@@ -954,6 +1044,7 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
         st = ORC_E_ARG;
     }
     free(mot);
+    free(starts);
     s->sweep_ctr++;
     return st;
 }

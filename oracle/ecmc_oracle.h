@@ -76,6 +76,20 @@ int orc_create(orc_sys **out, double L, double sigma, double bmax, int n_cells, 
                const double *pos, int64_t n_bonds, const int32_t *bonds);
 void orc_destroy(orc_sys *s);
 
+/* As orc_create, but hard-sphere overlaps in the start are accepted (tethers are still
+ * checked): the phantom start of the push-off. */
+int orc_create_overlapping(orc_sys **out, double L, double sigma, double bmax, int n_cells, int64_t n_beads,
+                           const double *pos, int64_t n_bonds, const int32_t *bonds);
+
+/* Push-off (Sec. II.B) at working diameter d in (0, sigma] for the following sweeps: a pair
+ * closer than d (squared distance below d^2 (1 - 1e-9)) is no hard-sphere event, and every EC
+ * starts at a motile bead that overlaps some bead; d = 0 returns to plain ECs at sigma.
+ * Refused with springs or swap moves on. */
+int orc_set_pushoff(orc_sys *s, double d);
+
+/* Pairs closer than d (squared distance below d^2 (1 - 1e-9)), by brute force. */
+int64_t orc_count_overlaps(const orc_sys *s, double d);
+
 /* event_cap: loop iterations allowed per EC (0 = default 10^7).
  * check: 0 none; 1 invariants after every event; 2 also brute-force next-event search. */
 int orc_set_options(orc_sys *s, int64_t event_cap, int check);

@@ -15,10 +15,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libecmc.so")
 # (source, extra macros, object tag): the phase and sweep kernels are built a second time for
-# harmonic springs
+# harmonic springs, the sweep kernel a third time for the push-off
 SOURCES = [(os.path.join(CSRC, f), d, t) for f, d, t in (
     ("ecmc_kernels.hip", (), ""), ("ecmc_phase.hip", (), ""), ("ecmc_phase.hip", ("ECMC_SPRING_TU=1",), ".spring"),
-    ("ecmc_sweep.hip", (), ""), ("ecmc_sweep.hip", ("ECMC_SPRING_TU=1",), ".spring"), ("ecmc_api.cpp", (), ""))]
+    ("ecmc_sweep.hip", (), ""), ("ecmc_sweep.hip", ("ECMC_SPRING_TU=1",), ".spring"),
+    ("ecmc_sweep.hip", ("ECMC_PUSH_TU=1",), ".push"), ("ecmc_api.cpp", (), ""))]
 HEADERS = [os.path.join(CSRC, f) for f in ("ecmc_device.h", "ecmc_internal.h")]
 ARCH = os.environ.get("ECMC_OFFLOAD_ARCH", "gfx950")
 

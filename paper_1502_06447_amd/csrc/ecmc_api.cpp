@@ -23,6 +23,9 @@ namespace {
 constexpr int64_t DEFAULT_EVENT_CAP = 10000000;
 constexpr int DEFAULT_CAP = 16;
 constexpr int MAX_BINS = 1024;
+// time limit of one dependency wait of the sweep kernel, far beyond any domain's run time (a
+// guard against a broken invariant, so that every wait ends)
+constexpr int WAIT_SECONDS = 30;
 constexpr int SLOW_SLOTS = 512;  // workspace staging slots of the dependency-ordered sweep
 
 // ---------------------------------------------------------------- plan
@@ -112,6 +115,7 @@ struct ecmc_ctx {
     Layout lay{};
     char *ws = nullptr;
     uint32_t sweep_ctr = 0;           // host count of sweeps (the device holds the authoritative one)
+    unsigned long long wait_ticks = 0;  // limit of one dependency wait, in steady-counter ticks
     std::string err;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;
     template <class T>
@@ -229,6 +233,8 @@ ecmc_status plan(const std::vector<MeltIn> &in, double sigma, double lmax, const
     if (!(o.spring_k == 0.0 || (o.spring_k >= 1e-6 && o.spring_k <= 1e12)))
         return fail(c, ECMC_E_ARG, "spring_k must be 0 (tethers) or in [1e-6, 1e12] (got %g)", o.spring_k);
     if (o.spring_k > 0.0 && o.swap_moves) return fail(c, ECMC_E_ARG, "swap moves cannot be combined with springs");
+    if (o.overlapping_start && (o.spring_k > 0.0 || o.swap_moves))
+        return fail(c, ECMC_E_ARG, "an overlapping start (push-off) takes tethers without swap moves");
     if (in.empty()) return fail(c, ECMC_E_ARG, "no melts");
     const bool batch = in.size() > 1;
     if (batch && o.tiling != ECMC_TILING_CHECKER)
@@ -410,7 +416,7 @@ ecmc_status build_cells(ecmc_ctx *c, int m, HostState &hs, bool validate) {
                         const double ex = min_image(hs.px[j] - hs.px[i], L);
                         const double ey = min_image(hs.py[j] - hs.py[i], L);
                         const double ez = min_image(hs.pz[j] - hs.pz[i], L);
-                        if (ex * ex + ey * ey + ez * ez < lim_ov)
+                        if (!c->opt.overlapping_start && ex * ex + ey * ey + ez * ez < lim_ov)
                             return fail(c, ECMC_E_OVERLAP, "melt %d: beads %lld and %lld overlap", m, (long long)(i - b0),
                                         (long long)(j - b0));
                     }
@@ -487,7 +493,8 @@ ecmc_status check_device(ecmc_ctx *c) {
     if (e & ERR_CELL) return fail(c, ECMC_E_CELL_OVERFLOW, "a cell exceeded its capacity %d", c->cap);
     if (e & ERR_STUCK) return fail(c, ECMC_E_STUCK, "an EC exceeded %lld iterations", (long long)c->opt.event_cap);
     if (e & ERR_RECOUNT) return fail(c, ECMC_E_DEVICE, "a domain's cell lists changed between its count and its staging");
-    if (e & ERR_WAIT) return fail(c, ECMC_E_DEVICE, "a wait of the dependency-ordered sweep ran out of polls");
+    if (e & ERR_WAIT)
+        return fail(c, ECMC_E_DEVICE, "a wait of the dependency-ordered sweep ran out of time (%d s)", WAIT_SECONDS);
     return ECMC_OK;
 }
 
@@ -535,6 +542,15 @@ ecmc_status init_impl(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *mel
         return bail(fail(c, ECMC_E_WORKSPACE, "workspace needs %zu bytes, 256-byte aligned (got %zu)", c->lay.total,
                          opt->workspace_bytes));
     c->ws = (char *)opt->workspace;
+    {
+        // the guard on a dependency wait of the sweep kernel: WAIT_SECONDS of the device's
+        // constant-rate counter (its rate in kHz; 100 MHz if the runtime does not say)
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+            khz = 100000;
+        c->wait_ticks = (unsigned long long)khz * 1000ull * WAIT_SECONDS;
+    }
     if (c->p.bpl2) {
         // by phases (also for a sweep-capable melt when only some colours run)
         if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
@@ -646,7 +662,10 @@ ecmc_status ecmc_init_batch(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_des
     return init_impl(out, n_melts, melts, sigma, l_max, opt, polymers(n_melts, melts));
 }
 
-ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed, uint32_t colour_mask) {
+namespace {
+// One sweep; push > 0 runs the push-off at working diameter `push` (plain FP64 search, one
+// dependency-ordered launch, which the melt's staging must allow).
+ecmc_status sweep_impl(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed, uint32_t colour_mask, double push) {
     if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
     if (n_chains < 0 || !std::isfinite(ell) || !(ell >= 0)) return fail(c, ECMC_E_ARG, "need n_chains >= 0, ell >= 0");
     const bool batch = c->p.melts.size() > 1;
@@ -704,6 +723,14 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     a.exact_search = c->opt.precision == ECMC_PREC_FP64 ? 1 : 0;
     a.swap = c->opt.swap_moves ? 1 : 0;
     a.two_over_k = c->opt.spring_k > 0.0 ? 2.0 / c->opt.spring_k : 0.0;
+    a.wait_ticks = c->wait_ticks;
+    if (push > 0.0) {
+        if (!c->p.sweep || (colour_mask & 0xFFu) != 0xFFu || c->opt.spring_k > 0.0 || c->opt.swap_moves)
+            return fail(c, ECMC_E_ARG, "the push-off needs the one-launch checkerboard sweep of tethered chains");
+        a.sig2 = push * push;
+        a.ov2 = a.sig2 * (1.0 - 1e-9);
+        a.exact_search = 1;
+    }
     a.sigma = c->sigma;
     const bool spring = c->opt.spring_k > 0.0;
     const bool log = c->opt.event_log_capacity > 0;
@@ -771,8 +798,9 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
             // advances the device-side sweep counter
             st = timed([&]() -> ecmc_status {
                 int waves = 0;
-                HIP_OK(c, spring ? launch_sweep_spring(a, c->p.bpl, log, &waves, c->stream)
-                                 : launch_sweep(a, c->p.bpl, log, &waves, c->stream));
+                HIP_OK(c, push > 0.0 ? launch_sweep_push(a, c->p.bpl, log, &waves, c->stream)
+                          : spring   ? launch_sweep_spring(a, c->p.bpl, log, &waves, c->stream)
+                                     : launch_sweep(a, c->p.bpl, log, &waves, c->stream));
                 return ECMC_OK;
             });
             if (st == ECMC_OK) c->sweep_ctr++;
@@ -790,8 +818,76 @@ ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64
     return ECMC_OK;
 }
 
+// Pairs of every melt whose squared distance is below q_lim (the overlaps of the push-off).
+ecmc_status count_pairs_below(ecmc_ctx *c, double q_lim, int64_t *n) {
+    HIP_OK(c, hipMemsetAsync(c->ws + c->lay.hist, 0, 8, c->stream));
+    PairArgs a{};
+    a.px = c->dev<double>(c->lay.px);
+    a.py = c->dev<double>(c->lay.py);
+    a.pz = c->dev<double>(c->lay.pz);
+    a.ccount = c->dev<int32_t>(c->lay.ccount);
+    a.cids = c->dev<int32_t>(c->lay.cids);
+    a.cap = c->cap;
+    a.melts = c->dev<MeltDev>(c->lay.melts);
+    a.n_melts = (int)c->p.melts.size();
+    a.cells = c->p.cells;
+    a.nbins = 1;
+    a.rmax = std::sqrt(q_lim);
+    a.q_lim = q_lim;
+    a.hist = c->dev<unsigned long long>(c->lay.hist);
+    HIP_OK(c, launch_pairs(a, c->stream));
+    ecmc_status st = check_device(c);
+    if (st) return st;
+    unsigned long long v = 0;
+    HIP_OK(c, hipMemcpy(&v, a.hist, 8, hipMemcpyDeviceToHost));
+    *n = (int64_t)v;
+    return ECMC_OK;
+}
+}  // namespace
+
+ecmc_status ecmc_sweep_colours(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed, uint32_t colour_mask) {
+    return sweep_impl(c, n_chains, ell, seed, colour_mask, 0.0);
+}
+
 ecmc_status ecmc_sweep(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed) {
-    return ecmc_sweep_colours(c, n_chains, ell, seed, 0xFFu);
+    return sweep_impl(c, n_chains, ell, seed, 0xFFu, 0.0);
+}
+
+ecmc_status ecmc_pushoff_sweep(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed, double diameter) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    if (!(diameter > 0.0) || !(diameter <= c->sigma))
+        return fail(c, ECMC_E_ARG, "the push-off diameter must be in (0, sigma] (got %g)", diameter);
+    return sweep_impl(c, n_chains, ell, seed, 0xFFu, diameter);
+}
+
+ecmc_status ecmc_count_overlaps(ecmc_ctx *c, double diameter, int64_t *n) {
+    if (!c || !n) return fail(c, ECMC_E_ARG, "null argument");
+    if (!(diameter > 0.0) || !(diameter <= c->sigma))
+        return fail(c, ECMC_E_ARG, "the diameter must be in (0, sigma] (got %g)", diameter);
+    return count_pairs_below(c, diameter * diameter * (1.0 - 1e-9), n);
+}
+
+ecmc_status ecmc_pushoff(ecmc_ctx *c, double d_start, int32_t stages, double ell, uint64_t seed,
+                         int64_t max_sweeps, int64_t *sweeps_done, int64_t *overlaps_left) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    if (!(d_start > 0.0) || !(d_start <= c->sigma) || stages < 1 || max_sweeps < 0 || !(ell > 0.0) || !std::isfinite(ell))
+        return fail(c, ECMC_E_ARG, "need 0 < d_start <= sigma, stages >= 1, max_sweeps >= 0, ell > 0");
+    int64_t done = 0, left = 0;
+    for (int s = 1; s <= stages; ++s) {
+        // working diameters from d_start up to sigma in equal steps (the last one exactly sigma)
+        const double d = s == stages ? c->sigma : d_start + (c->sigma - d_start) * (double)s / (double)stages;
+        for (int64_t k = 0;; ++k) {
+            ecmc_status st = ecmc_count_overlaps(c, d, &left);
+            if (st) return st;
+            if (left == 0 || k >= max_sweeps) break;
+            if ((st = sweep_impl(c, c->nb, ell, seed + (uint64_t)done, 0xFFu, d))) return st;
+            ++done;
+        }
+        if (left) break;
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (overlaps_left) *overlaps_left = left;
+    return check_device(c);
 }
 
 ecmc_status ecmc_synchronize(ecmc_ctx *c) {

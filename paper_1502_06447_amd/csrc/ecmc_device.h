@@ -203,11 +203,14 @@ __device__ __forceinline__ double sqrt_nonneg(double x) {
 // d_par > 0 and the present length otherwise, (k/2)(b - sigma)^2 grows by dE at
 // b_end = sigma + sqrt((b0 - sigma)^2 + g) with g = 2 dE / k.  The general correctly
 // rounded square root is used there: its arguments are not bounded away from 0.
-template <bool WRAP, bool SPRING = false>
+//
+// Push-off (Sec. II.B, PUSH): a bead closer to the pivot than the working diameter (squared
+// distance below ov2 = d^2 (1 - 1e-9)) is no hard-sphere event; sig2 is then d^2.
+template <bool WRAP, bool SPRING = false, bool PUSH = false>
 __device__ __forceinline__ bool exact_candidate(double A, double B, double C, int32_t meta, const Pivot &pv, int sha,
                                                 int shb, int shc, double sgnd, double sig2, double b2, double L,
                                                 bool partner, double &x, bool &hs, double gterm = 0.0,
-                                                double sigma = 0.0) {
+                                                double sigma = 0.0, double ov2 = 0.0) {
     double da = A - pv.a;
     double db = B - pv.b;
     double dc = C - pv.c;
@@ -224,6 +227,7 @@ __device__ __forceinline__ bool exact_candidate(double A, double B, double C, in
     const double pc = dc * dc;
     const double dperp2 = pb + pc;
     hs = (dpar > 0.0) && (dperp2 < sig2);
+    if (PUSH && hs && dpar * dpar + dperp2 < ov2) hs = false;
     double bb2 = b2;
     if (SPRING && partner && !hs) {
         const double b0 = __builtin_sqrt(dpar > 0.0 ? dperp2 : dpar * dpar + dperp2);
@@ -473,10 +477,10 @@ __device__ __forceinline__ Hit search(const Screen<BPL> &sc, const Stage &st, co
 // lane in chunks of 64 staged indices, then the wavefront minimum by (x, staged index, kind).
 // A loop over the staging area rather than over register slots, so that its register needs
 // do not grow with the staging capacity.
-template <bool SPRING = false>
+template <bool SPRING = false, bool PUSH = false>
 __device__ __forceinline__ Hit search_all(const Stage &st, const Pivot &pv, int S, int ax, int sha, int shb, int shc,
                                           double sgnd, double sig2, double b2, double L, bool wr, double g0 = 0.0,
-                                          double g1 = 0.0, double sigma = 0.0) {
+                                          double g1 = 0.0, double sigma = 0.0, double ov2 = 0.0) {
     const int lane = lane_id();
     const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
     const double *pA = st.axis(ax);
@@ -495,10 +499,10 @@ __device__ __forceinline__ Hit search_all(const Stage &st, const Pivot &pv, int 
             double x;
             bool hs;
             const bool ok =
-                wr ? exact_candidate<true, SPRING>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x, hs,
-                                                   gt, sigma)
-                   : exact_candidate<false, SPRING>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x, hs,
-                                                    gt, sigma);
+                wr ? exact_candidate<true, SPRING, PUSH>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x,
+                                                         hs, gt, sigma, ov2)
+                   : exact_candidate<false, SPRING, PUSH>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x,
+                                                          hs, gt, sigma, ov2);
             // a lane's indices increase, so on equal x the earlier bead keeps its place
             const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
             if (ok && (x < b.x || (x == b.x && kk < b.key))) {
@@ -741,8 +745,9 @@ __device__ __forceinline__ void store_pivot(const Pivot &pv, const Stage &st, do
 //
 // With springs (SPRING) the bond energies of every step are drawn from the key (sk0, sk1), and
 // an EC never retraces its path after a reflection (its draws differ), so whole periods are
-// not dropped.
-template <int BPL, bool LOG, bool EXACT, bool WHOLE, bool SPRING = false>
+// not dropped.  Nor are they in the push-off (PUSH, plain FP64 search only), where a pair that
+// stops overlapping no longer lets the pivot through on its way back.
+template <int BPL, bool LOG, bool EXACT, bool WHOLE, bool SPRING = false, bool PUSH = false>
 __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const Stage &st,
                                        Lanes<lane_slots(BPL, EXACT), WHOLE> &R,
                                        int P0, int ax, int sgn, bool wr, int k, const ScreenK &K, Tally &t,
@@ -803,7 +808,8 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
         if constexpr (EXACT) {
             double g0 = 0.0, g1 = 0.0;
             if constexpr (SPRING) spring_terms(a, f, k, step, sk0, sk1, g0, g1);
-            hit = search_all<SPRING>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, g0, g1, a.sigma);
+            hit = search_all<SPRING, PUSH>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, g0, g1, a.sigma,
+                                           a.ov2);
         } else {
             Screen<BPL> sc;
             screen<BPL, WHOLE, SPRING>(sc, R, pv, sha, shb, shc, sgnd, K);
@@ -928,7 +934,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
                 t.inc(kind == 0 ? C_HS_REFLECT : C_TETHER_REFLECT);
                 if (LOG)
                     log_event(a, f, k, step, st.id[pv.P], st.id[j], kind == 0 ? ECMC_EV_HS_REFLECT : ECMC_EV_TETHER_REFLECT);
-                if (!SPRING && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+                if (!SPRING && !PUSH && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
                     store_pivot(pv, st, pA, R);
                     return true;
                 }
@@ -972,7 +978,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
             pv.fa = frame_u(pv.a, c, fsa, L, Oa);
             t.inc(C_WALL);
             if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_WALL);
-            if (!SPRING && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+            if (!SPRING && !PUSH && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
                 store_pivot(pv, st, pA, R);
                 return true;
             }
@@ -1064,7 +1070,24 @@ struct StageMem {
 // One domain from its cell lists to the written-back result: stage its S0 beads (the count
 // the caller took, S0 <= min(cap, 64 BPL)), run its K ECs, write back the motile beads and
 // the domain's cell lists, flush the counters.
-template <int BPL, bool LOG, bool EXACT, bool WHOLE, bool SPRING = false>
+// Push-off: whether staged bead i overlaps another staged bead (minimum image of the raw
+// coordinates, squared distance summed over x, y, z in that order, below ov2).  Every bead within
+// the working diameter of a motile bead is staged.
+__device__ __forceinline__ bool overlaps_staged(const PhaseArgs &a, const double *P0r, const double *P1r,
+                                                const double *P2r, int S, int i) {
+    const double xi = P0r[i], yi = P1r[i], zi = P2r[i];
+    for (int j = 0; j < S; ++j) {
+        if (j == i) continue;
+        const double d0 = min_image(P0r[j] - xi, a.L, a.halfL);
+        const double d1 = min_image(P1r[j] - yi, a.L, a.halfL);
+        const double d2 = min_image(P2r[j] - zi, a.L, a.halfL);
+        const double q0 = d0 * d0, q1 = d1 * d1, q2 = d2 * d2;
+        if ((q0 + q1) + q2 < a.ov2) return true;
+    }
+    return false;
+}
+
+template <int BPL, bool LOG, bool EXACT, bool WHOLE, bool SPRING = false, bool PUSH = false>
 __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F, bool wraps, int S0,
                                             const StageMem &m) {
     constexpr int NS = lane_slots(BPL, EXACT);
@@ -1194,13 +1217,38 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
     for (int k = 0; k < a.K && nmot > 0 && ok; ++k) {
         uint32_t ctr[4] = {(uint32_t)k, f.domain, a.sweep, 2u * a.stream};
         philox4x32_10(ctr, a.key0, a.key1);
-        const int P0 = __builtin_amdgcn_readfirstlane(m.mot[scale_u32(ctr[0], (uint32_t)nmot)]);
+        int P0;
+        if constexpr (PUSH) {
+            // the EC starts at the r-th motile bead (ascending id) that overlaps some bead, r drawn
+            // among them; none left: the domain is done.  Counted, then found by a second pass.
+            int nst = 0;
+            for (int base = 0; base < nmot; base += 64) {
+                const bool ov = base + lane < nmot && overlaps_staged(a, P0r, P1r, P2r, S, m.mot[base + lane]);
+                nst += __popcll(__ballot(ov));
+            }
+            if (nst == 0) break;
+            int r = (int)scale_u32(ctr[0], (uint32_t)nst);
+            P0 = -1;
+            for (int base = 0; base < nmot && P0 < 0; base += 64) {
+                const bool ov = base + lane < nmot && overlaps_staged(a, P0r, P1r, P2r, S, m.mot[base + lane]);
+                const unsigned long long bal = __ballot(ov);
+                const int c = __popcll(bal);
+                if (r < c) {
+                    const unsigned long long hit = __ballot(ov && mbcnt(bal) == r);
+                    const int wl = (int)(__ffsll((long long)hit) - 1);
+                    P0 = __builtin_amdgcn_readfirstlane(m.mot[base + wl]);
+                }
+                r -= c;
+            }
+        } else {
+            P0 = __builtin_amdgcn_readfirstlane(m.mot[scale_u32(ctr[0], (uint32_t)nmot)]);
+        }
         const uint32_t dir = scale_u32(ctr[1], 6u);
         const int ax = __builtin_amdgcn_readfirstlane((int)(dir >> 1));
         const int sgn = __builtin_amdgcn_readfirstlane((dir & 1u) ? -1 : 1);
         if constexpr (!EXACT) rotate(R, cur, ax);
         cur = ax;
-        ok = run_ec<BPL, LOG, EXACT, WHOLE, SPRING>(a, f, st, R, P0, ax, sgn, wraps, k, K, t, sk0, sk1);
+        ok = run_ec<BPL, LOG, EXACT, WHOLE, SPRING, PUSH>(a, f, st, R, P0, ax, sgn, wraps, k, K, t, sk0, sk1);
     }
     __syncthreads();
 

@@ -108,6 +108,11 @@ struct PhaseArgs {
     int nslow, slow_cap;       // slots, beads per slot (0: no slots)
     // harmonic springs (Eq. (2)): 2 / k, 0 for tethers; sigma for the spring formula
     double two_over_k, sigma;
+    // a wait of the dependency-ordered sweep gives up (ERR_WAIT) after this many ticks of the
+    // device's constant-rate counter
+    unsigned long long wait_ticks;
+    // push-off (Sec. II.B): sig2 is the working diameter squared, ov2 = sig2 (1 - 1e-9)
+    double ov2;
 };
 
 struct ObsArgs {
@@ -139,6 +144,7 @@ struct PairArgs {
     int nbins;
     double rmax;
     unsigned long long *hist;  // [nbins]
+    double q_lim;              // > 0: count the pairs with squared distance below q_lim in bin 0 instead
 };
 
 // launchers (ecmc_kernels.hip)
@@ -149,6 +155,7 @@ hipError_t launch_phase(const PhaseArgs &a, int bpl, bool log, int grid, hipStre
 hipError_t launch_phase_spring(const PhaseArgs &a, int bpl, bool log, int grid, hipStream_t s);
 hipError_t launch_sweep(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s);
 hipError_t launch_sweep_spring(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s);
+hipError_t launch_sweep_push(const PhaseArgs &a, int bpl, bool log, int *grid, hipStream_t s);  // FP64 search only
 bool sweep_bpl_supported(int bpl);
 constexpr int SLOW_SLOT_BYTES_PER_BEAD = 3 * 8 + 4 * 4;  // staging slot: positions + 4 int32 rows
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);

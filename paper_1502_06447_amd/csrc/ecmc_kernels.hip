@@ -295,6 +295,11 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pairs(const PairArgs a) {
                     const double q1 = d1 * d1;
                     const double q2 = d2 * d2;
                     const double dd = (q0 + q1) + q2;
+                    if (a.q_lim > 0.0) {
+                        // overlap count of the push-off: squared distance below q_lim
+                        if (dd < a.q_lim) atomicAdd(&s_hist[0], 1u);
+                        continue;
+                    }
                     if (!(dd < r2max * 1.0000001)) continue;  // cheap pre-test; the exact one below
                     const double r = __builtin_sqrt(dd);
                     if (!(r < a.rmax)) continue;

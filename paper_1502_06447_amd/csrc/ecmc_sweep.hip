@@ -13,7 +13,7 @@
 // Persistent waves take tickets from one counter in colour-major order.  A wave only waits on
 // domains of smaller tickets, which running waves hold and finish without waiting on larger
 // ones, so the waits always end.  As a guard against a broken invariant every wait gives up
-// after a fixed number of polls and flags ERR_WAIT.  Completion is published with an
+// after a fixed wall-clock time (far beyond any domain's run time) and flags ERR_WAIT.  Completion is published with an
 // agent-scope release (the per-XCD L2 caches are written back) and observed with an
 // agent-scope acquire.
 //
@@ -21,11 +21,18 @@
 // device workspace instead and run with the plain FP64 search (identical results).
 #include "ecmc_device.h"
 
-// Built twice: for tethers, and with ECMC_SPRING_TU=1 for harmonic springs (Eq. (2)).
+// Built three times: for tethers, with ECMC_SPRING_TU=1 for harmonic springs (Eq. (2)), and
+// with ECMC_PUSH_TU=1 for the push-off of overlapping starts (Sec. II.B, FP64 search only).
 #ifndef ECMC_SPRING_TU
 #define ECMC_SPRING_TU 0
 #endif
-#if ECMC_SPRING_TU
+#ifndef ECMC_PUSH_TU
+#define ECMC_PUSH_TU 0
+#endif
+#if ECMC_PUSH_TU
+#define K_SWEEP k_sweep_push
+#define SWEEP_LAUNCHER launch_sweep_push
+#elif ECMC_SPRING_TU
 #define K_SWEEP k_sweep_spring
 #define SWEEP_LAUNCHER launch_sweep_spring
 #else
@@ -38,10 +45,16 @@ namespace ecmc {
 namespace {
 
 constexpr bool SPRING = ECMC_SPRING_TU != 0;
+constexpr bool PUSH = ECMC_PUSH_TU != 0;
 
-// polls of one wait before it gives up; a poll sleeps about 8 * 64 cycles, so the limit is
-// about a second, far beyond any real wait (a domain takes well under a millisecond)
-constexpr unsigned WAIT_POLLS = 1u << 20;
+// Whether a wait that started at t0 (steady-counter ticks) has run out of time: a.wait_ticks
+// ticks of the constant-rate counter, set on the host to many seconds.  A bound in time rather
+// than in polls: a domain's run time varies by orders of magnitude with the bond model and the
+// event log (a spring domain runs ~45 times the events of a tether domain), a poll's latency
+// with the memory system.
+__device__ __forceinline__ bool out_of_time(const PhaseArgs &a, unsigned long long t0) {
+    return (unsigned long long)wall_clock64() - t0 > a.wait_ticks;
+}
 
 // Wait until this launch has finished every neighbour of domain f whose colour comes earlier,
 // then acquire what they wrote.
@@ -59,10 +72,11 @@ __device__ __forceinline__ void wait_for_earlier(const PhaseArgs &a, const Frame
         need = col < f.colour;
         nb = (f.dom[0] + ox + nd) % nd + nd * ((f.dom[1] + oy + nd) % nd + nd * ((f.dom[2] + oz + nd) % nd));
     }
-    for (unsigned polls = 0;; ++polls) {
+    const unsigned long long t0 = (unsigned long long)wall_clock64();
+    for (;;) {
         need = need && __hip_atomic_load(&done[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch;
         if (!__ballot(need)) break;
-        if (polls >= WAIT_POLLS) {
+        if (__builtin_amdgcn_readfirstlane((int)out_of_time(a, t0))) {
             if (lane == 0) atomicOr(a.err, ERR_WAIT);
             break;
         }
@@ -77,7 +91,8 @@ __device__ __forceinline__ void wait_for_earlier(const PhaseArgs &a, const Frame
 __device__ __forceinline__ int take_slot(const PhaseArgs &a, uint32_t start) {
     int got = -1;
     if (lane_id() == 0) {
-        for (unsigned polls = 0; got < 0; ++polls) {
+        const unsigned long long t0 = (unsigned long long)wall_clock64();
+        while (got < 0) {
             const int nslow = a.nslow;
             uint32_t *lock = a.slow_lock;
             for (int i = 0; i < nslow && got < 0; ++i) {
@@ -85,7 +100,7 @@ __device__ __forceinline__ int take_slot(const PhaseArgs &a, uint32_t start) {
                 if (atomicCAS(&lock[s], 0u, 1u) == 0u) got = s;
             }
             if (got >= 0) break;
-            if (polls >= WAIT_POLLS) {
+            if (out_of_time(a, t0)) {
                 atomicOr(a.err, ERR_WAIT);
                 break;
             }
@@ -152,7 +167,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
     int slot = -1;
     if (S <= SMAX) {
         const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
-        domain_body<BPL, LOG, EXACT, false, SPRING>(b, f, F, wraps, S, m);
+        domain_body<BPL, LOG, EXACT, false, SPRING, PUSH>(b, f, F, wraps, S, m);
     } else if (S <= a.slow_cap) {
         slot = take_slot(a, t);
         if (slot >= 0) {
@@ -161,7 +176,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
             double *base = a.slow + (size_t)slot * (size_t)cap * (SLOW_SLOT_BYTES_PER_BEAD / 8);
             int32_t *ib = reinterpret_cast<int32_t *>(base + 3 * (size_t)cap);
             const StageMem m = {base, ib, ib + cap, ib + 2 * cap, ib + 3 * cap, cap};
-            domain_body<16, LOG, true, false, SPRING>(b, f, F, wraps, S, m);
+            domain_body<16, LOG, true, false, SPRING, PUSH>(b, f, F, wraps, S, m);
         }
     } else if (lane == 0) {
         atomicOr(a.err, ERR_STAGE);
@@ -197,13 +212,17 @@ hipError_t launch_sweep_v(const PhaseArgs &a, int *grid, hipStream_t s) {
 
 template <int BPL>
 hipError_t launch_sweep_b(const PhaseArgs &a, bool log, int *grid, hipStream_t s) {
+    if constexpr (PUSH) {
+        // the push-off runs the plain FP64 search only
+        return log ? launch_sweep_v<BPL, true, true>(a, grid, s) : launch_sweep_v<BPL, false, true>(a, grid, s);
+    }
     if (log) return a.exact_search ? launch_sweep_v<BPL, true, true>(a, grid, s) : launch_sweep_v<BPL, true, false>(a, grid, s);
     return a.exact_search ? launch_sweep_v<BPL, false, true>(a, grid, s) : launch_sweep_v<BPL, false, false>(a, grid, s);
 }
 
 }  // namespace
 
-#if !ECMC_SPRING_TU
+#if !ECMC_SPRING_TU && !ECMC_PUSH_TU
 bool sweep_bpl_supported(int bpl) {
     switch (bpl) {
         case 1: case 2: case 3: case 4: case 6: case 8: return true;

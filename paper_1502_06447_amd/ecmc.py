@@ -42,6 +42,7 @@ class ecmc_options(ctypes.Structure):
         ("swap_moves", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
         ("stage_tier", ctypes.c_int32),
+        ("overlapping_start", ctypes.c_int32),
         ("spring_k", ctypes.c_double),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -108,7 +109,7 @@ EXPORTS = (
     "ecmc_stage_capacity", "ecmc_destroy", "ecmc_status_str", "ecmc_last_error",
     "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
     "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
-    "ecmc_pair_histogram",
+    "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff",
 )
 
 
@@ -140,6 +141,9 @@ def lib():
         "ecmc_msd": (st, [vp, vp, i64, vp]),
         "ecmc_end_to_end_histogram": (st, [vp, i32, dbl, vp]),
         "ecmc_pair_histogram": (st, [vp, i32, dbl, vp]),
+        "ecmc_pushoff_sweep": (st, [vp, i64, dbl, u64, dbl]),
+        "ecmc_count_overlaps": (st, [vp, dbl, P(i64)]),
+        "ecmc_pushoff": (st, [vp, dbl, i32, dbl, u64, i64, P(i64), P(i64)]),
         "ecmc_get_positions": (st, [vp, vp]),
         "ecmc_get_cells": (st, [vp, vp]),
         "ecmc_get_images": (st, [vp, vp]),
@@ -292,6 +296,7 @@ class Options:
     schedule: int = SCHED_SWEEP
     stage_tier: int = 0
     spring_k: float = 0.0  # > 0: harmonic springs of this constant, capped at l_max
+    overlapping_start: bool = False  # accept overlaps in the start (the push-off's phantom chains)
 
 
 def _native_options(o: "Options") -> ecmc_options:
@@ -309,6 +314,7 @@ def _native_options(o: "Options") -> ecmc_options:
     opt.schedule = o.schedule
     opt.stage_tier = o.stage_tier
     opt.spring_k = float(o.spring_k)
+    opt.overlapping_start = 1 if o.overlapping_start else 0
     return opt
 
 
@@ -468,6 +474,26 @@ class Melt:
                                       mid.ctypes.data, ctypes.byref(n_poly)), "ecmc_observables", self.ctx)
         assert n_poly.value == M
         return {"r2": r2, "rg2": rg2, "hist": hist, "mid": mid, "n_poly": M}
+
+    def pushoff_sweep(self, n_chains: int, ell: float, seed: int, diameter: float):
+        """One push-off sweep (Sec. II.B) at working diameter d: overlapping pairs are no events,
+        ECs start at overlapping beads."""
+        _check(lib().ecmc_pushoff_sweep(self.ctx, int(n_chains), float(ell), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                        float(diameter)), "ecmc_pushoff_sweep", self.ctx)
+
+    def count_overlaps(self, diameter: float) -> int:
+        """Pairs closer than d (squared distance below d^2 (1 - 1e-9))."""
+        n = ctypes.c_int64()
+        _check(lib().ecmc_count_overlaps(self.ctx, float(diameter), ctypes.byref(n)), "ecmc_count_overlaps", self.ctx)
+        return n.value
+
+    def pushoff(self, d_start: float, stages: int, ell: float = 2.0, seed: int = 1, max_sweeps: int = 10000):
+        """The slow push-off: working diameters from d_start up to sigma in `stages` steps, push-off
+        sweeps at each until no overlap is left.  Returns (sweeps run, overlaps left)."""
+        done, left = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ecmc_pushoff(self.ctx, float(d_start), int(stages), float(ell), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                  int(max_sweeps), ctypes.byref(done), ctypes.byref(left)), "ecmc_pushoff", self.ctx)
+        return done.value, left.value
 
     def snapshot(self, out=None):
         """Middle bead and centre of mass of every polymer, image-unwrapped, as a device tensor

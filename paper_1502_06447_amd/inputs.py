@@ -25,6 +25,10 @@ Recipes (all draws from ``numpy.random.default_rng(seed)``):
 * ``hs_fluid``     - unbonded spheres on a lattice (pressure checks).
 * ``isolated_chain`` / ``dimer`` - single short chains in a large box.
 * ``batch_melts``  - many independent melts of mixed N, M and eta.
+* ``phantom_chains`` - the start of the push-off (Sec. II.B): phantom non-reversal
+  random walks with bond length sigma, each bond direction uniform on the cap
+  within theta_max of the previous one, first beads uniform in the box; beads
+  overlap freely until the push-off removes the overlaps.
 """
 from __future__ import annotations
 
@@ -42,6 +46,8 @@ __all__ = [
     "isolated_chain",
     "dimer",
     "batch_melts",
+    "phantom_chains",
+    "theta_max_for",
 ]
 
 
@@ -257,3 +263,45 @@ def batch_melts(n_melts: int, seed: int, n_choices=(16, 32, 64, 128, 256),
         out.append(lattice_chains(M, N, eta, seed=int(rng.integers(0, 2 ** 31)), sigma=sigma,
                                   b_max=b_max))
     return out
+
+
+def theta_max_for(c: float) -> float:
+    """Opening angle theta_max (radians) of the non-reversal walk whose bonds are uniform on the cap
+    within theta_max of the previous bond: <cos theta> = (1 + cos theta_max) / 2 = cos^2(theta_max / 2)
+    (Sec. II.B), and c = (1 + <cos theta>) / (1 - <cos theta>) fixes <cos theta> = (c - 1) / (c + 1)."""
+    mean_cos = (c - 1.0) / (c + 1.0)
+    return 2.0 * math.acos(math.sqrt(mean_cos))
+
+
+def phantom_chains(n_poly: int, n_per: int, eta: float, seed: int, c: float = 1.9, sigma: float = 1.0,
+                   b_max: float = 1.4, L: float | None = None) -> Melt:
+    """Phantom chains for the push-off (Sec. II.B): bond length sigma, vanishing excluded volume,
+    grown as non-reversal random walks whose bond directions are uniform on the cap within
+    theta_max of the previous bond (theta_max from c: 112.3 degrees for c = 1.9); the first bead
+    of each chain and its first bond direction are uniform.  The box is sized for packing
+    fraction eta at diameter sigma (or given as L)."""
+    rng = np.random.default_rng(seed)
+    n = n_poly * n_per
+    if L is None:
+        L = box_for(n, eta, sigma)
+    cos_max = math.cos(theta_max_for(c))
+    pos = np.zeros((n_poly, n_per, 3))
+    pos[:, 0] = rng.uniform(0.0, L, size=(n_poly, 3))
+    t = rng.normal(size=(n_poly, 3))
+    t /= np.linalg.norm(t, axis=1)[:, None]
+    for k in range(1, n_per):
+        if k > 1:
+            # a direction on the cap around t: cos uniform in [cos theta_max, 1], azimuth uniform
+            ct = rng.uniform(cos_max, 1.0, size=n_poly)
+            st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+            ph = rng.uniform(0.0, 2.0 * math.pi, size=n_poly)
+            a = np.where(np.abs(t[:, 0:1]) < 0.9, np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 1.0, 0.0]]))
+            e1 = np.cross(t, a)
+            e1 /= np.linalg.norm(e1, axis=1)[:, None]
+            e2 = np.cross(t, e1)
+            t = ct[:, None] * t + (st * np.cos(ph))[:, None] * e1 + (st * np.sin(ph))[:, None] * e2
+            t /= np.linalg.norm(t, axis=1)[:, None]
+        pos[:, k] = pos[:, k - 1] + sigma * t
+    return Melt(L=L, positions=_wrap(pos.reshape(-1, 3), L), bonds=_chain_bonds(n_poly, n_per), sigma=sigma,
+                b_max=b_max, n_poly=n_poly, n_per=n_per,
+                meta={"recipe": "phantom", "seed": seed, "c": c, "theta_max": theta_max_for(c)})

@@ -47,6 +47,9 @@ MUTANTS = {
     "pair_no_image": ("for (int a = 0; a < 3; ++a) d[a] = mi(s, s->r[3 * j + a] - s->r[3 * i + a]);\n            const double q0",
                       "for (int a = 0; a < 3; ++a) d[a] = s->r[3 * j + a] - s->r[3 * i + a];\n            const double q0"),
     "e2e_squared": ("floor(sqrt(r2[q]) / rmax * (double)nbins)", "floor(r2[q] / rmax * (double)nbins)"),
+    "push_no_ignore": ("    if (s->push && dpar * dpar + dperp2 < s->ov2) return 0; /* push-off: an overlapping pair */\n", ""),
+    "push_start_all": ("if (!s->push || overlaps_any(s, list[i])) out[k++] = list[i];", "out[k++] = list[i];"),
+    "push_margin": ("s->ov2 = s->sig2 * (1.0 - 1e-9);", "s->ov2 = s->sig2 * (1.0 + 1e-9);"),
     # equivalent mutants: no observable difference is expected
     # (W = 0 means every event between the two reflections had zero length, so the zero-length
     # cycle search ends the same EC a few steps later with the same positions)

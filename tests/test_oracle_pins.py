@@ -1008,3 +1008,106 @@ def test_msd_series_closed_forms_and_brute_force():
     alt = np.stack([np.concatenate([base[:, :3] + (t % 2) * w, base[:, 3:]], axis=1) for t in range(T)])
     g1, g2 = oracle.msd_series(alt)
     assert np.allclose(g2[1::2], w @ w, rtol=1e-12) and np.allclose(g2[2::2], 0, atol=1e-24)
+
+
+# ------------------------------------------------------------------ push-off (Sec. II.B)
+def test_phantom_chains_follow_the_non_reversal_law():
+    """Phantom non-reversal walks: bonds of length sigma, successive bonds at most theta_max apart,
+    <cos theta> = cos^2(theta_max / 2) = (c - 1)/(c + 1) (theta_max = 112.29 degrees for c = 1.9),
+    and <R^2> of the freely rotating chain with alpha = <cos theta>:
+    n b^2 [(1 + a)/(1 - a) - 2 a (1 - a^n) / (n (1 - a)^2)] for n bonds."""
+    assert abs(math.degrees(inputs.theta_max_for(1.9)) - 112.29) < 0.01
+    m = inputs.phantom_chains(4000, 40, 0.45, seed=8)
+    p = m.positions.reshape(4000, 40, 3)
+    b = np.diff(p, axis=1)
+    b -= m.L * np.round(b / m.L)
+    assert np.abs(np.linalg.norm(b, axis=2) - 1.0).max() < 1e-12
+    t = b / np.linalg.norm(b, axis=2)[..., None]
+    cos = np.sum(t[:, 1:] * t[:, :-1], axis=2)
+    assert cos.min() >= math.cos(inputs.theta_max_for(1.9)) - 1e-12
+    a = 0.9 / 2.9
+    assert abs(cos.mean() - a) < 4 * cos.std() / math.sqrt(cos.size)
+    n = 39
+    R2 = np.sum(np.sum(b, axis=1) ** 2, axis=1)
+    want = n * ((1 + a) / (1 - a) - 2 * a * (1 - a ** n) / (n * (1 - a) ** 2))
+    assert abs(R2.mean() - want) < 4 * R2.std() / math.sqrt(len(R2)), (R2.mean(), want)
+
+
+def test_pushoff_hand_case_passes_through_an_overlapping_bead():
+    """Beads A (5, 5, 5), B (5.5, 5, 5) overlapping at d = 1, C (7.8, 5, 5).  An EC of length 2
+    from A along +x ignores B (an overlapping pair is no event) and meets C after 1.8: A ends at
+    6.8, 1.3 from B (the overlap is gone), and C takes the remaining 0.2 to 8.0; B stays.
+    Without the push-off A would be lifted to B at once."""
+    pos = np.array([[5.0, 5.0, 5.0], [5.5, 5.0, 5.0], [7.8, 5.0, 5.0]])
+    o = oracle.Oracle(12.0, 1.0, 1.4, pos, np.zeros((0, 2), dtype=np.int32), overlapping=True)
+    o.set_pushoff(1.0)
+    assert o.count_overlaps(1.0) == 1
+    o.run_ec(0, 0, 2.0)
+    p = o.positions()
+    assert abs(p[0, 0] - 6.8) < 1e-14 and p[1, 0] == 5.5 and abs(p[2, 0] - 8.0) < 1e-14
+    assert np.array_equal(p[:, 1:], pos[:, 1:])
+    assert o.count_overlaps(1.0) == 0
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle(12.0, 1.0, 1.4, pos, np.zeros((0, 2), dtype=np.int32))  # plain create refuses it
+    # a pair exactly in contact is no overlap: A is lifted to B at once and B takes the whole move
+    pos = np.array([[5.0, 5.0, 5.0], [6.0, 5.0, 5.0]])
+    o = oracle.Oracle(12.0, 1.0, 1.4, pos, np.zeros((0, 2), dtype=np.int32), overlapping=True)
+    o.set_pushoff(1.0)
+    assert o.count_overlaps(1.0) == 0
+    o.run_ec(0, 0, 0.5)
+    p = o.positions()
+    assert p[0, 0] == 5.0 and p[1, 0] == 6.5
+
+
+def test_pushoff_starts_only_at_overlapping_beads():
+    """One overlapping pair in a dilute fluid of 64 spheres: every EC of a push-off sweep starts
+    at a bead that overlaps (the first event record of each EC names its start), and once no
+    overlap is left no further EC runs."""
+    m = inputs.hs_fluid(64, 0.05, seed=4)
+    pos = m.positions.copy()
+    pos[1] = pos[0] + np.array([0.3, 0.2, 0.1])
+    o = oracle.Oracle(m.L, 1.0, 1.4, pos, np.zeros((0, 2), dtype=np.int32), overlapping=True)
+    base = o.count_overlaps(1.0)
+    assert base >= 1
+    o.set_pushoff(1.0)
+    o.enable_log(100000)
+    o.sweep(64, 0.7, 5)
+    log = o.event_log()
+    c, _ = o.counters()
+    # cell crossings are not logged and keep the pivot: the first record of an EC names its start
+    first = {}
+    for r in log:
+        first.setdefault(int(r["ec"]), int(r["pivot"]))
+    assert c[oracle.C_EC] >= 1 and len(first) == c[oracle.C_EC]
+    assert set(first.values()) <= {0, 1} | set(np.flatnonzero(
+        [np.any([np.sum(((pos[i] - pos[j] + m.L / 2) % m.L - m.L / 2) ** 2) < 1 for j in range(64) if j != i])
+         for i in range(64)]).tolist())
+    assert o.count_overlaps(1.0) <= base
+
+
+def test_pushoff_never_creates_overlaps_and_ends_valid():
+    """The slow push-off of 40 phantom chains of 16 beads at eta = 0.30 (c = 1.9), working
+    diameters 0.1 ... 1 in ten steps, checkerboard sweeps of ECs of length 2 sigma: the number of
+    overlapping pairs never grows within a stage (a moving bead stops at every bead it does not
+    overlap), every stage ends with none, and the end is a valid start at sigma (the plain
+    create accepts it, tethers within b_max)."""
+    m = inputs.phantom_chains(40, 16, 0.30, seed=6)
+    n = int(m.L // 1.4)
+    n -= n % 2 + (2 if (n // 2) % 2 else 0)
+    o = oracle.Oracle(m.L, 1.0, 1.4, m.positions, m.bonds, n_cells=n, overlapping=True, check=1)
+    seed = 0
+    for k in range(1, 11):
+        d = 0.1 * k if k < 10 else 1.0
+        o.set_pushoff(d)
+        prev = o.count_overlaps(d)
+        sweeps = 0
+        while prev and sweeps < 400:
+            o.sweep(m.n_beads, 2.0, 77 + seed, tiling=1, D=2)
+            seed += 1
+            sweeps += 1
+            now = o.count_overlaps(d)
+            assert now <= prev
+            prev = now
+        assert prev == 0, (d, sweeps)
+    o.set_pushoff(0.0)
+    oracle.Oracle(m.L, 1.0, 1.4, o.positions(), m.bonds, n_cells=n)
