@@ -82,6 +82,15 @@ WORKLOADS = {
 }
 
 
+def checker_cells(L: float, b_max: float, D: int) -> int:
+    """The largest cell grid with edge > b_max that a checkerboard of D^3-cell domains tiles
+    (n a multiple of D with n / D even)."""
+    n = int(L // b_max)
+    while n > 0 and (L / n <= b_max or n % D or (n // D) % 2):
+        n -= 1
+    return n
+
+
 def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False, spring_k: float = 0.0,
                  b_max: float = 1.4) -> dict:
     """The CPU oracle (serial, one core) on a bounded sample of the same workload: an
@@ -90,10 +99,7 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False, sp
     from paper_1502_06447_amd import inputs
 
     m = inputs.lattice_chains(64, 64, w["eta"], seed=seed, b_max=b_max)
-    # the largest cell grid with edge > b_max that the checkerboard of D^3-cell domains tiles
-    n = int(m.L // b_max)
-    while n > 0 and (m.L / n <= b_max or n % w["D"] or (n // w["D"]) % 2):
-        n -= 1
+    n = checker_cells(m.L, b_max, w["D"])
     o = oracle.Oracle.from_melt(m, n_cells=n)
     o.set_swap(swap)
     o.set_spring(spring_k)
@@ -145,7 +151,8 @@ def precision_check(melt, w, sweeps: int, swap: bool = False, spring_k: float = 
     res = {}
     for name, prec in (("mixed", ecmc.PREC_MIXED), ("fp64", ecmc.PREC_FP64)):
         g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], precision=prec,
-                                                   swap_moves=swap, spring_k=spring_k))
+                                                   swap_moves=swap, spring_k=spring_k,
+                                                   n_cells=checker_cells(melt.L, melt.b_max, w["D"])))
         for i in range(sweeps):
             g.sweep(melt.n_beads, w["ell"], 7000 + i)
         g.synchronize()
@@ -357,8 +364,10 @@ def main():
         print(f"# copy probe: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
     melt = inputs.lattice_chains(w["M"], w["N"], w["eta"], seed=args.seed, b_max=b_max)
     prec = ecmc.PREC_MIXED if args.precision == "mixed" else ecmc.PREC_FP64
+    n_cells = checker_cells(melt.L, b_max, w["D"])
     g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], time_kernels=True,
-                                               precision=prec, swap_moves=args.swap, spring_k=args.springs))
+                                               precision=prec, swap_moves=args.swap, spring_k=args.springs,
+                                               n_cells=n_cells))
     nb = melt.n_beads
     n = g.n_cells
     beads_per_cell = nb / n ** 3

@@ -60,8 +60,10 @@
  *    in contact by an earlier event, up to rounding, as obstacles); an overlapping pair is no
  *    hard-sphere event for either bead, and every EC starts from a motile bead that overlaps
  *    some bead (the k-th draw picks among them in ascending id; a domain with none runs no
- *    EC); the periodic reduction is off (a pair that stops overlapping no longer lets the
- *    pivot through on the way back).
+ *    EC).  The periodic reduction stays on: the push-off prepares a start and samples
+ *    nothing, and without it a bead caught between two immotile contacts with a gap of
+ *    rounding size bounces for ever; where a pair that stopped overlapping changes the way
+ *    back, it merely shortens that EC.
  */
 #include "ecmc_oracle.h"
 
@@ -819,7 +821,7 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
             } else {
                 log_event(s, dm, step, p, b.j, b.kind == 0 ? ORC_EV_HS_REFLECT : ORC_EV_TETHER_REFLECT);
                 s->cnt[b.kind == 0 ? ORC_C_HS_REFLECT : ORC_C_TETHER_REFLECT]++;
-                if (!s->spring && !s->push && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+                if (!s->spring && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
                 reflected = 1;
                 xref = xmax;
                 sgn = -sgn;
@@ -863,7 +865,7 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
         } else {
             log_event(s, dm, step, p, -1, ORC_EV_WALL);
             s->cnt[ORC_C_WALL]++;
-            if (!s->spring && !s->push && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+            if (!s->spring && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
             reflected = 1;
             xref = xmax;
             sgn = -sgn;

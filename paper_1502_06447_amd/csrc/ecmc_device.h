@@ -745,8 +745,9 @@ __device__ __forceinline__ void store_pivot(const Pivot &pv, const Stage &st, do
 //
 // With springs (SPRING) the bond energies of every step are drawn from the key (sk0, sk1), and
 // an EC never retraces its path after a reflection (its draws differ), so whole periods are
-// not dropped.  Nor are they in the push-off (PUSH, plain FP64 search only), where a pair that
-// stops overlapping no longer lets the pivot through on its way back.
+// not dropped.  The push-off (PUSH, plain FP64 search only) keeps the shortcut: it prepares a
+// start and samples nothing, and where a pair that stopped overlapping changes the way back the
+// shortcut merely shortens that EC.
 template <int BPL, bool LOG, bool EXACT, bool WHOLE, bool SPRING = false, bool PUSH = false>
 __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const Stage &st,
                                        Lanes<lane_slots(BPL, EXACT), WHOLE> &R,
@@ -934,7 +935,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
                 t.inc(kind == 0 ? C_HS_REFLECT : C_TETHER_REFLECT);
                 if (LOG)
                     log_event(a, f, k, step, st.id[pv.P], st.id[j], kind == 0 ? ECMC_EV_HS_REFLECT : ECMC_EV_TETHER_REFLECT);
-                if (!SPRING && !PUSH && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+                if (!SPRING && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
                     store_pivot(pv, st, pA, R);
                     return true;
                 }
@@ -978,7 +979,7 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
             pv.fa = frame_u(pv.a, c, fsa, L, Oa);
             t.inc(C_WALL);
             if (LOG) log_event(a, f, k, step, st.id[pv.P], -1, ECMC_EV_WALL);
-            if (!SPRING && !PUSH && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
+            if (!SPRING && reflected && repeat_reflection<LOG>(a, f, k, step, st.id[pv.P], xref, xmax, t)) {
                 store_pivot(pv, st, pA, R);
                 return true;
             }

@@ -549,11 +549,11 @@ def test_springs_c3_full_size_sampled_domains(melt_c3_spring):
     beads of those domains must end with identical positions, cells and images (colour 0
     runs first, so its domains see only the start)."""
     m = melt_c3_spring
-    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, spring_k=30.0))
+    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=56, spring_k=30.0))
     n = g.n_cells
     assert n == 56
     nd = n // 2
-    o = oracle.Oracle.from_melt(m)
+    o = oracle.Oracle.from_melt(m, n_cells=56)
     o.set_spring(30.0)
     assert o.n_cells == n
     cells0 = o.cells()
@@ -641,7 +641,7 @@ def test_end_to_end_and_pair_histograms_match_the_oracle(melt_c2):
 
 # ------------------------------------------------------------------ push-off (Sec. II.B)
 def _pushoff_pair(melt, n, log=4_000_000):
-    g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=n,
+    g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=n, cell_capacity=32,
                                                overlapping_start=True, event_log_capacity=log))
     o = oracle.Oracle(melt.L, melt.sigma, melt.b_max, melt.positions, melt.bonds, n_cells=n, overlapping=True)
     o.enable_log(log)
@@ -656,11 +656,11 @@ def _phantom_cells(melt):
 
 
 def test_pushoff_sweeps_bit_exact():
-    """Push-off sweeps (overlapping pairs are no events, ECs start at overlapping beads) on 40
-    phantom chains of 16 beads at eta = 0.30: at working diameters 0.5, 0.8 and 1, two sweeps
-    each with ECs of length 2 sigma; every event, the positions, cells, images, counters and the
-    overlap counts as in the oracle."""
-    m = inputs.phantom_chains(40, 16, 0.30, seed=6)
+    """Push-off sweeps (overlapping pairs are no events, ECs start at overlapping beads) on 200
+    phantom chains of 16 beads at eta = 0.30 (n = 12, D = 2): at working diameters 0.5, 0.8 and
+    1, two sweeps each with ECs of length 2 sigma; every event, the positions, cells, images,
+    counters and the overlap counts as in the oracle."""
+    m = inputs.phantom_chains(200, 16, 0.30, seed=6)
     n = _phantom_cells(m)
     g, o = _pushoff_pair(m, n)
     seed = 0
@@ -683,7 +683,7 @@ def test_pushoff_loop_reaches_a_valid_start():
     no bond longer than b_max), and plain sweeps run on it."""
     m = inputs.phantom_chains(500, 32, 0.35, seed=9)
     n = _phantom_cells(m)
-    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=n,
+    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=n, cell_capacity=32,
                                             overlapping_start=True))
     assert g.count_overlaps(1.0) > 1000
     sweeps, left = g.pushoff(0.1, 10, ell=2.0, seed=5, max_sweeps=3000)
