@@ -678,15 +678,16 @@ def test_pushoff_sweeps_bit_exact():
 
 def test_pushoff_loop_reaches_a_valid_start():
     """The native slow push-off (ten working diameters up to sigma, sweeps until no overlap is
-    left at each) on 500 phantom chains of 32 beads at eta = 0.35 (c = 1.9): no overlap is left,
-    the state is a valid start (the oracle's plain create accepts it: no pair closer than sigma,
-    no bond longer than b_max), and plain sweeps run on it."""
-    m = inputs.phantom_chains(500, 32, 0.35, seed=9)
+    left at each) on 150 phantom chains of 32 beads at eta = 0.35 (c = 1.9; the oracle, run the
+    same way, needs 585 sweeps at the last diameter): no overlap is left, the state is a valid
+    start (the oracle's plain create accepts it: no pair closer than sigma, no bond longer than
+    b_max), and plain sweeps run on it."""
+    m = inputs.phantom_chains(150, 32, 0.35, seed=9)
     n = _phantom_cells(m)
     g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=n, cell_capacity=32,
                                             overlapping_start=True))
-    assert g.count_overlaps(1.0) > 1000
-    sweeps, left = g.pushoff(0.1, 10, ell=2.0, seed=5, max_sweeps=3000)
+    assert g.count_overlaps(1.0) > 300
+    sweeps, left = g.pushoff(0.1, 10, ell=2.0, seed=5, max_sweeps=5000)
     print(f"push-off: {sweeps} sweeps, {left} overlaps left")
     assert left == 0 and g.count_overlaps(1.0) == 0
     oracle.Oracle(m.L, 1.0, m.b_max, g.positions(), m.bonds, n_cells=n)
