@@ -122,6 +122,45 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False, sp
             "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
 
 
+def _oracle_worker(args):
+    """One independent oracle instance (its own 64 x 64 melt and seeds) for `seconds` of work:
+    (collision events, ECs, seconds)."""
+    w, seconds, seed, spring_k, b_max = args
+    import oracle
+    from paper_1502_06447_amd import inputs
+    m = inputs.lattice_chains(64, 64, w["eta"], seed=seed, b_max=b_max)
+    o = oracle.Oracle.from_melt(m, n_cells=checker_cells(m.L, b_max, w["D"]))
+    o.set_spring(spring_k)
+    for s in range(2):
+        o.sweep(m.n_beads, w["ell"], 100 + s, tiling=1, D=w["D"])
+    c0, _ = o.counters()
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < seconds:
+        o.sweep(m.n_beads, w["ell"], 200 + k, tiling=1, D=w["D"])
+        k += 1
+    dt = time.perf_counter() - t0
+    c1, _ = o.counters()
+    ev = int(sum(c1[i] - c0[i] for i in (oracle.C_HS_LIFT, oracle.C_TETHER_LIFT, oracle.C_HS_REFLECT,
+                                          oracle.C_TETHER_REFLECT, oracle.C_SWAP)))
+    return ev, int(c1[oracle.C_EC] - c0[oracle.C_EC]), dt
+
+
+def cpu_baseline_all_cores(w, seconds: float = 1.5, spring_k: float = 0.0, b_max: float = 1.4) -> dict:
+    """The oracle on every host core at once (up to 16): P independent instances, each on its own
+    64 x 64 melt (independent by construction, as the domains of one colour or the melts of a
+    batch are), for `seconds` each.  Forked before the GPU is touched."""
+    import multiprocessing as mp
+    P = max(1, min(os.cpu_count() or 1, 16))
+    with mp.get_context("fork").Pool(P) as pool:
+        res = pool.map(_oracle_worker, [(w, seconds, 50 + i, spring_k, b_max) for i in range(P)])
+    wall = max(r[2] for r in res)
+    return {"value": sum(r[0] for r in res) / wall, "unit": "collision events/s", "cores": P, "kind": "oracle",
+            "sample": f"{P} independent 64 x 64 melts (4,096 beads each), one per core, {seconds} s each after "
+                      "2 warm-up sweeps",
+            "ec_per_s": sum(r[1] for r in res) / wall}
+
+
 def copy_bandwidth(gib: int = 2, reps: int = 5) -> float:
     """HBM bandwidth of a plain device-to-device copy on this GPU, GB/s (read + written bytes
     over the best of a few HIP-event-timed copies)."""
@@ -346,6 +385,10 @@ def main():
             sys.exit(2)
         return main_batch(args)
     b_max = args.spring_cap if args.springs else 1.4
+    all_cores = None
+    if not args.no_cpu_baseline:
+        # the all-cores oracle leg runs first, in forked workers, before this process touches the GPU
+        all_cores = cpu_baseline_all_cores(WORKLOADS[args.workload], spring_k=args.springs, b_max=b_max)
 
     import numpy as np
     import torch
@@ -451,6 +494,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, seconds=args.cpu_seconds, swap=args.swap, spring_k=args.springs,
                                            b_max=b_max)
         out["cpu_baseline"]["vs_gpu"] = value / out["cpu_baseline"]["value"]
+        out["cpu_baseline"]["all_cores"] = all_cores
     print(json.dumps(out), flush=True)
 
 
