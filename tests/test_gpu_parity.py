@@ -693,3 +693,38 @@ def test_pushoff_loop_reaches_a_valid_start():
     oracle.Oracle(m.L, 1.0, m.b_max, g.positions(), m.bonds, n_cells=n)
     g.sweep(m.n_beads, 20.0, 11)
     g.synchronize()
+
+
+def test_c4_full_batch_sampled_melts_match_the_oracle():
+    """The 256-melt batch of the benchmark (8.4M beads, N from 16 to 256, eta 0.35-0.45) at full
+    size in its launch configuration (one dependency-ordered launch per sweep for all melts, the
+    256-bead staging tier the autotuner picks, larger frames in workspace slots): after two
+    sweeps, five sampled melts (the smallest, the largest, the one with the largest cells and two
+    at random) replayed alone in the oracle (stream m, the batch's ECs per domain) end with the
+    same positions, cells and images bit for bit."""
+    melts = inputs.batch_melts(256, 3)
+    g = ecmc.Melt.from_batch(melts, ecmc.Options(stage_tier=256))
+    infos = [g.melt_info(m) for m in range(g.n_melts)]
+    total_domains = sum(i["n_domains"] for i in infos)
+    n_ec = g.n_beads
+    K = -(-n_ec // total_domains)
+    for s in range(2):
+        g.sweep(n_ec, 20.0, 1000 + s)
+    g.synchronize()
+    assert g.counters()["error_flags"] == 0
+    pos, cells, img = g.positions(), g.cells(), g.images()
+    sizes = [i["n_beads"] for i in infos]
+    edge = [i["cell_size"] for i in infos]
+    rng = np.random.default_rng(2)
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), int(np.argmax(edge))}
+                  | set(int(x) for x in rng.choice(len(melts), 2, replace=False)))
+    for m in pick:
+        info, melt = infos[m], melts[m]
+        o = oracle.Oracle.from_melt(melt, n_cells=info["n_cells"])
+        o.set_stream(m)
+        for s in range(2):
+            o.sweep(K * info["n_domains"], 20.0, 1000 + s, tiling=1, D=info["domain_cells"])
+        b0, nb = info["first_bead"], info["n_beads"]
+        assert np.array_equal(pos[b0:b0 + nb], o.positions()), m
+        assert np.array_equal(cells[b0:b0 + nb], o.cells()), m
+        assert np.array_equal(img[b0:b0 + nb], o.images()), m
