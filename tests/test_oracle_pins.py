@@ -1111,3 +1111,21 @@ def test_pushoff_never_creates_overlaps_and_ends_valid():
         assert prev == 0, (d, sweeps)
     o.set_pushoff(0.0)
     oracle.Oracle(m.L, 1.0, 1.4, o.positions(), m.bonds, n_cells=n)
+
+
+def test_pair_correlation_of_uniform_points_is_one():
+    """g(r) from pair counts: for 3,000 independent uniform points in a periodic cube the
+    normalisation by the ideal-gas counts N (N - 1) / 2 (4 pi / 3)(r_hi^3 - r_lo^3) / V gives
+    g = 1 in every bin within its Poisson error (counts from the oracle's all-pairs histogram)."""
+    from paper_1502_06447_amd.ecmc import pair_correlation
+    rng = np.random.default_rng(12)
+    L, N = 20.0, 3000
+    pos = rng.uniform(0, L, size=(N, 3))
+    o = oracle.Oracle(L, 1e-3, 1.4, pos, np.zeros((0, 2), dtype=np.int32), overlapping=True)
+    h = o.pair_histogram(40, 4.0)
+    g = pair_correlation(h, 4.0, N, L ** 3)
+    ok = h > 0
+    err = 1.0 / np.sqrt(h[ok])
+    assert np.all(np.abs(g[ok] - 1.0) < 5 * err + 1e-12), g
+    assert abs(np.sum(h[10:]) / np.sum(0.5 * N * (N - 1) * 4 * np.pi / 3 * (np.linspace(0, 4, 41)[11:] ** 3
+                                                                            - np.linspace(0, 4, 41)[10:-1] ** 3) / L ** 3) - 1) < 0.01
