@@ -91,6 +91,18 @@ def checker_cells(L: float, b_max: float, D: int) -> int:
     return n
 
 
+def grid_cells(L: float, b_max: float, w) -> int:
+    """Cells per axis for the workload's partition: the checkerboard grid, or for tile-joint
+    (tiles of D^3 cells at pitch D + 1) the largest n with edge > b_max that the pitch divides."""
+    if w.get("tiling", 1) == 2:
+        P = w["D"] + 1
+        n = int(L // b_max)
+        while n > 0 and (L / n <= b_max or n % P or n // P < 2):
+            n -= 1
+        return n
+    return checker_cells(L, b_max, w["D"])
+
+
 def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False, spring_k: float = 0.0,
                  b_max: float = 1.4) -> dict:
     """The CPU oracle (serial, one core) on a bounded sample of the same workload: an
@@ -99,24 +111,25 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False, sp
     from paper_1502_06447_amd import inputs
 
     m = inputs.lattice_chains(64, 64, w["eta"], seed=seed, b_max=b_max)
-    n = checker_cells(m.L, b_max, w["D"])
+    n = grid_cells(m.L, b_max, w)
     o = oracle.Oracle.from_melt(m, n_cells=n)
     o.set_swap(swap)
     o.set_spring(spring_k)
     for s in range(2):  # melt the lattice like the GPU warm-up does
-        o.sweep(m.n_beads, w["ell"], 100 + s, tiling=1, D=w["D"])
+        o.sweep(m.n_beads, w["ell"], 100 + s, tiling=w.get("tiling", 1), D=w["D"])
     c0, _ = o.counters()
     t0 = time.perf_counter()
     k = 0
     while time.perf_counter() - t0 < seconds:
-        o.sweep(m.n_beads, w["ell"], 200 + k, tiling=1, D=w["D"])
+        o.sweep(m.n_beads, w["ell"], 200 + k, tiling=w.get("tiling", 1), D=w["D"])
         k += 1
     dt = time.perf_counter() - t0
     c1, _ = o.counters()
     ev = int(sum(c1[i] - c0[i] for i in (oracle.C_HS_LIFT, oracle.C_TETHER_LIFT, oracle.C_HS_REFLECT,
                                           oracle.C_TETHER_REFLECT, oracle.C_SWAP)))
     return {"value": ev / dt, "unit": "collision events/s", "cores": 1, "kind": "oracle",
-            "sample": f"64 x 64 beads (4,096), eta={w['eta']}, ell={w['ell']}, D={w['D']}, {n}^3 cells"
+            "sample": f"64 x 64 beads (4,096), eta={w['eta']}, ell={w['ell']}, "
+                      + ("tile-joint " if w.get("tiling", 1) == 2 else "") + f"D={w['D']}, {n}^3 cells"
                       + (f", springs k={spring_k} capped at {b_max}" if spring_k else "") + f": {k} sweeps "
                       f"after 2 warm-up sweeps, {dt:.1f} s, single thread",
             "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
@@ -129,15 +142,15 @@ def _oracle_worker(args):
     import oracle
     from paper_1502_06447_amd import inputs
     m = inputs.lattice_chains(64, 64, w["eta"], seed=seed, b_max=b_max)
-    o = oracle.Oracle.from_melt(m, n_cells=checker_cells(m.L, b_max, w["D"]))
+    o = oracle.Oracle.from_melt(m, n_cells=grid_cells(m.L, b_max, w))
     o.set_spring(spring_k)
     for s in range(2):
-        o.sweep(m.n_beads, w["ell"], 100 + s, tiling=1, D=w["D"])
+        o.sweep(m.n_beads, w["ell"], 100 + s, tiling=w.get("tiling", 1), D=w["D"])
     c0, _ = o.counters()
     t0 = time.perf_counter()
     k = 0
     while time.perf_counter() - t0 < seconds:
-        o.sweep(m.n_beads, w["ell"], 200 + k, tiling=1, D=w["D"])
+        o.sweep(m.n_beads, w["ell"], 200 + k, tiling=w.get("tiling", 1), D=w["D"])
         k += 1
     dt = time.perf_counter() - t0
     c1, _ = o.counters()
@@ -189,9 +202,9 @@ def precision_check(melt, w, sweeps: int, swap: bool = False, spring_k: float = 
     from paper_1502_06447_amd import ecmc
     res = {}
     for name, prec in (("mixed", ecmc.PREC_MIXED), ("fp64", ecmc.PREC_FP64)):
-        g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], precision=prec,
+        g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=w.get("tiling", 1), domain_cells=w["D"], precision=prec,
                                                    swap_moves=swap, spring_k=spring_k,
-                                                   n_cells=checker_cells(melt.L, melt.b_max, w["D"])))
+                                                   n_cells=grid_cells(melt.L, melt.b_max, w)))
         for i in range(sweeps):
             g.sweep(melt.n_beads, w["ell"], 7000 + i)
         g.synchronize()
@@ -364,6 +377,9 @@ def main():
     ap.add_argument("--swap", action="store_true", help="swap moves at hard-sphere contacts (Sec. II.C)")
     ap.add_argument("--springs", type=float, default=0.0, metavar="K",
                     help="bonds as harmonic springs of constant K (Eq. (2), k_B T / sigma^2); 0 = tethers")
+    ap.add_argument("--tiling", default="checker", choices=("checker", "joint"),
+                    help="checker: D^3-cell domains in 8 colour phases (default); joint: the tile-joint "
+                         "partition (D^3-cell tiles at pitch D + 1 with immotile joints, one phase)")
     ap.add_argument("--spring-cap", type=float, default=1.8, metavar="B",
                     help="with --springs: bond length cap in sigma (cells get an edge > B)")
     ap.add_argument("--no-precision-check", action="store_true",
@@ -388,13 +404,14 @@ def main():
     all_cores = None
     if not args.no_cpu_baseline:
         # the all-cores oracle leg runs first, in forked workers, before this process touches the GPU
-        all_cores = cpu_baseline_all_cores(WORKLOADS[args.workload], spring_k=args.springs, b_max=b_max)
+        all_cores = cpu_baseline_all_cores(dict(WORKLOADS[args.workload], tiling=2 if args.tiling == "joint" else 1),
+                                           spring_k=args.springs, b_max=b_max)
 
     import numpy as np
     import torch
     from paper_1502_06447_amd import ecmc, inputs
 
-    w = WORKLOADS[args.workload]
+    w = dict(WORKLOADS[args.workload], tiling=2 if args.tiling == "joint" else 1)
     torch.cuda.set_device(0)
     if args.copy_probe > 0:
         nbytes = args.copy_probe << 20
@@ -407,8 +424,8 @@ def main():
         print(f"# copy probe: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
     melt = inputs.lattice_chains(w["M"], w["N"], w["eta"], seed=args.seed, b_max=b_max)
     prec = ecmc.PREC_MIXED if args.precision == "mixed" else ecmc.PREC_FP64
-    n_cells = checker_cells(melt.L, b_max, w["D"])
-    g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=w["D"], time_kernels=True,
+    n_cells = grid_cells(melt.L, b_max, w)
+    g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=w.get("tiling", 1), domain_cells=w["D"], time_kernels=True,
                                                precision=prec, swap_moves=args.swap, spring_k=args.springs,
                                                n_cells=n_cells))
     nb = melt.n_beads
@@ -443,7 +460,7 @@ def main():
     B = bytes_per_event(beads_per_cell)
     kernel_s = kms / 1e3  # HIP events around each sweep launch (or colour phase, by phases)
     achieved = events * B / kernel_s / 1e9 if kernel_s > 0 else 0.0
-    traffic = (measured_traffic() if args.workload == "c3" and not args.swap and not args.springs
+    traffic = (measured_traffic() if args.workload == "c3" and not args.swap and not args.springs and w["tiling"] == 1
                and args.precision == "mixed" else None)
     out = {
         "metric": "collision events/s",
@@ -459,11 +476,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {w['label']}, ell={w['ell']} sigma, checkerboard D={w['D']}, "
-                        f"{n}^3 cells, FP64 results ({args.precision} event search)"
+            "workload": f"{args.workload}: {w['label']}, ell={w['ell']} sigma, "
+                        + (f"checkerboard D={w['D']}, " if w["tiling"] == 1 else
+                           f"tile-joint {w['D']}^3-cell tiles at pitch {w['D'] + 1}, ")
+                        + f"{n}^3 cells, FP64 results ({args.precision} event search)"
                         + (", swap moves" if args.swap else "")
                         + (f", harmonic springs k={args.springs} capped at {b_max} sigma" if args.springs else ""),
             "precision": args.precision, "swap_moves": bool(args.swap),
+            "tiling": "checkerboard" if w["tiling"] == 1 else "tile-joint",
             "bonds": (f"spring k={args.springs}, cap {b_max} sigma" if args.springs else "tether 1.4 sigma"),
             "beads": nb, "chains": w["M"], "beads_per_chain": w["N"], "eta": w["eta"], "ell": w["ell"],
             "domain_cells": w["D"], "cells_per_axis": n, "parallelism": "single GPU",

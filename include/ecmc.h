@@ -58,7 +58,7 @@ typedef enum {
 } ecmc_status;
 
 enum { ECMC_PREC_FP64 = 0, ECMC_PREC_MIXED = 1 };
-enum { ECMC_TILING_WHOLE = 0, ECMC_TILING_CHECKER = 1 };
+enum { ECMC_TILING_WHOLE = 0, ECMC_TILING_CHECKER = 1, ECMC_TILING_JOINT = 2 };
 enum { ECMC_SCHED_SWEEP = 0, ECMC_SCHED_PHASES = 1 };
 
 /* event kinds in the event log */
@@ -88,7 +88,12 @@ typedef struct {
                                    results are identical to ECMC_PREC_FP64, which evaluates
                                    every staged bead in FP64 at every event (the plain kernel) */
     int32_t tiling;             /* ECMC_TILING_WHOLE: one domain, every bead motile;
-                                   ECMC_TILING_CHECKER: D^3-cell domains, 8 colour phases  */
+                                   ECMC_TILING_CHECKER: D^3-cell domains, 8 colour phases;
+                                   ECMC_TILING_JOINT: the tile-joint partition (Sec. II.A),
+                                   D^3-cell tiles at pitch D + 1 (the cell after each tile an
+                                   immotile joint), all tiles in one phase; n a multiple of
+                                   D + 1 with n / (D + 1) >= 2, D >= 1; single melts, run by
+                                   phases                                                  */
     int32_t n_cells;            /* cells per axis; 0 = largest n with L/n > l_max           */
     int32_t domain_cells;       /* D, cells per domain edge (checkerboard)                  */
     int32_t cell_capacity;      /* bead slots per cell; 0 = 16                              */

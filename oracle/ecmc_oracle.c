@@ -27,7 +27,9 @@
  *  - the pivot reaching a cell face is a bookkeeping event: its coordinate is set to
  *    the face value (not accumulated), and the EC goes on with the same pivot;
  *  - domains: D^3 blocks of cells, integer offset per axis drawn per sweep, eight
- *    colours by domain-index parity, run in colour order 0..7;
+ *    colours by domain-index parity, run in colour order 0..7; or (tile-joint, Sec. II.A)
+ *    D^3-cell tiles at pitch D + 1, the cell after each tile along every axis a joint that no
+ *    tile moves, offset in [0, D + 1), all tiles in one phase;
  *  - reflection at an immotile bead and at a wall reverses v (s -> -s);
  *  - ties: END before interaction before cell face; interactions ordered by
  *    (x, bead id, hard sphere before tether);
@@ -426,6 +428,7 @@ int64_t orc_log_count(const orc_sys *s) { return s->log_n; }
 typedef struct {
     int tiled;      /* 0: whole box, every bead motile, no walls */
     int D;          /* cells per domain edge */
+    int P;          /* domain pitch: D (checkerboard) or D + 1 (tile-joint: a joint cell after each tile) */
     int off[3];     /* partition offset (cells) */
     int dom[3];     /* active domain coordinates */
     uint32_t sweep, domain, colour, ec;
@@ -433,13 +436,17 @@ typedef struct {
 } orc_dom;
 
 static int dom_coord(const orc_sys *s, const orc_dom *dm, int c, int a) {
-    return ((c - dm->off[a]) % s->n + s->n) % s->n / dm->D;
+    return ((c - dm->off[a]) % s->n + s->n) % s->n / dm->P;
 }
 
+/* a cell is in the active domain when it lies in the domain's pitch block and, with tile-joint,
+ * not in the joint cell that ends the block */
 static int cell_in_domain(const orc_sys *s, const orc_dom *dm, const int32_t c[3]) {
     if (!dm->tiled) return 1;
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
         if (dom_coord(s, dm, c[a], a) != dm->dom[a]) return 0;
+        if (((c[a] - dm->off[a]) % s->n + s->n) % s->n % dm->P >= dm->D) return 0;
+    }
     return 1;
 }
 
@@ -879,6 +886,7 @@ int orc_run_ec(orc_sys *s, int32_t p, int dir, double ell) {
     orc_dom dm;
     memset(&dm, 0, sizeof dm);
     dm.D = 1;
+    dm.P = 1;
     return run_ec(s, &dm, p, dir >> 1, (dir & 1) ? -1 : 1, ell);
 }
 
@@ -974,6 +982,7 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
         /* one domain: the whole box */
         dm.tiled = 0;
         dm.D = 1;
+        dm.P = 1;
         for (int64_t i = 0; i < s->nb; ++i) mot[i] = (int32_t)i;
         for (int64_t k = 0; k < n_ec && st == ORC_OK; ++k) {
             const int64_t ms = start_beads(s, mot, s->nb, starts);
@@ -986,31 +995,39 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
             dm.ec = (uint32_t)k;
             st = run_ec(s, &dm, p, (int)(dir >> 1), (dir & 1) ? -1 : 1, ell);
         }
-    } else if (tiling == 1) {
+    } else if (tiling == 1 || tiling == 2) {
+        /* checkerboard (1): D^3-cell domains, 8 colour phases; tile-joint (2, Sec. II.A): tiles of
+         * D^3 cells, each followed along every axis by one joint cell that no tile moves, all
+         * tiles at once in one phase */
         const int n = s->n;
-        if (D < 2 || n % D != 0 || (n / D) % 2 != 0) {
+        const int P = tiling == 2 ? D + 1 : D;
+        if ((tiling == 1 && (D < 2 || n % D != 0 || (n / D) % 2 != 0)) ||
+            (tiling == 2 && (D < 1 || n % P != 0 || n / P < 2))) {
             free(mot);
+            free(starts);
             return ORC_E_BOX;
         }
-        const int nd = n / D;
+        const int nd = n / P;
         const int64_t ndom = (int64_t)nd * nd * nd;
         const int64_t K = (n_ec + ndom - 1) / ndom;
         dm.tiled = 1;
         dm.D = D;
+        dm.P = P;
         {
             const uint32_t ctr[4] = {0u, 0u, sweep, 2u * s->stream + 1u};
             uint32_t u[4];
             orc_philox4x32_10(ctr, key, u);
-            for (int a = 0; a < 3; ++a) dm.off[a] = (int)below(u[a], (uint32_t)D);
+            for (int a = 0; a < 3; ++a) dm.off[a] = (int)below(u[a], (uint32_t)P);
         }
-        for (int colour = 0; colour < 8 && st == ORC_OK; ++colour) {
+        const int phases = tiling == 2 ? 1 : 8;
+        for (int colour = 0; colour < phases && st == ORC_OK; ++colour) {
             if (!((colour_mask >> colour) & 1u)) continue;
             dm.colour = (uint32_t)colour;
             for (int dz = 0; dz < nd && st == ORC_OK; ++dz)
                 for (int dy = 0; dy < nd && st == ORC_OK; ++dy)
                     for (int dx = 0; dx < nd && st == ORC_OK; ++dx) {
-                        if ((dx & 1) != (colour & 1) || (dy & 1) != ((colour >> 1) & 1) ||
-                            (dz & 1) != ((colour >> 2) & 1))
+                        if (tiling == 1 && ((dx & 1) != (colour & 1) || (dy & 1) != ((colour >> 1) & 1) ||
+                                            (dz & 1) != ((colour >> 2) & 1)))
                             continue;
                         dm.dom[0] = dx;
                         dm.dom[1] = dy;
@@ -1022,9 +1039,9 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
                         for (int tz = 0; tz < D; ++tz)
                             for (int ty = 0; ty < D; ++ty)
                                 for (int tx = 0; tx < D; ++tx) {
-                                    const int c = cidx(s, (dm.off[0] + dx * D + tx) % n,
-                                                       (dm.off[1] + dy * D + ty) % n,
-                                                       (dm.off[2] + dz * D + tz) % n);
+                                    const int c = cidx(s, (dm.off[0] + dx * P + tx) % n,
+                                                       (dm.off[1] + dy * P + ty) % n,
+                                                       (dm.off[2] + dz * P + tz) % n);
                                     for (int t = 0; t < s->ccount[c]; ++t) mot[m++] = s->clist[c][t];
                                 }
                         if (m == 0) continue;

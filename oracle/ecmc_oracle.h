@@ -111,7 +111,11 @@ int orc_set_log(orc_sys *s, orc_event *buf, int64_t cap);
 int64_t orc_log_count(const orc_sys *s);
 
 /* One sweep: tiling 0 = whole box (one domain, every bead motile), 1 = checkerboard of
- * D^3-cell domains in 8 colour phases.  colour_mask selects which phases run. */
+ * D^3-cell domains in 8 colour phases (n % D == 0, n / D even), 2 = tile-joint (Sec. II.A):
+ * D^3-cell tiles at pitch D + 1, the cell after each tile along every axis an immotile joint,
+ * all tiles in one phase (n % (D + 1) == 0, n / (D + 1) >= 2; D = 1 allowed: the offset in
+ * [0, D + 1) still moves the partition).  colour_mask selects which phases run (bit 0 alone
+ * for tile-joint). */
 int orc_sweep(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, int D,
               uint32_t colour_mask);
 

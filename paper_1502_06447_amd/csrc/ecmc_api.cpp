@@ -155,6 +155,11 @@ ecmc_status plan_melt(double L, int64_t nb, double lmax, int n_req, int D_req, i
     while (nmax > 0 && !(L / nmax > lmax)) --nmax;
     int n = n_req > 0 ? n_req : nmax;
     int D = D_req;
+    if (tiling == ECMC_TILING_JOINT) {
+        // tiles of D^3 cells at pitch D + 1: n a multiple of the pitch, at least two tiles per axis
+        if (D < 1) D = 2;
+        if (n_req <= 0) n = nmax - nmax % (D + 1);
+    }
     if (tiling == ECMC_TILING_CHECKER && D_req == 0) {
         if (n_req > 0) {
             for (D = 2; D <= n && !(n % D == 0 && (n / D) % 2 == 0); ++D) {
@@ -187,6 +192,13 @@ ecmc_status plan_melt(double L, int64_t nb, double lmax, int n_req, int D_req, i
         mp.D = D;
         mp.nd = n / D;
         mp.ndpc = (mp.nd / 2) * (mp.nd / 2) * (mp.nd / 2);
+    } else if (tiling == ECMC_TILING_JOINT) {
+        if (D < 1 || n % (D + 1) != 0 || n / (D + 1) < 2)
+            return fail(c, ECMC_E_BOX, "tile-joint needs D >= 1, n %% (D + 1) == 0 and n/(D + 1) >= 2 (melt %d: n = %d, D = %d)",
+                        m, n, D);
+        mp.D = D;
+        mp.nd = n / (D + 1);
+        mp.ndpc = mp.nd * mp.nd * mp.nd;  // every tile in the one phase
     } else {
         return fail(c, ECMC_E_ARG, "unknown tiling %d", tiling);
     }
@@ -304,7 +316,7 @@ ecmc_status plan(const std::vector<MeltIn> &in, double sigma, double lmax, const
         p.bpl2 = nxt == std::end(ok) ? 0 : *nxt;
         p.bpl3 = (p.bpl2 && p.bpl2 < 16) ? 16 : 0;
     }
-    if (!p.whole && o.schedule == ECMC_SCHED_SWEEP && sweep_bpl_supported(p.bpl)) {
+    if (o.tiling == ECMC_TILING_CHECKER && o.schedule == ECMC_SCHED_SWEEP && sweep_bpl_supported(p.bpl)) {
         p.sweep = true;
         if (p.bpl2 && most > 64 * p.bpl) {
             // automatic capacity: the domains above the LDS staging area go to workspace slots
@@ -609,7 +621,7 @@ ecmc_melt_desc single_melt(double box, int64_t n_beads, const double *positions,
     d.n_bonds = n_bonds;
     d.bonds = bonds;
     d.n_cells = o.n_cells;
-    d.domain_cells = o.tiling == ECMC_TILING_CHECKER ? o.domain_cells : 0;
+    d.domain_cells = o.tiling != ECMC_TILING_WHOLE ? o.domain_cells : 0;
     return d;
 }
 
@@ -724,6 +736,7 @@ ecmc_status sweep_impl(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed,
     a.swap = c->opt.swap_moves ? 1 : 0;
     a.two_over_k = c->opt.spring_k > 0.0 ? 2.0 / c->opt.spring_k : 0.0;
     a.wait_ticks = c->wait_ticks;
+    a.joint = c->opt.tiling == ECMC_TILING_JOINT ? 1 : 0;
     if (push > 0.0) {
         if (!c->p.sweep || (colour_mask & 0xFFu) != 0xFFu || c->opt.spring_k > 0.0 || c->opt.swap_moves)
             return fail(c, ECMC_E_ARG, "the push-off needs the one-launch checkerboard sweep of tethered chains");
@@ -806,7 +819,14 @@ ecmc_status sweep_impl(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed,
             if (st == ECMC_OK) c->sweep_ctr++;
             return st;
         }
-        for (int colour = 0; colour < 8 && st == ECMC_OK && a.K > 0; ++colour) {
+        if (a.joint) {
+            // tile-joint: all tiles in one phase (colour bit 0)
+            if ((colour_mask & 1u) && a.K > 0) {
+                a.colour = 0;
+                st = phase(m0.ndpc);
+            }
+        }
+        for (int colour = 0; colour < 8 && st == ECMC_OK && a.K > 0 && !a.joint; ++colour) {
             if (!((colour_mask >> colour) & 1u)) continue;
             a.colour = colour;
             st = phase(m0.ndpc);

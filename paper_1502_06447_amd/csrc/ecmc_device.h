@@ -994,7 +994,11 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
 // Domain b of a colour: its first cell per axis (ds), the frame of domain plus one-cell halo
 // (fs, origin O, edge F cells), and whether that frame wraps the box.  The colour of a
 // domain is the parity of its grid coordinates, (d_x & 1) | (d_y & 1) << 1 | (d_z & 1) << 2.
-template <bool WHOLE>
+//
+// Tile-joint (JOINT, Sec. II.A): domain b of the single phase is tile (b mod nd, ...) and the
+// tiles sit at pitch D + 1, so that the cell after each tile along every axis is a joint that no
+// tile moves (it is in the halo of the tiles on either side).
+template <bool WHOLE, bool JOINT = false>
 __device__ __forceinline__ void frame_of(const PhaseArgs &a, int colour, int b, const int off[3], int dom0, Frame &f,
                                          int &F, bool &wraps) {
     const int n = a.n;
@@ -1002,18 +1006,24 @@ __device__ __forceinline__ void frame_of(const PhaseArgs &a, int colour, int b, 
     dom[0] = dom[1] = dom[2] = 0;
     f.domain = 0;
     f.colour = colour;
-    if (!WHOLE) {
+    if (!WHOLE && JOINT) {
+        dom[0] = b % a.nd;
+        dom[1] = (b / a.nd) % a.nd;
+        dom[2] = b / (a.nd * a.nd);
+        f.domain = (uint32_t)b;
+    } else if (!WHOLE) {
         const int nd2 = a.nd >> 1;
         dom[0] = 2 * (b % nd2) + (colour & 1);
         dom[1] = 2 * ((b / nd2) % nd2) + ((colour >> 1) & 1);
         dom[2] = 2 * (b / (nd2 * nd2)) + ((colour >> 2) & 1);
         f.domain = (uint32_t)(dom[0] + a.nd * (dom[1] + a.nd * dom[2]));
     }
+    const int pitch = JOINT ? a.D + 1 : a.D;
     f.gdomain = (uint32_t)dom0 + f.domain;
     F = WHOLE ? n : a.D + 2;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        f.ds[ax] = WHOLE ? 0 : (off[ax] + dom[ax] * a.D) % n;
+        f.ds[ax] = WHOLE ? 0 : (off[ax] + dom[ax] * pitch) % n;
         f.fs[ax] = WHOLE ? 0 : (f.ds[ax] - 1 + n) % n;
         f.O[ax] = WHOLE ? 0.0 : face(f.fs[ax], n, a.h, a.L);
     }

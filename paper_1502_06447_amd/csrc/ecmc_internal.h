@@ -113,6 +113,8 @@ struct PhaseArgs {
     unsigned long long wait_ticks;
     // push-off (Sec. II.B): sig2 is the working diameter squared, ov2 = sig2 (1 - 1e-9)
     double ov2;
+    // 1: tile-joint partition (D^3-cell tiles at pitch D + 1, all in one phase)
+    int joint;
 };
 
 struct ObsArgs {

@@ -12,11 +12,12 @@ namespace {
 template <bool WHOLE>
 __global__ __launch_bounds__(64) void k_count(const PhaseArgs a) {
     int off[3];
-    partition_offsets(a, a.D, a.dstate[0], 0u, off);
+    partition_offsets(a, a.joint ? a.D + 1 : a.D, a.dstate[0], 0u, off);
     Frame f;
     int F;
     bool wraps;
-    frame_of<WHOLE>(a, a.colour, blockIdx.x, off, 0, f, F, wraps);
+    if (a.joint) frame_of<WHOLE, true>(a, a.colour, blockIdx.x, off, 0, f, F, wraps);
+    else frame_of<WHOLE>(a, a.colour, blockIdx.x, off, 0, f, F, wraps);
     const int S = frame_count(a, f, F);
     if (lane_id() == 0) a.dstage[blockIdx.x] = S;
 }

@@ -33,11 +33,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
     PhaseArgs b = a;
     b.sweep = a.dstate[0];
     int off[3];
-    partition_offsets(b, b.D, b.sweep, 0u, off);
+    partition_offsets(b, b.joint ? b.D + 1 : b.D, b.sweep, 0u, off);
     Frame f;
     int F;
     bool wraps;
-    frame_of<WHOLE>(b, b.colour, blockIdx.x, off, 0, f, F, wraps);
+    if (b.joint) frame_of<WHOLE, true>(b, b.colour, blockIdx.x, off, 0, f, F, wraps);
+    else frame_of<WHOLE>(b, b.colour, blockIdx.x, off, 0, f, F, wraps);
     // The count comes from k_count, taken before any tier of this phase ran: a block of
     // another tier may be rewriting this domain's cell lists, so a count read here could be
     // a half-updated one.  A domain outside this launch's tier belongs to another launch.

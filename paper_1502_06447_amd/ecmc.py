@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("ECMC_LIB") or os.path.join(_HERE, "libecmc.so")
 
 OK, E_ARG, E_OVERLAP, E_TETHER, E_BOX, E_CELL_OVERFLOW, E_STUCK, E_DEVICE, E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 PREC_FP64, PREC_MIXED = 0, 1
-TILING_WHOLE, TILING_CHECKER = 0, 1
+TILING_WHOLE, TILING_CHECKER, TILING_JOINT = 0, 1, 2
 SCHED_SWEEP, SCHED_PHASES = 0, 1
 EV_HS_LIFT, EV_TETHER_LIFT, EV_HS_REFLECT, EV_TETHER_REFLECT, EV_WALL, EV_END, EV_PERIOD, EV_CYCLE, EV_SWAP = range(9)
 

@@ -50,6 +50,7 @@ MUTANTS = {
     "push_no_ignore": ("    if (s->push && dpar * dpar + dperp2 < s->ov2) return 0; /* push-off: an overlapping pair */\n", ""),
     "push_start_all": ("if (!s->push || overlaps_any(s, list[i])) out[k++] = list[i];", "out[k++] = list[i];"),
     "push_margin": ("s->ov2 = s->sig2 * (1.0 - 1e-9);", "s->ov2 = s->sig2 * (1.0 + 1e-9);"),
+    "joint_moves": ("        if (((c[a] - dm->off[a]) % s->n + s->n) % s->n % dm->P >= dm->D) return 0;\n", ""),
     # equivalent mutants: no observable difference is expected
     # (W = 0 means every event between the two reflections had zero length, so the zero-length
     # cycle search ends the same EC a few steps later with the same positions)

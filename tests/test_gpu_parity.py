@@ -728,3 +728,27 @@ def test_c4_full_batch_sampled_melts_match_the_oracle():
         assert np.array_equal(pos[b0:b0 + nb], o.positions()), m
         assert np.array_equal(cells[b0:b0 + nb], o.cells()), m
         assert np.array_equal(img[b0:b0 + nb], o.images()), m
+
+
+# ------------------------------------------------------------------ tile-joint partition (Sec. II.A)
+@pytest.mark.parametrize("exact", [False, True])
+def test_tile_joint_c1_event_sequence_bit_exact(melt_c1, exact):
+    """The tile-joint partition on the 16 x 16 melt (n = 4, tiles of 1 cell at pitch 2: 8 tiles,
+    all at once; joints immotile): 4 sweeps of 256 ECs, every event as in the oracle, both
+    precisions."""
+    p, g, o = _pair(melt_c1, ecmc.TILING_JOINT, D=1, n_cells=4, precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
+    for s in range(4):
+        p.sweep(256, 10.0, 600 + s)
+    n, _ = _compare(g, o)
+    assert n > 2_000
+
+
+@pytest.mark.parametrize("D", [1, 2])
+def test_tile_joint_c2_dense_melt_bit_exact(melt_c2, D):
+    """Tile-joint on the 500 x 32 melt at eta = 0.45 (n = 18: pitch 2 with 1-cell tiles, 729 tiles;
+    pitch 3 with 2^3-cell tiles, 216 tiles), 2 sweeps of 16,000 ECs with ell = 20 sigma."""
+    p, g, o = _pair(melt_c2, ecmc.TILING_JOINT, D=D, n_cells=18, log=40_000_000)
+    for s in range(2):
+        p.sweep(16000, 20.0, 700 + s)
+    n, _ = _compare(g, o)
+    assert n > 100_000

@@ -1129,3 +1129,45 @@ def test_pair_correlation_of_uniform_points_is_one():
     assert np.all(np.abs(g[ok] - 1.0) < 5 * err + 1e-12), g
     assert abs(np.sum(h[10:]) / np.sum(0.5 * N * (N - 1) * 4 * np.pi / 3 * (np.linspace(0, 4, 41)[11:] ** 3
                                                                             - np.linspace(0, 4, 41)[10:-1] ** 3) / L ** 3) - 1) < 0.01
+
+
+# ------------------------------------------------------------------ tile-joint partition (Sec. II.A)
+@pytest.mark.parametrize("D,L", [(1, 9.0), (2, 9.0)])
+def test_tile_joint_dimer_bond_length_distribution(D, L):
+    """The tile-joint partition (tiles of D^3 cells at pitch D + 1, immotile joints between them,
+    all tiles at once) samples the isolated dimer's p(r) ~ r^2 on [sigma, b_max] like the other
+    schedules (n = 6 cells: pitch 2 with D = 1, pitch 3 with D = 2)."""
+    r = _dimer_samples(2, D, L, 12000, seed=31 + D)
+    assert r.min() >= 1.0 - 1e-10 and r.max() <= 1.4 + 1e-10
+    ks = _ks_uniform_r2(r[::5])
+    assert ks.pvalue > 1e-3, ks
+    mean_exact = 0.75 * (1.4 ** 4 - 1) / (1.4 ** 3 - 1)
+    blocks = r.reshape(120, 100).mean(axis=1)
+    assert abs(r.mean() - mean_exact) < 5 * blocks.std() / math.sqrt(len(blocks))
+
+
+@pytest.mark.parametrize("D", [1, 2])
+def test_tile_joint_sweep_leaves_the_joints_alone(D):
+    """One tile-joint sweep of the 500 x 32 melt on 18^3 cells: beads in joint cells (the cell
+    after each tile along any axis, from the sweep's offsets (0, 0, sweep, 1)) keep their
+    positions, cells and images bit for bit, every tile bead stays in its tile, and many tile
+    beads move."""
+    from tests.test_oracle_pins import _philox_py
+    m = inputs.lattice_chains(500, 32, 0.45, seed=2)
+    o = oracle.Oracle.from_melt(m, n_cells=18)
+    P, n = D + 1, 18
+    c0, p0, i0 = o.cells(), o.positions(), o.images()
+    o.sweep(m.n_beads, 20.0, 44, tiling=2, D=D)
+    u = _philox_py([0, 0, 0, 1], [44, 0])
+    off = np.array([(u[a] * P) >> 32 for a in range(3)])
+    t = (c0 - off) % n
+    joint = np.any(t % P == D, axis=1)
+    assert joint.sum() > 1000 and (~joint).sum() > 1000
+    c1, p1 = o.cells(), o.positions()
+    assert np.array_equal(p1[joint], p0[joint]) and np.array_equal(c1[joint], c0[joint])
+    assert np.array_equal(o.images()[joint], i0[joint])
+    assert np.array_equal(((c1 - off) % n)[~joint] // P, t[~joint] // P)
+    assert np.all(((c1 - off) % n)[~joint] % P < D)
+    assert np.count_nonzero(np.any(p1[~joint] != p0[~joint], axis=1)) > 1000
+    with pytest.raises(oracle.OracleError):
+        o.sweep(10, 1.0, 1, tiling=2, D=4)  # pitch 5 does not divide 18
