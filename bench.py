@@ -364,6 +364,14 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def workload_of(args) -> dict:
+    """The workload's parameters with the partition chosen on the command line."""
+    w = dict(WORKLOADS[args.workload], tiling=2 if args.tiling == "joint" else 1)
+    if args.domain_cells > 0:
+        w["D"] = args.domain_cells
+    return w
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -380,6 +388,8 @@ def main():
     ap.add_argument("--tiling", default="checker", choices=("checker", "joint"),
                     help="checker: D^3-cell domains in 8 colour phases (default); joint: the tile-joint "
                          "partition (D^3-cell tiles at pitch D + 1 with immotile joints, one phase)")
+    ap.add_argument("--domain-cells", type=int, default=0, metavar="D",
+                    help="domain (checkerboard) or tile (tile-joint) edge in cells; 0 = the workload's (2)")
     ap.add_argument("--spring-cap", type=float, default=1.8, metavar="B",
                     help="with --springs: bond length cap in sigma (cells get an edge > B)")
     ap.add_argument("--no-precision-check", action="store_true",
@@ -404,14 +414,13 @@ def main():
     all_cores = None
     if not args.no_cpu_baseline:
         # the all-cores oracle leg runs first, in forked workers, before this process touches the GPU
-        all_cores = cpu_baseline_all_cores(dict(WORKLOADS[args.workload], tiling=2 if args.tiling == "joint" else 1),
-                                           spring_k=args.springs, b_max=b_max)
+        all_cores = cpu_baseline_all_cores(workload_of(args), spring_k=args.springs, b_max=b_max)
 
     import numpy as np
     import torch
     from paper_1502_06447_amd import ecmc, inputs
 
-    w = dict(WORKLOADS[args.workload], tiling=2 if args.tiling == "joint" else 1)
+    w = workload_of(args)
     torch.cuda.set_device(0)
     if args.copy_probe > 0:
         nbytes = args.copy_probe << 20
