@@ -752,3 +752,26 @@ def test_tile_joint_c2_dense_melt_bit_exact(melt_c2, D):
         p.sweep(16000, 20.0, 700 + s)
     n, _ = _compare(g, o)
     assert n > 100_000
+
+
+# ------------------------------------------------------------------ statistics on the GPU
+@pytest.mark.parametrize("eta,n_beads", [(0.10, 500), (0.20, 500)])
+def test_gpu_pressure_from_lifts_matches_carnahan_starling(eta, n_beads):
+    """Unbonded spheres in whole-box mode on the GPU: beta P / rho = 1 + <sum of lift separations
+    along v> / ell (the event-chain pressure estimator) against Carnahan-Starling, within 2 %
+    (500 spheres, 400 sweeps of 500 ECs with ell = 4 sigma after 20 melting sweeps)."""
+    cs = (1 + eta + eta ** 2 - eta ** 3) / (1 - eta) ** 3
+    m = inputs.hs_fluid(n_beads, eta, seed=3)
+    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_WHOLE))
+    ell = 4.0
+    for s in range(20):
+        g.sweep(n_beads, ell, 50 + s)
+    g.synchronize()
+    c0 = g.counters()
+    for s in range(400):
+        g.sweep(n_beads, ell, 500 + s)
+    g.synchronize()
+    c1 = g.counters()
+    n_ec = c1["ec"] - c0["ec"]
+    Z = 1 + (c1["sum_delta"] - c0["sum_delta"]) / (n_ec * ell)
+    assert abs(Z - cs) / cs < 0.02, (Z, cs)

@@ -1171,3 +1171,25 @@ def test_tile_joint_sweep_leaves_the_joints_alone(D):
     assert np.count_nonzero(np.any(p1[~joint] != p0[~joint], axis=1)) > 1000
     with pytest.raises(oracle.OracleError):
         o.sweep(10, 1.0, 1, tiling=2, D=4)  # pitch 5 does not divide 18
+
+
+def test_end_to_end_distribution_of_long_random_walks_is_gaussian():
+    """W(R) of long ideal chains (the appendix's Gaussian end-to-end distribution): 2,000
+    freely jointed chains of 100 unit bonds (phantom walks with c = 1, i.e. no angle
+    restriction) binned by the oracle against 4 pi R^2 (3 / (2 pi n))^(3/2) exp(-3 R^2 / (2 n))
+    integrated over each bin; chi-square over the bins expecting at least 5 chains."""
+    from scipy import integrate, stats
+    M, N = 2000, 101
+    m = inputs.phantom_chains(M, N, 0.05, seed=13, c=1.0)
+    o = oracle.Oracle(m.L, 1e-3, 1.4, m.positions, m.bonds, overlapping=True)
+    nb, rmax = 30, 30.0
+    h = o.end_to_end_histogram(nb, rmax)
+    n = N - 1
+    w = lambda R: 4 * math.pi * R * R * (3 / (2 * math.pi * n)) ** 1.5 * math.exp(-3 * R * R / (2 * n))
+    edges = np.linspace(0, rmax, nb + 1)
+    p = np.array([integrate.quad(w, edges[k], edges[k + 1])[0] for k in range(nb)])
+    p[-1] += integrate.quad(w, rmax, np.inf)[0]  # the last bin also holds |R| >= r_max
+    e = M * p
+    ok = e >= 5
+    chi2 = float(np.sum((h[ok] - e[ok]) ** 2 / e[ok]))
+    assert stats.chi2.sf(chi2, ok.sum() - 1) > 1e-3, (chi2, ok.sum())
