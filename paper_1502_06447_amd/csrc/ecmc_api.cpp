@@ -1309,10 +1309,14 @@ ecmc_status policy_descs(int32_t n_melts, const ecmc_melt_desc *melts, double lm
 // workspace slots, so a tier below the largest melts' frames trades their speed for that of
 // the rest.
 std::vector<int> tier_candidates(double typical) {
+    // from the tier that holds the typical frame with three standard deviations of its bead count
+    // to spare (as the automatic staging capacity does): below it a large share of the domains
+    // runs from workspace slots, which is many times slower
     static const int tiers[] = {64, 128, 192, 256, 384, 512};
+    const double need = typical + 3.0 * std::sqrt(typical);
     std::vector<int> out;
     for (int t : tiers)
-        if (t >= typical && out.size() < 4) out.push_back(t);
+        if (t >= need && out.size() < 4) out.push_back(t);
     if (out.empty()) out.push_back(512);
     return out;
 }
