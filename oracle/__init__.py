@@ -84,6 +84,8 @@ def lib():
         L.orc_pair_histogram.restype = ctypes.c_int
         L.orc_end_to_end_histogram.argtypes = [vp, ctypes.c_int, dbl, vp]
         L.orc_end_to_end_histogram.restype = ctypes.c_int
+        L.orc_internal_distances.argtypes = [vp, i64, vp, vp]
+        L.orc_internal_distances.restype = ctypes.c_int
         L.orc_gyration.argtypes = [vp, i64, vp]
         L.orc_gyration.restype = None
         L.orc_shape.argtypes = [vp, vp, vp]
@@ -296,6 +298,18 @@ class Oracle:
         if st != OK:
             raise OracleError(st, "orc_end_to_end_histogram")
         return h
+
+    def internal_distances(self, n_max: int) -> tuple[np.ndarray, np.ndarray]:
+        """R^2(n) of Sec. II.B: the mean squared chain vector between two beads of one polymer n
+        bonds apart (summed bond by bond), over all such pairs, for n = 0..n_max, and the number of
+        pairs behind each mean (a mean with no pairs is 0)."""
+        n_max = int(n_max)
+        s = np.zeros(n_max + 1)
+        c = np.zeros(n_max + 1, dtype=np.int64)
+        st = lib().orc_internal_distances(self._h, n_max, s.ctypes.data, c.ctypes.data)
+        if st != OK:
+            raise OracleError(st, "orc_internal_distances")
+        return np.divide(s, c, out=np.zeros_like(s), where=c > 0), c
 
     def snapshot(self) -> np.ndarray:
         """Per polymer: the middle bead floor(N/2) and the centre of mass, both image-unwrapped,

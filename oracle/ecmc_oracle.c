@@ -1224,6 +1224,36 @@ int orc_end_to_end_histogram(const orc_sys *s, int nbins, double rmax, int64_t *
     return ORC_OK;
 }
 
+/* Internal distances R^2(n) (Sec. II.B, the check of start configurations against a long run):
+ * for every polymer and every pair of its beads t < t' with t' - t = n <= n_max, the squared
+ * length of the chain vector from bead t to bead t', which is the sum of the minimum-image bond
+ * vectors between them, walked bond by bond from t.  sum[n] adds these squared lengths and
+ * count[n] counts the pairs; n = 0 counts every bead once with length 0. */
+int orc_internal_distances(const orc_sys *s, int64_t n_max, double *sum, int64_t *count) {
+    if (n_max < 0) return ORC_E_ARG;
+    for (int64_t n = 0; n <= n_max; ++n) {
+        sum[n] = 0.0;
+        count[n] = 0;
+    }
+    for (int64_t q = 0; q < s->npoly; ++q) {
+        const int64_t a = s->pstart[q], e = s->pstart[q + 1];
+        for (int64_t t = a; t < e; ++t) {
+            count[0]++;
+            double R[3] = {0.0, 0.0, 0.0};
+            for (int64_t t2 = t + 1; t2 < e && t2 - t <= n_max; ++t2) {
+                const int32_t i0 = s->porder[t2 - 1], i1 = s->porder[t2];
+                for (int k = 0; k < 3; ++k) R[k] += mi(s, s->r[3 * i1 + k] - s->r[3 * i0 + k]);
+                const double q0 = R[0] * R[0];
+                const double q1 = R[1] * R[1];
+                const double q2 = R[2] * R[2];
+                sum[t2 - t] += (q0 + q1) + q2;
+                count[t2 - t]++;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
 /* ---------------------------------------------------------------- accessors */
 int64_t orc_n_beads(const orc_sys *s) { return s->nb; }
 int orc_n_cells(const orc_sys *s) { return s->n; }

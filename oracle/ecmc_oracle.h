@@ -150,6 +150,8 @@ int orc_pair_histogram(const orc_sys *s, int nbins, double rmax, int64_t *hist);
 /* End-to-end distance distribution W(R): histogram over polymers of |R|, bins of width
  * r_max / nbins from 0, values at or above r_max counted in the last bin. */
 int orc_end_to_end_histogram(const orc_sys *s, int nbins, double rmax, int64_t *hist);
+/* R^2(n): sums of squared chain vectors between beads n bonds apart, and their counts, n = 0..n_max */
+int orc_internal_distances(const orc_sys *s, int64_t n_max, double *sum, int64_t *count);
 
 int64_t orc_n_beads(const orc_sys *s);
 int orc_n_cells(const orc_sys *s);

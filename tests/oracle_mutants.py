@@ -46,6 +46,10 @@ MUTANTS = {
                    "for (int64_t j = 0; j < s->nb; ++j) {\n            if (j == i) continue;"),
     "pair_no_image": ("for (int a = 0; a < 3; ++a) d[a] = mi(s, s->r[3 * j + a] - s->r[3 * i + a]);\n            const double q0",
                       "for (int a = 0; a < 3; ++a) d[a] = s->r[3 * j + a] - s->r[3 * i + a];\n            const double q0"),
+    "r2n_lag_shift": ("sum[t2 - t] += (q0 + q1) + q2;", "sum[t2 - t - 1] += (q0 + q1) + q2;"),
+    "r2n_no_image": ("for (int k = 0; k < 3; ++k) R[k] += mi(s, s->r[3 * i1 + k] - s->r[3 * i0 + k]);",
+                     "for (int k = 0; k < 3; ++k) R[k] += s->r[3 * i1 + k] - s->r[3 * i0 + k];"),
+    "r2n_drop_z": ("sum[t2 - t] += (q0 + q1) + q2;", "sum[t2 - t] += q0 + q1;"),
     "e2e_squared": ("floor(sqrt(r2[q]) / rmax * (double)nbins)", "floor(r2[q] / rmax * (double)nbins)"),
     "push_no_ignore": ("    if (s->push && dpar * dpar + dperp2 < s->ov2) return 0; /* push-off: an overlapping pair */\n", ""),
     "push_start_all": ("if (!s->push || overlaps_any(s, list[i])) out[k++] = list[i];", "out[k++] = list[i];"),
