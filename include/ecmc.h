@@ -317,6 +317,16 @@ ecmc_status ecmc_msd(ecmc_ctx *ctx, const double *snaps_device, int64_t T, doubl
  * nbins in [1, 1024].  Synchronises. */
 ecmc_status ecmc_end_to_end_histogram(ecmc_ctx *ctx, int32_t nbins, double r_max, int64_t *hist);
 
+/* Internal distances R^2(n) (Sec. II.B, where start configurations are checked against a long
+ * run through R^2(n)/n): for n = 0..n_max, the mean over every pair of beads of one polymer that
+ * are n bonds apart (all polymers, all melts of a batch) of the squared chain vector between
+ * them, the sum of the minimum-image bond vectors in between.  Host r2 [n_max + 1] receives the
+ * means (0 where no pair exists), host pairs [n_max + 1] (or null) the number of pairs behind
+ * each (sum over chains of max(N - n, 0)).  n_max in [0, 2047]; chains of at most 2048 beads.
+ * The sums are taken per block in a fixed order, so a state gives the same result on every
+ * call.  Synchronises. */
+ecmc_status ecmc_internal_distances(ecmc_ctx *ctx, int32_t n_max, double *r2, int64_t *pairs);
+
 /* Pair counts behind the pair correlation g(r): the pairs i < j of one melt (summed over the
  * melts of a batch) whose minimum-image distance r is below r_max, binned by
  * floor(r / r_max * nbins) (clamped to nbins - 1).  r_max may not exceed the smallest cell

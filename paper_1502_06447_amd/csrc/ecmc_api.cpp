@@ -54,7 +54,7 @@ struct Plan {
 
 struct Layout {
     size_t px, py, pz, cellp, img, part, ccount, cids, dstage, done, queue, dstate, slow_lock, slow, melts, porder,
-        pstart, polyL, r2, rg2, mid, shape, hist, cnt, dsum, err, log_n, log;
+        pstart, polyL, r2, rg2, mid, shape, hist, lags, cnt, dsum, err, log_n, log;
     size_t total;
 };
 
@@ -92,6 +92,9 @@ Layout make_layout(const Plan &p, int64_t npoly_max, int cap, int64_t log_cap) {
     l.mid = take(24 * np);
     l.shape = take(96 * np);  // gyration tensor, eigenvalues, centre of mass: 12 doubles per polymer
     l.hist = take(8 * MAX_BINS);
+    // internal distances: a row of per-lag sums per block, then the total
+    l.lags = take(8 * (size_t)(std::min<int64_t>(npoly_max, LAG_BLOCKS) + 1) *
+                  (size_t)std::min<int64_t>(std::max<int64_t>(p.nb, 1), LAG_MAX_BEADS));
     l.cnt = take(8 * NCNT);
     l.dsum = take(8);
     l.err = take(4);
@@ -110,6 +113,7 @@ struct ecmc_ctx {
     hipEvent_t fork = nullptr, join = nullptr;
     double sigma = 0, lmax = 0, sig2 = 0, b2 = 0;
     int64_t nb = 0, npoly = 0;
+    std::vector<int64_t> chain_count;  // polymers per chain length (index = beads)
     Plan p;
     int cap = DEFAULT_CAP;
     Layout lay{};
@@ -607,6 +611,11 @@ ecmc_status init_impl(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *mel
     c->npoly = (int64_t)hs.pstart.size();
     if (c->npoly > npoly_layout) return bail(fail(c, ECMC_E_ARG, "more polymers than the layout holds"));
     hs.pstart.push_back((int32_t)nb);
+    for (int64_t q = 0; q < c->npoly; ++q) {
+        const size_t len = (size_t)(hs.pstart[q + 1] - hs.pstart[q]);
+        if (c->chain_count.size() <= len) c->chain_count.resize(len + 1, 0);
+        c->chain_count[len]++;
+    }
     if ((st = upload(c, hs, true))) return bail(st);
     *out = c;
     return ECMC_OK;
@@ -1012,6 +1021,40 @@ ecmc_status ecmc_end_to_end_histogram(ecmc_ctx *c, int32_t nbins, double r_max, 
     ecmc_status st = check_device(c);
     if (st) return st;
     HIP_OK(c, hipMemcpy(hist, o.rhist, 8 * nbins, hipMemcpyDeviceToHost));
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_internal_distances(ecmc_ctx *c, int32_t n_max, double *r2, int64_t *pairs) {
+    if (!c || !r2) return fail(c, ECMC_E_ARG, "null argument");
+    if (n_max < 0 || n_max >= LAG_MAX_BEADS) return fail(c, ECMC_E_ARG, "n_max must be in [0, %d]", LAG_MAX_BEADS - 1);
+    const int64_t longest = (int64_t)c->chain_count.size() - 1;
+    if (longest > LAG_MAX_BEADS)
+        return fail(c, ECMC_E_ARG, "internal distances take chains of at most %d beads (the longest has %lld)",
+                    LAG_MAX_BEADS, (long long)longest);
+    if (longest < 1) {  // no beads
+        for (int32_t n = 0; n <= n_max; ++n) {
+            r2[n] = 0.0;
+            if (pairs) pairs[n] = 0;
+        }
+        return ECMC_OK;
+    }
+    const int nlag = (int)std::min<int64_t>(n_max, longest - 1) + 1;
+    const int rows = (int)std::min<int64_t>(c->npoly, LAG_BLOCKS);
+    ObsArgs o = obs_args(c);
+    o.nlag = nlag;
+    o.lagsum = c->dev<double>(c->lay.lags);
+    HIP_OK(c, launch_internal(o, rows, c->stream));
+    ecmc_status st = check_device(c);
+    if (st) return st;
+    std::vector<double> total(nlag);
+    HIP_OK(c, hipMemcpy(total.data(), o.lagsum + (size_t)rows * nlag, 8 * (size_t)nlag, hipMemcpyDeviceToHost));
+    for (int32_t n = 0; n <= n_max; ++n) {
+        // pairs n bonds apart: max(N - n, 0) in a chain of N beads
+        int64_t cnt = 0;
+        for (size_t len = (size_t)n + 1; len < c->chain_count.size(); ++len) cnt += c->chain_count[len] * ((int64_t)len - n);
+        r2[n] = n < nlag && cnt > 0 ? total[n] / (double)cnt : 0.0;
+        if (pairs) pairs[n] = cnt;
+    }
     return ECMC_OK;
 }
 

@@ -354,6 +354,88 @@ __global__ __launch_bounds__(MSD_THREADS) void k_msd(const double *snaps, long l
     }
 }
 
+// ------------------------------------------------------------------ internal distances
+// R^2(n) of the start-configuration check (Sec. II.B): block b takes polymers b, b + G, ... in
+// turn.  Wave 0 unwraps the chain into LDS as prefix sums of minimum-image bond vectors (as
+// k_observables does); thread t then owns the lags t + 1 + 256 k and adds |u_{i+n} - u_i|^2
+// over i for each (lanes read consecutive u_{i+n}, u_i is a broadcast).  Each block writes its
+// per-lag sums as row b of a [G][nlag] array and k_lag_total adds the rows in block order, so
+// the result does not depend on timing.
+constexpr int LAG_THREADS = 256;
+constexpr int LAGS_PER_THREAD = LAG_MAX_BEADS / LAG_THREADS;
+
+__global__ __launch_bounds__(LAG_THREADS) void k_internal(const ObsArgs a) {
+    __shared__ double ux[LAG_MAX_BEADS], uy[LAG_MAX_BEADS], uz[LAG_MAX_BEADS];
+    const int tid = (int)threadIdx.x;
+    double acc[LAGS_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < LAGS_PER_THREAD; ++k) acc[k] = 0.0;
+    for (int64_t q = blockIdx.x; q < a.npoly; q += gridDim.x) {
+        const double L = a.polyL[q], halfL = 0.5 * L;
+        auto mi = [&](double d) { return d > halfL ? d - L : (d < -halfL ? d + L : d); };
+        const int64_t s = a.pstart[q];
+        const int N = (int)(a.pstart[q + 1] - s);  // at most LAG_MAX_BEADS (checked by the host)
+        if (tid < 64) {
+            double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+            for (int base = 0; base < N; base += 64) {
+                const int t = base + tid;
+                double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+                if (t < N && t > 0) {
+                    const int ia = a.porder[s + t - 1], ib = a.porder[s + t];
+                    d0 = mi(a.px[ib] - a.px[ia]);
+                    d1 = mi(a.py[ib] - a.py[ia]);
+                    d2 = mi(a.pz[ib] - a.pz[ia]);
+                }
+                const double u0 = c0 + wave_scan_f64(d0);
+                const double u1 = c1 + wave_scan_f64(d1);
+                const double u2 = c2 + wave_scan_f64(d2);
+                if (t < N) {
+                    ux[t] = u0;
+                    uy[t] = u1;
+                    uz[t] = u2;
+                }
+                c0 = rdlane(u0, 63);
+                c1 = rdlane(u1, 63);
+                c2 = rdlane(u2, 63);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < LAGS_PER_THREAD; ++k) {
+            const int n = tid + 1 + k * LAG_THREADS;
+            if (n < N && n < a.nlag) {
+                double sum = 0.0;
+                for (int i = 0; i + n < N; ++i) {
+                    const double d0 = ux[i + n] - ux[i];
+                    const double d1 = uy[i + n] - uy[i];
+                    const double d2 = uz[i + n] - uz[i];
+                    const double q0 = d0 * d0;
+                    const double q1 = d1 * d1;
+                    const double q2 = d2 * d2;
+                    sum += (q0 + q1) + q2;
+                }
+                acc[k] += sum;
+            }
+        }
+        __syncthreads();
+    }
+    double *row = a.lagsum + (int64_t)blockIdx.x * a.nlag;
+#pragma unroll
+    for (int k = 0; k < LAGS_PER_THREAD; ++k) {
+        const int n = tid + 1 + k * LAG_THREADS;
+        if (n < a.nlag) row[n] = acc[k];
+    }
+    if (tid == 0) row[0] = 0.0;
+}
+
+__global__ __launch_bounds__(LAG_THREADS) void k_lag_total(double *lagsum, int rows, int nlag) {
+    const int n = (int)(blockIdx.x * LAG_THREADS + threadIdx.x);
+    if (n >= nlag) return;
+    double sum = 0.0;
+    for (int b = 0; b < rows; ++b) sum += lagsum[(int64_t)b * nlag + n];
+    lagsum[(int64_t)rows * nlag + n] = sum;
+}
+
 }  // namespace
 
 bool bpl_supported(int bpl) {
@@ -395,6 +477,15 @@ hipError_t launch_msd(const double *snaps, int64_t T, int64_t npoly, double *out
     if (T <= 0) return hipSuccess;
     if (T > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_msd, dim3((unsigned)T), dim3(MSD_THREADS), 0, s, snaps, (long long)T, (long long)npoly, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_internal(const ObsArgs &a, int rows, hipStream_t s) {
+    if (a.npoly <= 0 || a.nlag < 1) return hipSuccess;
+    if (a.nlag > LAG_MAX_BEADS || rows < 1 || rows > LAG_BLOCKS || rows > a.npoly) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_internal, dim3((unsigned)rows), dim3(LAG_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_lag_total, dim3((unsigned)((a.nlag + LAG_THREADS - 1) / LAG_THREADS)), dim3(LAG_THREADS), 0, s,
+                       a.lagsum, rows, a.nlag);
     return hipGetLastError();
 }
 

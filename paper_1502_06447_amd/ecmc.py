@@ -109,7 +109,7 @@ EXPORTS = (
     "ecmc_stage_capacity", "ecmc_destroy", "ecmc_status_str", "ecmc_last_error",
     "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
     "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
-    "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff",
+    "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff", "ecmc_internal_distances",
 )
 
 
@@ -141,6 +141,7 @@ def lib():
         "ecmc_msd": (st, [vp, vp, i64, vp]),
         "ecmc_end_to_end_histogram": (st, [vp, i32, dbl, vp]),
         "ecmc_pair_histogram": (st, [vp, i32, dbl, vp]),
+        "ecmc_internal_distances": (st, [vp, i32, vp, vp]),
         "ecmc_pushoff_sweep": (st, [vp, i64, dbl, u64, dbl]),
         "ecmc_count_overlaps": (st, [vp, dbl, P(i64)]),
         "ecmc_pushoff": (st, [vp, dbl, i32, dbl, u64, i64, P(i64), P(i64)]),
@@ -526,6 +527,15 @@ class Melt:
         _check(lib().ecmc_end_to_end_histogram(self.ctx, int(nbins), float(r_max), h.ctypes.data),
                "ecmc_end_to_end_histogram", self.ctx)
         return h
+
+    def internal_distances(self, n_max: int) -> tuple[np.ndarray, np.ndarray]:
+        """R^2(n) of Sec. II.B for n = 0..n_max: the mean squared chain vector between beads of
+        one polymer n bonds apart, over all such pairs, and the number of pairs behind each."""
+        r2 = np.zeros(int(n_max) + 1)
+        pairs = np.zeros(int(n_max) + 1, dtype=np.int64)
+        _check(lib().ecmc_internal_distances(self.ctx, int(n_max), r2.ctypes.data, pairs.ctypes.data),
+               "ecmc_internal_distances", self.ctx)
+        return r2, pairs
 
     def pair_histogram(self, nbins: int, r_max: float) -> np.ndarray:
         """Pair counts behind g(r): pairs i < j of a melt with r < r_max (<= the cell edge)."""

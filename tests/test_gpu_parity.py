@@ -639,6 +639,75 @@ def test_end_to_end_and_pair_histograms_match_the_oracle(melt_c2):
         g.pair_histogram(10, 1.01 * g.h)
 
 
+# Internal distances R^2(n): the GPU sums squares of differences of prefix sums of the bond
+# vectors, blockwise; the oracle walks every pair bond by bond.  Both are FP64 and round
+# differently.  With unit roundoff u = 2^-53, chains of N beads with bonds below 1.4 and
+# |R| >= sigma = 1 for n >= 1, a prefix sum is off by at most N^2 * 1.4 u, which puts a relative
+# error below 2 * 2 N^2 * 1.4 u on a squared length (N = 64: 2.5e-12); the sum of m positive
+# terms adds at most m u on either side (m = 16,000 at the 500 x 32 melt: 1.8e-12).  The
+# tests use 1e-11 below 20,000 pairs per lag, and m u + 1e-11 above.
+def _r2n_tol(pairs):
+    return 1e-11 + pairs.max() * 2.0 ** -53
+
+
+def test_internal_distances_match_the_oracle(melt_c2):
+    """R^2(n) for n = 0..40 (past the 32-bead chains) after three sweeps of the 500 x 32 melt,
+    against the oracle in the same state: identical pair counts, means to the rounding bound,
+    zeros beyond the chains, and the same result on a second call (a fixed summation order)."""
+    p, g, o = _pair(melt_c2, ecmc.TILING_CHECKER, D=2, n_cells=16, log=0)
+    for s in range(3):
+        p.sweep(16000, 20.0, 970 + s)
+    g.synchronize()
+    r2, cnt = g.internal_distances(40)
+    r2o, cnto = o.internal_distances(40)
+    assert np.array_equal(cnt, cnto) and np.array_equal(cnt[:32], 500 * (32 - np.arange(32)))
+    assert np.allclose(r2, r2o, rtol=_r2n_tol(cnt), atol=0), np.abs(r2 / np.where(r2o > 0, r2o, 1) - 1).max()
+    assert r2[0] == 0.0 and np.all(r2[32:] == 0.0) and 1.0 <= r2[1] <= 1.4 ** 2  # n = 1: bonds in [sigma, b_max]
+    r2b, _ = g.internal_distances(40)
+    assert np.array_equal(r2, r2b)
+    assert g.internal_distances(0)[0][0] == 0.0
+    with pytest.raises(ecmc.EcmcError):
+        g.internal_distances(2048)
+
+
+def test_internal_distances_of_a_batch_match_the_oracle(small_batch):
+    """A batch of four melts with chains of 16 to 64 beads, each in its own box: the GPU's
+    R^2(n) over the whole batch equals the pair-weighted mean of the oracle's per-melt results."""
+    g = ecmc.Melt.from_batch(small_batch, ecmc.Options())
+    g.sweep(g.n_beads, 20.0, 990)
+    g.synchronize()
+    r2, cnt = g.internal_distances(70)
+    pos = g.positions()
+    tot, ctot, b0 = np.zeros(71), np.zeros(71, dtype=np.int64), 0
+    for m, melt in enumerate(small_batch):
+        info = g.melt_info(m)
+        nb = info["n_beads"]
+        o = oracle.Oracle.from_melt(melt, n_cells=info["n_cells"])
+        o.set_stream(m)
+        o.sweep(-(-g.n_beads // sum(g.melt_info(k)["n_domains"] for k in range(g.n_melts))) * info["n_domains"],
+                20.0, 990, tiling=1, D=info["domain_cells"])
+        assert np.array_equal(pos[b0:b0 + nb], o.positions()), m
+        r, c = o.internal_distances(70)
+        tot += r * c
+        ctot += c
+        b0 += nb
+    assert np.array_equal(cnt, ctot)
+    want = np.divide(tot, ctot, out=np.zeros_like(tot), where=ctot > 0)
+    assert np.allclose(r2, want, rtol=_r2n_tol(cnt), atol=0)
+    assert np.all(r2[64:] == 0.0)
+
+
+def test_internal_distances_c3_full_size(melt_c3):
+    """The 1,048,576-bead benchmark melt (16,384 chains of 64) in its start state, chains wrapped
+    through the box: R^2(n) for every n against the oracle on the whole melt."""
+    g = ecmc.Melt.from_melt(melt_c3, ecmc.Options())
+    r2, cnt = g.internal_distances(63)
+    o = oracle.Oracle.from_melt(melt_c3, n_cells=g.n_cells)
+    r2o, cnto = o.internal_distances(63)
+    assert np.array_equal(cnt, cnto) and cnt[63] == 16384
+    assert np.allclose(r2, r2o, rtol=_r2n_tol(cnt), atol=0), np.abs(r2[1:] / r2o[1:] - 1).max()
+
+
 # ------------------------------------------------------------------ push-off (Sec. II.B)
 def _pushoff_pair(melt, n, log=4_000_000):
     g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=n, cell_capacity=32,
