@@ -56,6 +56,7 @@ struct Layout {
     size_t px, py, pz, cellp, img, part, ccount, cids, dstage, done, queue, dstate, slow_lock, slow, melts, porder,
         pstart, polyL, r2, rg2, mid, shape, hist, lags, cnt, dsum, err, log_n, log;
     size_t total;
+    int64_t lag_slots;  // partial sums the internal-distance area holds (blocks x lags)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -92,9 +93,10 @@ Layout make_layout(const Plan &p, int64_t npoly_max, int cap, int64_t log_cap) {
     l.mid = take(24 * np);
     l.shape = take(96 * np);  // gyration tensor, eigenvalues, centre of mass: 12 doubles per polymer
     l.hist = take(8 * MAX_BINS);
-    // internal distances: a row of per-lag sums per block, then the total
-    l.lags = take(8 * (size_t)(std::min<int64_t>(npoly_max, LAG_BLOCKS) + 1) *
-                  (size_t)std::min<int64_t>(std::max<int64_t>(p.nb, 1), LAG_MAX_BEADS));
+    // internal distances: per-block partial sums of every lag, then the totals
+    const int64_t lag_max = std::min<int64_t>(std::max<int64_t>(p.nb, 1), LAG_MAX_BEADS);
+    l.lag_slots = std::min<int64_t>(LAG_SLOTS, std::max<int64_t>(npoly_max, 1) * lag_max);
+    l.lags = take(8 * (size_t)(l.lag_slots + lag_max));
     l.cnt = take(8 * NCNT);
     l.dsum = take(8);
     l.err = take(4);
@@ -1039,11 +1041,12 @@ ecmc_status ecmc_internal_distances(ecmc_ctx *c, int32_t n_max, double *r2, int6
         return ECMC_OK;
     }
     const int nlag = (int)std::min<int64_t>(n_max, longest - 1) + 1;
-    const int rows = (int)std::min<int64_t>(c->npoly, LAG_BLOCKS);
+    // one polymer per block while the partial sums fit
+    const int rows = (int)std::min<int64_t>(c->npoly, c->lay.lag_slots / nlag);
     ObsArgs o = obs_args(c);
     o.nlag = nlag;
     o.lagsum = c->dev<double>(c->lay.lags);
-    HIP_OK(c, launch_internal(o, rows, c->stream));
+    HIP_OK(c, launch_internal(o, rows, (int)longest, c->stream));
     ecmc_status st = check_device(c);
     if (st) return st;
     std::vector<double> total(nlag);

@@ -134,11 +134,12 @@ struct ObsArgs {
     int rbins;
     double rmax;
     int nlag;                  // internal distances: lags 0..nlag-1
-    double *lagsum;            // [rows + 1][nlag] per-block sums, then their total
+    double *lagsum;            // [nlag][rows] per-block sums, then [nlag] their totals
 };
 
-// internal distances: blocks of the per-lag sums, and the longest chain they take
-constexpr int LAG_BLOCKS = 512;
+// internal distances: room for the per-block partial sums (blocks x lags), and the longest
+// chain they take
+constexpr int LAG_SLOTS = 1 << 20;
 constexpr int LAG_MAX_BEADS = 2048;
 
 // Pair counts behind g(r): every pair of one melt closer than rmax (at most a cell edge).
@@ -170,7 +171,7 @@ hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
 hipError_t launch_shape(const ObsArgs &a, hipStream_t s);
 hipError_t launch_pairs(const PairArgs &a, hipStream_t s);
 hipError_t launch_msd(const double *snaps, int64_t T, int64_t npoly, double *out, hipStream_t s);
-hipError_t launch_internal(const ObsArgs &a, int rows, hipStream_t s);
+hipError_t launch_internal(const ObsArgs &a, int rows, int longest, hipStream_t s);
 bool bpl_supported(int bpl);
 
 }  // namespace ecmc

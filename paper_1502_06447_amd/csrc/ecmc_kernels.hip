@@ -356,25 +356,24 @@ __global__ __launch_bounds__(MSD_THREADS) void k_msd(const double *snaps, long l
 
 // ------------------------------------------------------------------ internal distances
 // R^2(n) of the start-configuration check (Sec. II.B): block b takes polymers b, b + G, ... in
-// turn.  Wave 0 unwraps the chain into LDS as prefix sums of minimum-image bond vectors (as
-// k_observables does); thread t then owns the lags t + 1 + 256 k and adds |u_{i+n} - u_i|^2
-// over i for each (lanes read consecutive u_{i+n}, u_i is a broadcast).  Each block writes its
-// per-lag sums as row b of a [G][nlag] array and k_lag_total adds the rows in block order, so
-// the result does not depend on timing.
+// turn.  Wave 0 unwraps the chain into LDS (sized for the longest chain) as prefix sums of
+// minimum-image bond vectors, as k_observables does; thread t then owns the lags t + 1 + T j
+// (T threads, a multiple of 64 covering the lags) and adds |u_{i+n} - u_i|^2 over i for each
+// into its own LDS slot (lanes read consecutive u_{i+n}, u_i is a broadcast).  Block b writes
+// its sum for lag n to lagsum[n G + b]; k_lag_total then adds each lag's G partial sums in a
+// fixed tree, so the result does not depend on timing.
 constexpr int LAG_THREADS = 256;
-constexpr int LAGS_PER_THREAD = LAG_MAX_BEADS / LAG_THREADS;
 
-__global__ __launch_bounds__(LAG_THREADS) void k_internal(const ObsArgs a) {
-    __shared__ double ux[LAG_MAX_BEADS], uy[LAG_MAX_BEADS], uz[LAG_MAX_BEADS];
-    const int tid = (int)threadIdx.x;
-    double acc[LAGS_PER_THREAD];
-#pragma unroll
-    for (int k = 0; k < LAGS_PER_THREAD; ++k) acc[k] = 0.0;
+__global__ __launch_bounds__(LAG_THREADS) void k_internal(const ObsArgs a, int stride) {
+    extern __shared__ double lag_lds[];
+    double *ux = lag_lds, *uy = lag_lds + stride, *uz = lag_lds + 2 * stride, *acc = lag_lds + 3 * stride;
+    const int tid = (int)threadIdx.x, T = (int)blockDim.x;
+    for (int n = tid; n < a.nlag; n += T) acc[n] = 0.0;
     for (int64_t q = blockIdx.x; q < a.npoly; q += gridDim.x) {
         const double L = a.polyL[q], halfL = 0.5 * L;
         auto mi = [&](double d) { return d > halfL ? d - L : (d < -halfL ? d + L : d); };
         const int64_t s = a.pstart[q];
-        const int N = (int)(a.pstart[q + 1] - s);  // at most LAG_MAX_BEADS (checked by the host)
+        const int N = (int)(a.pstart[q + 1] - s);  // at most stride (checked by the host)
         if (tid < 64) {
             double c0 = 0.0, c1 = 0.0, c2 = 0.0;
             for (int base = 0; base < N; base += 64) {
@@ -400,40 +399,40 @@ __global__ __launch_bounds__(LAG_THREADS) void k_internal(const ObsArgs a) {
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < LAGS_PER_THREAD; ++k) {
-            const int n = tid + 1 + k * LAG_THREADS;
-            if (n < N && n < a.nlag) {
-                double sum = 0.0;
-                for (int i = 0; i + n < N; ++i) {
-                    const double d0 = ux[i + n] - ux[i];
-                    const double d1 = uy[i + n] - uy[i];
-                    const double d2 = uz[i + n] - uz[i];
-                    const double q0 = d0 * d0;
-                    const double q1 = d1 * d1;
-                    const double q2 = d2 * d2;
-                    sum += (q0 + q1) + q2;
-                }
-                acc[k] += sum;
+        const int nend = N < a.nlag ? N : a.nlag;
+        for (int n = tid + 1; n < nend; n += T) {
+            double sum = 0.0;
+            for (int i = 0; i + n < N; ++i) {
+                const double d0 = ux[i + n] - ux[i];
+                const double d1 = uy[i + n] - uy[i];
+                const double d2 = uz[i + n] - uz[i];
+                const double q0 = d0 * d0;
+                const double q1 = d1 * d1;
+                const double q2 = d2 * d2;
+                sum += (q0 + q1) + q2;
             }
+            acc[n] += sum;
         }
         __syncthreads();
     }
-    double *row = a.lagsum + (int64_t)blockIdx.x * a.nlag;
-#pragma unroll
-    for (int k = 0; k < LAGS_PER_THREAD; ++k) {
-        const int n = tid + 1 + k * LAG_THREADS;
-        if (n < a.nlag) row[n] = acc[k];
-    }
-    if (tid == 0) row[0] = 0.0;
+    const int64_t G = gridDim.x;
+    for (int n = tid; n < a.nlag; n += T) a.lagsum[n * G + blockIdx.x] = acc[n];
 }
 
+// one block per lag: thread t adds the partial sums t, t + 256, ... in order, then a fixed tree
 __global__ __launch_bounds__(LAG_THREADS) void k_lag_total(double *lagsum, int rows, int nlag) {
-    const int n = (int)(blockIdx.x * LAG_THREADS + threadIdx.x);
-    if (n >= nlag) return;
+    __shared__ double red[LAG_THREADS];
+    const int n = (int)blockIdx.x, tid = (int)threadIdx.x;
+    const double *row = lagsum + (int64_t)n * rows;
     double sum = 0.0;
-    for (int b = 0; b < rows; ++b) sum += lagsum[(int64_t)b * nlag + n];
-    lagsum[(int64_t)rows * nlag + n] = sum;
+    for (int b = tid; b < rows; b += LAG_THREADS) sum += row[b];
+    red[tid] = sum;
+    __syncthreads();
+    for (int w = LAG_THREADS / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) lagsum[(int64_t)nlag * rows + n] = red[0];
 }
 
 }  // namespace
@@ -480,12 +479,18 @@ hipError_t launch_msd(const double *snaps, int64_t T, int64_t npoly, double *out
     return hipGetLastError();
 }
 
-hipError_t launch_internal(const ObsArgs &a, int rows, hipStream_t s) {
+hipError_t launch_internal(const ObsArgs &a, int rows, int longest, hipStream_t s) {
     if (a.npoly <= 0 || a.nlag < 1) return hipSuccess;
-    if (a.nlag > LAG_MAX_BEADS || rows < 1 || rows > LAG_BLOCKS || rows > a.npoly) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_internal, dim3((unsigned)rows), dim3(LAG_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_lag_total, dim3((unsigned)((a.nlag + LAG_THREADS - 1) / LAG_THREADS)), dim3(LAG_THREADS), 0, s,
-                       a.lagsum, rows, a.nlag);
+    if (longest < 1 || longest > LAG_MAX_BEADS || a.nlag > longest || rows < 1 || rows > a.npoly ||
+        (int64_t)rows * a.nlag > LAG_SLOTS)
+        return hipErrorInvalidValue;
+    // threads: a multiple of 64 covering the lags 1..nlag-1, at most 256
+    int threads = 64 * ((a.nlag - 1 + 63) / 64);
+    if (threads < 64) threads = 64;
+    if (threads > LAG_THREADS) threads = LAG_THREADS;
+    hipLaunchKernelGGL(k_internal, dim3((unsigned)rows), dim3((unsigned)threads), (size_t)(24 * longest + 8 * a.nlag), s, a,
+                       longest);
+    hipLaunchKernelGGL(k_lag_total, dim3((unsigned)a.nlag), dim3(LAG_THREADS), 0, s, a.lagsum, rows, a.nlag);
     return hipGetLastError();
 }
 
