@@ -254,17 +254,14 @@ def melt_c3():
     return inputs.lattice_chains(16384, 64, 0.45, seed=3)
 
 
-@pytest.mark.parametrize("swap", [False, True])
-def test_c3_full_size_sampled_domains(melt_c3, swap):
-    """1,048,576 beads (16,384 x 64, eta = 0.45, n = 76, D = 2) in the launch configuration
-    the benchmark times: one colour phase on the GPU; the oracle replays 32 sampled domains
-    of that phase (domains of one phase never interact), and the beads of those domains
-    must end with identical positions, cells and image counters; without and with swaps."""
-    m = melt_c3
-    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, swap_moves=swap))
+def _sampled_domains(m, swap, precision=ecmc.PREC_MIXED, seed=77):
+    """One colour phase of a 1,048,576-bead melt (n = 76, D = 2) on the GPU; the oracle replays 32
+    sampled domains of that phase, whose beads must end identical (positions, cells, images)."""
+    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, swap_moves=swap,
+                                            precision=precision))
     assert g.n_cells == 76
     n_ec = m.n_beads
-    g.sweep(n_ec, 20.0, 77, colour_mask=0x01)
+    g.sweep(n_ec, 20.0, seed, colour_mask=0x01)
     g.synchronize()
     o = oracle.Oracle.from_melt(m)
     o.set_swap(swap)
@@ -273,10 +270,10 @@ def test_c3_full_size_sampled_domains(melt_c3, swap):
     nd = 38
     colour0 = [d for d in range(nd ** 3) if (d % nd) % 2 == 0 and (d // nd % nd) % 2 == 0 and (d // nd ** 2) % 2 == 0]
     pick = np.sort(rng.choice(colour0, 32, replace=False))
-    o.sweep_subset(n_ec, 20.0, 77, 2, 0x01, pick)
+    o.sweep_subset(n_ec, 20.0, seed, 2, 0x01, pick)
     # the beads of the sampled domains: offsets of sweep 0 from the Philox draw (0, 0, 0, 1)
     from tests.test_oracle_pins import _philox_py
-    u = _philox_py([0, 0, 0, 1], [77, 0])
+    u = _philox_py([0, 0, 0, 1], [seed, 0])
     off = np.array([(u[a] * 2) >> 32 for a in range(3)])
     dom = ((cells0 - off) % 76) // 2
     did = dom[:, 0] + nd * (dom[:, 1] + nd * dom[:, 2])
@@ -289,7 +286,53 @@ def test_c3_full_size_sampled_domains(melt_c3, swap):
     assert np.array_equal(g.images()[mine], o.images()[mine])
     c, _ = o.counters()
     assert c[oracle.C_EC] == 20 * len(np.unique(did[np.isin(did, pick)]))
+    return g
+
+
+@pytest.mark.parametrize("swap", [False, True])
+def test_c3_full_size_sampled_domains(melt_c3, swap):
+    """1,048,576 beads (16,384 x 64, eta = 0.45, n = 76, D = 2) in the launch configuration
+    the benchmark times: one colour phase on the GPU; the oracle replays 32 sampled domains
+    of that phase (domains of one phase never interact), and the beads of those domains
+    must end with identical positions, cells and image counters; without and with swaps."""
+    g = _sampled_domains(melt_c3, swap)
     assert (g.counters()["swap"] > 0) == swap   # over the whole phase (rarely accepted from a lattice start)
+
+
+@pytest.fixture(scope="module")
+def melt_c5():
+    return inputs.lattice_chains(2048, 512, 0.45, seed=5)
+
+
+@pytest.mark.parametrize("swap,precision", [(False, ecmc.PREC_MIXED), (True, ecmc.PREC_MIXED), (True, ecmc.PREC_FP64)])
+def test_c5_long_chains_full_size_sampled_domains(melt_c5, swap, precision):
+    """The long-chain melt (2,048 chains of 512 beads, 1,048,576 beads, eta = 0.45) as the
+    benchmark's --workload c5 runs it, without and with swaps, in the mixed and the plain FP64
+    search: one colour phase on the GPU, 32 sampled domains replayed by the oracle, identical."""
+    g = _sampled_domains(melt_c5, swap, precision, seed=78)
+    assert g.counters()["error_flags"] == 0
+
+
+def test_c5_middle_bead_msd(melt_c5):
+    """g1 and g2 of the long chains: the GPU's start snapshot (middle bead 256 and centre of mass of
+    every chain, unwrapped) equals the oracle's; over four sweeps the device series gives g1, g2
+    equal to the numpy definition on the same series, with g1 growing."""
+    import torch
+    g = ecmc.Melt.from_melt(melt_c5, ecmc.Options(swap_moves=True))
+    snaps = torch.empty((5, 2048, 6), dtype=torch.float64, device="cuda")
+    g.snapshot(out=snaps[0])
+    g.synchronize()
+    ref = oracle.Oracle.from_melt(melt_c5).snapshot()
+    assert np.allclose(snaps[0].cpu().numpy(), ref, rtol=0, atol=1e-9 * melt_c5.L)
+    for s in range(4):
+        g.sweep(melt_c5.n_beads, 20.0, 820 + s)
+        g.snapshot(out=snaps[s + 1])
+    g.synchronize()
+    got = snaps.cpu().numpy()
+    g1, g2 = g.msd(snaps)
+    r1, r2 = oracle.msd_series(got)
+    assert np.allclose(g1, r1, rtol=1e-12, atol=0) and np.allclose(g2, r2, rtol=1e-12, atol=0)
+    assert 0.0 < g1[1] < g1[2] < g1[4]
 
 
 def test_c3_schedules_agree_at_full_size(melt_c3):
