@@ -335,6 +335,26 @@ def test_c5_middle_bead_msd(melt_c5):
     assert 0.0 < g1[1] < g1[2] < g1[4]
 
 
+@pytest.mark.parametrize("precision", [ecmc.PREC_MIXED, ecmc.PREC_FP64])
+def test_c3_subsample_r2_and_drift_against_the_oracle(precision):
+    """A 4,096-bead subsample of the large-melt workload (64 chains of 64 at eta = 0.45, ell = 20,
+    D = 2), ten full sweeps in each precision against the oracle's: no position drift at all and
+    the same <R^2> and <R_g^2> to the summation order."""
+    m = inputs.lattice_chains(64, 64, 0.45, seed=12)
+    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, precision=precision))
+    o = oracle.Oracle.from_melt(m, n_cells=g.n_cells)
+    for s in range(10):
+        g.sweep(m.n_beads, 20.0, 40 + s)
+        o.sweep(m.n_beads, 20.0, 40 + s, tiling=1, D=2)
+    g.synchronize()
+    assert np.array_equal(g.positions(), o.positions()) and np.array_equal(g.images(), o.images())
+    og, oo = g.observables(nbins=8), o.observables(nbins=8)
+    assert og["r2"].mean() == pytest.approx(oo["r2"].mean(), rel=1e-12)
+    assert og["rg2"].mean() == pytest.approx(oo["rg2"].mean(), rel=1e-12)
+    assert g.counters()["ec"] == o.counters()[0][oracle.C_EC] >= 10 * m.n_beads
+    assert g.counters()["error_flags"] == 0
+
+
 def test_c3_schedules_agree_at_full_size(melt_c3):
     """At 1,048,576 beads (6,859 domains per colour, a few hundred of them above the LDS
     staging area) two sweeps in one launch each and two sweeps by colour phases end in the
