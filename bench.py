@@ -278,11 +278,12 @@ def main_batch(args):
     nc = dc = None
     if not args.no_tune:
         t0 = time.perf_counter()
-        nc, dc, tune = ecmc.ecmc_tune_batch(melts, 1.0, 1.4, ecmc._native_options(opts), nb, ell, trial_sweeps=2)
+        nc, dc, tune = ecmc.ecmc_tune_batch(melts, 1.0, 1.4, ecmc._native_options(opts), nb, ell, trial_sweeps=2,
+                                            cache=args.tune_cache)
         tune["seconds"] = time.perf_counter() - t0
         opts.stage_tier = tune["stage_tier"]
         print(f"# tuned: stage tier {tune['stage_tier']}, policy {tune['policy']}, {tune['candidates']} candidates, "
-              f"{tune['seconds']:.1f} s", file=sys.stderr, flush=True)
+              f"{tune['seconds']:.1f} s{' (cached)' if tune['cached'] else ''}", file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
     g = ecmc.Melt.from_batch(melts, opts, n_cells=nc, domain_cells=dc, stream=stream)
     infos = [g.melt_info(m) for m in range(g.n_melts)]
@@ -397,6 +398,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner (automatic geometry and staging)")
+    ap.add_argument("--tune-cache", default=None, metavar="JSON",
+                    help="c4: reuse a tuning result stored in this file for the same batch, GPU and library")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device once (a plain copy kernel of known size, "
                          "the scale for hardware byte counters)")

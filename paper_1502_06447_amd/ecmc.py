@@ -7,6 +7,8 @@ the library is missing this module raises: there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import hashlib
+import json
 import os
 from dataclasses import dataclass
 
@@ -241,11 +243,79 @@ def ecmc_init_batch(melts, sigma: float, l_max: float, opt: ecmc_options, n_cell
     return h
 
 
+# Options that change what a sweep runs, and so the tuner's choice (the workspace, the stream and
+# the staging tier the tuner itself picks are left out).
+_TUNE_OPTION_FIELDS = ("precision", "tiling", "n_cells", "domain_cells", "cell_capacity", "stage_capacity",
+                       "event_cap", "event_log_capacity", "swap_moves", "schedule", "overlapping_start", "spring_k")
+
+
+def tune_key(melts, sigma: float, l_max: float, opt: ecmc_options, n_chains: int, ell: float, trial_sweeps: int,
+             device_name: str, library_digest: str) -> str:
+    """Key of a tuning result (SHA-256 hex): the geometry of every melt (box edge, beads, bonds),
+    sigma and l_max, the options that change what runs, the ECs per sweep, ell and the trial
+    length, the GPU's name and a digest of the library that was timed."""
+    items = {
+        "melts": [[float(m.L).hex(), int(m.n_beads), int(len(m.bonds))] for m in melts],
+        "sigma": float(sigma).hex(), "l_max": float(l_max).hex(),
+        "options": {k: (getattr(opt, k).hex() if isinstance(getattr(opt, k), float) else int(getattr(opt, k)))
+                    for k in _TUNE_OPTION_FIELDS},
+        "n_chains": int(n_chains), "ell": float(ell).hex(), "trial_sweeps": int(trial_sweeps),
+        "device": str(device_name), "library": str(library_digest),
+    }
+    return hashlib.sha256(json.dumps(items, sort_keys=True).encode()).hexdigest()
+
+
+def tune_cache_get(path: str, key: str):
+    """The cached (n_cells, domain_cells, result) under key in the JSON file at path, or None."""
+    try:
+        with open(path) as f:
+            entry = json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+    if not entry:
+        return None
+    return list(entry["n_cells"]), list(entry["domain_cells"]), dict(entry["result"])
+
+
+def tune_cache_put(path: str, key: str, n_cells, domain_cells, result: dict) -> None:
+    """Store a tuning result under key in the JSON file at path (other keys kept; the file is
+    replaced in one rename, so a reader never sees half of it)."""
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        table = {}
+    table[key] = {"n_cells": [int(x) for x in n_cells], "domain_cells": [int(x) for x in domain_cells],
+                  "result": {k: v for k, v in result.items() if k != "cached"}}
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _library_digest() -> str:
+    h = hashlib.sha256()
+    with open(LIB_PATH, "rb") as f:
+        for block in iter(lambda: f.read(1 << 20), b""):
+            h.update(block)
+    return h.hexdigest()
+
+
 def ecmc_tune_batch(melts, sigma: float, l_max: float, opt: ecmc_options, n_chains: int, ell: float,
-                    trial_sweeps: int = 2, device: str = "cuda"):
+                    trial_sweeps: int = 2, device: str = "cuda", cache: str | None = None):
     """Run the library's autotuner on a scratch workspace (a torch tensor freed on return).
-    Returns (n_cells, domain_cells, result): per-melt geometry and the chosen staging tier."""
+    Returns (n_cells, domain_cells, result): per-melt geometry and the chosen staging tier.
+    With cache (a JSON file path) a result stored for the same key (see tune_key) is returned
+    without timing anything, and a new one is stored; result["cached"] says which."""
     import torch
+    key = None
+    if cache:
+        key = tune_key(melts, sigma, l_max, opt, n_chains, ell, trial_sweeps, torch.cuda.get_device_name(device),
+                       _library_digest())
+        hit = tune_cache_get(cache, key)
+        if hit is not None:
+            hit[2]["cached"] = True
+            return hit
     descs, keep = _melt_descs(melts)
     n = ctypes.c_size_t()
     _check(lib().ecmc_tune_workspace_size(len(melts), descs, sigma, l_max, ctypes.byref(opt), ctypes.byref(n)),
@@ -261,7 +331,11 @@ def ecmc_tune_batch(melts, sigma: float, l_max: float, opt: ecmc_options, n_chai
                                  int(trial_sweeps), nc, dc, ctypes.byref(res)), "ecmc_tune_batch")
     torch.cuda.synchronize()
     del scratch
-    return list(nc), list(dc), res.as_dict()
+    result = res.as_dict()
+    if cache:
+        tune_cache_put(cache, key, list(nc), list(dc), result)
+    result["cached"] = False
+    return list(nc), list(dc), result
 
 
 def ecmc_sweep(ctx, n_chains: int, ell: float, seed: int):

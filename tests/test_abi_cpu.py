@@ -129,3 +129,36 @@ def test_product_shape_descriptors_agree_with_oracle():
     a, b = ecmc.shape_descriptors(lam), oracle.shape_descriptors(lam)
     for k in b:
         assert abs(a[k] - b[k]) < 1e-12, k
+
+
+def test_tuner_cache_key_and_file(tmp_path):
+    """The tuner cache: the key is stable for equal inputs and changes with a melt's box, its bead
+    count, ell, an option that changes what runs, the GPU and the library; a stored result comes
+    back as written, other keys survive a second store, and a damaged file reads as a miss."""
+    melts = inputs.batch_melts(3, 11, n_choices=(16, 32), beads_range=(1000, 3000))
+    opt = ecmc.ecmc_default_options()
+    args = (melts, 1.0, 1.4, opt, 2000, 20.0, 2, "gpu-a", "lib-1")
+    k0 = ecmc.tune_key(*args)
+    assert k0 == ecmc.tune_key(*args) and len(k0) == 64
+    other = list(melts)
+    other[1] = inputs.batch_melts(3, 12, n_choices=(16, 32), beads_range=(1000, 3000))[1]
+    changed = [ecmc.tune_key(other, *args[1:]),
+               ecmc.tune_key(melts, 1.0, 1.4, opt, 2001, 20.0, 2, "gpu-a", "lib-1"),
+               ecmc.tune_key(melts, 1.0, 1.4, opt, 2000, 10.0, 2, "gpu-a", "lib-1"),
+               ecmc.tune_key(melts, 1.0, 1.4, opt, 2000, 20.0, 2, "gpu-b", "lib-1"),
+               ecmc.tune_key(melts, 1.0, 1.4, opt, 2000, 20.0, 2, "gpu-a", "lib-2")]
+    opt2 = ecmc.ecmc_default_options()
+    opt2.precision = ecmc.PREC_FP64
+    changed.append(ecmc.tune_key(melts, 1.0, 1.4, opt2, 2000, 20.0, 2, "gpu-a", "lib-1"))
+    assert len(set(changed + [k0])) == len(changed) + 1
+    path = str(tmp_path / "tune.json")
+    assert ecmc.tune_cache_get(path, k0) is None
+    res = {"stage_tier": 256, "policy": 0, "ms_per_sweep": 1.5, "ecs_per_s": 2e8, "candidates": 3, "cached": False}
+    ecmc.tune_cache_put(path, k0, [12, 14, 16], [2, 2, 2], res)
+    ecmc.tune_cache_put(path, changed[0], [8, 8, 8], [2, 2, 2], dict(res, stage_tier=128))
+    nc, dc, got = ecmc.tune_cache_get(path, k0)
+    assert nc == [12, 14, 16] and dc == [2, 2, 2] and got == {k: v for k, v in res.items() if k != "cached"}
+    assert ecmc.tune_cache_get(path, changed[0])[2]["stage_tier"] == 128
+    with open(path, "w") as f:
+        f.write("{not json")
+    assert ecmc.tune_cache_get(path, k0) is None

@@ -537,14 +537,22 @@ def test_graph_of_sweeps_replays_like_eager_sweeps(small_batch):
         assert all(ce[k] == cg[k] for k in ("hs_lift", "hs_reflect", "ec", "steps", "cross", "wall")), rep
 
 
-def test_autotuner_returns_a_configuration_that_runs(small_batch):
+def test_autotuner_returns_a_configuration_that_runs(small_batch, tmp_path):
     """The autotuner times its candidates on a scratch workspace and returns per-melt cells and
-    domain edges and a staging tier that a batch context accepts and sweeps with."""
+    domain edges and a staging tier that a batch context accepts and sweeps with.  Through a
+    cache file, a second call returns the stored choice without timing anything."""
     melts = small_batch
     nb = sum(m.n_beads for m in melts)
     opts = ecmc.Options()
-    nc, dc, res = ecmc.ecmc_tune_batch(melts, 1.0, 1.4, ecmc._native_options(opts), nb, 20.0, trial_sweeps=1)
+    cache = str(tmp_path / "tune.json")
+    nc, dc, res = ecmc.ecmc_tune_batch(melts, 1.0, 1.4, ecmc._native_options(opts), nb, 20.0, trial_sweeps=1,
+                                       cache=cache)
     assert res["candidates"] >= 1 and res["ecs_per_s"] > 0 and res["stage_tier"] in (64, 128, 192, 256, 384, 512)
+    assert res["cached"] is False
+    nc2, dc2, res2 = ecmc.ecmc_tune_batch(melts, 1.0, 1.4, ecmc._native_options(opts), nb, 20.0, trial_sweeps=1,
+                                          cache=cache)
+    assert res2["cached"] is True and (nc2, dc2) == (nc, dc)
+    assert {k: v for k, v in res2.items() if k != "cached"} == {k: v for k, v in res.items() if k != "cached"}
     for m, n, D in zip(melts, nc, dc):
         assert n >= 4 and D >= 2 and n % D == 0 and (n // D) % 2 == 0 and m.L / n > 1.4
     opts.stage_tier = res["stage_tier"]
