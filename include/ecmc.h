@@ -296,6 +296,16 @@ ecmc_status ecmc_count_overlaps(ecmc_ctx *ctx, double diameter, int64_t *n);
 ecmc_status ecmc_pushoff(ecmc_ctx *ctx, double d_start, int32_t stages, double ell, uint64_t seed,
                          int64_t max_sweeps, int64_t *sweeps_done, int64_t *overlaps_left);
 
+/* State check on the GPU: the conditions every EC keeps (Sec. II: no two hard spheres overlap, no
+ * tether is longer than its maximum, and each bead stays in the cell that lists it), counted
+ * without copying the state to the host.  overlaps: pairs closer than sigma (1 - tol);
+ * stretched: bonds longer than l_max (1 + tol), in minimum image; misplaced: beads outside the
+ * closed interval of the cell whose list holds them or whose cell word names another cell, plus
+ * beads a list could not hold and the difference between the beads listed and n_beads.  tol in
+ * [0, 1e-3]; any output pointer may be null.  Synchronises.  For callers that validate long
+ * runs, restored checkpoints or push-off results at full size. */
+ecmc_status ecmc_check_state(ecmc_ctx *ctx, double tol, int64_t *overlaps, int64_t *stretched, int64_t *misplaced);
+
 /* Snapshot for the mean-square displacements g1 and g2 (Sec. IV.A): per polymer the middle bead
  * floor(N/2) and the centre of mass, both image-unwrapped (as ecmc_observables and ecmc_shape
  * give them), written as snap [n_poly][6] (x, y, z of the bead, then of the centre) to DEVICE

@@ -898,6 +898,39 @@ ecmc_status ecmc_count_overlaps(ecmc_ctx *c, double diameter, int64_t *n) {
     return count_pairs_below(c, diameter * diameter * (1.0 - 1e-9), n);
 }
 
+ecmc_status ecmc_check_state(ecmc_ctx *c, double tol, int64_t *overlaps, int64_t *stretched, int64_t *misplaced) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    if (!(tol >= 0.0) || !(tol <= 1e-3)) return fail(c, ECMC_E_ARG, "tol must be in [0, 1e-3] (got %g)", tol);
+    int64_t ov = 0;
+    ecmc_status st = count_pairs_below(c, c->sig2 * (1.0 - tol), &ov);
+    if (st) return st;
+    HIP_OK(c, hipMemsetAsync(c->ws + c->lay.hist, 0, 24, c->stream));
+    PairArgs a{};
+    a.px = c->dev<double>(c->lay.px);
+    a.py = c->dev<double>(c->lay.py);
+    a.pz = c->dev<double>(c->lay.pz);
+    a.ccount = c->dev<int32_t>(c->lay.ccount);
+    a.cids = c->dev<int32_t>(c->lay.cids);
+    a.cap = c->cap;
+    a.melts = c->dev<MeltDev>(c->lay.melts);
+    a.n_melts = (int)c->p.melts.size();
+    a.cells = c->p.cells;
+    a.hist = c->dev<unsigned long long>(c->lay.hist);
+    a.part = c->dev<int32_t>(c->lay.part);
+    a.cellp = c->dev<int32_t>(c->lay.cellp);
+    a.b2lim = c->b2 * (1.0 + tol);
+    HIP_OK(c, launch_check(a, c->stream));
+    if ((st = check_device(c))) return st;
+    unsigned long long v[3] = {0, 0, 0};
+    HIP_OK(c, hipMemcpy(v, a.hist, 24, hipMemcpyDeviceToHost));
+    const int64_t listed = (int64_t)v[2];
+    if (overlaps) *overlaps = ov;
+    if (stretched) *stretched = (int64_t)v[0];
+    // a bead listed twice or not at all is misplaced too
+    if (misplaced) *misplaced = (int64_t)v[1] + (listed > c->nb ? listed - c->nb : c->nb - listed);
+    return ECMC_OK;
+}
+
 ecmc_status ecmc_pushoff(ecmc_ctx *c, double d_start, int32_t stages, double ell, uint64_t seed,
                          int64_t max_sweeps, int64_t *sweeps_done, int64_t *overlaps_left) {
     if (!c) return fail(nullptr, ECMC_E_ARG, "null context");

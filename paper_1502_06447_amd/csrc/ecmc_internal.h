@@ -154,6 +154,10 @@ struct PairArgs {
     double rmax;
     unsigned long long *hist;  // [nbins]
     double q_lim;              // > 0: count the pairs with squared distance below q_lim in bin 0 instead
+    // state check (k_check): tethered partners, cell words, the squared bond limit; hist[0..2]
+    // receive stretched bonds, misplaced beads and the beads the cell lists hold
+    const int32_t *part, *cellp;
+    double b2lim;
 };
 
 // launchers (ecmc_kernels.hip)
@@ -170,6 +174,7 @@ constexpr int SLOW_SLOT_BYTES_PER_BEAD = 3 * 8 + 4 * 4;  // staging slot: positi
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
 hipError_t launch_shape(const ObsArgs &a, hipStream_t s);
 hipError_t launch_pairs(const PairArgs &a, hipStream_t s);
+hipError_t launch_check(const PairArgs &a, hipStream_t s);
 hipError_t launch_msd(const double *snaps, int64_t T, int64_t npoly, double *out, hipStream_t s);
 hipError_t launch_internal(const ObsArgs &a, int rows, int longest, hipStream_t s);
 bool bpl_supported(int bpl);

@@ -316,6 +316,71 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_pairs(const PairArgs a) {
         if (s_hist[i]) atomicAdd(&a.hist[i], (unsigned long long)s_hist[i]);
 }
 
+// ------------------------------------------------------------------ state check
+// The conditions every EC keeps, checked on the device: one thread per cell of all melts.  Each
+// bead the cell lists must lie in the cell's closed interval [k h, face(k + 1)] on every axis and
+// carry the cell's index in its cell word; each bond (i, j > i) must be at most the limit in
+// minimum image.  Counts go to LDS, then one global add per counter and block.
+__global__ __launch_bounds__(PAIR_THREADS) void k_check(const PairArgs a) {
+    __shared__ unsigned s_cnt[3];
+    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    unsigned stretched = 0, misplaced = 0, listed = 0;
+    for (long long c = (long long)blockIdx.x * PAIR_THREADS + threadIdx.x; c < a.cells;
+         c += (long long)gridDim.x * PAIR_THREADS) {
+        int lo = 0, hi = a.n_melts - 1;  // the melt of cell c: the last whose first cell is <= c
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.melts[mid].cell0 <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        const MeltDev &M = a.melts[lo];
+        const int n = M.n;
+        const double L = M.L, h = M.h, halfL = M.halfL;
+        const int lc = (int)(c - M.cell0);
+        const int k[3] = {lc % n, (lc / n) % n, lc / (n * n)};
+        double blo[3], bhi[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            blo[ax] = (double)k[ax] * h;
+            bhi[ax] = k[ax] + 1 < n ? (double)(k[ax] + 1) * h : L;
+        }
+        int ni = a.ccount[c];
+        if (ni > a.cap) {  // an overflowing list: the beads it could not hold are misplaced
+            misplaced += (unsigned)(ni - a.cap);
+            ni = a.cap;
+        }
+        for (int ii = 0; ii < ni; ++ii) {
+            const int i = a.cids[c * a.cap + ii];
+            ++listed;
+            const double r[3] = {a.px[i], a.py[i], a.pz[i]};
+            const int32_t w = a.cellp[i];
+            bool bad = false;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+                bad = bad || !(r[ax] >= blo[ax] && r[ax] <= bhi[ax]) || ((w >> (ax * CELL_BITS)) & CELL_MASK) != k[ax];
+            misplaced += bad ? 1u : 0u;
+            for (int t = 0; t < 2; ++t) {
+                const int j = a.part[2 * i + t];
+                if (j <= i) continue;  // no partner (-1), or the pair is checked from j
+                double d0 = a.px[j] - r[0], d1 = a.py[j] - r[1], d2 = a.pz[j] - r[2];
+                d0 = d0 > halfL ? d0 - L : (d0 < -halfL ? d0 + L : d0);
+                d1 = d1 > halfL ? d1 - L : (d1 < -halfL ? d1 + L : d1);
+                d2 = d2 > halfL ? d2 - L : (d2 < -halfL ? d2 + L : d2);
+                const double q0 = d0 * d0;
+                const double q1 = d1 * d1;
+                const double q2 = d2 * d2;
+                stretched += ((q0 + q1) + q2) > a.b2lim ? 1u : 0u;
+            }
+        }
+    }
+    if (stretched) atomicAdd(&s_cnt[0], stretched);
+    if (misplaced) atomicAdd(&s_cnt[1], misplaced);
+    if (listed) atomicAdd(&s_cnt[2], listed);
+    __syncthreads();
+    if (threadIdx.x < 3 && s_cnt[threadIdx.x]) atomicAdd(&a.hist[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+}
+
 // ------------------------------------------------------------------ mean-square displacements
 // g1 and g2 of Sec. IV.A from T snapshots [T][P][6] (middle bead, centre of mass): one block
 // per lag d, its threads over the (T - d) P pairs of snapshots d apart, summed in FP64 and
@@ -469,6 +534,14 @@ hipError_t launch_pairs(const PairArgs &a, hipStream_t s) {
     long long grid = (a.cells + PAIR_THREADS - 1) / PAIR_THREADS;
     if (grid > 4096) grid = 4096;
     hipLaunchKernelGGL(k_pairs, dim3((unsigned)grid), dim3(PAIR_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(const PairArgs &a, hipStream_t s) {
+    if (a.cells <= 0) return hipSuccess;
+    long long grid = (a.cells + PAIR_THREADS - 1) / PAIR_THREADS;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_check, dim3((unsigned)grid), dim3(PAIR_THREADS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -112,6 +112,7 @@ EXPORTS = (
     "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
     "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
     "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff", "ecmc_internal_distances",
+    "ecmc_check_state",
 )
 
 
@@ -144,6 +145,7 @@ def lib():
         "ecmc_end_to_end_histogram": (st, [vp, i32, dbl, vp]),
         "ecmc_pair_histogram": (st, [vp, i32, dbl, vp]),
         "ecmc_internal_distances": (st, [vp, i32, vp, vp]),
+        "ecmc_check_state": (st, [vp, dbl, P(i64), P(i64), P(i64)]),
         "ecmc_pushoff_sweep": (st, [vp, i64, dbl, u64, dbl]),
         "ecmc_count_overlaps": (st, [vp, dbl, P(i64)]),
         "ecmc_pushoff": (st, [vp, dbl, i32, dbl, u64, i64, P(i64), P(i64)]),
@@ -601,6 +603,14 @@ class Melt:
         _check(lib().ecmc_end_to_end_histogram(self.ctx, int(nbins), float(r_max), h.ctypes.data),
                "ecmc_end_to_end_histogram", self.ctx)
         return h
+
+    def check_state(self, tol: float = 1e-10) -> dict:
+        """Invariants of the current state counted on the GPU: overlapping pairs (closer than
+        sigma (1 - tol)), stretched bonds (longer than l_max (1 + tol)) and misplaced beads."""
+        ov, st, mp = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ecmc_check_state(self.ctx, float(tol), ctypes.byref(ov), ctypes.byref(st), ctypes.byref(mp)),
+               "ecmc_check_state", self.ctx)
+        return {"overlaps": ov.value, "stretched": st.value, "misplaced": mp.value}
 
     def internal_distances(self, n_max: int) -> tuple[np.ndarray, np.ndarray]:
         """R^2(n) of Sec. II.B for n = 0..n_max: the mean squared chain vector between beads of

@@ -248,6 +248,49 @@ def test_checkpoint_restore_continues_bit_exact(melt_c1):
     assert np.array_equal(a.images(), c.images())
 
 
+def _brute_check(p, c, bonds, L, h, n, tol=1e-10):
+    """Overlaps, stretched bonds and misplaced beads of a state by brute force (numpy)."""
+    d = p[None, :, :] - p[:, None, :]
+    d -= L * np.round(d / L)
+    q = np.einsum("ijk,ijk->ij", d, d)
+    iu = np.triu_indices(len(p), 1)
+    overlaps = int(np.count_nonzero(q[iu] < 1.0 * (1 - tol)))
+    b = p[bonds[:, 1]] - p[bonds[:, 0]]
+    b -= L * np.round(b / L)
+    stretched = int(np.count_nonzero(np.einsum("ij,ij->i", b, b) > 1.4 ** 2 * (1 + tol)))
+    hi = np.where(c + 1 < n, (c + 1) * h, L)
+    misplaced = int(np.count_nonzero(np.any((p < c * h) | (p > hi), axis=1)))
+    return {"overlaps": overlaps, "stretched": stretched, "misplaced": misplaced}
+
+
+def test_state_check_counts_planted_faults(melt_c1):
+    """The device state check on the 16 x 16 melt: nothing after three sweeps.  Then faults are
+    planted from the host through set_state, which accepts a coordinate up to 1e-12 past its cell:
+    a chain end moved along its bond to 3 sigma from its partner, and a bead put 4e-13 past its
+    cell's upper face.  The counts equal a brute-force count of the planted state."""
+    g = ecmc.Melt.from_melt(melt_c1, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=4))
+    for s in range(3):
+        g.sweep(256, 10.0, 60 + s)
+    g.synchronize()
+    assert g.check_state() == {"overlaps": 0, "stretched": 0, "misplaced": 0}
+    pos, cells, img = g.positions(), g.cells(), g.images()
+    L, h, n = melt_c1.L, g.h, g.n_cells
+    assert _brute_check(pos, cells, melt_c1.bonds, L, h, n) == {"overlaps": 0, "stretched": 0, "misplaced": 0}
+    p, c = pos.copy(), cells.copy()
+    d = pos[0] - pos[1]
+    d -= L * np.round(d / L)
+    p[0] = np.mod(pos[1] + 3.0 * d / np.linalg.norm(d), L)
+    c[0] = np.minimum(np.floor(p[0] / h).astype(np.int32), n - 1)
+    k = next(i for i in range(8, len(p)) if c[i, 0] < n - 1)
+    p[k, 0] = (c[k, 0] + 1) * h + 4e-13
+    g.set_state(p, c, img, g.sweep_counter)
+    got = g.check_state()
+    want = _brute_check(p, c, melt_c1.bonds, L, h, n)
+    assert got == want and got["stretched"] >= 1 and got["misplaced"] == 1, (got, want)
+    with pytest.raises(ecmc.EcmcError):
+        g.check_state(tol=0.1)
+
+
 # ------------------------------------------------------------------ full-size sample
 @pytest.fixture(scope="module")
 def melt_c3():
@@ -386,6 +429,7 @@ def test_c3_invariants_after_full_sweeps(melt_c3):
     for s in range(2):
         g.sweep(m.n_beads, 20.0, 500 + s)
     g.synchronize()
+    assert g.check_state() == {"overlaps": 0, "stretched": 0, "misplaced": 0}
     pos = g.positions()
     L = m.L
     # shape analysis of all 16,384 chains against the oracle put into the same state
