@@ -366,10 +366,16 @@ def main_batch(args):
 
 
 def workload_of(args) -> dict:
-    """The workload's parameters with the partition chosen on the command line."""
-    w = dict(WORKLOADS[args.workload], tiling=2 if args.tiling == "joint" else 1)
+    """The workload's parameters with the partition chosen on the command line.  Without one,
+    tethers run on the checkerboard of 2^3-cell domains and springs on 1-cell tile-joint tiles
+    (their fastest partitions: spring cells are larger, and a 3^3-cell frame keeps the staging
+    tier small)."""
+    tiling = args.tiling or ("joint" if args.springs > 0 else "checker")
+    w = dict(WORKLOADS[args.workload], tiling=2 if tiling == "joint" else 1)
     if args.domain_cells > 0:
         w["D"] = args.domain_cells
+    elif args.tiling is None and args.springs > 0:
+        w["D"] = 1
     return w
 
 
@@ -386,11 +392,13 @@ def main():
     ap.add_argument("--swap", action="store_true", help="swap moves at hard-sphere contacts (Sec. II.C)")
     ap.add_argument("--springs", type=float, default=0.0, metavar="K",
                     help="bonds as harmonic springs of constant K (Eq. (2), k_B T / sigma^2); 0 = tethers")
-    ap.add_argument("--tiling", default="checker", choices=("checker", "joint"),
-                    help="checker: D^3-cell domains in 8 colour phases (default); joint: the tile-joint "
-                         "partition (D^3-cell tiles at pitch D + 1 with immotile joints, one phase)")
+    ap.add_argument("--tiling", default=None, choices=("checker", "joint"),
+                    help="checker: D^3-cell domains in 8 colour phases (the default for tethers); joint: the "
+                         "tile-joint partition (D^3-cell tiles at pitch D + 1 with immotile joints, one phase; "
+                         "the default for springs, with D = 1)")
     ap.add_argument("--domain-cells", type=int, default=0, metavar="D",
-                    help="domain (checkerboard) or tile (tile-joint) edge in cells; 0 = the workload's (2)")
+                    help="domain (checkerboard) or tile (tile-joint) edge in cells; 0 = the workload's (2), "
+                         "or 1 for springs on their default partition")
     ap.add_argument("--spring-cap", type=float, default=1.8, metavar="B",
                     help="with --springs: bond length cap in sigma (cells get an edge > B)")
     ap.add_argument("--no-precision-check", action="store_true",
@@ -515,8 +523,11 @@ def main():
             "algorithmic_bytes_per_launch": events * B / max(launches, 1),
             "bytes_per_event": B,
             "note": "achieved: algorithmic bytes (18-cell forward cell-list scan per collision event) over the "
-                    "HIP-event time of the sweep launches (one dependency-ordered kernel per sweep); traffic: "
-                    "measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated by a copy)",
+                    "HIP-event time of the sweep launches ("
+                    + ("one dependency-ordered kernel per sweep" if w.get("tiling", 1) == 1 else
+                       "the tile-joint phase: its staging tiers on two streams, one phase per sweep")
+                    + "); traffic: measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated "
+                      "by a copy)",
         },
     }
     out["roofline"]["measured_copy_GBps"] = copy_bandwidth()

@@ -652,6 +652,30 @@ def test_springs_c2_dense_melt_bit_exact(melt_c2_spring, exact, sched):
     assert n > 250_000
 
 
+@pytest.mark.parametrize("exact", [False, True])
+def test_springs_tile_joint_c1_event_sequence_bit_exact(melt_c1_spring, exact):
+    """Springs (k sigma^2 = 30, capped at 1.8 sigma) on the tile-joint partition with 1-cell tiles
+    at pitch 2 (n = 4: 8 tiles in one phase, the joints immotile): 3 sweeps of 256 ECs, every
+    event as in the oracle, both precisions."""
+    p, g, o = _pair(melt_c1_spring, ecmc.TILING_JOINT, D=1, n_cells=4, spring_k=30.0,
+                    precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
+    for s in range(3):
+        p.sweep(256, 10.0, 420 + s)
+    n, _ = _compare(g, o)
+    c = g.counters()
+    assert n > 5_000 and c["tether_lift"] > 50 and c["periodic"] == 0 and c["wall"] > 0
+
+
+def test_springs_tile_joint_c2_dense_melt_bit_exact(melt_c2_spring):
+    """The 500 x 32 spring melt (cap 1.6 sigma) on 1-cell tiles at pitch 2 (n = 16: 512 tiles),
+    the partition the spring benchmark runs: 2 sweeps of 16,000 ECs with ell = 20 sigma."""
+    p, g, o = _pair(melt_c2_spring, ecmc.TILING_JOINT, D=1, n_cells=16, log=40_000_000, spring_k=30.0)
+    for s in range(2):
+        p.sweep(16000, 20.0, 520 + s)
+    n, _ = _compare(g, o)
+    assert n > 250_000
+
+
 @pytest.fixture(scope="module")
 def melt_c3_spring():
     return inputs.lattice_chains(16384, 64, 0.45, seed=3, b_max=1.8)
