@@ -681,6 +681,25 @@ def melt_c3_spring():
     return inputs.lattice_chains(16384, 64, 0.45, seed=3, b_max=1.8)
 
 
+def test_springs_tile_joint_c3_full_size_clean_and_precision_exact(melt_c3_spring):
+    """The spring benchmark's configuration at full size (1,048,576 beads, cap 1.8 sigma, 1-cell tiles
+    at pitch 2 on 58^3 cells): one sweep in each precision ends in identical states with identical
+    counters, and the device state check finds no overlap, stretched bond or misplaced bead."""
+    runs = []
+    for prec in (ecmc.PREC_MIXED, ecmc.PREC_FP64):
+        g = ecmc.Melt.from_melt(melt_c3_spring, ecmc.Options(tiling=ecmc.TILING_JOINT, domain_cells=1, n_cells=58,
+                                                             spring_k=30.0, precision=prec))
+        g.sweep(melt_c3_spring.n_beads, 20.0, 88)
+        g.synchronize()
+        assert g.check_state() == {"overlaps": 0, "stretched": 0, "misplaced": 0}
+        runs.append((g.positions(), g.images(), g.counters()))
+        g.close()
+    (p0, i0, c0), (p1, i1, c1) = runs
+    assert np.array_equal(p0, p1) and np.array_equal(i0, i1)
+    assert all(c0[k] == c1[k] for k in ("hs_lift", "tether_lift", "hs_reflect", "tether_reflect", "wall", "ec", "steps"))
+    assert c0["ec"] >= melt_c3_spring.n_beads and c0["tether_lift"] > 0 and c0["error_flags"] == 0
+
+
 def test_springs_c3_full_size_sampled_domains(melt_c3_spring):
     """1,048,576 beads bonded by springs (k sigma^2 = 30, cap 1.8 sigma: n = 56, D = 2) in
     the launch configuration the benchmark times for springs (one launch per sweep): after
