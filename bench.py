@@ -365,6 +365,32 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def msd_run(g, nb: int, w, sweeps: int, seed0: int) -> dict:
+    """Untimed: continue the run for `sweeps` sweeps with a snapshot of every chain's middle bead and
+    centre of mass after each (Sec. IV.A), then g1 and g2 over all time origins on the GPU; reported at
+    lags 1, 2, 4, ... sweeps with the collision events the run took."""
+    import torch
+    snaps = torch.empty((sweeps + 1, g.n_poly, 6), dtype=torch.float64, device="cuda")
+    c0 = g.counters()
+    g.snapshot(out=snaps[0])
+    t0 = time.perf_counter()
+    for s in range(sweeps):
+        g.sweep(nb, w["ell"], seed0 + s)
+        g.snapshot(out=snaps[s + 1])
+        if (s + 1) % 100 == 0:
+            g.synchronize()
+            print(f"# msd run: {s + 1}/{sweeps} sweeps", file=sys.stderr, flush=True)
+    g1, g2 = g.msd(snaps)
+    dt = time.perf_counter() - t0
+    c1 = g.counters()
+    ev = sum(c1[k] - c0[k] for k in ("hs_lift", "tether_lift", "hs_reflect", "tether_reflect", "swap"))
+    lags = [1 << k for k in range(sweeps.bit_length()) if (1 << k) <= sweeps]
+    return {"sweeps": sweeps, "collision_events": int(ev), "seconds": dt, "lags_sweeps": lags,
+            "g1": [float(g1[d]) for d in lags], "g2": [float(g2[d]) for d in lags],
+            "note": "middle bead (g1) and middle bead relative to the centre of mass (g2), sigma^2, averaged "
+                    "over chains and time origins; from the start state, not an equilibrated melt"}
+
+
 def workload_of(args) -> dict:
     """The workload's parameters with the partition chosen on the command line.  Without one,
     tethers run on the checkerboard of 2^3-cell domains and springs on 1-cell tile-joint tiles
@@ -404,6 +430,9 @@ def main():
     ap.add_argument("--no-precision-check", action="store_true",
                     help="skip the untimed comparison of the two precisions after the timed steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--msd-sweeps", type=int, default=0, metavar="S",
+                    help="after the timed steps (untimed): S more sweeps with a snapshot after each, and g1, g2 "
+                         "(Sec. IV.A) at lags 1, 2, 4, ... sweeps in the JSON line")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner (automatic geometry and staging)")
     ap.add_argument("--tune-cache", default=None, metavar="JSON",
@@ -531,6 +560,8 @@ def main():
         },
     }
     out["roofline"]["measured_copy_GBps"] = copy_bandwidth()
+    if args.msd_sweeps > 0:
+        out["msd"] = msd_run(g, nb, w, args.msd_sweeps, 1000 + args.warmup + args.steps)
     if not args.no_precision_check:
         out["precision_check"] = precision_check(melt, w, sweeps=2, swap=args.swap, spring_k=args.springs)
     if not args.no_cpu_baseline:
