@@ -162,3 +162,22 @@ def test_tuner_cache_key_and_file(tmp_path):
     with open(path, "w") as f:
         f.write("{not json")
     assert ecmc.tune_cache_get(path, k0) is None
+
+
+def test_bench_partition_defaults():
+    """bench.py's workload geometry: tethers default to the 2^3-cell checkerboard, springs to 1-cell
+    tile-joint tiles; an explicit --tiling or --domain-cells wins; the tile-joint grid is divisible
+    by the pitch with cells wider than the bond cap."""
+    import argparse
+    import bench
+    ns = lambda **kw: argparse.Namespace(**{"workload": "c3", "tiling": None, "domain_cells": 0, "springs": 0.0, **kw})
+    assert (bench.workload_of(ns())["tiling"], bench.workload_of(ns())["D"]) == (1, 2)
+    w = bench.workload_of(ns(springs=30.0))
+    assert (w["tiling"], w["D"]) == (2, 1)
+    w = bench.workload_of(ns(springs=30.0, tiling="checker"))
+    assert (w["tiling"], w["D"]) == (1, 2)
+    w = bench.workload_of(ns(springs=30.0, domain_cells=2))
+    assert (w["tiling"], w["D"]) == (2, 2)
+    L = 106.85512104226243
+    n = bench.grid_cells(L, 1.8, bench.workload_of(ns(springs=30.0)))
+    assert n == 58 and n % 2 == 0 and L / n > 1.8
