@@ -534,6 +534,20 @@ class Melt:
         _check(lib().ecmc_set_state(self.ctx, p.ctypes.data, c.ctypes.data, i.ctypes.data, int(sweep_counter)),
                "ecmc_set_state", self.ctx)
 
+    def save_checkpoint(self, path: str) -> None:
+        """Write the state a run resumes from (positions, cells, image counters, sweep counter) to an
+        .npz file.  The random numbers are counter-based on (seed, sweep counter, domain, EC), so a
+        context restored from it continues bit for bit as the original would."""
+        np.savez(path, positions=self.positions(), cells=self.cells(), images=self.images(),
+                 sweep_counter=np.array([self.sweep_counter], dtype=np.uint32), n_beads=np.array([self.n_beads]))
+
+    def load_checkpoint(self, path: str) -> None:
+        """Restore a state written by save_checkpoint into this context (same melt geometry)."""
+        with np.load(path, allow_pickle=False) as f:
+            if int(f["n_beads"][0]) != self.n_beads:
+                raise ValueError(f"checkpoint holds {int(f['n_beads'][0])} beads, this melt {self.n_beads}")
+            self.set_state(f["positions"], f["cells"], f["images"], int(f["sweep_counter"][0]))
+
     def kernel_time(self):
         ms = ctypes.c_double()
         n = ctypes.c_int64()

@@ -291,6 +291,33 @@ def test_state_check_counts_planted_faults(melt_c1):
         g.check_state(tol=0.1)
 
 
+def test_checkpoint_file_resume_gives_identical_event_logs(melt_c2, tmp_path):
+    """Checkpoint and resume through a file on the 500 x 32 melt: four sweeps in one run against two
+    sweeps, a checkpoint file, a new context restored from it and two more sweeps.  The last two
+    sweeps' event logs, the final state and the counters of those sweeps are identical."""
+    opts = dict(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=16, event_log_capacity=4_000_000)
+    a = ecmc.Melt.from_melt(melt_c2, ecmc.Options(**opts))
+    for s in range(2):
+        a.sweep(16000, 20.0, 30 + s)
+    path = str(tmp_path / "ckpt.npz")
+    a.save_checkpoint(path)
+    a.clear_event_log()
+    a.reset_counters()
+    for s in range(2, 4):
+        a.sweep(16000, 20.0, 30 + s)
+    a.synchronize()
+    b = ecmc.Melt.from_melt(melt_c2, ecmc.Options(**opts))
+    b.load_checkpoint(path)
+    for s in range(2, 4):
+        b.sweep(16000, 20.0, 30 + s)
+    b.synchronize()
+    la, lb = _sorted(a.event_log()), _sorted(b.event_log())
+    assert len(la) > 100_000 and np.array_equal(la, lb)
+    assert np.array_equal(a.positions(), b.positions()) and np.array_equal(a.images(), b.images())
+    ca, cb = a.counters(), b.counters()
+    assert all(ca[k] == cb[k] for k in ("hs_lift", "tether_lift", "hs_reflect", "wall", "cross", "ec", "steps"))
+
+
 # ------------------------------------------------------------------ full-size sample
 @pytest.fixture(scope="module")
 def melt_c3():
