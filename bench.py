@@ -393,15 +393,13 @@ def msd_run(g, nb: int, w, sweeps: int, seed0: int) -> dict:
 
 def workload_of(args) -> dict:
     """The workload's parameters with the partition chosen on the command line.  Without one,
-    tethers run on the checkerboard of 2^3-cell domains and springs on 1-cell tile-joint tiles
-    (their fastest partitions: spring cells are larger, and a 3^3-cell frame keeps the staging
-    tier small)."""
-    tiling = args.tiling or ("joint" if args.springs > 0 else "checker")
+    tethers and springs both run on the checkerboard of 2^3-cell domains (every partition on
+    offer has domains of at least 2 cells per edge: smaller ones would keep each bead in its
+    cell for good)."""
+    tiling = args.tiling or "checker"
     w = dict(WORKLOADS[args.workload], tiling=2 if tiling == "joint" else 1)
     if args.domain_cells > 0:
         w["D"] = args.domain_cells
-    elif args.tiling is None and args.springs > 0:
-        w["D"] = 1
     return w
 
 

@@ -92,8 +92,9 @@ typedef struct {
                                    ECMC_TILING_JOINT: the tile-joint partition (Sec. II.A),
                                    D^3-cell tiles at pitch D + 1 (the cell after each tile an
                                    immotile joint), all tiles in one phase; n a multiple of
-                                   D + 1 with n / (D + 1) >= 2, D >= 1; single melts, run by
-                                   phases                                                  */
+                                   D + 1 with n / (D + 1) >= 2, D >= 2 (1-cell tiles would
+                                   wall every bead into its cell: ECMC_E_BOX); single melts,
+                                   run by phases                                           */
     int32_t n_cells;            /* cells per axis; 0 = largest n with L/n > l_max           */
     int32_t domain_cells;       /* D, cells per domain edge (checkerboard)                  */
     int32_t cell_capacity;      /* bead slots per cell; 0 = 16                              */

@@ -61,6 +61,7 @@ def lib():
         L.orc_destroy.argtypes = [vp]
         L.orc_set_options.argtypes = [vp, i64, ctypes.c_int]
         L.orc_set_swap.argtypes = [vp, ctypes.c_int]
+        L.orc_set_periodic_skip.argtypes = [vp, ctypes.c_int]
         L.orc_set_swap.restype = ctypes.c_int
         L.orc_set_spring.argtypes = [vp, dbl]
         L.orc_set_spring.restype = ctypes.c_int
@@ -187,6 +188,11 @@ class Oracle:
         """Swap moves at hard-sphere contacts (Sec. II.C) for the following ECs."""
         if lib().orc_set_swap(self._h, 1 if on else 0) != OK:
             raise ValueError("swap moves cannot be combined with springs")
+
+    def set_periodic_skip(self, on: bool = True):
+        """Whole periods of an EC dropped after its second reflection (the default), or the plain
+        loop of Sec. II steps 1-4 that runs every bounce until x_max is used up."""
+        lib().orc_set_periodic_skip(self._h, 1 if on else 0)
 
     def set_pushoff(self, d: float):
         """Push-off (Sec. II.B) at working diameter d for the following sweeps (d = 0: off)."""

@@ -93,6 +93,7 @@ struct orc_sys {
     int swap;          /* swap moves at hard-sphere contacts (Sec. II.C) */
     int spring;        /* bonds are harmonic springs capped at b_max (Eq. (2)) */
     int push;          /* push-off: overlapping pairs ignored, ECs start at overlapping beads */
+    int no_skip;       /* 1: the plain loop of Sec. II steps 1-4, whole periods never dropped */
     double ov2;        /* squared overlap distance of the push-off: d^2 (1 - 1e-9) */
     double spring_k, two_over_k;
     uint32_t stream;   /* random stream index m (counter word 3 = 2 m, 2 m + 1) */
@@ -398,6 +399,14 @@ int orc_set_options(orc_sys *s, int64_t event_cap, int check) {
 int orc_set_swap(orc_sys *s, int on) {
     if (on && (s->spring || s->push)) return ORC_E_ARG;
     s->swap = on ? 1 : 0;
+    return ORC_OK;
+}
+
+/* The periodic reduction on (1, the default) or off (0).  Off, every EC is the plain loop of
+ * Sec. II steps 1-4: it runs until x_max is used up (or the zero-length cycle search or the
+ * event cap ends it), bouncing between its two stops as often as the length requires. */
+int orc_set_periodic_skip(orc_sys *s, int on) {
+    s->no_skip = on ? 0 : 1;
     return ORC_OK;
 }
 
@@ -828,7 +837,7 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
             } else {
                 log_event(s, dm, step, p, b.j, b.kind == 0 ? ORC_EV_HS_REFLECT : ORC_EV_TETHER_REFLECT);
                 s->cnt[b.kind == 0 ? ORC_C_HS_REFLECT : ORC_C_TETHER_REFLECT]++;
-                if (!s->spring && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+                if (!s->spring && !s->no_skip && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
                 reflected = 1;
                 xref = xmax;
                 sgn = -sgn;
@@ -872,7 +881,7 @@ static int run_ec(orc_sys *s, orc_dom *dm, int32_t p, int axis, int sgn, double 
         } else {
             log_event(s, dm, step, p, -1, ORC_EV_WALL);
             s->cnt[ORC_C_WALL]++;
-            if (!s->spring && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
+            if (!s->spring && !s->no_skip && reflected && periodic(s, dm, step, p, xref, &xmax)) return ORC_OK;
             reflected = 1;
             xref = xmax;
             sgn = -sgn;
@@ -1002,7 +1011,7 @@ static int sweep_impl(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int t
         const int n = s->n;
         const int P = tiling == 2 ? D + 1 : D;
         if ((tiling == 1 && (D < 2 || n % D != 0 || (n / D) % 2 != 0)) ||
-            (tiling == 2 && (D < 1 || n % P != 0 || n / P < 2))) {
+            (tiling == 2 && (D < 2 || n % P != 0 || n / P < 2))) {
             free(mot);
             free(starts);
             return ORC_E_BOX;

@@ -98,6 +98,10 @@ int orc_set_options(orc_sys *s, int64_t event_cap, int check);
  * (ORC_E_ARG) while springs are on. */
 int orc_set_swap(orc_sys *s, int on);
 
+/* The periodic reduction (whole periods of an EC dropped after its second reflection) on (1, the
+ * default) or off (0: the plain loop of Sec. II steps 1-4, until x_max is used up). */
+int orc_set_periodic_skip(orc_sys *s, int on);
+
 /* Bonds as harmonic springs (k/2)(b - sigma)^2 of spring constant k > 0 (Eq. (2), in units
  * of k_B T / sigma^2), still capped at b_max; k = 0 (the default) gives tethers.  Refused
  * (ORC_E_ARG) for k < 0, a non-finite k, or while swap moves are on.  A single EC of
@@ -113,9 +117,9 @@ int64_t orc_log_count(const orc_sys *s);
 /* One sweep: tiling 0 = whole box (one domain, every bead motile), 1 = checkerboard of
  * D^3-cell domains in 8 colour phases (n % D == 0, n / D even), 2 = tile-joint (Sec. II.A):
  * D^3-cell tiles at pitch D + 1, the cell after each tile along every axis an immotile joint,
- * all tiles in one phase (n % (D + 1) == 0, n / (D + 1) >= 2; D = 1 allowed: the offset in
- * [0, D + 1) still moves the partition).  colour_mask selects which phases run (bit 0 alone
- * for tile-joint). */
+ * all tiles in one phase (n % (D + 1) == 0, n / (D + 1) >= 2, D >= 2: a 1-cell tile has a wall
+ * at every face, so no bead could ever leave its cell).  colour_mask selects which phases run
+ * (bit 0 alone for tile-joint). */
 int orc_sweep(orc_sys *s, int64_t n_ec, double ell, uint64_t seed, int tiling, int D,
               uint32_t colour_mask);
 

@@ -199,8 +199,10 @@ ecmc_status plan_melt(double L, int64_t nb, double lmax, int n_req, int D_req, i
         mp.nd = n / D;
         mp.ndpc = (mp.nd / 2) * (mp.nd / 2) * (mp.nd / 2);
     } else if (tiling == ECMC_TILING_JOINT) {
-        if (D < 1 || n % (D + 1) != 0 || n / (D + 1) < 2)
-            return fail(c, ECMC_E_BOX, "tile-joint needs D >= 1, n %% (D + 1) == 0 and n/(D + 1) >= 2 (melt %d: n = %d, D = %d)",
+        // D >= 2: a 1-cell tile has a wall at every face, so no bead could ever leave the cell
+        // it started in, whatever the offset (the partition must let every bead move, Sec. II.A)
+        if (D < 2 || n % (D + 1) != 0 || n / (D + 1) < 2)
+            return fail(c, ECMC_E_BOX, "tile-joint needs D >= 2, n %% (D + 1) == 0 and n/(D + 1) >= 2 (melt %d: n = %d, D = %d)",
                         m, n, D);
         mp.D = D;
         mp.nd = n / (D + 1);

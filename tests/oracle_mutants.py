@@ -22,14 +22,16 @@ MUTANTS = {
     "dpar_sign": ("*dpar = sgn > 0 ? d[axis] : -d[axis];", "*dpar = d[axis];"),
     "no_tether": ("consider(&best, orc_bond_x(s, dpar, dperp2, g ? g[t] : -1.0), q, 1, dpar);\n    }\n    return best;",
                   "}\n    return best;"),
-    "delta_sign": ("s->sum_delta += b.dpar - b.x;", "s->sum_delta += b.dpar + b.x;"),
+    "delta_sign": ("ORC_C_TETHER_LIFT]++;\n                s->sum_delta += b.dpar - b.x;",
+                   "ORC_C_TETHER_LIFT]++;\n                s->sum_delta += b.dpar + b.x;"),
     "no_reflect": ("sgn = -sgn;\n            }\n            continue;", "p = b.j;\n            }\n            continue;"),
     "wall_pass": ("if (cell_in_domain(s, dm, cn)) {", "if (1) {"),
     "cell_skip": ("for (int dx = -1; dx <= 1; ++dx) {\n                const int raw",
                   "for (int dx = -1; dx <= 0; ++dx) {\n                const int raw"),
     "rg_index": ("if (rg2) rg2[q] = g / (double)N;", "if (rg2) rg2[q] = g / (double)(N - 1);"),
-    "pivot_rng": ("const int32_t p = mot[below(u[0], (uint32_t)m)];",
-                  "const int32_t p = mot[below(u[0], (uint32_t)(m > 1 ? m - 1 : m))];"),
+    "pivot_rng": ("const int32_t p = starts[below(u[0], (uint32_t)ms)];\n                            const uint32_t",
+                  "const int32_t p = starts[below(u[0], (uint32_t)(ms > 1 ? ms - 1 : ms))];\n"
+                  "                            const uint32_t"),
     "period_half": ("const double r = fmod(*xmax, W + W);", "const double r = fmod(*xmax, W);"),
     "swap_skip_j": ("        if (u >= 0 && dist2(s, rp, u == p ? rj : &s->r[3 * u]) > s->b2) return 0;\n", ""),
     "swap_image_sign": ("        s->img[3 * p + a] += sh;", "        s->img[3 * p + a] -= sh;"),
@@ -42,8 +44,8 @@ MUTANTS = {
     "ln_series_short": ("for (int n = 10; n >= 0; --n)", "for (int n = 8; n >= 0; --n)"),
     "ln_reduction": ("if (f < 0.70710678118654752440) {", "if (f < 0.5) {"),
     "pair_drop_z": ("const double r = sqrt((q0 + q1) + q2);", "const double r = sqrt(q0 + q1);"),
-    "pair_twice": ("for (int64_t j = i + 1; j < s->nb; ++j) {",
-                   "for (int64_t j = 0; j < s->nb; ++j) {\n            if (j == i) continue;"),
+    "pair_twice": ("for (int64_t j = i + 1; j < s->nb; ++j) {\n            double d[3];",
+                   "for (int64_t j = 0; j < s->nb; ++j) {\n            if (j == i) continue;\n            double d[3];"),
     "pair_no_image": ("for (int a = 0; a < 3; ++a) d[a] = mi(s, s->r[3 * j + a] - s->r[3 * i + a]);\n            const double q0",
                       "for (int a = 0; a < 3; ++a) d[a] = s->r[3 * j + a] - s->r[3 * i + a];\n            const double q0"),
     "r2n_lag_shift": ("sum[t2 - t] += (q0 + q1) + q2;", "sum[t2 - t - 1] += (q0 + q1) + q2;"),
@@ -54,6 +56,15 @@ MUTANTS = {
     "push_no_ignore": ("    if (s->push && dpar * dpar + dperp2 < s->ov2) return 0; /* push-off: an overlapping pair */\n", ""),
     "push_start_all": ("if (!s->push || overlaps_any(s, list[i])) out[k++] = list[i];", "out[k++] = list[i];"),
     "push_margin": ("s->ov2 = s->sig2 * (1.0 - 1e-9);", "s->ov2 = s->sig2 * (1.0 + 1e-9);"),
+    # the periodic reduction: applied from the first reflection on (it then ends every EC at its
+    # first reflection), or the switch to the plain loop ignored
+    "period_first_reflection": ("ORC_C_WALL]++;\n            if (!s->spring && !s->no_skip && reflected && periodic(",
+                                "ORC_C_WALL]++;\n            if (!s->spring && !s->no_skip && periodic("),
+    "plain_loop_ignored": ("s->no_skip = on ? 0 : 1;", "s->no_skip = 0;"),
+    # the zero-length cycle search never finds the repeated state
+    "cycle_never_detected": ("if (p == saved_p && sgn == saved_sgn && c == saved_c) {", "if (0) {"),
+    # tile-joint with 1-cell tiles accepted (no bead could leave its cell)
+    "joint_accepts_single_cells": ("(tiling == 2 && (D < 2 ||", "(tiling == 2 && (D < 1 ||"),
     "joint_moves": ("        if (((c[a] - dm->off[a]) % s->n + s->n) % s->n % dm->P >= dm->D) return 0;\n", ""),
     # equivalent mutants: no observable difference is expected
     # (W = 0 means every event between the two reflections had zero length, so the zero-length
@@ -82,7 +93,7 @@ def main(names):
         subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared", "-o", lib,
                         os.path.join(d, "m.c"), "-lm"], check=True)
         env = dict(os.environ, ECMC_ORACLE_LIB=lib)
-        r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
                             os.path.join(HERE, "test_oracle_pins.py")], env=env, capture_output=True, text=True,
                            cwd=ROOT)
         caught = r.returncode != 0

@@ -47,6 +47,14 @@ def test_workspace_size_and_geometry_errors():
     with pytest.raises(ecmc.EcmcError) as e:
         ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
     assert e.value.code == ecmc.E_BOX
+    o.tiling = ecmc.TILING_JOINT  # 1-cell tiles: a wall at every face, no bead ever leaves its cell
+    for n_cells in (0, 58, 76):
+        o.n_cells = n_cells
+        with pytest.raises(ecmc.EcmcError) as e:
+            ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o)
+        assert e.value.code == ecmc.E_BOX
+    o.domain_cells, o.n_cells = 2, 75  # 2^3-cell tiles at pitch 3
+    assert ecmc.ecmc_workspace_size(106.8551, 1.0, 1.4, 1 << 20, o) > 0
     o = ecmc.ecmc_default_options()
     with pytest.raises(ecmc.EcmcError) as e:
         ecmc.ecmc_workspace_size(5.0, 1.0, 1.4, 10, o)          # n = 3 < 4
@@ -165,19 +173,21 @@ def test_tuner_cache_key_and_file(tmp_path):
 
 
 def test_bench_partition_defaults():
-    """bench.py's workload geometry: tethers default to the 2^3-cell checkerboard, springs to 1-cell
-    tile-joint tiles; an explicit --tiling or --domain-cells wins; the tile-joint grid is divisible
-    by the pitch with cells wider than the bond cap."""
+    """bench.py's workload geometry: tethers and springs both default to the 2^3-cell checkerboard;
+    an explicit --tiling or --domain-cells wins; the tile-joint grid is divisible by the pitch with
+    cells wider than the bond cap; no default partition has domains or tiles of a single cell."""
     import argparse
     import bench
     ns = lambda **kw: argparse.Namespace(**{"workload": "c3", "tiling": None, "domain_cells": 0, "springs": 0.0, **kw})
     assert (bench.workload_of(ns())["tiling"], bench.workload_of(ns())["D"]) == (1, 2)
     w = bench.workload_of(ns(springs=30.0))
-    assert (w["tiling"], w["D"]) == (2, 1)
-    w = bench.workload_of(ns(springs=30.0, tiling="checker"))
     assert (w["tiling"], w["D"]) == (1, 2)
-    w = bench.workload_of(ns(springs=30.0, domain_cells=2))
+    w = bench.workload_of(ns(springs=30.0, tiling="joint"))
     assert (w["tiling"], w["D"]) == (2, 2)
+    w = bench.workload_of(ns(springs=30.0, tiling="joint", domain_cells=3))
+    assert (w["tiling"], w["D"]) == (2, 3)
     L = 106.85512104226243
     n = bench.grid_cells(L, 1.8, bench.workload_of(ns(springs=30.0)))
-    assert n == 58 and n % 2 == 0 and L / n > 1.8
+    assert n == 56 and n % 4 == 0 and L / n > 1.8
+    n = bench.grid_cells(L, 1.8, bench.workload_of(ns(springs=30.0, tiling="joint")))
+    assert n == 57 and n % 3 == 0 and L / n > 1.8

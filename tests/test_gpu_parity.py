@@ -679,28 +679,16 @@ def test_springs_c2_dense_melt_bit_exact(melt_c2_spring, exact, sched):
     assert n > 250_000
 
 
-@pytest.mark.parametrize("exact", [False, True])
-def test_springs_tile_joint_c1_event_sequence_bit_exact(melt_c1_spring, exact):
-    """Springs (k sigma^2 = 30, capped at 1.8 sigma) on the tile-joint partition with 1-cell tiles
-    at pitch 2 (n = 4: 8 tiles in one phase, the joints immotile): 3 sweeps of 256 ECs, every
-    event as in the oracle, both precisions."""
-    p, g, o = _pair(melt_c1_spring, ecmc.TILING_JOINT, D=1, n_cells=4, spring_k=30.0,
-                    precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
-    for s in range(3):
-        p.sweep(256, 10.0, 420 + s)
-    n, _ = _compare(g, o)
-    c = g.counters()
-    assert n > 5_000 and c["tether_lift"] > 50 and c["periodic"] == 0 and c["wall"] > 0
-
-
 def test_springs_tile_joint_c2_dense_melt_bit_exact(melt_c2_spring):
-    """The 500 x 32 spring melt (cap 1.6 sigma) on 1-cell tiles at pitch 2 (n = 16: 512 tiles),
-    the partition the spring benchmark runs: 2 sweeps of 16,000 ECs with ell = 20 sigma."""
-    p, g, o = _pair(melt_c2_spring, ecmc.TILING_JOINT, D=1, n_cells=16, log=40_000_000, spring_k=30.0)
+    """The 500 x 32 spring melt (cap 1.6 sigma) on 2^3-cell tiles at pitch 3 (n = 15: 125 tiles in
+    one phase, the joints immotile): 2 sweeps of 16,000 ECs with ell = 20 sigma, every event as in
+    the oracle."""
+    p, g, o = _pair(melt_c2_spring, ecmc.TILING_JOINT, D=2, n_cells=15, log=40_000_000, spring_k=30.0)
     for s in range(2):
         p.sweep(16000, 20.0, 520 + s)
     n, _ = _compare(g, o)
-    assert n > 250_000
+    c = g.counters()
+    assert n > 250_000 and c["tether_lift"] > 50 and c["periodic"] == 0 and c["wall"] > 0
 
 
 @pytest.fixture(scope="module")
@@ -709,12 +697,12 @@ def melt_c3_spring():
 
 
 def test_springs_tile_joint_c3_full_size_clean_and_precision_exact(melt_c3_spring):
-    """The spring benchmark's configuration at full size (1,048,576 beads, cap 1.8 sigma, 1-cell tiles
-    at pitch 2 on 58^3 cells): one sweep in each precision ends in identical states with identical
-    counters, and the device state check finds no overlap, stretched bond or misplaced bead."""
+    """The 1,048,576-bead spring melt (cap 1.8 sigma) at full size on 2^3-cell tiles at pitch 3
+    (57^3 cells): one sweep in each precision ends in identical states with identical counters,
+    and the device state check finds no overlap, stretched bond or misplaced bead."""
     runs = []
     for prec in (ecmc.PREC_MIXED, ecmc.PREC_FP64):
-        g = ecmc.Melt.from_melt(melt_c3_spring, ecmc.Options(tiling=ecmc.TILING_JOINT, domain_cells=1, n_cells=58,
+        g = ecmc.Melt.from_melt(melt_c3_spring, ecmc.Options(tiling=ecmc.TILING_JOINT, domain_cells=2, n_cells=57,
                                                              spring_k=30.0, precision=prec))
         g.sweep(melt_c3_spring.n_beads, 20.0, 88)
         g.synchronize()
@@ -986,26 +974,47 @@ def test_c4_full_batch_sampled_melts_match_the_oracle():
 
 # ------------------------------------------------------------------ tile-joint partition (Sec. II.A)
 @pytest.mark.parametrize("exact", [False, True])
-def test_tile_joint_c1_event_sequence_bit_exact(melt_c1, exact):
-    """The tile-joint partition on the 16 x 16 melt (n = 4, tiles of 1 cell at pitch 2: 8 tiles,
-    all at once; joints immotile): 4 sweeps of 256 ECs, every event as in the oracle, both
-    precisions."""
-    p, g, o = _pair(melt_c1, ecmc.TILING_JOINT, D=1, n_cells=4, precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
-    for s in range(4):
-        p.sweep(256, 10.0, 600 + s)
+def test_tile_joint_c3_subsample_event_sequence_bit_exact(exact):
+    """The tile-joint partition on a 64 x 64 melt at eta = 0.45 (n = 12: 2^3-cell tiles at pitch 3,
+    64 tiles in one phase; joints immotile): 3 sweeps of 4,096 ECs, every event as in the oracle,
+    both precisions."""
+    m = inputs.lattice_chains(64, 64, 0.45, seed=7)
+    p, g, o = _pair(m, ecmc.TILING_JOINT, D=2, n_cells=12, log=20_000_000,
+                    precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
+    for s in range(3):
+        p.sweep(4096, 20.0, 600 + s)
     n, _ = _compare(g, o)
-    assert n > 2_000
+    assert n > 50_000 and g.counters()["wall"] > 0
 
 
-@pytest.mark.parametrize("D", [1, 2])
-def test_tile_joint_c2_dense_melt_bit_exact(melt_c2, D):
-    """Tile-joint on the 500 x 32 melt at eta = 0.45 (n = 18: pitch 2 with 1-cell tiles, 729 tiles;
-    pitch 3 with 2^3-cell tiles, 216 tiles), 2 sweeps of 16,000 ECs with ell = 20 sigma."""
-    p, g, o = _pair(melt_c2, ecmc.TILING_JOINT, D=D, n_cells=18, log=40_000_000)
+@pytest.mark.parametrize("D,n_cells", [(2, 18), (5, 18)])
+def test_tile_joint_c2_dense_melt_bit_exact(melt_c2, D, n_cells):
+    """Tile-joint on the 500 x 32 melt at eta = 0.45 (n = 18: pitch 3 with 2^3-cell tiles, 216
+    tiles; pitch 6 with 5^3-cell tiles, 27 tiles), 2 sweeps of 16,000 ECs with ell = 20 sigma."""
+    p, g, o = _pair(melt_c2, ecmc.TILING_JOINT, D=D, n_cells=n_cells, log=40_000_000)
     for s in range(2):
         p.sweep(16000, 20.0, 700 + s)
     n, _ = _compare(g, o)
     assert n > 100_000
+
+
+# ------------------------------------------------------------------ zero-length cycles
+@pytest.mark.parametrize("exact", [False, True])
+def test_zero_length_cycle_event_sequence_bit_exact(exact):
+    """Three beads (sigma = 5, b_max = 6, every distance exact) where a move along x, or a move of
+    the tethered pair along y or z, is a run of zero-length events that comes round for ever (A
+    touches B, B's tether to C is taut, C touches A; the tether alone stops B and C across it).
+    Whole-box sweeps of 6 ECs: the GPU ends the same ECs with CYCLE at the same step as the
+    oracle, in both precisions, and what moves freely moves the same."""
+    c = np.array([16.0, 16.0, 16.0])
+    pos = np.array([c - [3.0, 4.0, 0.0], c, c - [6.0, 0.0, 0.0]])
+    m = inputs.Melt(L=32.0, positions=pos, bonds=np.array([[1, 2]], dtype=np.int32), sigma=5.0, b_max=6.0)
+    p, g, o = _pair(m, ecmc.TILING_WHOLE, n_cells=4, log=10_000,
+                    precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED)
+    for s in range(4):
+        p.sweep(6, 7.5, 40 + s)
+    n, _ = _compare(g, o)
+    assert g.counters()["cycle"] >= 2
 
 
 # ------------------------------------------------------------------ statistics on the GPU

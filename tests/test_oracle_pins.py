@@ -1181,11 +1181,11 @@ def test_pair_correlation_of_uniform_points_is_one():
 
 
 # ------------------------------------------------------------------ tile-joint partition (Sec. II.A)
-@pytest.mark.parametrize("D,L", [(1, 9.0), (2, 9.0)])
+@pytest.mark.parametrize("D,L", [(2, 9.0), (3, 12.0)])
 def test_tile_joint_dimer_bond_length_distribution(D, L):
     """The tile-joint partition (tiles of D^3 cells at pitch D + 1, immotile joints between them,
     all tiles at once) samples the isolated dimer's p(r) ~ r^2 on [sigma, b_max] like the other
-    schedules (n = 6 cells: pitch 2 with D = 1, pitch 3 with D = 2)."""
+    schedules (pitch 3 on 6 cells, pitch 4 on 8 cells)."""
     r = _dimer_samples(2, D, L, 12000, seed=31 + D)
     assert r.min() >= 1.0 - 1e-10 and r.max() <= 1.4 + 1e-10
     ks = _ks_uniform_r2(r[::5])
@@ -1195,7 +1195,7 @@ def test_tile_joint_dimer_bond_length_distribution(D, L):
     assert abs(r.mean() - mean_exact) < 5 * blocks.std() / math.sqrt(len(blocks))
 
 
-@pytest.mark.parametrize("D", [1, 2])
+@pytest.mark.parametrize("D", [2, 5])
 def test_tile_joint_sweep_leaves_the_joints_alone(D):
     """One tile-joint sweep of the 500 x 32 melt on 18^3 cells: beads in joint cells (the cell
     after each tile along any axis, from the sweep's offsets (0, 0, sweep, 1)) keep their
@@ -1242,3 +1242,185 @@ def test_end_to_end_distribution_of_long_random_walks_is_gaussian():
     ok = e >= 5
     chi2 = float(np.sum((h[ok] - e[ok]) ** 2 / e[ok]))
     assert stats.chi2.sf(chi2, ok.sum() - 1) > 1e-3, (chi2, ok.sum())
+
+
+def test_partitions_with_single_cell_domains_are_refused():
+    """Domains (checkerboard) or tiles (tile-joint) of one cell are refused: a 1-cell domain has a
+    wall at every face, so no bead could ever leave the cell it starts in, whatever the offset,
+    and the sampler would not be ergodic (Sec. II.A: the decomposition changes so that it is).
+    With 2-cell tiles beads do change cells."""
+    m = inputs.lattice_chains(500, 32, 0.45, seed=2)
+    o = oracle.Oracle.from_melt(m, n_cells=18)
+    for tiling in (1, 2):
+        with pytest.raises(oracle.OracleError):
+            o.sweep(m.n_beads, 20.0, 1, tiling=tiling, D=1)
+    c0 = o.cells()
+    for k in range(3):
+        o.sweep(m.n_beads, 20.0, 50 + k, tiling=2, D=2)
+    assert np.count_nonzero(np.any(o.cells() != c0, axis=1)) > 500
+
+
+# ------------------------------------------------------------------ decomposed short chains (Sec. II.A)
+def _tiled_chain_run(N, L, n_cells, tiling, D, sweeps, ell, seed, swap=False, spring_k=0.0, b_max=1.4):
+    """R^2 and R_g^2 of an isolated chain after each of `sweeps` decomposed sweeps of 2N ECs."""
+    m = inputs.isolated_chain(N, L, seed=seed, b_max=b_max)
+    o = oracle.Oracle.from_melt(m, n_cells=n_cells)
+    o.set_swap(swap)
+    o.set_spring(spring_k)
+    R2 = np.empty(sweeps)
+    Rg2 = np.empty(sweeps)
+    for k in range(sweeps):
+        o.sweep(2 * N, ell, 31 * seed + 7919 * k, tiling=tiling, D=D)
+        x = o.positions()
+        x = x - x[0]
+        x -= L * np.round(x / L)
+        R2[k] = np.sum((x[-1] - x[0]) ** 2)
+        Rg2[k] = np.mean(np.sum((x - x.mean(axis=0)) ** 2, axis=1))
+    c, _ = o.counters()
+    return R2, Rg2, c
+
+
+def _agrees_with_blocks(a, ref, n_blocks=60, z=4.0):
+    """Mean of a correlated series (block averages give its error) against independent samples."""
+    bl = a[: len(a) // n_blocks * n_blocks].reshape(n_blocks, -1).mean(axis=1)
+    err = math.sqrt(bl.var(ddof=1) / n_blocks + ref.var() / len(ref))
+    return abs(a.mean() - ref.mean()) < z * err, (a.mean(), ref.mean(), err)
+
+
+@pytest.mark.parametrize("tiling,D,n_cells", [(1, 2, 8), (2, 2, 9)])
+@pytest.mark.parametrize("N,swap", [(3, False), (5, False), (3, True), (5, True)])
+def test_short_chain_on_every_partition_matches_direct_sampler(tiling, D, n_cells, N, swap):
+    """The decomposition leaves the sampled distribution unchanged (Sec. II.A): an isolated
+    tethered chain in a box of 13.4 sigma, swept on the 2^3-cell checkerboard (8^3 cells, chains
+    spanning several domains) and on 2^3-cell tile-joint tiles (9^3 cells), with and without swap
+    moves, has the <R^2> and <R_g^2> of exact direct rejection sampling.  60,000 sweeps; the
+    error of the EC means comes from 60 block averages."""
+    R2, Rg2, c = _tiled_chain_run(N, 13.4, n_cells, tiling, D, 60000, 6.1, seed=N + 10 * tiling + 100 * swap,
+                                  swap=swap)
+    ref = _direct_chain_samples(np.random.default_rng(300 + N), N, 40000)
+    R2r, Rg2r, _ = _shape(ref)
+    for a, r in ((R2, R2r), (Rg2, Rg2r)):
+        ok, info = _agrees_with_blocks(a, r)
+        assert ok, info
+    assert c[oracle.C_WALL] > 1000 and c[oracle.C_CROSS] > 1000  # the chain meets walls and crosses cells
+    assert (c[oracle.C_SWAP] > 1000) == swap
+
+
+@pytest.mark.parametrize("tiling,D,n_cells", [(1, 2, 8), (2, 2, 6)])
+@pytest.mark.parametrize("N", [3, 5])
+def test_short_spring_chain_on_every_partition_matches_direct_sampler(tiling, D, n_cells, N):
+    """As above for harmonic springs (k sigma^2 = 10, capped at 2 sigma; Eq. (2)) in a box of
+    16.8 sigma: the 2^3-cell checkerboard on 8^3 cells and 2^3-cell tile-joint tiles on 6^3
+    cells against direct Boltzmann sampling of the spring chain."""
+    k = 10.0
+    R2, Rg2, c = _tiled_chain_run(N, 16.8, n_cells, tiling, D, 60000, 4.1, seed=N + 10 * tiling, spring_k=k,
+                                  b_max=2.0)
+    ref = _direct_spring_chain_samples(np.random.default_rng(400 + N), N, 40000, k)
+    R2r, Rg2r, _ = _shape(ref)
+    for a, r in ((R2, R2r), (Rg2, Rg2r)):
+        ok, info = _agrees_with_blocks(a, r)
+        assert ok, info
+    assert c[oracle.C_WALL] > 1000 and c[oracle.C_CROSS] > 1000
+
+
+# ------------------------------------------------------------------ the periodic reduction against the plain loop
+def _by_ec(log):
+    out = {}
+    for e in log:
+        out.setdefault((int(e["domain"]), int(e["ec"])), []).append((int(e["pivot"]), int(e["target"]),
+                                                                      int(e["kind"])))
+    return out
+
+
+@pytest.mark.parametrize("ell,pos_tol", [(3.0, 1e-9), (10.0, None)])
+def test_periodic_reduction_matches_the_plain_loop(melt_c1, ell, pos_tol):
+    """Sec. II steps 1-4 run an EC until x_max is used up.  After its second reflection an EC
+    retraces its path between the two stops (every lift is undone by the reverse lift), so the
+    plain loop's events are those of the reduced EC with whole periods inserted: the events up to
+    the second reflection, then m > 0 repeats of a block of 2 (R2 - R1) events (R1, R2 the two
+    reflections), then the reduced EC's remaining events.  Checked for every EC of 20
+    checkerboard sweeps of the 16 x 16 melt, one colour phase at a time from the same state.
+    Positions agree to 1e-9 sigma at ell = 3 sigma; at ell = 10 sigma the plain loop's hundreds
+    of bounces accumulate rounding (a few 1e-5 sigma), and only the events are compared."""
+    a = oracle.Oracle.from_melt(melt_c1, n_cells=4)
+    b = oracle.Oracle.from_melt(melt_c1, n_cells=4)
+    b.set_periodic_skip(False)
+    a.enable_log(200000)
+    b.enable_log(4000000)
+    refl = (oracle.EV_HS_REFLECT, oracle.EV_TETHER_REFLECT, oracle.EV_WALL)
+    n_ec = n_per = 0
+    for s in range(20):
+        sc = a.sweep_counter
+        for col in range(8):
+            na, nb = len(a.event_log()), len(b.event_log())
+            state = (a.positions(), a.cells(), a.images(), sc)
+            for o in (a, b):
+                o.set_state(*state)
+                o.sweep(256, ell, 500 + s, tiling=1, D=2, colour_mask=1 << col)
+            ga, gb = _by_ec(a.event_log()[na:]), _by_ec(b.event_log()[nb:])
+            assert set(ga) == set(gb)
+            for key, A in ga.items():
+                B = gb[key]
+                kinds = [e[2] for e in A]
+                n_ec += 1
+                if oracle.EV_PERIOD not in kinds:
+                    assert A == B, key
+                    continue
+                n_per += 1
+                iP = kinds.index(oracle.EV_PERIOD)
+                r = [i for i in range(iP) if kinds[i] in refl]
+                assert len(r) == 2 and r[1] == iP - 1
+                P = 2 * (r[1] - r[0])
+                pre, suf = A[:iP], A[iP + 1:]
+                mid = B[len(pre):len(B) - len(suf)]
+                assert B[:len(pre)] == pre and B[len(B) - len(suf):] == suf, key
+                assert len(mid) > 0 and len(mid) % P == 0, (key, len(mid), P)
+                assert all(mid[i] == mid[i + P] for i in range(len(mid) - P)), key
+            if pos_tol is not None:
+                assert np.abs(a.positions() - b.positions()).max() <= pos_tol
+        a.set_state(a.positions(), a.cells(), a.images(), sc + 1)
+    assert n_ec > 4000 and n_per > 1000
+    cb, _ = b.counters()
+    assert cb[oracle.C_PERIOD] == 0
+
+
+def _zero_length_cycle_system():
+    """Three beads in a plane (sigma = 5, b_max = 6, so that every distance below is exact):
+    B at the centre, C 6 behind it along -x (their tether taut), A at B - (3, 4, 0), touching B
+    and C.  Along +x every event has length 0: A touches B, B's tether to C is taut, C touches
+    A, and so on for ever; along -x the same cycle runs the other way round (B touches A, A
+    touches C, C's tether to B is taut).  Along z the taut tether alone stops B and C, each
+    handing the move to the other; A moves freely."""
+    c = np.array([16.0, 16.0, 16.0])
+    pos = np.array([c - [3.0, 4.0, 0.0], c, c - [6.0, 0.0, 0.0]])
+    return pos, [[1, 2]]
+
+
+@pytest.mark.parametrize("skip", [True, False])
+def test_zero_length_cycle_is_detected(skip):
+    """A run of zero-length events that comes back to the same (pivot, direction, pivot cell)
+    repeats forever with nothing moving; the cycle search ends the EC (logged CYCLE) once the
+    cycle has come round, with every position unchanged, with and without the periodic
+    reduction (the plain loop has no other way to stop).  The free move of A along z ends
+    normally."""
+    pos, bonds = _zero_length_cycle_system()
+    cases = [(p0, 0, {0: 1, 1: 2, 2: 0}) for p0 in range(3)] + [(p0, 1, {1: 0, 0: 2, 2: 1}) for p0 in range(3)]
+    cases += [(1, 4, {1: 2, 2: 1}), (2, 5, {1: 2, 2: 1})]
+    for p0, d, nxt in cases:
+        o = oracle.Oracle(32.0, 5.0, 6.0, pos, bonds, n_cells=4)
+        o.set_periodic_skip(skip)
+        o.set_options(event_cap=1000, check=2)
+        o.enable_log(100)
+        o.run_ec(p0, d, 7.5)
+        log = o.event_log()
+        assert log["kind"][-1] == oracle.EV_CYCLE and np.all(log["kind"][:-1] <= oracle.EV_TETHER_LIFT)
+        assert 2 <= len(log) <= 9 and int(log["pivot"][0]) == p0
+        assert all(nxt[int(e["pivot"])] == int(e["target"]) for e in log[:-1]), log
+        assert np.array_equal(o.positions(), pos)
+        c, _ = o.counters()
+        assert c[oracle.C_CYCLE] == 1
+    o = oracle.Oracle(32.0, 5.0, 6.0, pos, bonds, n_cells=4)
+    o.enable_log(100)
+    o.run_ec(0, 4, 7.5)
+    assert list(o.event_log()["kind"]) == [oracle.EV_END]
+    assert o.positions()[0, 2] == 16.0 + 7.5
