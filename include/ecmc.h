@@ -189,6 +189,17 @@ void ecmc_default_options(ecmc_options *opt);
 ecmc_status ecmc_workspace_size(double box, double sigma, double l_max, int64_t n_beads,
                                 const ecmc_options *opt, size_t *bytes);
 
+/* The single-precision screen of the event search (ECMC_PREC_MIXED), as derived for a melt
+ * of n_beads in a cube of edge box with these options (host only, no device is touched).
+ * Screening coordinates are the frame coordinates rounded once to float; for the candidate
+ * formulas of Sec. II (contact and tether distances) the screen's float estimate lies within
+ * err of the exact FP64 distance, a float d_par above p_sure means the exact one is positive,
+ * and a float d_perp^2 below in_lo (at or above in_hi) means the exact one is below (not below)
+ * sigma^2.  out[4] = {p_sure, in_lo, in_hi, err}; geo[3] = {cell edge h, frame edge X over
+ * which the coordinates range (L for the whole box), box L}.  Errors as ecmc_workspace_size. */
+ecmc_status ecmc_screen_constants(double box, double sigma, double l_max, int64_t n_beads,
+                                  const ecmc_options *opt, float out[4], double geo[3]);
+
 /* Bytes of device workspace ecmc_init_batch needs for these melts (positions and bonds are
  * not read; n_beads and n_bonds are). */
 ecmc_status ecmc_workspace_size_batch(int32_t n_melts, const ecmc_melt_desc *melts, double sigma,

@@ -673,6 +673,24 @@ ecmc_status ecmc_workspace_size(double box, double sigma, double l_max, int64_t 
     return ECMC_OK;
 }
 
+ecmc_status ecmc_screen_constants(double box, double sigma, double l_max, int64_t n_beads, const ecmc_options *opt,
+                                  float out[4], double geo[3]) {
+    if (!opt || !out || !geo) return fail(nullptr, ECMC_E_ARG, "null argument");
+    const ecmc_melt_desc d = single_melt(box, n_beads, nullptr, 0, nullptr, *opt);
+    Plan p;
+    ecmc_status st = plan(melt_inputs(1, &d), sigma, l_max, *opt, p, nullptr);
+    if (st) return st;
+    const MeltPlan &mp = p.melts[0];
+    out[0] = mp.p_sure;
+    out[1] = mp.in_lo;
+    out[2] = mp.in_hi;
+    out[3] = mp.err_f;
+    geo[0] = mp.h;
+    geo[1] = p.whole ? mp.L : (mp.D + 2) * mp.h;
+    geo[2] = mp.L;
+    return ECMC_OK;
+}
+
 ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, int64_t n_beads,
                       const double *positions, int64_t n_bonds, const int32_t *bonds, const ecmc_options *opt) {
     if (!opt) return fail(nullptr, ECMC_E_ARG, "null argument");

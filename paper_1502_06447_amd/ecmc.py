@@ -112,7 +112,7 @@ EXPORTS = (
     "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
     "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
     "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff", "ecmc_internal_distances",
-    "ecmc_check_state",
+    "ecmc_check_state", "ecmc_screen_constants",
 )
 
 
@@ -134,6 +134,7 @@ def lib():
     sig = {
         "ecmc_default_options": (None, [opt_p]),
         "ecmc_workspace_size": (st, [dbl, dbl, dbl, i64, opt_p, P(ctypes.c_size_t)]),
+        "ecmc_screen_constants": (st, [dbl, dbl, dbl, i64, opt_p, vp, vp]),
         "ecmc_init": (st, [P(vp), dbl, dbl, dbl, i64, vp, i64, vp, opt_p]),
         "ecmc_sweep": (st, [vp, i64, dbl, u64]),
         "ecmc_sweep_colours": (st, [vp, i64, dbl, u64, u32]),
@@ -199,6 +200,17 @@ def ecmc_workspace_size(box: float, sigma: float, l_max: float, n_beads: int, op
     _check(lib().ecmc_workspace_size(box, sigma, l_max, n_beads, ctypes.byref(opt), ctypes.byref(n)),
            "ecmc_workspace_size")
     return n.value
+
+
+def ecmc_screen_constants(box: float, sigma: float, l_max: float, n_beads: int, opt: ecmc_options) -> dict:
+    """The single-precision screen's constants for this geometry (host only): p_sure, in_lo, in_hi,
+    err (float32 values) and the cell edge h, frame edge X and box L."""
+    out = np.zeros(4, dtype=np.float32)
+    geo = np.zeros(3, dtype=np.float64)
+    _check(lib().ecmc_screen_constants(box, sigma, l_max, n_beads, ctypes.byref(opt), out.ctypes.data,
+                                       geo.ctypes.data), "ecmc_screen_constants")
+    return {"p_sure": out[0], "in_lo": out[1], "in_hi": out[2], "err": out[3], "h": float(geo[0]),
+            "X": float(geo[1]), "L": float(geo[2])}
 
 
 def ecmc_init(box, sigma, l_max, positions, bonds, opt: ecmc_options):

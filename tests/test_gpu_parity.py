@@ -987,10 +987,10 @@ def test_tile_joint_c3_subsample_event_sequence_bit_exact(exact):
     assert n > 50_000 and g.counters()["wall"] > 0
 
 
-@pytest.mark.parametrize("D,n_cells", [(2, 18), (5, 18)])
+@pytest.mark.parametrize("D,n_cells", [(2, 18), (3, 16)])
 def test_tile_joint_c2_dense_melt_bit_exact(melt_c2, D, n_cells):
     """Tile-joint on the 500 x 32 melt at eta = 0.45 (n = 18: pitch 3 with 2^3-cell tiles, 216
-    tiles; pitch 6 with 5^3-cell tiles, 27 tiles), 2 sweeps of 16,000 ECs with ell = 20 sigma."""
+    tiles; n = 16: pitch 4 with 3^3-cell tiles, 64 tiles), 2 sweeps of 16,000 ECs with ell = 20 sigma."""
     p, g, o = _pair(melt_c2, ecmc.TILING_JOINT, D=D, n_cells=n_cells, log=40_000_000)
     for s in range(2):
         p.sweep(16000, 20.0, 700 + s)
