@@ -349,6 +349,16 @@ ecmc_status ecmc_end_to_end_histogram(ecmc_ctx *ctx, int32_t nbins, double r_max
  * call.  Synchronises. */
 ecmc_status ecmc_internal_distances(ecmc_ctx *ctx, int32_t n_max, double *r2, int64_t *pairs);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, hosts that forbid allocation): ecmc_internal_distances with its per-block partial
+ * sums in a static array of the library (8 MiB per device, resolved once per device at init,
+ * held until the process ends) instead of the context's workspace.  Arguments, results,
+ * errors and the summation order are those of ecmc_internal_distances, so the two return the
+ * same values for a state.  Allocates nothing, host or device.  Every call on one device uses
+ * that device's one array: calls that overlap on a device (two threads, two contexts, two
+ * streams) race and give wrong sums.  Synchronises. */
+ecmc_status ecmc_internal_distances_noalloc(ecmc_ctx *ctx, int32_t n_max, double *r2, int64_t *pairs);
+
 /* Pair counts behind the pair correlation g(r): the pairs i < j of one melt (summed over the
  * melts of a batch) whose minimum-image distance r is below r_max, binned by
  * floor(r / r_max * nbins) (clamped to nbins - 1).  r_max may not exceed the smallest cell

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,7 +19,31 @@
 
 using namespace ecmc;
 
+// Device memory of ecmc_internal_distances_noalloc: the per-block partial sums of R^2(n), as many
+// as the internal-distance area of a workspace can hold (LAG_SLOTS) plus the lag totals, 8 MiB
+// on each device.  Host code never names the array in a launch or a copy: its name there is a
+// host-side stand-in, and the device address comes from hipGetSymbolAddress at init.
+static constexpr int64_t NOALLOC_LAG_SLOTS = LAG_SLOTS;
+static __device__ __align__(256) double scratch[NOALLOC_LAG_SLOTS + LAG_MAX_BEADS];
+
 namespace {
+
+// per device: the address of scratch, resolved once with that device current
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES] = {};
+
+hipError_t resolve_scratch(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[dev] = (double *)ptr;
+    return hipSuccess;
+}
 
 constexpr int64_t DEFAULT_EVENT_CAP = 10000000;
 constexpr int DEFAULT_CAP = 16;
@@ -110,6 +135,7 @@ Layout make_layout(const Plan &p, int64_t npoly_max, int cap, int64_t log_cap) {
 
 struct ecmc_ctx {
     ecmc_options opt;
+    int device = -1;                  // the device current at init
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;       // second stream for the larger staging tiers (by phases)
     hipEvent_t fork = nullptr, join = nullptr;
@@ -620,6 +646,15 @@ ecmc_status init_impl(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *mel
         if (c->chain_count.size() <= len) c->chain_count.resize(len + 1, 0);
         c->chain_count[len]++;
     }
+    {
+        // the device of the context, with the address of its static scratch (once per device)
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = resolve_scratch(dev);
+        if (e != hipSuccess)
+            return bail(fail(c, ECMC_E_DEVICE, "resolving the static scratch of device %d: %s", dev, hipGetErrorString(e)));
+        c->device = dev;
+    }
     if ((st = upload(c, hs, true))) return bail(st);
     *out = c;
     return ECMC_OK;
@@ -996,6 +1031,44 @@ ObsArgs obs_args(ecmc_ctx *c) {
     o.bmax = c->lmax;
     return o;
 }
+
+// R^2(n) with the per-block partial sums in lagsum, which holds slots + LAG_MAX_BEADS doubles
+// (blocks x lags, then the lag totals).  The number of blocks depends only on the state and on
+// slots, and every slot the sums read is written first in the same call, so nothing is cleared.
+ecmc_status internal_distances(ecmc_ctx *c, int32_t n_max, double *r2, int64_t *pairs, double *lagsum, int64_t slots) {
+    if (!r2) return fail(c, ECMC_E_ARG, "null argument");
+    if (n_max < 0 || n_max >= LAG_MAX_BEADS) return fail(c, ECMC_E_ARG, "n_max must be in [0, %d]", LAG_MAX_BEADS - 1);
+    const int64_t longest = (int64_t)c->chain_count.size() - 1;
+    if (longest > LAG_MAX_BEADS)
+        return fail(c, ECMC_E_ARG, "internal distances take chains of at most %d beads (the longest has %lld)",
+                    LAG_MAX_BEADS, (long long)longest);
+    for (int32_t n = 0; n <= n_max; ++n) {
+        r2[n] = 0.0;
+        if (pairs) pairs[n] = 0;
+    }
+    if (longest < 1) return ECMC_OK;  // no beads
+    const int nlag = (int)std::min<int64_t>(n_max, longest - 1) + 1;
+    // one polymer per block while the partial sums fit
+    const int rows = (int)std::min<int64_t>(c->npoly, slots / nlag);
+    if (rows < 1 || (int64_t)rows * nlag + nlag > slots + LAG_MAX_BEADS)
+        return fail(c, ECMC_E_ARG, "the partial sums of %d lags do not fit %lld slots", nlag, (long long)slots);
+    ObsArgs o = obs_args(c);
+    o.nlag = nlag;
+    o.lagsum = lagsum;
+    HIP_OK(c, launch_internal(o, rows, (int)longest, c->stream));
+    ecmc_status st = check_device(c);
+    if (st) return st;
+    // the lag totals land in r2[0..nlag) and are divided there by the pair counts
+    HIP_OK(c, hipMemcpy(r2, o.lagsum + (size_t)rows * nlag, 8 * (size_t)nlag, hipMemcpyDeviceToHost));
+    for (int32_t n = 0; n <= n_max; ++n) {
+        // pairs n bonds apart: max(N - n, 0) in a chain of N beads
+        int64_t cnt = 0;
+        for (size_t len = (size_t)n + 1; len < c->chain_count.size(); ++len) cnt += c->chain_count[len] * ((int64_t)len - n);
+        r2[n] = n < nlag && cnt > 0 ? r2[n] / (double)cnt : 0.0;
+        if (pairs) pairs[n] = cnt;
+    }
+    return ECMC_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1080,38 +1153,15 @@ ecmc_status ecmc_end_to_end_histogram(ecmc_ctx *c, int32_t nbins, double r_max, 
 }
 
 ecmc_status ecmc_internal_distances(ecmc_ctx *c, int32_t n_max, double *r2, int64_t *pairs) {
-    if (!c || !r2) return fail(c, ECMC_E_ARG, "null argument");
-    if (n_max < 0 || n_max >= LAG_MAX_BEADS) return fail(c, ECMC_E_ARG, "n_max must be in [0, %d]", LAG_MAX_BEADS - 1);
-    const int64_t longest = (int64_t)c->chain_count.size() - 1;
-    if (longest > LAG_MAX_BEADS)
-        return fail(c, ECMC_E_ARG, "internal distances take chains of at most %d beads (the longest has %lld)",
-                    LAG_MAX_BEADS, (long long)longest);
-    if (longest < 1) {  // no beads
-        for (int32_t n = 0; n <= n_max; ++n) {
-            r2[n] = 0.0;
-            if (pairs) pairs[n] = 0;
-        }
-        return ECMC_OK;
-    }
-    const int nlag = (int)std::min<int64_t>(n_max, longest - 1) + 1;
-    // one polymer per block while the partial sums fit
-    const int rows = (int)std::min<int64_t>(c->npoly, c->lay.lag_slots / nlag);
-    ObsArgs o = obs_args(c);
-    o.nlag = nlag;
-    o.lagsum = c->dev<double>(c->lay.lags);
-    HIP_OK(c, launch_internal(o, rows, (int)longest, c->stream));
-    ecmc_status st = check_device(c);
-    if (st) return st;
-    std::vector<double> total(nlag);
-    HIP_OK(c, hipMemcpy(total.data(), o.lagsum + (size_t)rows * nlag, 8 * (size_t)nlag, hipMemcpyDeviceToHost));
-    for (int32_t n = 0; n <= n_max; ++n) {
-        // pairs n bonds apart: max(N - n, 0) in a chain of N beads
-        int64_t cnt = 0;
-        for (size_t len = (size_t)n + 1; len < c->chain_count.size(); ++len) cnt += c->chain_count[len] * ((int64_t)len - n);
-        r2[n] = n < nlag && cnt > 0 ? total[n] / (double)cnt : 0.0;
-        if (pairs) pairs[n] = cnt;
-    }
-    return ECMC_OK;
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    return internal_distances(c, n_max, r2, pairs, c->dev<double>(c->lay.lags), c->lay.lag_slots);
+}
+
+ecmc_status ecmc_internal_distances_noalloc(ecmc_ctx *c, int32_t n_max, double *r2, int64_t *pairs) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    double *ptr = c->device >= 0 && c->device < MAX_DEVICES ? g_scratch[c->device] : nullptr;
+    if (!ptr) return fail(c, ECMC_E_DEVICE, "the static scratch of device %d was not resolved at init", c->device);
+    return internal_distances(c, n_max, r2, pairs, ptr, NOALLOC_LAG_SLOTS);
 }
 
 ecmc_status ecmc_pair_histogram(ecmc_ctx *c, int32_t nbins, double r_max, int64_t *hist) {

@@ -112,7 +112,7 @@ EXPORTS = (
     "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
     "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
     "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff", "ecmc_internal_distances",
-    "ecmc_check_state", "ecmc_screen_constants",
+    "ecmc_check_state", "ecmc_screen_constants", "ecmc_internal_distances_noalloc",
 )
 
 
@@ -146,6 +146,7 @@ def lib():
         "ecmc_end_to_end_histogram": (st, [vp, i32, dbl, vp]),
         "ecmc_pair_histogram": (st, [vp, i32, dbl, vp]),
         "ecmc_internal_distances": (st, [vp, i32, vp, vp]),
+        "ecmc_internal_distances_noalloc": (st, [vp, i32, vp, vp]),
         "ecmc_check_state": (st, [vp, dbl, P(i64), P(i64), P(i64)]),
         "ecmc_pushoff_sweep": (st, [vp, i64, dbl, u64, dbl]),
         "ecmc_count_overlaps": (st, [vp, dbl, P(i64)]),
@@ -645,6 +646,15 @@ class Melt:
         pairs = np.zeros(int(n_max) + 1, dtype=np.int64)
         _check(lib().ecmc_internal_distances(self.ctx, int(n_max), r2.ctypes.data, pairs.ctypes.data),
                "ecmc_internal_distances", self.ctx)
+        return r2, pairs
+
+    def internal_distances_noalloc(self, n_max: int) -> tuple[np.ndarray, np.ndarray]:
+        """internal_distances with the partial sums in the library's static per-device array
+        (no workspace, no allocation); calls that overlap on one device race."""
+        r2 = np.zeros(int(n_max) + 1)
+        pairs = np.zeros(int(n_max) + 1, dtype=np.int64)
+        _check(lib().ecmc_internal_distances_noalloc(self.ctx, int(n_max), r2.ctypes.data, pairs.ctypes.data),
+               "ecmc_internal_distances_noalloc", self.ctx)
         return r2, pairs
 
     def pair_histogram(self, nbins: int, r_max: float) -> np.ndarray:
