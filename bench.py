@@ -260,6 +260,22 @@ def batch_cpu_baseline(melt, ell: float, D: int, n_cells: int, seconds: float) -
             "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
 
 
+def copy_probe(mib: int) -> None:
+    """One device-to-device copy of mib MiB (a plain copy kernel of known size, the scale for
+    hardware byte counters); nothing for mib = 0."""
+    if mib <= 0:
+        return
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    print(f"# copy probe: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
+
+
 def main_batch(args):
     """The batched workload: tuned geometry and staging, K sweeps captured into one HIP graph
     (the sweep loop), replayed once in the timed region after W eager warm-up sweeps."""
@@ -269,6 +285,7 @@ def main_batch(args):
 
     w = WORKLOADS["c4"]
     torch.cuda.set_device(0)
+    copy_probe(args.copy_probe)
     melts = inputs.batch_melts(w["melts"], args.seed)
     nb = sum(m.n_beads for m in melts)
     ell = w["ell"]
@@ -417,12 +434,11 @@ def main():
     ap.add_argument("--springs", type=float, default=0.0, metavar="K",
                     help="bonds as harmonic springs of constant K (Eq. (2), k_B T / sigma^2); 0 = tethers")
     ap.add_argument("--tiling", default=None, choices=("checker", "joint"),
-                    help="checker: D^3-cell domains in 8 colour phases (the default for tethers); joint: the "
+                    help="checker: D^3-cell domains in 8 colour phases (the default); joint: the "
                          "tile-joint partition (D^3-cell tiles at pitch D + 1 with immotile joints, one phase; "
-                         "the default for springs, with D = 1)")
+                         "D >= 2)")
     ap.add_argument("--domain-cells", type=int, default=0, metavar="D",
-                    help="domain (checkerboard) or tile (tile-joint) edge in cells; 0 = the workload's (2), "
-                         "or 1 for springs on their default partition")
+                    help="domain (checkerboard) or tile (tile-joint) edge in cells; 0 = the workload's (2)")
     ap.add_argument("--spring-cap", type=float, default=1.8, metavar="B",
                     help="with --springs: bond length cap in sigma (cells get an edge > B)")
     ap.add_argument("--no-precision-check", action="store_true",
@@ -460,48 +476,47 @@ def main():
 
     w = workload_of(args)
     torch.cuda.set_device(0)
-    if args.copy_probe > 0:
-        nbytes = args.copy_probe << 20
-        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        print(f"# copy probe: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
+    copy_probe(args.copy_probe)
     melt = inputs.lattice_chains(w["M"], w["N"], w["eta"], seed=args.seed, b_max=b_max)
-    prec = ecmc.PREC_MIXED if args.precision == "mixed" else ecmc.PREC_FP64
     n_cells = grid_cells(melt.L, b_max, w)
-    g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=w.get("tiling", 1), domain_cells=w["D"], time_kernels=True,
-                                               precision=prec, swap_moves=args.swap, spring_k=args.springs,
-                                               n_cells=n_cells))
     nb = melt.n_beads
+
+    def timed_run(precision: str):
+        """W untimed and K timed sweeps (each followed by the observables) of a fresh context."""
+        prec = ecmc.PREC_MIXED if precision == "mixed" else ecmc.PREC_FP64
+        g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=w.get("tiling", 1), domain_cells=w["D"], time_kernels=True,
+                                                   precision=prec, swap_moves=args.swap, spring_k=args.springs,
+                                                   n_cells=n_cells))
+
+        def step(i):
+            g.sweep(nb, w["ell"], 1000 + i)
+            g.observables(nbins=32)
+
+        for i in range(args.warmup):
+            step(i)
+            print(f"# {precision} warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        g.synchronize()
+        g.kernel_time()
+        c0 = g.counters()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(args.warmup + i)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.synchronize()
+        c1 = g.counters()
+        kms, launches = g.kernel_time()
+        d = {k: c1[k] - c0[k] for k in c1 if k not in ("error_flags",)}
+        events = d["hs_lift"] + d["tether_lift"] + d["hs_reflect"] + d["tether_reflect"] + d["swap"]
+        print(f"# {precision}: {args.steps} timed sweeps in {dt:.4f} s", file=sys.stderr, flush=True)
+        return g, dt, d, events, kms, launches
+
+    g, dt, d, events, kms, launches = timed_run(args.precision)
     n = g.n_cells
     beads_per_cell = nb / n ** 3
     print(f"# {args.workload}: {nb} beads, L={melt.L:.4f}, n={n}, h={g.h:.4f}, staging {g.stage_capacity}",
           file=sys.stderr, flush=True)
-
-    def step(i):
-        g.sweep(nb, w["ell"], 1000 + i)
-        g.observables(nbins=32)
-
-    for i in range(args.warmup):
-        step(i)
-        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    g.synchronize()
-    g.kernel_time()
-    c0 = g.counters()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(args.warmup + i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    g.synchronize()
-    c1 = g.counters()
-    kms, launches = g.kernel_time()
-    d = {k: c1[k] - c0[k] for k in c1 if k not in ("error_flags",)}
-    events = d["hs_lift"] + d["tether_lift"] + d["hs_reflect"] + d["tether_reflect"] + d["swap"]
     ecs = d["ec"]
     value = events / dt
     B = bytes_per_event(beads_per_cell)
@@ -556,6 +571,18 @@ def main():
                     + "); traffic: measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated "
                       "by a copy)",
         },
+    }
+    # the other precision timed in the same way, from the same start and seeds: its results are
+    # the same FP64 trajectory, so the two rates compare like for like
+    other = "fp64" if args.precision == "mixed" else "mixed"
+    g_o, dt_o, d_o, events_o, kms_o, launches_o = timed_run(other)
+    del g_o
+    ach_o = events_o * B / (kms_o / 1e3) / 1e9 if kms_o > 0 else 0.0
+    out[other] = {
+        "value": events_o / dt_o, "unit": "events/s", "ms_per_step": dt_o / args.steps * 1e3,
+        "bead_sweeps_per_s": d_o["ec"] / dt_o, "kernel_ms_per_step": kms_o / args.steps,
+        "roofline_achieved_GBps": ach_o, "frac": ach_o / HBM_PEAK_GBS,
+        "same_trajectory": bool(events_o == events and d_o["ec"] == ecs),
     }
     out["roofline"]["measured_copy_GBps"] = copy_bandwidth()
     if args.msd_sweeps > 0:
