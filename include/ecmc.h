@@ -136,6 +136,18 @@ typedef struct {
     void *workspace;            /* device memory owned by the caller (256-byte aligned)     */
     size_t workspace_bytes;
     void *stream;               /* hipStream_t for every launch and copy; NULL = default    */
+    void *side_stream;          /* caller's second hipStream_t (or NULL): by phases, the rare
+                                   domains of the larger staging tiers run on it, concurrently
+                                   with the first tier (the library orders it against `stream`
+                                   with events of its own).  NULL: every tier runs on `stream`,
+                                   one after the other (identical results).  The library
+                                   creates no stream                                       */
+    int32_t wait_limit_us;      /* guard on one dependency wait of the one-launch sweep
+                                   (0 = 30 s): a wait that runs out leaves its domain as it
+                                   was, flags the device error word (bit 5) and the next
+                                   synchronising call returns ECMC_E_DEVICE.  Far above any
+                                   domain's run time; small values exist to test that path */
+    int32_t reserved;           /* 0 */
 } ecmc_options;
 
 typedef struct {
@@ -146,7 +158,9 @@ typedef struct {
     double sum_delta;           /* sum over lifts and swaps of (d_par - x): pressure estimator */
     uint32_t error_flags;       /* device error word (bit 0 staging, 1 cell, 2 stuck,
                                    3 log full, 4 cell lists changed during staging,
-                                   5 a wait of the sweep launch ran out of polls)           */
+                                   5 a wait of the sweep launch ran out of time); it stays
+                                   set, and every synchronising call fails, until
+                                   ecmc_clear_error                                         */
     uint32_t pad;
 } ecmc_counters;
 
@@ -373,6 +387,10 @@ ecmc_status ecmc_get_cells(ecmc_ctx *ctx, int32_t *out);
 ecmc_status ecmc_get_images(ecmc_ctx *ctx, int32_t *out);
 ecmc_status ecmc_get_counters(ecmc_ctx *ctx, ecmc_counters *out);
 ecmc_status ecmc_reset_counters(ecmc_ctx *ctx);
+/* Clears the device error word (ecmc_counters.error_flags) after the caller has handled the
+ * ECMC_E_* it caused; the state is whatever the failed call left (a domain whose wait ran out
+ * is left as it was before that sweep).  Synchronises. */
+ecmc_status ecmc_clear_error(ecmc_ctx *ctx);
 
 /* Copies up to capacity log records (unordered across domains) to out and the total
  * number written since the last clear to *n_total. */

@@ -137,7 +137,7 @@ struct ecmc_ctx {
     ecmc_options opt;
     int device = -1;                  // the device current at init
     hipStream_t stream = nullptr;
-    hipStream_t side = nullptr;       // second stream for the larger staging tiers (by phases)
+    hipStream_t side = nullptr;       // the caller's second stream for the larger staging tiers (or none)
     hipEvent_t fork = nullptr, join = nullptr;
     double sigma = 0, lmax = 0, sig2 = 0, b2 = 0;
     int64_t nb = 0, npoly = 0;
@@ -595,14 +595,16 @@ ecmc_status init_impl(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *mel
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
             khz = 100000;
-        c->wait_ticks = (unsigned long long)khz * 1000ull * WAIT_SECONDS;
+        c->wait_ticks = opt->wait_limit_us > 0 ? (unsigned long long)khz * (unsigned long long)opt->wait_limit_us / 1000ull
+                                               : (unsigned long long)khz * 1000ull * WAIT_SECONDS;
     }
-    if (c->p.bpl2) {
-        // by phases (also for a sweep-capable melt when only some colours run)
-        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+    if (c->p.bpl2 && opt->side_stream) {
+        // by phases (also for a sweep-capable melt when only some colours run): the larger
+        // tiers on the caller's second stream, ordered against the first by two events
+        c->side = (hipStream_t)opt->side_stream;
+        if (hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess)
-            return bail(fail(c, ECMC_E_DEVICE, "creating the second stream failed"));
+            return bail(fail(c, ECMC_E_DEVICE, "creating the events of the second stream failed"));
     }
 
     HostState hs;
@@ -838,25 +840,31 @@ ecmc_status sweep_impl(ecmc_ctx *c, int64_t n_chains, double ell, uint64_t seed,
             // domain's cell lists could be half-updated and claim that domain twice)
             HIP_OK(c, launch_count(a, grid, c->stream));
             // the tiers take disjoint sets of domains of one colour, which never interact: the
-            // larger (rarer) tiers run on a second stream concurrently with the first
-            if (c->p.bpl2) {
+            // larger (rarer) tiers run on the caller's second stream concurrently with the
+            // first, or after it on the same stream
+            hipStream_t ts = c->side ? c->side : c->stream;
+            if (c->p.bpl2 && c->side) {
                 HIP_OK(c, hipEventRecord(c->fork, c->stream));
                 HIP_OK(c, hipStreamWaitEvent(c->side, c->fork, 0));
-                PhaseArgs b = a;
-                b.stage_lo = 64 * c->p.bpl;
-                b.stage_hi = c->p.bpl3 ? 64 * c->p.bpl2 : 0x7fffffff;
-                HIP_OK(c, phase_launch(b, c->p.bpl2, grid, c->side));
-                if (c->p.bpl3) {
-                    b.stage_lo = 64 * c->p.bpl2;
-                    b.stage_hi = 0x7fffffff;
-                    HIP_OK(c, phase_launch(b, c->p.bpl3, grid, c->side));
-                }
-                HIP_OK(c, hipEventRecord(c->join, c->side));
             }
             a.stage_lo = 0;
             a.stage_hi = c->p.bpl2 ? 64 * c->p.bpl : 0x7fffffff;
             HIP_OK(c, phase_launch(a, c->p.bpl, grid, c->stream));
-            if (c->p.bpl2) HIP_OK(c, hipStreamWaitEvent(c->stream, c->join, 0));
+            if (c->p.bpl2) {
+                PhaseArgs b = a;
+                b.stage_lo = 64 * c->p.bpl;
+                b.stage_hi = c->p.bpl3 ? 64 * c->p.bpl2 : 0x7fffffff;
+                HIP_OK(c, phase_launch(b, c->p.bpl2, grid, ts));
+                if (c->p.bpl3) {
+                    b.stage_lo = 64 * c->p.bpl2;
+                    b.stage_hi = 0x7fffffff;
+                    HIP_OK(c, phase_launch(b, c->p.bpl3, grid, ts));
+                }
+                if (c->side) {
+                    HIP_OK(c, hipEventRecord(c->join, c->side));
+                    HIP_OK(c, hipStreamWaitEvent(c->stream, c->join, 0));
+                }
+            }
             return ECMC_OK;
         });
     };
@@ -1257,6 +1265,15 @@ ecmc_status ecmc_reset_counters(ecmc_ctx *c) {
     return ECMC_OK;
 }
 
+ecmc_status ecmc_clear_error(ecmc_ctx *c) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (c->side) HIP_OK(c, hipStreamSynchronize(c->side));
+    HIP_OK(c, hipMemsetAsync(c->ws + c->lay.err, 0, 4, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return ECMC_OK;
+}
+
 ecmc_status ecmc_get_event_log(ecmc_ctx *c, ecmc_event *out, int64_t capacity, int64_t *n_total) {
     if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
     HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -1377,10 +1394,7 @@ ecmc_status ecmc_get_melt_info(const ecmc_ctx *c, int32_t m, ecmc_melt_info *out
 
 void ecmc_destroy(ecmc_ctx *c) {
     if (!c) return;
-    if (c->side) {
-        (void)hipStreamSynchronize(c->side);
-        (void)hipStreamDestroy(c->side);
-    }
+    if (c->side) (void)hipStreamSynchronize(c->side);  // the caller's stream: not destroyed here
     if (c->fork) (void)hipEventDestroy(c->fork);
     if (c->join) (void)hipEventDestroy(c->join);
     if (!c->timing.empty()) {

@@ -16,7 +16,7 @@ enum : uint32_t {
     ERR_STUCK = 1u << 2,  // an EC exceeded the per-EC iteration cap
     ERR_LOG = 1u << 3,    // event log full (records dropped; informational)
     ERR_RECOUNT = 1u << 4,  // a domain's cell lists no longer matched its count (internal error)
-    ERR_WAIT = 1u << 5,     // a wait of the dependency-ordered sweep ran out of polls (internal error)
+    ERR_WAIT = 1u << 5,     // a wait of the dependency-ordered sweep ran out of time (internal error)
 };
 
 // counter slots in the device counter block

@@ -57,8 +57,10 @@ __device__ __forceinline__ bool out_of_time(const PhaseArgs &a, unsigned long lo
 }
 
 // Wait until this launch has finished every neighbour of domain f whose colour comes earlier,
-// then acquire what they wrote.
-__device__ __forceinline__ void wait_for_earlier(const PhaseArgs &a, const Frame &f) {
+// then acquire what they wrote.  Returns false if the wait ran out of time (ERR_WAIT flagged):
+// a neighbour may then still be writing the shared halo, so the caller leaves the domain as it
+// is.
+__device__ __forceinline__ bool wait_for_earlier(const PhaseArgs &a, const Frame &f) {
     const int lane = lane_id();
     const int nd = a.nd;
     const uint32_t *done = a.done;  // the melt's stamps
@@ -73,16 +75,19 @@ __device__ __forceinline__ void wait_for_earlier(const PhaseArgs &a, const Frame
         nb = (f.dom[0] + ox + nd) % nd + nd * ((f.dom[1] + oy + nd) % nd + nd * ((f.dom[2] + oz + nd) % nd));
     }
     const unsigned long long t0 = (unsigned long long)wall_clock64();
+    bool ok = true;
     for (;;) {
         need = need && __hip_atomic_load(&done[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch;
         if (!__ballot(need)) break;
         if (__builtin_amdgcn_readfirstlane((int)out_of_time(a, t0))) {
             if (lane == 0) atomicOr(a.err, ERR_WAIT);
+            ok = false;
             break;
         }
         __builtin_amdgcn_s_sleep(8);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
 }
 
 // A free staging slot, searched from `start`; -1 (and ERR_WAIT) if none came free in time.
@@ -162,10 +167,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
     int F;
     bool wraps;
     frame_of<false>(b, colour, r - M.tick0, off, M.dom0, f, F, wraps);
-    wait_for_earlier(b, f);
-    const int S = frame_count(b, f, F);
+    // after a wait that ran out of time the domain is left untouched; its stamp is still
+    // published below, so that the waits of later colours end and the error reaches the host
+    const bool ready = wait_for_earlier(b, f);
+    const int S = ready ? frame_count(b, f, F) : 0;
     int slot = -1;
-    if (S <= SMAX) {
+    if (!ready) {
+        // nothing to do
+    } else if (S <= SMAX) {
         const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
         domain_body<BPL, LOG, EXACT, false, SPRING, PUSH>(b, f, F, wraps, S, m);
     } else if (S <= a.slow_cap) {

@@ -49,6 +49,9 @@ class ecmc_options(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
+        ("side_stream", ctypes.c_void_p),
+        ("wait_limit_us", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -112,7 +115,7 @@ EXPORTS = (
     "ecmc_workspace_size_batch", "ecmc_init_batch", "ecmc_n_melts", "ecmc_get_melt_info",
     "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
     "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff", "ecmc_internal_distances",
-    "ecmc_check_state", "ecmc_screen_constants", "ecmc_internal_distances_noalloc",
+    "ecmc_check_state", "ecmc_screen_constants", "ecmc_internal_distances_noalloc", "ecmc_clear_error",
 )
 
 
@@ -156,6 +159,7 @@ def lib():
         "ecmc_get_images": (st, [vp, vp]),
         "ecmc_get_counters": (st, [vp, P(ecmc_counters)]),
         "ecmc_reset_counters": (st, [vp]),
+        "ecmc_clear_error": (st, [vp]),
         "ecmc_get_event_log": (st, [vp, vp, i64, P(i64)]),
         "ecmc_clear_event_log": (st, [vp]),
         "ecmc_set_state": (st, [vp, vp, vp, vp, u32]),
@@ -387,6 +391,7 @@ class Options:
     stage_tier: int = 0
     spring_k: float = 0.0  # > 0: harmonic springs of this constant, capped at l_max
     overlapping_start: bool = False  # accept overlaps in the start (the push-off's phantom chains)
+    wait_limit_us: int = 0  # guard on a dependency wait of the one-launch sweep (0 = 30 s)
 
 
 def _native_options(o: "Options") -> ecmc_options:
@@ -405,6 +410,7 @@ def _native_options(o: "Options") -> ecmc_options:
     opt.stage_tier = o.stage_tier
     opt.spring_k = float(o.spring_k)
     opt.overlapping_start = 1 if o.overlapping_start else 0
+    opt.wait_limit_us = int(o.wait_limit_us)
     return opt
 
 
@@ -413,17 +419,17 @@ class Melt:
     torch-owned workspace."""
 
     def __init__(self, L: float, sigma: float, b_max: float, positions, bonds, options: Options | None = None,
-                 device: str = "cuda", stream=None):
+                 device: str = "cuda", stream=None, side_stream=None):
         opt = _native_options(options or Options())
         pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
-        self._attach(opt, ecmc_workspace_size(L, sigma, b_max, pos.shape[0], opt), device, stream, options)
+        self._attach(opt, ecmc_workspace_size(L, sigma, b_max, pos.shape[0], opt), device, stream, options, side_stream)
         self.L, self.sigma, self.b_max = float(L), float(sigma), float(b_max)
         self.n_beads = pos.shape[0]
         self.ctx = ecmc_init(L, sigma, b_max, pos, bonds, opt)
         # linear chains (the library rejects anything else): one polymer per bead minus bonds
         self.n_poly = self.n_beads - int(np.asarray(bonds).reshape(-1, 2).shape[0])
 
-    def _attach(self, opt, nbytes, device, stream, options):
+    def _attach(self, opt, nbytes, device, stream, options, side_stream=None):
         import torch
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
@@ -431,6 +437,8 @@ class Melt:
         opt.workspace_bytes = nbytes
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         opt.stream = self.stream.cuda_stream
+        self.side_stream = side_stream
+        opt.side_stream = side_stream.cuda_stream if side_stream is not None else None
         self.opt = opt
         self.log_capacity = int((options or Options()).event_log_capacity)
 
@@ -526,6 +534,10 @@ class Melt:
 
     def reset_counters(self):
         _check(lib().ecmc_reset_counters(self.ctx), "ecmc_reset_counters", self.ctx)
+
+    def clear_error(self):
+        """Clear the device error word after handling the error it caused."""
+        _check(lib().ecmc_clear_error(self.ctx), "ecmc_clear_error", self.ctx)
 
     def event_log(self) -> np.ndarray:
         n = ctypes.c_int64()
