@@ -236,23 +236,27 @@ ecmc_status ecmc_init(ecmc_ctx **out, double box, double sigma, double l_max, in
 ecmc_status ecmc_init_batch(ecmc_ctx **out, int32_t n_melts, const ecmc_melt_desc *melts,
                             double sigma, double l_max, const ecmc_options *opt);
 
-/* The autotuner of the batched form.  Candidates: the LDS staging tier (64, 128, 192, 256,
- * 384 or 512 beads per domain frame: up to four, from the smallest that holds the mean frame
- * of the melt holding the median bead; larger frames go to workspace slots) and
- * two domain policies per melt: 0 = D = 2 on the largest multiple of 4 cells per axis, 1 =
- * the (n, D) of smallest typical frame among n from that multiple up to the largest n
- * (n/D even).  Each candidate is initialised in opt->workspace (scratch; it must hold
- * ecmc_tune_workspace_size bytes) and timed over trial_sweeps sweeps of n_chains ECs of
- * length ell after one untimed sweep; the fastest in ECs per second is returned:
- * n_cells and domain_cells per melt (for ecmc_melt_desc) and the staging tier (for
- * ecmc_options.stage_tier).  Synchronises; the caller's melts are only read. */
+/* The autotuner of the batched form (checkerboard, one-launch sweeps: the tile-joint
+ * partition is offered for single melts only).  Candidates: two domain policies per melt
+ * (the domain tiling: 0 = D = 2 on the largest multiple of 4 cells per axis, 1 = the (n, D)
+ * of smallest typical frame among n from that multiple up to the largest n, n/D even), for
+ * each the LDS staging tier (64, 128, 192, 256, 384 or 512 beads per domain frame, i.e. 1 to
+ * 8 beads per lane of the wavefront that runs a domain's ECs: up to four, from the smallest
+ * that holds the mean frame of the melt holding the median bead; larger frames go to
+ * workspace slots), and for each tier both searches (ECMC_PREC_MIXED and ECMC_PREC_FP64,
+ * identical results).  Each candidate is initialised in opt->workspace (scratch; it must
+ * hold ecmc_tune_workspace_size bytes) and timed over trial_sweeps sweeps of n_chains ECs of
+ * length ell after one untimed sweep; the fastest in ECs per second is returned: n_cells and
+ * domain_cells per melt (for ecmc_melt_desc), the staging tier (for
+ * ecmc_options.stage_tier) and the precision (ecmc_options.precision).  Synchronises; the
+ * caller's melts are only read. */
 typedef struct {
     int32_t stage_tier;
     int32_t policy;
     double ms_per_sweep;        /* of the fastest candidate                                 */
     double ecs_per_s;
     int32_t candidates;         /* candidates timed                                         */
-    int32_t pad;
+    int32_t precision;          /* ECMC_PREC_* of the fastest candidate                      */
 } ecmc_tune_result;
 
 ecmc_status ecmc_tune_workspace_size(int32_t n_melts, const ecmc_melt_desc *melts, double sigma,
@@ -380,6 +384,24 @@ ecmc_status ecmc_internal_distances_noalloc(ecmc_ctx *ctx, int32_t n_max, double
  * counts N (N - 1) / 2 * 4 pi (r_hi^3 - r_lo^3) / (3 V) of each bin.  Host hist [nbins], nbins
  * in [1, 1024].  Synchronises. */
 ecmc_status ecmc_pair_histogram(ecmc_ctx *ctx, int32_t nbins, double r_max, int64_t *hist);
+
+/* Ensemble shape descriptors of the appendix (Table II) from per-polymer gyration eigenvalues
+ * (host eig [n_poly][3], as ecmc_shape returns them; any order within a polymer).  With the moment of inertia eigenvalues
+ * I_i = tr G - l_i taken in descending order (the order in which the asphericity
+ * b = (I1 + I2)/2 - I3 and the acylindricity c = I1 - I2 are non-negative), out[5] =
+ * <kappa^2> with kappa^2 = 4 (1 - 3 (I1 I2 + I2 I3 + I3 I1) / (tr I)^2), <I1 + I2 - I3>/<tr I>,
+ * <I1 - I2 + I3>/<tr I>, <-I1 + I2 + I3>/<tr I> and <4 b^2 + 3 c^2>/<tr I>^2, sums over
+ * polymers in index order.  Host only; ECMC_E_ARG for n_poly < 1, non-finite eigenvalues or a
+ * polymer of zero inertia. */
+ecmc_status ecmc_shape_descriptors(const double *eig, int64_t n_poly, double out[5]);
+
+/* The pair correlation g(r) (appendix: the local order behind the small-R oscillations of
+ * W(R)) from pair counts hist [nbins] of r in [0, r_max) (ecmc_pair_histogram): each bin
+ * divided by the ideal-gas count of its shell, sum over the n_melts melts of
+ * N_m (N_m - 1) / 2 * 4 pi (r_hi^3 - r_lo^3) / (3 V_m) (host n_beads [n_melts], volumes
+ * [n_melts]).  Host only; writes g [nbins]. */
+ecmc_status ecmc_pair_correlation(const int64_t *hist, int32_t nbins, double r_max, int32_t n_melts,
+                                  const int64_t *n_beads, const double *volumes, double *g);
 
 /* Host copies of the state: positions [n][3], cell indices [n][3], image counters [n][3]. */
 ecmc_status ecmc_get_positions(ecmc_ctx *ctx, double *out);

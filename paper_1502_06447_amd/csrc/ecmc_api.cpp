@@ -1265,6 +1265,60 @@ ecmc_status ecmc_reset_counters(ecmc_ctx *c) {
     return ECMC_OK;
 }
 
+ecmc_status ecmc_shape_descriptors(const double *eig, int64_t n_poly, double out[5]) {
+    if (!eig || !out || n_poly < 1) return fail(nullptr, ECMC_E_ARG, "need eigenvalues of at least one polymer");
+    // moment of inertia eigenvalues I_i = tr G - l_i, descending with l ascending: the order
+    // in which b = (I1 + I2)/2 - I3 and c = I1 - I2 are non-negative (appendix, Table II)
+    double k2 = 0.0, s123 = 0.0, s132 = 0.0, s231 = 0.0, sol = 0.0, str = 0.0;
+    for (int64_t q = 0; q < n_poly; ++q) {
+        double l1 = eig[3 * q], l2 = eig[3 * q + 1], l3 = eig[3 * q + 2];
+        if (!(std::isfinite(l1) && std::isfinite(l2) && std::isfinite(l3)))
+            return fail(nullptr, ECMC_E_ARG, "polymer %lld: eigenvalues not finite", (long long)q);
+        // l1 >= l2 >= l3 whatever order they come in
+        if (l1 < l2) std::swap(l1, l2);
+        if (l2 < l3) std::swap(l2, l3);
+        if (l1 < l2) std::swap(l1, l2);
+        const double tot = l1 + l2 + l3;
+        const double i1 = tot - l3, i2 = tot - l2, i3 = tot - l1;
+        const double tr = i1 + i2 + i3;
+        if (!(tr > 0.0)) return fail(nullptr, ECMC_E_ARG, "polymer %lld: zero inertia", (long long)q);
+        const double pair = i1 * i2 + i2 * i3 + i3 * i1;
+        const double b = 0.5 * (i1 + i2) - i3, c = i1 - i2;
+        k2 += 4.0 * (1.0 - 3.0 * pair / (tr * tr));
+        s123 += i1 + i2 - i3;
+        s132 += i1 - i2 + i3;
+        s231 += -i1 + i2 + i3;
+        sol += 4.0 * b * b + 3.0 * c * c;
+        str += tr;
+    }
+    const double m = (double)n_poly, mt = str / m;
+    out[0] = k2 / m;
+    out[1] = s123 / m / mt;
+    out[2] = s132 / m / mt;
+    out[3] = s231 / m / mt;
+    out[4] = sol / m / (mt * mt);
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_pair_correlation(const int64_t *hist, int32_t nbins, double r_max, int32_t n_melts,
+                                  const int64_t *n_beads, const double *volumes, double *g) {
+    if (!hist || !g || !n_beads || !volumes || nbins < 1 || n_melts < 1 || !(r_max > 0.0) || !std::isfinite(r_max))
+        return fail(nullptr, ECMC_E_ARG, "need nbins >= 1, r_max > 0 and at least one melt");
+    // ideal-gas pairs per unit shell volume, summed over the melts: sum_m N_m (N_m - 1) / (2 V_m)
+    double dens = 0.0;
+    for (int32_t m = 0; m < n_melts; ++m) {
+        if (n_beads[m] < 0 || !(volumes[m] > 0.0)) return fail(nullptr, ECMC_E_ARG, "melt %d: bad size", m);
+        dens += 0.5 * (double)n_beads[m] * (double)(n_beads[m] - 1) / volumes[m];
+    }
+    const double pi = 3.14159265358979323846;
+    for (int32_t k = 0; k < nbins; ++k) {
+        const double lo = r_max * k / nbins, hi = r_max * (k + 1) / nbins;
+        const double shell = 4.0 * pi / 3.0 * (hi * hi * hi - lo * lo * lo);
+        g[k] = dens > 0.0 ? (double)hist[k] / (dens * shell) : 0.0;
+    }
+    return ECMC_OK;
+}
+
 ecmc_status ecmc_clear_error(ecmc_ctx *c) {
     if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
     HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -1567,12 +1621,16 @@ ecmc_status ecmc_tune_batch(int32_t n_melts, const ecmc_melt_desc *melts, double
         };
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
             return done(fail(nullptr, ECMC_E_DEVICE, "creating timing events failed"));
-        for (int tier : tiers) {
-            // the staging tier only changes which kernel runs: the layout (with its workspace
-            // slots for the larger domains) is the one of the smallest tier
+        for (int cand = 0; cand < 2 * (int)tiers.size(); ++cand) {
+            // the staging tier and the search precision only change which kernel runs (the two
+            // searches give identical results): the layout (with its workspace slots for the
+            // larger domains) is the one of the smallest tier
+            const int tier = tiers[cand / 2];
+            const int prec = cand % 2 ? ECMC_PREC_FP64 : ECMC_PREC_MIXED;
             const int bpl = tier / 64;
             if (!sweep_bpl_supported(bpl)) continue;
             c->p.bpl = bpl;
+            c->opt.precision = prec;
             if ((st = ecmc_sweep(c, n_chains, ell, 0x5EEDu + (uint64_t)tier))) return done(st);
             ecmc_counters k0{}, k1{};
             if ((st = ecmc_get_counters(c, &k0))) return done(st);
@@ -1589,6 +1647,7 @@ ecmc_status ecmc_tune_batch(int32_t n_melts, const ecmc_melt_desc *melts, double
             if (rate > best_rate) {
                 best_rate = rate;
                 best->stage_tier = tier;
+                best->precision = prec;
                 best->policy = policy;
                 best->ms_per_sweep = ms / trial_sweeps;
                 best->ecs_per_s = rate;

@@ -82,10 +82,10 @@ class ecmc_melt_info(ctypes.Structure):
 
 class ecmc_tune_result(ctypes.Structure):
     _fields_ = [("stage_tier", ctypes.c_int32), ("policy", ctypes.c_int32), ("ms_per_sweep", ctypes.c_double),
-                ("ecs_per_s", ctypes.c_double), ("candidates", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("ecs_per_s", ctypes.c_double), ("candidates", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ecmc_counters(ctypes.Structure):
@@ -116,6 +116,7 @@ EXPORTS = (
     "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
     "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff", "ecmc_internal_distances",
     "ecmc_check_state", "ecmc_screen_constants", "ecmc_internal_distances_noalloc", "ecmc_clear_error",
+    "ecmc_shape_descriptors", "ecmc_pair_correlation",
 )
 
 
@@ -160,6 +161,8 @@ def lib():
         "ecmc_get_counters": (st, [vp, P(ecmc_counters)]),
         "ecmc_reset_counters": (st, [vp]),
         "ecmc_clear_error": (st, [vp]),
+        "ecmc_shape_descriptors": (st, [vp, i64, vp]),
+        "ecmc_pair_correlation": (st, [vp, i32, dbl, i32, vp, vp, vp]),
         "ecmc_get_event_log": (st, [vp, vp, i64, P(i64)]),
         "ecmc_clear_event_log": (st, [vp]),
         "ecmc_set_state": (st, [vp, vp, vp, vp, u32]),
@@ -676,6 +679,13 @@ class Melt:
                self.ctx)
         return h
 
+    def pair_correlation(self, nbins: int, r_max: float) -> np.ndarray:
+        """g(r) of the context's melts (pooled over a batch) for r < r_max (<= the cell edge):
+        the GPU pair counts normalised by the library."""
+        h = self.pair_histogram(nbins, r_max)
+        infos = [self.melt_info(m) for m in range(self.n_melts)]
+        return pair_correlation(h, r_max, [i["n_beads"] for i in infos], [i["box"] ** 3 for i in infos])
+
     def shape(self) -> dict:
         """Per polymer: gyration tensor [M, 6] (xx, yy, zz, xy, xz, yz), its eigenvalues [M, 3]
         (descending) and the image-unwrapped centre of mass [M, 3], computed on the GPU."""
@@ -690,30 +700,26 @@ class Melt:
 
 def shape_descriptors(eig) -> dict:
     """Ensemble shape descriptors (appendix, Table II) from per-polymer gyration eigenvalues
-    l1 >= l2 >= l3 (Melt.shape()["eig"]).  The moment of inertia eigenvalues are
-    I_i = tr G - l_i, here in descending order I1 >= I2 >= I3, the order under which the
-    asphericity b = (I1 + I2)/2 - I3 and acylindricity c = I1 - I2 are non-negative and the
-    quoted infinite-chain limits hold.  Returns <kappa^2> with
-    kappa^2 = 4 (1 - 3 (I1 I2 + I2 I3 + I3 I1) / (tr I)^2), the three ratios
-    <I1 + I2 - I3>/<tr I>, <I1 - I2 + I3>/<tr I>, <-I1 + I2 + I3>/<tr I>, and
-    <4 b^2 + 3 c^2> / <tr I>^2."""
-    lam = np.asarray(eig, dtype=np.float64).reshape(-1, 3)
-    tot = lam[:, 0] + lam[:, 1] + lam[:, 2]
-    i1, i2, i3 = tot - lam[:, 2], tot - lam[:, 1], tot - lam[:, 0]   # descending
-    tr = i1 + i2 + i3
-    pair = i1 * i2 + i2 * i3 + i3 * i1
-    b = 0.5 * (i1 + i2) - i3
-    c = i1 - i2
-    mt = tr.mean()
-    return {"kappa2": float(np.mean(4.0 * (1.0 - 3.0 * pair / tr ** 2))),
-            "r_123": float(np.mean(i1 + i2 - i3) / mt), "r_132": float(np.mean(i1 - i2 + i3) / mt),
-            "r_231": float(np.mean(-i1 + i2 + i3) / mt), "solc": float(np.mean(4 * b * b + 3 * c * c) / mt ** 2)}
+    (Melt.shape()["eig"]), computed by the library: <kappa^2>, the three ratios
+    <I1 + I2 - I3>/<tr I>, <I1 - I2 + I3>/<tr I>, <-I1 + I2 + I3>/<tr I> and
+    <4 b^2 + 3 c^2>/<tr I>^2 (I_i = tr G - l_i in descending order)."""
+    lam = np.ascontiguousarray(eig, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(5)
+    _check(lib().ecmc_shape_descriptors(lam.ctypes.data, lam.shape[0], out.ctypes.data), "ecmc_shape_descriptors")
+    return {"kappa2": float(out[0]), "r_123": float(out[1]), "r_132": float(out[2]), "r_231": float(out[3]),
+            "solc": float(out[4])}
 
 
-def pair_correlation(hist, r_max: float, n_beads: int, volume: float) -> np.ndarray:
-    """g(r) of one melt from its pair counts: each bin divided by the ideal-gas count
-    N (N - 1) / 2 * (4 pi / 3) (r_hi^3 - r_lo^3) / V."""
-    h = np.asarray(hist, dtype=np.float64)
-    edges = np.linspace(0.0, r_max, len(h) + 1)
-    shell = 4.0 * np.pi / 3.0 * (edges[1:] ** 3 - edges[:-1] ** 3)
-    return h / (0.5 * n_beads * (n_beads - 1) * shell / volume)
+def pair_correlation(hist, r_max: float, n_beads, volume) -> np.ndarray:
+    """g(r) from pair counts (ecmc_pair_histogram), computed by the library: each bin divided by
+    the ideal-gas count of its shell summed over the melts (n_beads and volume: one value per
+    melt, or scalars for one melt)."""
+    h = np.ascontiguousarray(hist, dtype=np.int64)
+    nb = np.ascontiguousarray(np.atleast_1d(n_beads), dtype=np.int64)
+    vol = np.ascontiguousarray(np.atleast_1d(volume), dtype=np.float64)
+    if nb.shape != vol.shape:
+        raise ValueError("one bead count and one volume per melt")
+    g = np.zeros(h.shape[0])
+    _check(lib().ecmc_pair_correlation(h.ctypes.data, h.shape[0], float(r_max), nb.shape[0], nb.ctypes.data,
+                                       vol.ctypes.data, g.ctypes.data), "ecmc_pair_correlation")
+    return g

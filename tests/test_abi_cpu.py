@@ -191,3 +191,31 @@ def test_bench_partition_defaults():
     assert n == 56 and n % 4 == 0 and L / n > 1.8
     n = bench.grid_cells(L, 1.8, bench.workload_of(ns(springs=30.0, tiling="joint")))
     assert n == 57 and n % 3 == 0 and L / n > 1.8
+
+
+def test_pair_correlation_pools_the_melts_of_a_batch():
+    """g(r) of two melts from their summed pair counts: each bin over the summed ideal-gas
+    counts N_m (N_m - 1) / 2 * 4 pi (r_hi^3 - r_lo^3) / (3 V_m); one melt alone reduces to it."""
+    import numpy as np
+    hist = np.array([0, 3, 40, 125, 260], dtype=np.int64)
+    r_max, nb, vol = 1.5, np.array([500, 2000]), np.array([1000.0, 8000.0])
+    g = ecmc.pair_correlation(hist, r_max, nb, vol)
+    edges = np.linspace(0.0, r_max, 6)
+    shell = 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    ideal = sum(n * (n - 1) / 2.0 / v for n, v in zip(nb, vol)) * shell
+    assert np.allclose(g, hist / ideal, rtol=1e-14, atol=0)
+    assert np.allclose(ecmc.pair_correlation(hist, r_max, 500, 1000.0), hist / (500 * 499 / 2 / 1000.0 * shell),
+                       rtol=1e-14, atol=0)
+    with pytest.raises(ecmc.EcmcError):
+        ecmc.pair_correlation(hist, -1.0, 500, 1000.0)
+
+
+def test_shape_descriptors_take_any_eigenvalue_order():
+    import numpy as np
+    rng = np.random.default_rng(4)
+    lam = rng.uniform(0.1, 3.0, (50, 3))
+    a = ecmc.shape_descriptors(np.sort(lam, axis=1)[:, ::-1])
+    b = ecmc.shape_descriptors(rng.permuted(lam, axis=1))
+    assert all(abs(a[k] - b[k]) < 1e-13 * max(1.0, abs(a[k])) for k in a)
+    with pytest.raises(ecmc.EcmcError):
+        ecmc.shape_descriptors(np.zeros((2, 3)))

@@ -36,7 +36,9 @@ def test_side_stream_gives_the_same_sweeps(melt_c2):
         g.close()
     (p0, c0, i0, n0), (p1, c1, i1, n1) = runs
     assert np.array_equal(p0, p1) and np.array_equal(c0, c1) and np.array_equal(i0, i1)
-    assert n0 == n1 and n0["ec"] >= 32000
+    # sum_delta is a floating-point sum over domains in completion order: equal to rounding
+    assert {k: v for k, v in n0.items() if k != "sum_delta"} == {k: v for k, v in n1.items() if k != "sum_delta"}
+    assert abs(n0["sum_delta"] - n1["sum_delta"]) <= 1e-12 * abs(n0["sum_delta"]) and n0["ec"] >= 32000
 
 
 def test_a_wait_that_runs_out_leaves_a_valid_state(melt_c2):
@@ -55,3 +57,19 @@ def test_a_wait_that_runs_out_leaves_a_valid_state(melt_c2):
     assert g.check_state(1e-12) == {"overlaps": 0, "stretched": 0, "misplaced": 0}
     pos = g.positions()
     assert np.all(np.isfinite(pos)) and np.all((pos >= 0.0) & (pos <= melt_c2.L))
+
+
+def test_pair_correlation_of_the_dense_melt(melt_c2):
+    """g(r) from the GPU pair counts, normalised by the library: zero inside the hard core
+    (no two beads closer than sigma), a contact peak above 1 just outside it (Sec. II: dense
+    hard spheres at eta = 0.45), and the same numbers as the library call on the counts."""
+    g = ecmc.Melt.from_melt(melt_c2, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=16))
+    for k in range(3):
+        g.sweep(16000, 20.0, 500 + k)
+    r_max = 0.95 * g.h
+    gr = g.pair_correlation(40, r_max)
+    h = g.pair_histogram(40, r_max)
+    assert np.array_equal(gr, ecmc.pair_correlation(h, r_max, melt_c2.n_beads, melt_c2.L ** 3))
+    edges = np.linspace(0.0, r_max, 41)
+    assert np.all(gr[edges[1:] <= 1.0] == 0.0)
+    assert gr[np.searchsorted(edges, 1.0)] > 1.5
