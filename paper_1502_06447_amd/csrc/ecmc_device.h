@@ -536,6 +536,100 @@ __device__ __forceinline__ Hit search_all(const Stage &st, const Pivot &pv, int 
     return h;
 }
 
+// The plain FP64 search of tethered chains with the square roots deferred.  Pass A takes every
+// staged bead of the lane's slots (staged index 64 k + lane) through the cheap part of
+// exact_candidate: the displacement, d_par, d_perp^2, whether it is a contact or a partner, and
+// the argument of the square root, kept in registers.  Pass B then evaluates x for the lane's
+// candidates only, one per pass in slot order, with the same operations as exact_candidate, so
+// that every x has the same bits; a pass runs while any lane has a candidate left (about 7
+// candidates among ~150 staged beads: usually one or two passes instead of one square root
+// per 64 staged beads).  The winner is the minimum by (x, staged index, kind), as in
+// search_all, and its record is read from LDS.
+template <int BPL>
+__device__ __forceinline__ Hit search_deferred(const Stage &st, const Pivot &pv, int S, int ax, int sha, int shb,
+                                               int shc, double sgnd, double sig2, double b2, double L, bool wr) {
+    const int lane = lane_id();
+    const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
+    const double *pA = st.axis(ax);
+    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
+    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
+    double dpar[BPL], arg[BPL];
+    unsigned cand = 0u, hsm = 0u;
+#pragma unroll
+    for (int k = 0; k < BPL; ++k) {
+        dpar[k] = 0.0;
+        arg[k] = 0.0;
+        const int idx = k * 64 + lane;
+        if (k * 64 < S && idx < S && idx != pv.P) {
+            const int32_t meta = st.meta[idx];
+            double da = pA[idx] - pv.a;
+            double db = pB[idx] - pv.b;
+            double dc = pC[idx] - pv.c;
+            if (wr) {
+                const int ea = (int)((meta >> sha) & CELL_MASK) - (int)((pv.meta >> sha) & CELL_MASK);
+                const int eb = (int)((meta >> shb) & CELL_MASK) - (int)((pv.meta >> shb) & CELL_MASK);
+                const int ec = (int)((meta >> shc) & CELL_MASK) - (int)((pv.meta >> shc) & CELL_MASK);
+                da = da + (ea > 1 ? -L : (ea < -1 ? L : 0.0));
+                db = db + (eb > 1 ? -L : (eb < -1 ? L : 0.0));
+                dc = dc + (ec > 1 ? -L : (ec < -1 ? L : 0.0));
+            }
+            const double dp = da * sgnd;
+            const double pb = db * db;
+            const double pc = dc * dc;
+            const double dperp2 = pb + pc;
+            const bool hs = (dp > 0.0) && (dperp2 < sig2);
+            const bool partner = (idx == q0) || (idx == q1);
+            dpar[k] = dp;
+            arg[k] = (hs ? sig2 : b2) - dperp2;
+            cand |= (hs || partner) ? (1u << k) : 0u;
+            hsm |= hs ? (1u << k) : 0u;
+        }
+    }
+    double bx = INF;
+    unsigned bkey = 0xFFFFFFFFu;
+    while (__ballot(cand != 0u)) {
+        const int k = cand ? __builtin_ctz(cand) : 0;
+        double dp = dpar[0], a = arg[0];
+#pragma unroll
+        for (int j = 1; j < BPL; ++j)
+            if (k == j) {
+                dp = dpar[j];
+                a = arg[j];
+            }
+        if (cand) {
+            const bool hs = (hsm >> k) & 1u;
+            if (!(a > 0.0)) a = 0.0;
+            const double sq = sqrt_nonneg(a);
+            double v = hs ? dp - sq : dp + sq;
+            if (!(v > 0.0)) v = 0.0;
+            const unsigned kk = (unsigned)((k * 64 + lane) * 2 + (hs ? 0 : 1));
+            if (v < bx || (v == bx && kk < bkey)) {
+                bx = v;
+                bkey = kk;
+            }
+            cand &= cand - 1u;
+        }
+    }
+    Hit h;
+    h.x = INF;
+    h.key = 0xFFFFFFFFu;
+    h.a = h.b = h.c = 0.0;
+    h.meta = 0;
+    h.part = -1;
+    const double xs = wave_min_nonneg_f64(bx);
+    if (!(xs < INF)) return h;
+    const unsigned key = wave_min_u32(bx == xs ? bkey : 0xFFFFFFFFu);
+    const int j = (int)(key >> 1);
+    h.x = xs;
+    h.key = key;
+    h.a = pA[j];
+    h.b = pB[j];
+    h.c = pC[j];
+    h.meta = __builtin_amdgcn_readfirstlane(st.meta[j]);
+    h.part = __builtin_amdgcn_readfirstlane(st.part[j]);
+    return h;
+}
+
 // Select element `slot` (uniform) of a lane's register array.  Written as a masked OR so
 // that the compiler cannot turn it into an indexed load, which would move the array out
 // of VGPRs into scratch memory.
@@ -809,8 +903,11 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
         if constexpr (EXACT) {
             double g0 = 0.0, g1 = 0.0;
             if constexpr (SPRING) spring_terms(a, f, k, step, sk0, sk1, g0, g1);
-            hit = search_all<SPRING, PUSH>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, g0, g1, a.sigma,
-                                           a.ov2);
+            if constexpr (!SPRING && !PUSH && BPL <= 8)
+                hit = search_deferred<BPL>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr);
+            else
+                hit = search_all<SPRING, PUSH>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, g0, g1,
+                                               a.sigma, a.ov2);
         } else {
             Screen<BPL> sc;
             screen<BPL, WHOLE, SPRING>(sc, R, pv, sha, shb, shc, sgnd, K);
