@@ -616,9 +616,25 @@ __device__ __forceinline__ Hit search_deferred(const Stage &st, const Pivot &pv,
     h.a = h.b = h.c = 0.0;
     h.meta = 0;
     h.part = -1;
-    const double xs = wave_min_nonneg_f64(bx);
-    if (!(xs < INF)) return h;
-    const unsigned key = wave_min_u32(bx == xs ? bkey : 0xFFFFFFFFu);
+    // The minimum by (x, key) in one wavefront reduction as a rule: rounding to single
+    // precision keeps the order (x1 <= x2 gives fl(x1) <= fl(x2), and the bit patterns of
+    // non-negative floats order like the numbers), so the winner is among the lanes whose
+    // fl(x) is the smallest; only when several lanes share it is the FP64 (x, key) minimum
+    // taken over those lanes.
+    const unsigned fb = (unsigned)__float_as_int((float)bx);
+    const unsigned fm = wave_min_u32(fb);
+    if (fm == 0x7F800000u) return h;  // +inf: no candidate in the wavefront
+    const unsigned long long tie = __ballot(fb == fm);
+    double xs;
+    unsigned key;
+    if (__popcll(tie) == 1) {
+        const int wl = (int)(__ffsll((long long)tie) - 1);
+        xs = rdlane(bx, wl);
+        key = (unsigned)rdlane((int)bkey, wl);
+    } else {
+        xs = wave_min_nonneg_f64(fb == fm ? bx : INF);
+        key = wave_min_u32(fb == fm && bx == xs ? bkey : 0xFFFFFFFFu);
+    }
     const int j = (int)(key >> 1);
     h.x = xs;
     h.key = key;
