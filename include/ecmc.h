@@ -82,11 +82,11 @@ enum {
 };
 
 typedef struct {
-    int32_t precision;          /* ECMC_PREC_MIXED (default): a single-precision screen of
-                                   every staged bead bounds its next-event distance, and only
-                                   the beads that can come first are evaluated in FP64; the
-                                   results are identical to ECMC_PREC_FP64, which evaluates
-                                   every staged bead in FP64 at every event (the plain kernel) */
+    int32_t precision;          /* ECMC_PREC_FP64 (default): every staged bead evaluated in
+                                   FP64 at every event (the plain kernel).  ECMC_PREC_MIXED: a
+                                   single-precision screen of every staged bead bounds its
+                                   next-event distance, and only the beads that can come first
+                                   are evaluated in FP64; identical results, slower on gfx950 */
     int32_t tiling;             /* ECMC_TILING_WHOLE: one domain, every bead motile;
                                    ECMC_TILING_CHECKER: D^3-cell domains, 8 colour phases;
                                    ECMC_TILING_JOINT: the tile-joint partition (Sec. II.A),
@@ -195,7 +195,7 @@ typedef struct {
     int32_t n_cells, domain_cells;
 } ecmc_melt_info;
 
-/* Fills *opt with the defaults (screened precision, checkerboard, D = 2, automatic sizes). */
+/* Fills *opt with the defaults (plain FP64 search, checkerboard, D = 2, automatic sizes). */
 void ecmc_default_options(ecmc_options *opt);
 
 /* Bytes of device workspace ecmc_init needs for n_beads beads in a cube of edge box

@@ -681,7 +681,7 @@ extern "C" {
 
 void ecmc_default_options(ecmc_options *o) {
     std::memset(o, 0, sizeof *o);
-    o->precision = ECMC_PREC_MIXED;
+    o->precision = ECMC_PREC_FP64;
     o->tiling = ECMC_TILING_CHECKER;
     o->domain_cells = 2;
 }

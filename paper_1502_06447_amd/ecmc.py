@@ -267,7 +267,8 @@ def ecmc_init_batch(melts, sigma: float, l_max: float, opt: ecmc_options, n_cell
 
 # Options that change what a sweep runs, and so the tuner's choice (the workspace, the stream and
 # the staging tier the tuner itself picks are left out).
-_TUNE_OPTION_FIELDS = ("precision", "tiling", "n_cells", "domain_cells", "cell_capacity", "stage_capacity",
+# (the precision is not among them: the tuner times both searches whatever the option says)
+_TUNE_OPTION_FIELDS = ("tiling", "n_cells", "domain_cells", "cell_capacity", "stage_capacity",
                        "event_cap", "event_log_capacity", "swap_moves", "schedule", "overlapping_start", "spring_k")
 
 
@@ -388,7 +389,7 @@ class Options:
     event_cap: int = 0
     event_log_capacity: int = 0
     time_kernels: bool = False
-    precision: int = PREC_MIXED
+    precision: int = PREC_FP64
     swap_moves: bool = False
     schedule: int = SCHED_SWEEP
     stage_tier: int = 0

@@ -32,7 +32,7 @@ def test_status_strings_and_defaults():
     for code in range(-8, 1):
         assert L.ecmc_status_str(code)
     o = ecmc.ecmc_default_options()
-    assert o.precision == ecmc.PREC_MIXED and o.tiling == ecmc.TILING_CHECKER and o.domain_cells == 2
+    assert o.precision == ecmc.PREC_FP64 and o.tiling == ecmc.TILING_CHECKER and o.domain_cells == 2
 
 
 def test_workspace_size_and_geometry_errors():
@@ -156,8 +156,12 @@ def test_tuner_cache_key_and_file(tmp_path):
                ecmc.tune_key(melts, 1.0, 1.4, opt, 2000, 20.0, 2, "gpu-b", "lib-1"),
                ecmc.tune_key(melts, 1.0, 1.4, opt, 2000, 20.0, 2, "gpu-a", "lib-2")]
     opt2 = ecmc.ecmc_default_options()
-    opt2.precision = ecmc.PREC_FP64
+    opt2.swap_moves = 1
     changed.append(ecmc.tune_key(melts, 1.0, 1.4, opt2, 2000, 20.0, 2, "gpu-a", "lib-1"))
+    # the tuner times both searches, so the precision option does not change the key
+    opt3 = ecmc.ecmc_default_options()
+    opt3.precision = ecmc.PREC_MIXED
+    assert ecmc.tune_key(melts, 1.0, 1.4, opt3, 2000, 20.0, 2, "gpu-a", "lib-1") == k0
     assert len(set(changed + [k0])) == len(changed) + 1
     path = str(tmp_path / "tune.json")
     assert ecmc.tune_cache_get(path, k0) is None
