@@ -1216,7 +1216,7 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
                                             const StageMem &m) {
     constexpr int NS = lane_slots(BPL, EXACT);
     // the loops over a lane's staged beads are unrolled where they fill register slots
-    constexpr int UNR = EXACT ? 1 : BPL;
+    constexpr int UNR = (EXACT && BPL > 4) ? 1 : BPL;
     const int lane = lane_id();
     const int n = a.n;
     const double L = a.L;
@@ -1243,11 +1243,18 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
         const int incl = wave_incl_scan(cnt);
         const int excl = incl - cnt;
         const int tot = rdlane(incl, 63);
-        for (int i = 0; i < cnt; ++i) {
-            const int at = S + excl + i;
-            if (at < S0) {
-                t_id[at] = a.cids[(long long)flat * a.cap + i];
-                t_meta[at] = word;
+        // four list entries per round, their loads in flight together
+        for (int i0 = 0; i0 < cnt; i0 += 4) {
+            int v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = i0 + j < cnt ? a.cids[(long long)flat * a.cap + i0 + j] : 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int at = S + excl + i0 + j;
+                if (i0 + j < cnt && at < S0) {
+                    t_id[at] = v[j];
+                    t_meta[at] = word;
+                }
             }
         }
         S += tot;
@@ -1259,13 +1266,44 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
     }
     f.S = S;
     __syncthreads();
-    // rank sort by bead id
-    for (int e = lane; e < S; e += 64) {
-        const int my = t_id[e];
-        int r = 0;
-        for (int i = 0; i < S; ++i) r += (t_id[i] < my) ? 1 : 0;
-        m.id[r] = my;
-        m.meta[r] = t_meta[e];
+    // rank sort by bead id (ids are distinct: a bead's rank is the number of smaller ids)
+    if constexpr (BPL <= 4) {
+        // the lane's ids in registers, every other id read lane by lane from them (no LDS
+        // round trip per comparison); past S an id larger than any
+        int my[BPL], r[BPL];
+#pragma unroll
+        for (int k = 0; k < BPL; ++k) {
+            const int e = k * 64 + lane;
+            my[k] = e < S ? t_id[e] : 0x7FFFFFFF;
+            r[k] = 0;
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < BPL; ++k2) {
+            if (k2 * 64 < S) {
+#pragma unroll
+                for (int j = 0; j < 64; ++j) {
+                    const int v = __builtin_amdgcn_readlane(my[k2], j);
+#pragma unroll
+                    for (int k = 0; k < BPL; ++k) r[k] += v < my[k] ? 1 : 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < BPL; ++k) {
+            const int e = k * 64 + lane;
+            if (e < S) {
+                m.id[r[k]] = my[k];
+                m.meta[r[k]] = t_meta[e];
+            }
+        }
+    } else {
+        for (int e = lane; e < S; e += 64) {
+            const int my = t_id[e];
+            int r = 0;
+            for (int i = 0; i < S; ++i) r += (t_id[i] < my) ? 1 : 0;
+            m.id[r] = my;
+            m.meta[r] = t_meta[e];
+        }
     }
     __syncthreads();
 
@@ -1277,45 +1315,76 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
         R.A[k] = R.B[k] = R.C[k] = 1.0e30f;
         if (WHOLE) R.META[k] = 0;
     }
-#pragma unroll UNR
-    for (int k = 0; k < BPL; ++k) {
-        const int idx = k * 64 + lane;
-        if (idx < S) {
-            const int id = m.id[idx];
-            const int32_t w = m.meta[idx];
-            const double x = a.px[id], y = a.py[id], z = a.pz[id];
-            P0r[idx] = x;
-            P1r[idx] = y;
-            P2r[idx] = z;
-            if constexpr (!EXACT) {
-                R.A[k] = frame_u(x, cell_of(w, 0), f.fs[0], L, f.O[0]);
-                R.B[k] = frame_u(y, cell_of(w, 1), f.fs[1], L, f.O[1]);
-                R.C[k] = frame_u(z, cell_of(w, 2), f.fs[2], L, f.O[2]);
-                if (WHOLE) R.META[k] = w;
+    // a partner's staged index by binary search over the ascending ids (0xFFFF: not staged)
+    auto staged_index = [&](int g) {
+        int found = 0xFFFF;
+        if (g >= 0) {
+            int lo = 0, hi = S - 1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int v = m.id[mid];
+                if (v == g) {
+                    found = mid;
+                    break;
+                }
+                if (v < g) lo = mid + 1;
+                else hi = mid - 1;
             }
-            int packed = -1;
-            if (w & MOTILE_BIT) {
-                packed = 0;
-                for (int tt = 0; tt < 2; ++tt) {
-                    const int g = a.part[2 * id + tt];
-                    int found = 0xFFFF;
-                    if (g >= 0) {
-                        int lo = 0, hi = S - 1;
-                        while (lo <= hi) {
-                            const int mid = (lo + hi) >> 1;
-                            const int v = m.id[mid];
-                            if (v == g) {
-                                found = mid;
-                                break;
-                            }
-                            if (v < g) lo = mid + 1;
-                            else hi = mid - 1;
-                        }
-                    }
-                    packed |= found << (16 * tt);
+        }
+        return found;
+    };
+    // one staged bead into LDS (and its screening copy into slot k)
+    auto stage_one = [&](int k, int idx, int32_t w, double x, double y, double z, int g0, int g1) {
+        P0r[idx] = x;
+        P1r[idx] = y;
+        P2r[idx] = z;
+        if constexpr (!EXACT) {
+            R.A[k] = frame_u(x, cell_of(w, 0), f.fs[0], L, f.O[0]);
+            R.B[k] = frame_u(y, cell_of(w, 1), f.fs[1], L, f.O[1]);
+            R.C[k] = frame_u(z, cell_of(w, 2), f.fs[2], L, f.O[2]);
+            if (WHOLE) R.META[k] = w;
+        }
+        m.part[idx] = (w & MOTILE_BIT) ? (staged_index(g0) | (staged_index(g1) << 16)) : -1;
+    };
+    if constexpr (BPL <= 4) {
+        // every slot's global loads first, so that they are in flight together
+        int32_t wk[BPL];
+        double xk[BPL], yk[BPL], zk[BPL];
+        int g0k[BPL], g1k[BPL];
+#pragma unroll
+        for (int k = 0; k < BPL; ++k) {
+            const int idx = k * 64 + lane;
+            wk[k] = 0;
+            xk[k] = yk[k] = zk[k] = 0.0;
+            g0k[k] = g1k[k] = -1;
+            if (idx < S) {
+                const int id = m.id[idx];
+                wk[k] = m.meta[idx];
+                xk[k] = a.px[id];
+                yk[k] = a.py[id];
+                zk[k] = a.pz[id];
+                if (wk[k] & MOTILE_BIT) {
+                    g0k[k] = a.part[2 * id];
+                    g1k[k] = a.part[2 * id + 1];
                 }
             }
-            m.part[idx] = packed;
+        }
+#pragma unroll
+        for (int k = 0; k < BPL; ++k) {
+            const int idx = k * 64 + lane;
+            if (idx < S) stage_one(k, idx, wk[k], xk[k], yk[k], zk[k], g0k[k], g1k[k]);
+        }
+    } else {
+#pragma unroll UNR
+        for (int k = 0; k < BPL; ++k) {
+            const int idx = k * 64 + lane;
+            if (idx < S) {
+                const int id = m.id[idx];
+                const int32_t w = m.meta[idx];
+                const bool mt = (w & MOTILE_BIT) != 0;
+                stage_one(k, idx, w, a.px[id], a.py[id], a.pz[id], mt ? a.part[2 * id] : -1,
+                          mt ? a.part[2 * id + 1] : -1);
+            }
         }
     }
     // motile list in ascending id
