@@ -594,6 +594,10 @@ def main():
         "same_trajectory": bool(events_o == events and d_o["ec"] == ecs),
         "traffic": measured_traffic(other) if plain_c3 else None,
     }
+    if traffic is not None:
+        # the measured HBM bytes of a launch per collision event, and as a rate over the launch time
+        out["roofline"]["traffic_bytes_per_event"] = traffic / (events / max(launches, 1))
+        out["roofline"]["traffic_GBps"] = traffic * launches / kernel_s / 1e9 if kernel_s > 0 else None
     out["roofline"]["measured_copy_GBps"] = copy_bandwidth()
     if args.msd_sweeps > 0:
         out["msd"] = msd_run(g, nb, w, args.msd_sweeps, 1000 + args.warmup + args.steps)

@@ -937,6 +937,26 @@ def test_pushoff_loop_reaches_a_valid_start():
     g.synchronize()
 
 
+def test_pushoff_reaches_a_valid_start_at_the_benchmark_density():
+    """The slow push-off of Sec. II.B at eta = 0.45 (100 phantom chains of 32 beads, c = 1.9):
+    20 working diameters from 0.145 sigma to sigma, ECs of 2 sigma, sweeps at each until no
+    overlap is left.  It ends with no overlap, the device state check is clean, the oracle's
+    plain create accepts the state as a start, and the internal distances R^2(n)/n stay close to
+    the phantom walk's law at short range (the push-off only nudges the chains apart)."""
+    m = inputs.phantom_chains(100, 32, 0.45, seed=9)
+    n = _phantom_cells(m)
+    g = ecmc.Melt.from_melt(m, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=n, cell_capacity=32,
+                                            overlapping_start=True))
+    assert g.count_overlaps(1.0) > 1000
+    sweeps, left = g.pushoff(0.145, 20, ell=2.0, seed=1, max_sweeps=20000)
+    print(f"push-off at eta 0.45: {sweeps} sweeps, {left} overlaps left")
+    assert left == 0 and g.count_overlaps(1.0) == 0
+    assert g.check_state(1e-12) == {"overlaps": 0, "stretched": 0, "misplaced": 0}
+    oracle.Oracle(m.L, 1.0, m.b_max, g.positions(), m.bonds, n_cells=n)
+    r2, cnt = g.internal_distances(8)
+    assert cnt[1] == 100 * 31 and 1.0 <= r2[1] <= 1.4 ** 2
+
+
 def test_c4_full_batch_sampled_melts_match_the_oracle():
     """The 256-melt batch of the benchmark (8.4M beads, N from 16 to 256, eta 0.35-0.45) at full
     size in its launch configuration (one dependency-ordered launch per sweep for all melts, the
