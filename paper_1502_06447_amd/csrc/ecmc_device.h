@@ -206,11 +206,13 @@ __device__ __forceinline__ double sqrt_nonneg(double x) {
 //
 // Push-off (Sec. II.B, PUSH): a bead closer to the pivot than the working diameter (squared
 // distance below ov2 = d^2 (1 - 1e-9)) is no hard-sphere event; sig2 is then d^2.
-template <bool WRAP, bool SPRING = false, bool PUSH = false>
-__device__ __forceinline__ bool exact_candidate(double A, double B, double C, int32_t meta, const Pivot &pv, int sha,
-                                                int shb, int shc, double sgnd, double sig2, double b2, double L,
-                                                bool partner, double &x, bool &hs, double gterm = 0.0,
-                                                double sigma = 0.0, double ov2 = 0.0) {
+// d_par and d_perp^2 of a staged bead relative to the pivot: the displacement in the rotated
+// frame (with the periodic shift from the cell-index difference added after the subtraction
+// when the frame wraps), d_par along the direction of motion.  Every search computes them
+// with this one sequence of operations, so that they agree on every bit.
+template <bool WRAP>
+__device__ __forceinline__ void rel_to_pivot(double A, double B, double C, int32_t meta, const Pivot &pv, int sha,
+                                             int shb, int shc, double sgnd, double L, double &dpar, double &dperp2) {
     double da = A - pv.a;
     double db = B - pv.b;
     double dc = C - pv.c;
@@ -222,10 +224,19 @@ __device__ __forceinline__ bool exact_candidate(double A, double B, double C, in
         db = db + (eb > 1 ? -L : (eb < -1 ? L : 0.0));
         dc = dc + (ec > 1 ? -L : (ec < -1 ? L : 0.0));
     }
-    const double dpar = da * sgnd;
+    dpar = da * sgnd;
     const double pb = db * db;
     const double pc = dc * dc;
-    const double dperp2 = pb + pc;
+    dperp2 = pb + pc;
+}
+
+template <bool WRAP, bool SPRING = false, bool PUSH = false>
+__device__ __forceinline__ bool exact_candidate(double A, double B, double C, int32_t meta, const Pivot &pv, int sha,
+                                                int shb, int shc, double sgnd, double sig2, double b2, double L,
+                                                bool partner, double &x, bool &hs, double gterm = 0.0,
+                                                double sigma = 0.0, double ov2 = 0.0) {
+    double dpar, dperp2;
+    rel_to_pivot<WRAP>(A, B, C, meta, pv, sha, shb, shc, sgnd, L, dpar, dperp2);
     hs = (dpar > 0.0) && (dperp2 < sig2);
     if (PUSH && hs && dpar * dpar + dperp2 < ov2) hs = false;
     double bb2 = b2;
@@ -536,6 +547,45 @@ __device__ __forceinline__ Hit search_all(const Stage &st, const Pivot &pv, int 
     return h;
 }
 
+// The wavefront minimum by (x, key) of the lanes' best candidates (bx = +inf where a lane has
+// none), and the winner's record read from the staging area.  One wavefront reduction as a
+// rule: rounding to single precision keeps the order (x1 <= x2 gives fl(x1) <= fl(x2), and
+// the bit patterns of non-negative floats order like the numbers), so the winner is among the
+// lanes whose fl(x) is the smallest; only when several lanes share it is the FP64 (x, key)
+// minimum taken over those lanes.
+__device__ __forceinline__ Hit winner(double bx, unsigned bkey, const Stage &st, const double *pA, const double *pB,
+                                      const double *pC) {
+    Hit h;
+    h.x = INF;
+    h.key = 0xFFFFFFFFu;
+    h.a = h.b = h.c = 0.0;
+    h.meta = 0;
+    h.part = -1;
+    const unsigned fb = (unsigned)__float_as_int((float)bx);
+    const unsigned fm = wave_min_u32(fb);
+    if (fm == 0x7F800000u) return h;  // +inf: no candidate in the wavefront
+    const unsigned long long tie = __ballot(fb == fm);
+    double xs;
+    unsigned key;
+    if (__popcll(tie) == 1) {
+        const int wl = (int)(__ffsll((long long)tie) - 1);
+        xs = rdlane(bx, wl);
+        key = (unsigned)rdlane((int)bkey, wl);
+    } else {
+        xs = wave_min_nonneg_f64(fb == fm ? bx : INF);
+        key = wave_min_u32(fb == fm && bx == xs ? bkey : 0xFFFFFFFFu);
+    }
+    const int j = (int)(key >> 1);
+    h.x = xs;
+    h.key = key;
+    h.a = pA[j];
+    h.b = pB[j];
+    h.c = pC[j];
+    h.meta = __builtin_amdgcn_readfirstlane(st.meta[j]);
+    h.part = __builtin_amdgcn_readfirstlane(st.part[j]);
+    return h;
+}
+
 // The plain FP64 search of tethered chains with the square roots deferred.  Pass A takes every
 // staged bead of the lane's slots (staged index 64 k + lane) through the cheap part of
 // exact_candidate: the displacement, d_par, d_perp^2, whether it is a contact or a partner, and
@@ -610,40 +660,66 @@ __device__ __forceinline__ Hit search_deferred(const Stage &st, const Pivot &pv,
             cand &= cand - 1u;
         }
     }
-    Hit h;
-    h.x = INF;
-    h.key = 0xFFFFFFFFu;
-    h.a = h.b = h.c = 0.0;
-    h.meta = 0;
-    h.part = -1;
-    // The minimum by (x, key) in one wavefront reduction as a rule: rounding to single
-    // precision keeps the order (x1 <= x2 gives fl(x1) <= fl(x2), and the bit patterns of
-    // non-negative floats order like the numbers), so the winner is among the lanes whose
-    // fl(x) is the smallest; only when several lanes share it is the FP64 (x, key) minimum
-    // taken over those lanes.
-    const unsigned fb = (unsigned)__float_as_int((float)bx);
-    const unsigned fm = wave_min_u32(fb);
-    if (fm == 0x7F800000u) return h;  // +inf: no candidate in the wavefront
-    const unsigned long long tie = __ballot(fb == fm);
-    double xs;
-    unsigned key;
-    if (__popcll(tie) == 1) {
-        const int wl = (int)(__ffsll((long long)tie) - 1);
-        xs = rdlane(bx, wl);
-        key = (unsigned)rdlane((int)bkey, wl);
-    } else {
-        xs = wave_min_nonneg_f64(fb == fm ? bx : INF);
-        key = wave_min_u32(fb == fm && bx == xs ? bkey : 0xFFFFFFFFu);
+    return winner(bx, bkey, st, pA, pB, pC);
+}
+
+// The plain FP64 search with the square roots deferred for every bond model (springs and the
+// push-off as well as tethers).  Pass A takes every staged bead of the lane's slots through
+// the displacement only and marks the beads that can be candidates at all: ahead within sigma
+// of the line of motion, or a partner of the pivot (a superset of what exact_candidate
+// accepts: the push-off drops some of the contacts).  Pass B runs exact_candidate itself on
+// the marked beads, one per pass in slot order, and keeps the lane's minimum by (x, staged
+// index, kind) as search_all does; so the winner is the same bead with the same x, and the
+// square roots (for springs also the bond-energy square roots of the partners) are taken for
+// about a dozen beads instead of every staged one.
+template <int BPL, bool SPRING, bool PUSH>
+__device__ __forceinline__ Hit search_filtered(const Stage &st, const Pivot &pv, int S, int ax, int sha, int shb,
+                                               int shc, double sgnd, double sig2, double b2, double L, bool wr,
+                                               double g0, double g1, double sigma, double ov2) {
+    const int lane = lane_id();
+    const int q0 = pv.part & 0xFFFF, q1 = (pv.part >> 16) & 0xFFFF;
+    const double *pA = st.axis(ax);
+    const double *pB = st.axis(ax == 2 ? 0 : ax + 1);
+    const double *pC = st.axis(ax == 0 ? 2 : ax - 1);
+    unsigned cand = 0u;
+#pragma unroll
+    for (int k = 0; k < BPL; ++k) {
+        const int idx = k * 64 + lane;
+        if (k * 64 < S && idx < S && idx != pv.P) {
+            const int32_t meta = st.meta[idx];
+            double dp, dperp2;
+            if (wr) rel_to_pivot<true>(pA[idx], pB[idx], pC[idx], meta, pv, sha, shb, shc, sgnd, L, dp, dperp2);
+            else rel_to_pivot<false>(pA[idx], pB[idx], pC[idx], meta, pv, sha, shb, shc, sgnd, L, dp, dperp2);
+            const bool ahead = (dp > 0.0) && (dperp2 < sig2);
+            const bool partner = (idx == q0) || (idx == q1);
+            cand |= (ahead || partner) ? (1u << k) : 0u;
+        }
     }
-    const int j = (int)(key >> 1);
-    h.x = xs;
-    h.key = key;
-    h.a = pA[j];
-    h.b = pB[j];
-    h.c = pC[j];
-    h.meta = __builtin_amdgcn_readfirstlane(st.meta[j]);
-    h.part = __builtin_amdgcn_readfirstlane(st.part[j]);
-    return h;
+    double bx = INF;
+    unsigned bkey = 0xFFFFFFFFu;
+    while (__ballot(cand != 0u)) {
+        if (cand) {
+            const int idx = __builtin_ctz(cand) * 64 + lane;
+            const double A = pA[idx], B = pB[idx], C = pC[idx];
+            const int32_t m = st.meta[idx];
+            const bool partner = (idx == q0) || (idx == q1);
+            const double gt = idx == q0 ? g0 : g1;
+            double x;
+            bool hs;
+            const bool ok =
+                wr ? exact_candidate<true, SPRING, PUSH>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x,
+                                                         hs, gt, sigma, ov2)
+                   : exact_candidate<false, SPRING, PUSH>(A, B, C, m, pv, sha, shb, shc, sgnd, sig2, b2, L, partner, x,
+                                                          hs, gt, sigma, ov2);
+            const unsigned kk = (unsigned)(idx * 2 + (hs ? 0 : 1));
+            if (ok && (x < bx || (x == bx && kk < bkey))) {
+                bx = x;
+                bkey = kk;
+            }
+            cand &= cand - 1u;
+        }
+    }
+    return winner(bx, bkey, st, pA, pB, pC);
 }
 
 // Select element `slot` (uniform) of a lane's register array.  Written as a masked OR so
@@ -770,8 +846,12 @@ __device__ __forceinline__ void spring_terms(const PhaseArgs &a, const Frame &f,
     philox4x32_10(c, sk0, sk1);
     const unsigned long long m0 = ((unsigned long long)c[1] << 21) | (unsigned long long)(c[0] >> 11);
     const unsigned long long m1 = ((unsigned long long)c[3] << 21) | (unsigned long long)(c[2] >> 11);
-    g0 = -ln_artanh((double)(m0 + 1ull) * 0x1p-53) * a.two_over_k;
-    g1 = -ln_artanh((double)(m1 + 1ull) * 0x1p-53) * a.two_over_k;
+    // both logarithms in one instruction stream: lane 0 takes slot 0's draw, lane 1 slot 1's
+    // (the same operations on each lane's own value; called with every lane active)
+    const unsigned long long m = (lane_id() & 1) ? m1 : m0;
+    const double g = -ln_artanh((double)(m + 1ull) * 0x1p-53) * a.two_over_k;
+    g0 = rdlane(g, 0);
+    g1 = rdlane(g, 1);
 }
 
 // A reflection after an earlier one in the same EC.  Between two reflections every move is
@@ -921,6 +1001,9 @@ __device__ __forceinline__ bool run_ec(const PhaseArgs &a, const Frame &f, const
             if constexpr (SPRING) spring_terms(a, f, k, step, sk0, sk1, g0, g1);
             if constexpr (!SPRING && !PUSH && BPL <= 8)
                 hit = search_deferred<BPL>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr);
+            else if constexpr (BPL <= 8)
+                hit = search_filtered<BPL, SPRING, PUSH>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, g0,
+                                                         g1, a.sigma, a.ov2);
             else
                 hit = search_all<SPRING, PUSH>(st, pv, f.S, ax, sha, shb, shc, sgnd, a.sig2, a.b2, L, wr, g0, g1,
                                                a.sigma, a.ov2);
