@@ -679,6 +679,27 @@ def test_springs_c2_dense_melt_bit_exact(melt_c2_spring, exact, sched):
     assert n > 250_000
 
 
+@pytest.mark.parametrize("sched", [ecmc.SCHED_SWEEP, ecmc.SCHED_PHASES])
+def test_springs_clustered_large_frames_bit_exact(melt_c2_spring, sched):
+    """Springs in the clustered 500 x 32 melt (box 1.35 times wider, n = 20, D = 2, cap 1.6 sigma):
+    the staging area is sized for the mean density, so the dense frames (more than twice the mean)
+    run from workspace slots (one launch per sweep) or from the larger staging tiers (by phases),
+    where the search evaluates every staged bead in full; every event as in the oracle."""
+    m = _clustered(melt_c2_spring, 1.35)
+    frame = 64 * m.n_beads / 20 ** 3
+    p, g, o = _pair(m, ecmc.TILING_CHECKER, D=2, n_cells=20, log=40_000_000, spring_k=30.0,
+                    precision=ecmc.PREC_FP64, schedule=sched)
+    cells = np.floor(m.positions / g.h).astype(int) % 20
+    dense = np.zeros((20, 20, 20), int)
+    np.add.at(dense, (cells[:, 0], cells[:, 1], cells[:, 2]), 1)
+    win = sum(np.roll(dense, (-a, -b, -c), axis=(0, 1, 2)) for a in range(4) for b in range(4) for c in range(4))
+    assert win.max() > 2 * frame > 100
+    for s in range(2):
+        p.sweep(m.n_beads, 20.0, 61 + s)
+    n, _ = _compare(g, o)
+    assert n > 100_000
+
+
 def test_springs_tile_joint_c2_dense_melt_bit_exact(melt_c2_spring):
     """The 500 x 32 spring melt (cap 1.6 sigma) on 2^3-cell tiles at pitch 3 (n = 15: 125 tiles in
     one phase, the joints immotile): 2 sweeps of 16,000 ECs with ell = 20 sigma, every event as in
