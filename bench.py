@@ -58,10 +58,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str):
-    """HBM bytes per sweep launch of the given search (fp64 or mixed) from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when there is none or the kernel sources have
-    changed since the counters were taken."""
+def profiled_value(key: str):
+    """A value of the committed C3 counter summary (rocprofv3 runs of the sweep kernel), or None
+    when there is none or the kernel sources have changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     fields = {}
@@ -69,10 +68,14 @@ def measured_traffic(precision: str):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].strip().split(": ", 1)
             fields[k.strip("`")] = v.strip().strip("`")
-    key = f"hbm_bytes_per_launch_{precision}"
     if fields.get("kernel_source_sha256") != kernel_source_hash() or key not in fields:
         return None
     return float(fields[key])
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per sweep launch of the given search (fp64 or mixed): FETCH_SIZE + WRITE_SIZE."""
+    return profiled_value(f"hbm_bytes_per_launch_{precision}")
 
 
 WORKLOADS = {
@@ -201,26 +204,46 @@ def copy_bandwidth(gib: int = 2, reps: int = 5) -> float:
 
 def precision_check(melt, w, sweeps: int, swap: bool = False, spring_k: float = 0.0) -> dict:
     """Both precisions from the same start through the same sweeps (untimed): the screened
-    kernel must reproduce the plain FP64 kernel bit for bit."""
+    kernel must reproduce the plain FP64 kernel bit for bit.  Reported: the largest position
+    difference, the shift of <R^2>, whether every event count agrees, and the event sequences
+    compared record by record (sorted by sweep, domain, EC and step): the index of the first
+    record where they differ (null: identical).  Springs run about 300 events per EC, whose
+    logs (~10 GB at this size) are not taken."""
     import numpy as np
     from paper_1502_06447_amd import ecmc
+    # about 9 records per tether EC (collision events, wall reflections, the periodic skip, the end)
+    log_cap = 0 if spring_k > 0 else int(16 * melt.n_beads * sweeps)
     res = {}
     for name, prec in (("mixed", ecmc.PREC_MIXED), ("fp64", ecmc.PREC_FP64)):
         g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=w.get("tiling", 1), domain_cells=w["D"], precision=prec,
                                                    swap_moves=swap, spring_k=spring_k,
-                                                   n_cells=grid_cells(melt.L, melt.b_max, w)))
+                                                   n_cells=grid_cells(melt.L, melt.b_max, w),
+                                                   event_log_capacity=log_cap))
         for i in range(sweeps):
             g.sweep(melt.n_beads, w["ell"], 7000 + i)
         g.synchronize()
-        res[name] = (g.positions(), g.observables(nbins=32)["r2"].mean(), g.counters())
+        log = None
+        if log_cap:
+            log = g.event_log()
+            log = log[np.lexsort((log["step"], log["ec"], log["domain"], log["sweep"]))]
+        res[name] = (g.positions(), g.observables(nbins=32)["r2"].mean(), g.counters(), log)
         g.close()
-    (pm, r2m, cm), (pf, r2f, cf) = res["mixed"], res["fp64"]
-    return {"sweeps": sweeps, "beads": int(melt.n_beads), "positions_identical": bool(np.array_equal(pm, pf)),
-            "max_position_drift": float(np.abs(pm - pf).max()), "r2_mixed": float(r2m), "r2_fp64": float(r2f),
-            "r2_shift": float(r2m - r2f),
-            # event counts exactly; the sum of lift overlaps to rounding (atomic adds in any order)
-            "event_counts_identical": all(cm[k] == cf[k] for k in cm if k not in ("error_flags", "sum_delta")),
-            "sum_delta_rel_diff": float(abs(cm["sum_delta"] - cf["sum_delta"]) / max(abs(cf["sum_delta"]), 1e-300))}
+    (pm, r2m, cm, lm), (pf, r2f, cf, lf) = res["mixed"], res["fp64"]
+    out = {"sweeps": sweeps, "beads": int(melt.n_beads), "positions_identical": bool(np.array_equal(pm, pf)),
+           "max_position_drift": float(np.abs(pm - pf).max()), "r2_mixed": float(r2m), "r2_fp64": float(r2f),
+           "r2_shift": float(r2m - r2f),
+           # event counts exactly; the sum of lift overlaps to rounding (atomic adds in any order)
+           "event_counts_identical": all(cm[k] == cf[k] for k in cm if k not in ("error_flags", "sum_delta")),
+           "sum_delta_rel_diff": float(abs(cm["sum_delta"] - cf["sum_delta"]) / max(abs(cf["sum_delta"]), 1e-300))}
+    if log_cap:
+        m = min(len(lm), len(lf))
+        diff = np.flatnonzero(lm[:m] != lf[:m])
+        first = int(diff[0]) if len(diff) else (m if len(lm) != len(lf) else None)
+        out["event_records"] = int(len(lf))
+        out["first_divergent_event"] = first
+        if first is not None and first < m:
+            out["first_divergent_key"] = {k: int(lf[first][k]) for k in ("sweep", "domain", "ec", "step")}
+    return out
 
 
 def batch_precision_check(melts, opts, nc, dc, ell: float, sweeps: int) -> dict:
@@ -593,7 +616,11 @@ def main():
         "roofline_achieved_GBps": ach_o, "frac": ach_o / HBM_PEAK_GBS,
         "same_trajectory": bool(events_o == events and d_o["ec"] == ecs),
         "traffic": measured_traffic(other) if plain_c3 else None,
+        "lds_bank_conflict_ratio": profiled_value(f"lds_bank_conflict_ratio_{other}") if plain_c3 else None,
     }
+    # LDS bank-conflict cycles over LDS-active cycles of the sweep kernel (SQ counters)
+    out["roofline"]["lds_bank_conflict_ratio"] = (profiled_value(f"lds_bank_conflict_ratio_{args.precision}")
+                                                  if plain_c3 else None)
     if traffic is not None:
         # the measured HBM bytes of a launch per collision event, and as a rate over the launch time
         out["roofline"]["traffic_bytes_per_event"] = traffic / (events / max(launches, 1))
