@@ -330,7 +330,7 @@ ecmc_status plan(const std::vector<MeltIn> &in, double sigma, double lmax, const
         p.bpl2 = 16;
     }
     int bpl = (p.stage + 63) / 64;
-    static const int ok[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    static const int ok[] = {1, 2, 3, 4, 6, 7, 8, 12, 16};
     int pick = 0;
     for (int v : ok)
         if (v >= bpl) {

@@ -1270,9 +1270,17 @@ struct StageMem {
     int32_t *id;     // staged bead ids, ascending
     int32_t *meta;   // cell words (+ motile bit)
     int32_t *part;   // tethered partners as staged indices; then the write-back counters
-    int32_t *mot;    // motile staged indices, ascending
+    unsigned long long *motm;  // one word per 64 staged indices: which of them are motile
+    int32_t *mot;    // the motile staged indices, ascending (push-off and small tiers only)
     int cap;
 };
+
+// Whether a domain body keeps its motile beads as a list of staged indices (4 B per staged bead)
+// or only as mask words (8 B per 64): the push-off scans the list; the LDS tiers of up to 4 beads
+// per lane keep it because their occupancy is bound by registers, not LDS, and the list's EC start
+// is the shorter, and so do the workspace slots (16 per lane, global memory); the LDS tiers of 6
+// to 8 beads per lane, whose occupancy LDS bounds, keep the mask words only.
+constexpr bool motile_list(int bpl, bool push) { return push || bpl <= 4 || bpl > 8; }
 
 // One domain from its cell lists to the written-back result: stage its S0 beads (the count
 // the caller took, S0 <= min(cap, 64 BPL)), run its K ECs, write back the motile beads and
@@ -1470,14 +1478,21 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
             }
         }
     }
-    // motile list in ascending id
+    // the motile beads (the domain's own; fixed while the domain runs: a bead never leaves the
+    // domain, and a swap exchanges two motile beads) as a list in ascending staged index
+    // (= ascending id), or as one mask word per 64 staged indices
+    constexpr bool LIST = motile_list(BPL, PUSH);
     int nmot = 0;
 #pragma unroll UNR
     for (int k = 0; k < BPL; ++k) {
         const int idx = k * 64 + lane;
         const bool mt = idx < S && (m.meta[idx] & MOTILE_BIT);
         const unsigned long long bal = __ballot(mt);
-        if (mt) m.mot[nmot + mbcnt(bal)] = idx;
+        if constexpr (LIST) {
+            if (mt) m.mot[nmot + mbcnt(bal)] = idx;
+        } else if (lane == 0) {
+            m.motm[k] = bal;
+        }
         nmot += __popcll(bal);
     }
     __syncthreads();
@@ -1516,8 +1531,26 @@ __device__ __forceinline__ void domain_body(const PhaseArgs &a, Frame &f, int F,
                 }
                 r -= c;
             }
-        } else {
+        } else if constexpr (LIST) {
             P0 = __builtin_amdgcn_readfirstlane(m.mot[scale_u32(ctr[0], (uint32_t)nmot)]);
+        } else {
+            // the r-th motile bead in ascending staged index: the mask word that holds it, then
+            // the lane whose rank among that word's motile lanes is what is left of r
+            int r = (int)scale_u32(ctr[0], (uint32_t)nmot);
+            P0 = 0;
+            for (int q = 0; q < BPL; ++q) {
+                const unsigned long long w = m.motm[q];
+                const unsigned long long mk =
+                    ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(w >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)w);
+                const int c = __popcll(mk);
+                if (r < c) {
+                    const bool mine = ((mk >> lane) & 1ull) && mbcnt(mk) == r;
+                    P0 = q * 64 + (int)(__ffsll((long long)__ballot(mine)) - 1);
+                    break;
+                }
+                r -= c;
+            }
         }
         const uint32_t dir = scale_u32(ctr[1], 6u);
         const int ax = __builtin_amdgcn_readfirstlane((int)(dir >> 1));

@@ -28,7 +28,8 @@ template <int BPL, bool LOG, bool EXACT, bool WHOLE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(BPL)))) void K_PHASE(const PhaseArgs a) {
     constexpr int SMAX = 64 * BPL;
     __shared__ double s_pos[3][SMAX];
-    __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[SMAX];
+    __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[motile_list(BPL, false) ? SMAX : 1];
+    __shared__ unsigned long long s_motm[motile_list(BPL, false) ? 1 : BPL];
     // this sweep's number and partition, from the device-side sweep counter
     PhaseArgs b = a;
     b.sweep = a.dstate[0];
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
         if (lane_id() == 0) atomicOr(a.err, ERR_STAGE);
         return;
     }
-    const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
+    const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_motm, s_mot, SMAX};
     domain_body<BPL, LOG, EXACT, WHOLE, SPRING>(b, f, F, wraps, S0, m);
 }
 
@@ -77,6 +78,7 @@ hipError_t PHASE_LAUNCHER(const PhaseArgs &a, int bpl, bool log, int grid, hipSt
         case 3: return launch_bpl<3>(a, log, grid, s);
         case 4: return launch_bpl<4>(a, log, grid, s);
         case 6: return launch_bpl<6>(a, log, grid, s);
+        case 7: return launch_bpl<7>(a, log, grid, s);
         case 8: return launch_bpl<8>(a, log, grid, s);
         case 12: return launch_bpl<12>(a, log, grid, s);
         case 16: return launch_bpl<16>(a, log, grid, s);

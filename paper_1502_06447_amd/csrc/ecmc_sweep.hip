@@ -131,7 +131,8 @@ template <int BPL, bool LOG, bool EXACT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(BPL)))) void K_SWEEP(const PhaseArgs a) {
     constexpr int SMAX = 64 * BPL;
     __shared__ double s_pos[3][SMAX];
-    __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[SMAX];
+    __shared__ int32_t s_id[SMAX], s_meta[SMAX], s_part[SMAX], s_mot[motile_list(BPL, PUSH) ? SMAX : 1];
+    __shared__ unsigned long long s_motm[motile_list(BPL, PUSH) ? 1 : BPL];
     const int lane = lane_id();
     // one ticket per workgroup, taken when the workgroup runs: ticket order, not launch order,
     // is the order of the waits.  Tickets run colour by colour, melt by melt within a colour.
@@ -175,16 +176,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(phase_waves(
     if (!ready) {
         // nothing to do
     } else if (S <= SMAX) {
-        const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_mot, SMAX};
+        const StageMem m = {&s_pos[0][0], s_id, s_meta, s_part, s_motm, s_mot, SMAX};
         domain_body<BPL, LOG, EXACT, false, SPRING, PUSH>(b, f, F, wraps, S, m);
     } else if (S <= a.slow_cap) {
         slot = take_slot(a, t);
         if (slot >= 0) {
-            // slot layout: three rows of positions, then id, meta, part, mot rows
+            // slot layout: three rows of positions, then id, meta, part and motile-list rows
             const int cap = a.slow_cap;
             double *base = a.slow + (size_t)slot * (size_t)cap * (SLOW_SLOT_BYTES_PER_BEAD / 8);
             int32_t *ib = reinterpret_cast<int32_t *>(base + 3 * (size_t)cap);
-            const StageMem m = {base, ib, ib + cap, ib + 2 * cap, ib + 3 * cap, cap};
+            const StageMem m = {base, ib, ib + cap, ib + 2 * cap, nullptr, ib + 3 * cap, cap};
             domain_body<16, LOG, true, false, SPRING, PUSH>(b, f, F, wraps, S, m);
         }
     } else if (lane == 0) {
@@ -234,7 +235,7 @@ hipError_t launch_sweep_b(const PhaseArgs &a, bool log, int *grid, hipStream_t s
 #if !ECMC_SPRING_TU && !ECMC_PUSH_TU
 bool sweep_bpl_supported(int bpl) {
     switch (bpl) {
-        case 1: case 2: case 3: case 4: case 6: case 8: return true;
+        case 1: case 2: case 3: case 4: case 6: case 7: case 8: return true;
         default: return false;
     }
 }
@@ -247,6 +248,7 @@ hipError_t SWEEP_LAUNCHER(const PhaseArgs &a, int bpl, bool log, int *grid, hipS
         case 3: return launch_sweep_b<3>(a, log, grid, s);
         case 4: return launch_sweep_b<4>(a, log, grid, s);
         case 6: return launch_sweep_b<6>(a, log, grid, s);
+        case 7: return launch_sweep_b<7>(a, log, grid, s);
         case 8: return launch_sweep_b<8>(a, log, grid, s);
         default: return hipErrorInvalidValue;
     }

@@ -128,6 +128,19 @@ def test_c2_dense_melt_bit_exact(melt_c2, D, n_cells, exact, sched):
     assert n > 250_000
 
 
+@pytest.mark.parametrize("exact,tier", [(True, 448), (False, 448), (True, 384)])
+def test_c2_dense_melt_wide_staging_tiers_bit_exact(melt_c2, exact, tier):
+    """The 500 x 32 melt (n = 18, D = 3, frames of about 340 beads) staged in the 448-bead tier (7
+    beads per lane) and the 384-bead tier (6 per lane; the frames above it run from workspace
+    slots), 2 sweeps of 16,000 ECs: every event as in the oracle."""
+    p, g, o = _pair(melt_c2, ecmc.TILING_CHECKER, D=3, n_cells=18, log=40_000_000,
+                    precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED, stage_tier=tier)
+    for s in range(2):
+        p.sweep(16000, 20.0, 15 + s)
+    n, _ = _compare(g, o)
+    assert n > 250_000
+
+
 def _clustered(melt, grow):
     """The chains of `melt` that do not cross its periodic boundary, unchanged, in a box `grow`
     times wider: a dense region next to an empty one, so that domain frames hold very
