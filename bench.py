@@ -45,6 +45,7 @@ def bytes_per_event(beads_per_cell: float) -> float:
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ecmc_sweep_c3_1M_hbm_traffic.md")
+BATCH_COUNTERS = os.path.join(ROOT, "profiles", "ecmc_sweep_c4_256melts_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1502_06447_amd", "csrc", f)
                   for f in ("ecmc_device.h", "ecmc_internal.h", "ecmc_kernels.hip", "ecmc_phase.hip",
                             "ecmc_sweep.hip")]
@@ -58,13 +59,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_value(key: str):
-    """A value of the committed C3 counter summary (rocprofv3 runs of the sweep kernel), or None
-    when there is none or the kernel sources have changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def profiled_value(key: str, summary: str = TRAFFIC_SUMMARY):
+    """A value of a committed counter summary (rocprofv3 runs of the sweep kernel; by default the
+    C3 one), or None when there is none or the kernel sources have changed since the counters were
+    taken."""
+    if not os.path.exists(summary):
         return None
     fields = {}
-    for line in open(TRAFFIC_SUMMARY):
+    for line in open(summary):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].strip().split(": ", 1)
             fields[k.strip("`")] = v.strip().strip("`")
@@ -366,6 +368,11 @@ def main_batch(args):
     occ = sum(i["n_beads"] * (i["n_beads"] / i["n_cells"] ** 3) for i in infos) / nb
     B = bytes_per_event(occ)
     achieved = events * B / kernel_s / 1e9 if kernel_s > 0 else 0.0
+    # the committed counters are of the configuration the tuner picks for this batch (the first
+    # geometry policy, 256-bead tier, plain FP64 search); another choice has none
+    profiled = (bool(tune) and tune["policy"] == 0 and opts.stage_tier == 256 and opts.precision == ecmc.PREC_FP64
+                and not args.swap)
+    traffic = profiled_value("hbm_bytes_per_launch_fp64", BATCH_COUNTERS) if profiled else None
     out = {
         "metric": "collision events/s",
         "value": value,
@@ -397,12 +404,18 @@ def main_batch(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "bytes_per_event": B,
+            "lds_bank_conflict_ratio": (profiled_value("lds_bank_conflict_ratio_fp64", BATCH_COUNTERS)
+                                        if profiled else None),
             "note": "algorithmic bytes (18-cell forward cell-list scan per collision event, bead-weighted mean "
-                    "cell occupancy) over the HIP-event time of the graph replay",
+                    "cell occupancy) over the HIP-event time of the graph replay; traffic: measured HBM bytes "
+                    "per sweep launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated by a copy)",
         },
     }
+    if traffic is not None:
+        out["roofline"]["traffic_bytes_per_event"] = traffic / (events / args.steps)
+        out["roofline"]["traffic_GBps"] = traffic * args.steps / kernel_s / 1e9 if kernel_s > 0 else None
     if not args.no_precision_check:
         out["precision_check"] = batch_precision_check(melts, opts, nc, dc, ell, sweeps=2)
     if not args.no_cpu_baseline:
