@@ -120,9 +120,10 @@ typedef struct {
                                    colour_mask other than all eight colours, or a staging
                                    capacity above 512 beads, always runs by phases          */
     int32_t stage_tier;         /* with stage_capacity = 0: beads of the LDS staging tier
-                                   (a multiple of 64 up to 512; 0 = sized for the typical
-                                   domain); larger domains are staged as for the automatic
-                                   capacity.  The knob ecmc_tune_batch sets                */
+                                   (a multiple of 64 up to 512, run as 64 x 1, 2, 3, 4, 6, 7
+                                   or 8 beads per lane, the next one up; 0 = sized for the
+                                   typical domain); larger domains are staged as for the
+                                   automatic capacity.  The knob ecmc_tune_batch sets      */
     int32_t overlapping_start;  /* nonzero: hard-sphere overlaps in the start are accepted (the
                                    phantom start of the push-off, ecmc_pushoff); tethers only,
                                    no swap moves.  Plain sweeps on an overlapping state are the
