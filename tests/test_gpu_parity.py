@@ -692,6 +692,19 @@ def test_springs_c2_dense_melt_bit_exact(melt_c2_spring, exact, sched):
     assert n > 250_000
 
 
+@pytest.mark.parametrize("exact", [True, False])
+def test_springs_c2_in_the_448_bead_tier_bit_exact(melt_c2_spring, exact):
+    """The 500 x 32 spring melt (n = 16, D = 2, frames of about 250 beads) staged in the 448-bead tier
+    (7 beads per lane, the motile beads as mask words), 2 sweeps of 16,000 ECs: every event as in
+    the oracle."""
+    p, g, o = _pair(melt_c2_spring, ecmc.TILING_CHECKER, D=2, n_cells=16, log=40_000_000, spring_k=30.0,
+                    precision=ecmc.PREC_FP64 if exact else ecmc.PREC_MIXED, stage_tier=448)
+    for s in range(2):
+        p.sweep(16000, 20.0, 540 + s)
+    n, _ = _compare(g, o)
+    assert n > 250_000
+
+
 @pytest.mark.parametrize("sched", [ecmc.SCHED_SWEEP, ecmc.SCHED_PHASES])
 def test_springs_clustered_large_frames_bit_exact(melt_c2_spring, sched):
     """Springs in the clustered 500 x 32 melt (box 1.35 times wider, n = 20, D = 2, cap 1.6 sigma):
