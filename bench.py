@@ -112,6 +112,20 @@ def grid_cells(L: float, b_max: float, w) -> int:
     return checker_cells(L, b_max, w["D"])
 
 
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: CPU model, logical CPUs, and those this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False, spring_k: float = 0.0,
                  b_max: float = 1.4) -> dict:
     """The CPU oracle (serial, one core) on a bounded sample of the same workload: an
@@ -141,7 +155,7 @@ def cpu_baseline(w, seconds: float = 12.0, seed: int = 5, swap: bool = False, sp
                       + ("tile-joint " if w.get("tiling", 1) == 2 else "") + f"D={w['D']}, {n}^3 cells"
                       + (f", springs k={spring_k} capped at {b_max}" if spring_k else "") + f": {k} sweeps "
                       f"after 2 warm-up sweeps, {dt:.1f} s, single thread",
-            "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
+            "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt, "host": host_cpu()}
 
 
 def _oracle_worker(args):
@@ -286,7 +300,7 @@ def batch_cpu_baseline(melt, ell: float, D: int, n_cells: int, seconds: float) -
     return {"value": ev / dt, "unit": "collision events/s", "cores": 1, "kind": "oracle",
             "sample": f"melt 0 of the batch ({melt.n_beads} beads, N={melt.n_per}, eta={melt.eta:.3f}), "
                       f"{n_cells}^3 cells, D={D}: {k} sweeps after 1 warm-up sweep, {dt:.1f} s, single thread",
-            "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt}
+            "ec_per_s": float(c1[oracle.C_EC] - c0[oracle.C_EC]) / dt, "host": host_cpu()}
 
 
 def copy_probe(mib: int) -> None:
