@@ -223,3 +223,21 @@ def test_shape_descriptors_take_any_eigenvalue_order():
     assert all(abs(a[k] - b[k]) < 1e-13 * max(1.0, abs(a[k])) for k in a)
     with pytest.raises(ecmc.EcmcError):
         ecmc.shape_descriptors(np.zeros((2, 3)))
+
+
+def test_bench_profiled_values_follow_the_kernel_source_hash(tmp_path):
+    """bench.py takes measured HBM traffic and LDS figures from a committed counter summary only while
+    the kernel sources still hash to the value recorded there (null otherwise, or without a summary)."""
+    import bench
+    good = tmp_path / "good.md"
+    good.write_text(f"text\n- `kernel_source_sha256`: `{bench.kernel_source_hash()}`\n"
+                    "- `hbm_bytes_per_launch_fp64`: `1.5e+09`\n- `lds_bank_conflict_ratio_fp64`: `6.0e-03`\n")
+    assert bench.profiled_value("hbm_bytes_per_launch_fp64", str(good)) == 1.5e9
+    assert bench.profiled_value("lds_bank_conflict_ratio_fp64", str(good)) == 6.0e-3
+    assert bench.profiled_value("hbm_bytes_per_launch_mixed", str(good)) is None
+    stale = tmp_path / "stale.md"
+    stale.write_text("- `kernel_source_sha256`: `0`\n- `hbm_bytes_per_launch_fp64`: `1.5e+09`\n")
+    assert bench.profiled_value("hbm_bytes_per_launch_fp64", str(stale)) is None
+    assert bench.profiled_value("hbm_bytes_per_launch_fp64", str(tmp_path / "absent.md")) is None
+    h = bench.host_cpu()
+    assert isinstance(h["logical_cpus"], int) and h["logical_cpus"] >= 1
