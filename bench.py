@@ -541,7 +541,9 @@ def main():
     nb = melt.n_beads
 
     def timed_run(precision: str):
-        """W untimed and K timed sweeps (each followed by the observables) of a fresh context."""
+        """W untimed and K timed sweeps of a fresh context, each followed by the observables, which
+        are added to running device sums (no host round trip between sweeps); their means over the
+        K timed sweeps are read after the timed region."""
         prec = ecmc.PREC_MIXED if precision == "mixed" else ecmc.PREC_FP64
         g = ecmc.Melt.from_melt(melt, ecmc.Options(tiling=w.get("tiling", 1), domain_cells=w["D"], time_kernels=True,
                                                    precision=prec, swap_moves=args.swap, spring_k=args.springs,
@@ -549,13 +551,14 @@ def main():
 
         def step(i):
             g.sweep(nb, w["ell"], 1000 + i)
-            g.observables(nbins=32)
+            g.observables_accumulate(nbins=32)
 
         for i in range(args.warmup):
             step(i)
             print(f"# {precision} warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
         g.synchronize()
         g.kernel_time()
+        g.observables_reset()
         c0 = g.counters()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -572,6 +575,7 @@ def main():
         return g, dt, d, events, kms, launches
 
     g, dt, d, events, kms, launches = timed_run(args.precision)
+    obs = g.observables_mean()
     n = g.n_cells
     beads_per_cell = nb / n ** 3
     print(f"# {args.workload}: {nb} beads, L={melt.L:.4f}, n={n}, h={g.h:.4f}, staging {g.stage_capacity}",
@@ -612,6 +616,9 @@ def main():
         "bead_sweeps_per_s": ecs / dt,
         "events_per_ec": events / max(ecs, 1),
         "counters": {k: int(v) if isinstance(v, int) else v for k, v in d.items()},
+        "observables": {"r2_mean": obs["r2"], "rg2_mean": obs["rg2"], "samples": obs["samples"],
+                        "note": "<R^2>, <R_g^2> per chain over the timed sweeps, sampled after each on the "
+                                "device"},
         "kernel_ms_per_step": kms / args.steps,
         "timed_launches": launches,
         "roofline": {

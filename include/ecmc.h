@@ -298,6 +298,22 @@ ecmc_status ecmc_synchronize(ecmc_ctx *ctx);
 ecmc_status ecmc_observables(ecmc_ctx *ctx, int32_t nbins, double *r2, double *rg2,
                              int64_t *hist, double *mid, int64_t *n_poly);
 
+/* Observables sampled every sweep without a host round trip (the averages over sweeps that
+ * Sec. IV.A reports): ecmc_observables_accumulate evaluates the quantities of ecmc_observables
+ * on the context's stream and adds the sums over all polymers of r2 and rg2, and the
+ * bond-length histogram, to running sums in device memory; it returns once the work is
+ * enqueued (asynchronous like ecmc_sweep).  nbins must stay the same until the next reset
+ * (ECMC_E_ARG otherwise).
+ * ecmc_observables_mean synchronises and returns <r2> and <rg2> per polymer and sample, the
+ * summed histogram (host hist [nbins] of the accumulating calls), and the number of samples
+ * (any output may be NULL).  The sums are added with atomics in any order: means agree with
+ * the per-sample averages of ecmc_observables to rounding, the histogram exactly.
+ * ecmc_observables_reset clears the running sums (a kernel on the stream). */
+ecmc_status ecmc_observables_accumulate(ecmc_ctx *ctx, int32_t nbins);
+ecmc_status ecmc_observables_mean(ecmc_ctx *ctx, double *r2_mean, double *rg2_mean, int64_t *hist,
+                                  int64_t *samples);
+ecmc_status ecmc_observables_reset(ecmc_ctx *ctx);
+
 /* Shape analysis (appendix, moment of inertia tensor; the centre of mass that g2 of Sec. IV.A
  * measures the middle bead against): per polymer, chains unwrapped from their smaller-id end,
  * the gyration tensor G = N^-1 sum (u - u_cm)(u - u_cm)^T as gyr [6] (xx, yy, zz, xy, xz, yz),

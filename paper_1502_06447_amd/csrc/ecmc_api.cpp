@@ -79,7 +79,7 @@ struct Plan {
 
 struct Layout {
     size_t px, py, pz, cellp, img, part, ccount, cids, dstage, done, queue, dstate, slow_lock, slow, melts, porder,
-        pstart, polyL, r2, rg2, mid, shape, hist, lags, cnt, dsum, err, log_n, log;
+        pstart, polyL, r2, rg2, mid, shape, hist, acc, lags, cnt, dsum, err, log_n, log;
     size_t total;
     int64_t lag_slots;  // partial sums the internal-distance area holds (blocks x lags)
 };
@@ -118,6 +118,7 @@ Layout make_layout(const Plan &p, int64_t npoly_max, int cap, int64_t log_cap) {
     l.mid = take(24 * np);
     l.shape = take(96 * np);  // gyration tensor, eigenvalues, centre of mass: 12 doubles per polymer
     l.hist = take(8 * MAX_BINS);
+    l.acc = take(8 * (2 * OBS_ACC_SLOTS + MAX_BINS));  // running sums of r2 and rg2, then a histogram
     // internal distances: per-block partial sums of every lag, then the totals
     const int64_t lag_max = std::min<int64_t>(std::max<int64_t>(p.nb, 1), LAG_MAX_BEADS);
     l.lag_slots = std::min<int64_t>(LAG_SLOTS, std::max<int64_t>(npoly_max, 1) * lag_max);
@@ -147,6 +148,8 @@ struct ecmc_ctx {
     Layout lay{};
     char *ws = nullptr;
     uint32_t sweep_ctr = 0;           // host count of sweeps (the device holds the authoritative one)
+    int64_t acc_samples = 0;          // observable samples in the running sums, and their bins
+    int32_t acc_nbins = 0;
     unsigned long long wait_ticks = 0;  // limit of one dependency wait, in steady-counter ticks
     std::string err;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timing;
@@ -525,6 +528,7 @@ ecmc_status upload(ecmc_ctx *c, const HostState &hs, bool topology) {
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.done, 0, 4 * (size_t)(c->p.domains + 1), s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.queue, 0, 8, s));
         HIP_OK(c, hipMemsetAsync(c->ws + c->lay.dstate, 0, 8, s));
+        HIP_OK(c, hipMemsetAsync(c->ws + c->lay.acc, 0, 8 * (2 * OBS_ACC_SLOTS + MAX_BINS), s));
         if (c->p.nslow > 0) HIP_OK(c, hipMemsetAsync(c->ws + c->lay.slow_lock, 0, 4 * (size_t)c->p.nslow, s));
     }
     HIP_OK(c, hipStreamSynchronize(s));
@@ -1100,6 +1104,57 @@ ecmc_status ecmc_observables(ecmc_ctx *c, int32_t nbins, double *r2, double *rg2
     if (rg2) HIP_OK(c, hipMemcpy(rg2, o.rg2, 8 * c->npoly, hipMemcpyDeviceToHost));
     if (mid) HIP_OK(c, hipMemcpy(mid, o.mid, 24 * c->npoly, hipMemcpyDeviceToHost));
     if (hist) HIP_OK(c, hipMemcpy(hist, o.hist, 8 * nbins, hipMemcpyDeviceToHost));
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_observables_accumulate(ecmc_ctx *c, int32_t nbins) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    if (nbins <= 0 || nbins > MAX_BINS) return fail(c, ECMC_E_ARG, "nbins must be in [1, %d]", MAX_BINS);
+    if (c->acc_samples > 0 && nbins != c->acc_nbins)
+        return fail(c, ECMC_E_ARG, "nbins %d differs from the %d of the running sums (reset them first)", nbins,
+                    c->acc_nbins);
+    ObsArgs o = obs_args(c);
+    o.nbins = nbins;
+    o.r2 = c->dev<double>(c->lay.r2);
+    o.rg2 = c->dev<double>(c->lay.rg2);
+    o.mid = c->dev<double>(c->lay.mid);
+    o.acc = c->dev<double>(c->lay.acc);
+    o.hist = c->dev<unsigned long long>(c->lay.acc + 8 * 2 * OBS_ACC_SLOTS);
+    HIP_OK(c, launch_observables(o, c->stream));
+    c->acc_nbins = nbins;
+    ++c->acc_samples;
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_observables_mean(ecmc_ctx *c, double *r2_mean, double *rg2_mean, int64_t *hist, int64_t *samples) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    ecmc_status st = check_device(c);
+    if (st) return st;
+    if (samples) *samples = c->acc_samples;
+    std::vector<double> acc(2 * OBS_ACC_SLOTS + MAX_BINS);
+    HIP_OK(c, hipMemcpy(acc.data(), c->ws + c->lay.acc, 8 * acc.size(), hipMemcpyDeviceToHost));
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < OBS_ACC_SLOTS; ++i) {
+        s0 += acc[i];
+        s1 += acc[OBS_ACC_SLOTS + i];
+    }
+    const double n = (double)c->acc_samples * (double)c->npoly;
+    if (r2_mean) *r2_mean = n > 0 ? s0 / n : 0.0;
+    if (rg2_mean) *rg2_mean = n > 0 ? s1 / n : 0.0;
+    if (hist)
+        for (int i = 0; i < c->acc_nbins; ++i) {
+            uint64_t v;
+            std::memcpy(&v, &acc[2 * OBS_ACC_SLOTS + i], 8);
+            hist[i] = (int64_t)v;
+        }
+    return ECMC_OK;
+}
+
+ecmc_status ecmc_observables_reset(ecmc_ctx *c) {
+    if (!c) return fail(nullptr, ECMC_E_ARG, "null context");
+    HIP_OK(c, launch_zero_u64(c->dev<unsigned long long>(c->lay.acc), 2 * OBS_ACC_SLOTS + MAX_BINS, c->stream));
+    c->acc_samples = 0;
+    c->acc_nbins = 0;
     return ECMC_OK;
 }
 

@@ -135,7 +135,12 @@ struct ObsArgs {
     double rmax;
     int nlag;                  // internal distances: lags 0..nlag-1
     double *lagsum;            // [nlag][rows] per-block sums, then [nlag] their totals
+    double *acc;               // running sums (or null): [OBS_ACC_SLOTS] of r2, then as many of rg2;
+                               // block b adds to slot b mod OBS_ACC_SLOTS
 };
+
+// slots of the running observable sums: the blocks of one launch spread their atomic adds over them
+constexpr int OBS_ACC_SLOTS = 64;
 
 // internal distances: room for the per-block partial sums (blocks x lags), and the longest
 // chain they take
@@ -172,6 +177,7 @@ hipError_t launch_sweep_push(const PhaseArgs &a, int bpl, bool log, int *grid, h
 bool sweep_bpl_supported(int bpl);
 constexpr int SLOW_SLOT_BYTES_PER_BEAD = 3 * 8 + 4 * 4;  // staging slot: positions + 4 int32 rows
 hipError_t launch_observables(const ObsArgs &a, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, long long n, hipStream_t s);
 hipError_t launch_shape(const ObsArgs &a, hipStream_t s);
 hipError_t launch_pairs(const PairArgs &a, hipStream_t s);
 hipError_t launch_check(const PairArgs &a, hipStream_t s);

@@ -61,8 +61,10 @@ constexpr int OBS_MAX_BINS = 1024;
 
 __global__ __launch_bounds__(64 * OBS_WAVES) void k_observables(const ObsArgs a) {
     __shared__ unsigned s_hist[OBS_MAX_BINS];
+    __shared__ double s_acc[2][OBS_WAVES];
     const int lane = lane_id();
     const int w = (int)threadIdx.x >> 6;
+    double acc_r2 = 0.0, acc_rg2 = 0.0;  // this wavefront's polymers (lane 0)
     for (int i = (int)threadIdx.x; i < a.nbins; i += 64 * OBS_WAVES) s_hist[i] = 0u;
     __syncthreads();
     for (int64_t q = (int64_t)blockIdx.x * OBS_WAVES + w; q < a.npoly; q += (int64_t)gridDim.x * OBS_WAVES) {
@@ -124,23 +126,48 @@ __global__ __launch_bounds__(64 * OBS_WAVES) void k_observables(const ObsArgs a)
             const double r0 = c0 * c0;
             const double r1 = c1 * c1;
             const double r2 = c2 * c2;
-            a.r2[q] = (r0 + r1) + r2;
+            const double e2 = (r0 + r1) + r2;
+            a.r2[q] = e2;
             const double g0 = m0 * m0;
             const double g1 = m1 * m1;
             const double g2 = m2 * m2;
-            a.rg2[q] = qq - ((g0 + g1) + g2);
+            const double gy2 = qq - ((g0 + g1) + g2);
+            a.rg2[q] = gy2;
+            acc_r2 += e2;
+            acc_rg2 += gy2;
             if (a.rhist) {
                 // W(R): |R| binned from 0 in rbins bins of width rmax / rbins, the rest in the last
-                int bin = (int)__builtin_floor(__builtin_sqrt(a.r2[q]) / a.rmax * (double)a.rbins);
+                int bin = (int)__builtin_floor(__builtin_sqrt(e2) / a.rmax * (double)a.rbins);
                 if (bin > a.rbins - 1) bin = a.rbins - 1;
                 atomicAdd(&a.rhist[bin], 1ull);
             }
         }
     }
+    if (lane == 0) {
+        s_acc[0][w] = acc_r2;
+        s_acc[1][w] = acc_rg2;
+    }
     __syncthreads();
     if (a.hist)
         for (int i = (int)threadIdx.x; i < a.nbins; i += 64 * OBS_WAVES)
             if (s_hist[i]) atomicAdd(&a.hist[i], (unsigned long long)s_hist[i]);
+    if (a.acc && threadIdx.x == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int i = 0; i < OBS_WAVES; ++i) {
+            t0 += s_acc[0][i];
+            t1 += s_acc[1][i];
+        }
+        const int slot = (int)(blockIdx.x % OBS_ACC_SLOTS);
+        atomicAdd(&a.acc[slot], t0);
+        atomicAdd(&a.acc[OBS_ACC_SLOTS + slot], t1);
+    }
+}
+
+// Clears n 8-byte words (a kernel rather than a memset node, so that the call can be captured
+// in a HIP graph).
+__global__ void k_zero_u64(unsigned long long *p, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0ull;
 }
 
 // Eigenvalues, descending, of a symmetric 3 x 3 matrix (xx, yy, zz, xy, xz, yz): the
@@ -564,6 +591,14 @@ hipError_t launch_internal(const ObsArgs &a, int rows, int longest, hipStream_t 
     hipLaunchKernelGGL(k_internal, dim3((unsigned)rows), dim3((unsigned)threads), (size_t)(24 * longest + 8 * a.nlag), s, a,
                        longest);
     hipLaunchKernelGGL(k_lag_total, dim3((unsigned)a.nlag), dim3(LAG_THREADS), 0, s, a.lagsum, rows, a.nlag);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long grid = (n + 255) / 256;
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)grid), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -116,7 +116,8 @@ EXPORTS = (
     "ecmc_tune_workspace_size", "ecmc_tune_batch", "ecmc_snapshot", "ecmc_msd", "ecmc_end_to_end_histogram",
     "ecmc_pair_histogram", "ecmc_pushoff_sweep", "ecmc_count_overlaps", "ecmc_pushoff", "ecmc_internal_distances",
     "ecmc_check_state", "ecmc_screen_constants", "ecmc_internal_distances_noalloc", "ecmc_clear_error",
-    "ecmc_shape_descriptors", "ecmc_pair_correlation",
+    "ecmc_shape_descriptors", "ecmc_pair_correlation", "ecmc_observables_accumulate", "ecmc_observables_mean",
+    "ecmc_observables_reset",
 )
 
 
@@ -144,6 +145,9 @@ def lib():
         "ecmc_sweep_colours": (st, [vp, i64, dbl, u64, u32]),
         "ecmc_synchronize": (st, [vp]),
         "ecmc_observables": (st, [vp, i32, vp, vp, vp, vp, P(i64)]),
+        "ecmc_observables_accumulate": (st, [vp, i32]),
+        "ecmc_observables_mean": (st, [vp, P(dbl), P(dbl), vp, P(i64)]),
+        "ecmc_observables_reset": (st, [vp]),
         "ecmc_shape": (st, [vp, vp, vp, vp, P(i64)]),
         "ecmc_snapshot": (st, [vp, vp]),
         "ecmc_msd": (st, [vp, vp, i64, vp]),
@@ -594,6 +598,25 @@ class Melt:
                                       mid.ctypes.data, ctypes.byref(n_poly)), "ecmc_observables", self.ctx)
         assert n_poly.value == M
         return {"r2": r2, "rg2": rg2, "hist": hist, "mid": mid, "n_poly": M}
+
+    def observables_accumulate(self, nbins: int = 20):
+        """Add this state's observables (sums over polymers of R^2 and R_g^2, the bond-length
+        histogram) to running device sums; asynchronous, no host round trip."""
+        _check(lib().ecmc_observables_accumulate(self.ctx, int(nbins)), "ecmc_observables_accumulate", self.ctx)
+        self._acc_nbins = int(nbins)
+
+    def observables_mean(self) -> dict:
+        """<R^2>, <R_g^2> per polymer and sample, the summed bond-length histogram and the sample
+        count of the running sums (synchronises)."""
+        r2, rg2, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        hist = np.zeros(max(getattr(self, "_acc_nbins", 0), 1), dtype=np.int64)
+        _check(lib().ecmc_observables_mean(self.ctx, ctypes.byref(r2), ctypes.byref(rg2), hist.ctypes.data,
+                                           ctypes.byref(n)), "ecmc_observables_mean", self.ctx)
+        return {"r2": r2.value, "rg2": rg2.value, "hist": hist[:getattr(self, "_acc_nbins", 0)], "samples": n.value}
+
+    def observables_reset(self):
+        _check(lib().ecmc_observables_reset(self.ctx), "ecmc_observables_reset", self.ctx)
+        self._acc_nbins = 0
 
     def pushoff_sweep(self, n_chains: int, ell: float, seed: int, diameter: float):
         """One push-off sweep (Sec. II.B) at working diameter d: overlapping pairs are no events,

@@ -6,6 +6,7 @@
   the guard is forced from the host with a wait limit of one microsecond, every kernel still
   ends normally, the call reports ECMC_E_DEVICE, and the state stays valid (no overlap, no
   stretched bond, every bead listed in its own cell).
+- The running device sums of the observables agree with the per-sweep observables.
 """
 import numpy as np
 import pytest
@@ -73,3 +74,36 @@ def test_pair_correlation_of_the_dense_melt(melt_c2):
     edges = np.linspace(0.0, r_max, 41)
     assert np.all(gr[edges[1:] <= 1.0] == 0.0)
     assert gr[np.searchsorted(edges, 1.0)] > 1.5
+
+
+def test_observables_accumulate_matches_the_per_sweep_observables(melt_c2):
+    """The running device sums of the observables (averages over sweeps, Sec. IV.A) against the
+    per-sweep results of ecmc_observables: <R^2> and <R_g^2> to rounding (the sums are atomic adds
+    in any order), the bond-length histogram exactly.  A reset clears them; another bin count
+    without a reset is refused."""
+    g = ecmc.Melt.from_melt(melt_c2, ecmc.Options(tiling=ecmc.TILING_CHECKER, domain_cells=2, n_cells=16))
+    g.observables_accumulate(nbins=24)  # cleared by the reset below
+    g.observables_reset()
+    r2s, rg2s, hist = [], [], np.zeros(24, dtype=np.int64)
+    for k in range(3):
+        g.sweep(16000, 20.0, 600 + k)
+        g.observables_accumulate(nbins=24)
+        o = g.observables(nbins=24)
+        r2s.append(o["r2"].mean())
+        rg2s.append(o["rg2"].mean())
+        hist += o["hist"]
+    m = g.observables_mean()
+    assert m["samples"] == 3
+    assert abs(m["r2"] - np.mean(r2s)) <= 1e-12 * np.mean(r2s)
+    assert abs(m["rg2"] - np.mean(rg2s)) <= 1e-12 * np.mean(rg2s)
+    assert np.array_equal(m["hist"], hist) and hist.sum() == 3 * 500 * 31
+    with pytest.raises(ecmc.EcmcError) as e:
+        g.observables_accumulate(nbins=10)
+    assert e.value.code == ecmc.E_ARG
+    g.observables_reset()
+    assert g.observables_mean()["samples"] == 0
+    g.observables_accumulate(nbins=10)
+    m = g.observables_mean()
+    assert m["samples"] == 1 and m["hist"].sum() == 500 * 31
+    o = g.observables(nbins=10)
+    assert np.array_equal(m["hist"], o["hist"]) and abs(m["r2"] - o["r2"].mean()) <= 1e-12 * o["r2"].mean()
