@@ -46,9 +46,9 @@ def bytes_per_event(beads_per_cell: float) -> float:
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ecmc_sweep_c3_1M_hbm_traffic.md")
 BATCH_COUNTERS = os.path.join(ROOT, "profiles", "ecmc_sweep_c4_256melts_counters.md")
+# the sources the profiled sweep kernel is built from: its translation unit and the headers it includes
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1502_06447_amd", "csrc", f)
-                  for f in ("ecmc_device.h", "ecmc_internal.h", "ecmc_kernels.hip", "ecmc_phase.hip",
-                            "ecmc_sweep.hip")]
+                  for f in ("ecmc_device.h", "ecmc_internal.h", "ecmc_sweep.hip")]
 
 
 def kernel_source_hash() -> str:
