@@ -6,7 +6,8 @@
   the guard is forced from the host with a wait limit of one microsecond, every kernel still
   ends normally, the call reports ECMC_E_DEVICE, and the state stays valid (no overlap, no
   stretched bond, every bead listed in its own cell).
-- The running device sums of the observables agree with the per-sweep observables.
+- The running device sums of the observables agree with the per-sweep observables, for a single
+  melt and for a batch.
 """
 import numpy as np
 import pytest
@@ -107,3 +108,23 @@ def test_observables_accumulate_matches_the_per_sweep_observables(melt_c2):
     assert m["samples"] == 1 and m["hist"].sum() == 500 * 31
     o = g.observables(nbins=10)
     assert np.array_equal(m["hist"], o["hist"]) and abs(m["r2"] - o["r2"].mean()) <= 1e-12 * o["r2"].mean()
+
+
+def test_observables_accumulate_over_a_batch_of_melts():
+    """The running sums over a batch: every polymer of every melt counts once per sample, so the
+    means equal those of the per-sweep observables over all polymers of the batch."""
+    melts = inputs.batch_melts(4, 11, n_choices=(16, 32, 64), beads_range=(1000, 3000))
+    g = ecmc.Melt.from_batch(melts, ecmc.Options())
+    r2s, rg2s, hist = [], [], np.zeros(16, dtype=np.int64)
+    for k in range(2):
+        g.sweep(g.n_beads, 20.0, 700 + k)
+        g.observables_accumulate(nbins=16)
+        o = g.observables(nbins=16)
+        assert o["n_poly"] == sum(m.n_poly for m in melts)
+        r2s.append(o["r2"].mean())
+        rg2s.append(o["rg2"].mean())
+        hist += o["hist"]
+    m = g.observables_mean()
+    assert m["samples"] == 2 and np.array_equal(m["hist"], hist)
+    assert abs(m["r2"] - np.mean(r2s)) <= 1e-12 * np.mean(r2s)
+    assert abs(m["rg2"] - np.mean(rg2s)) <= 1e-12 * np.mean(rg2s)
